@@ -260,14 +260,17 @@ int orc_state_collides(const orc_robot *rb, const orc_env *env, const double *q)
     return isnan(cm) ? 1 : (cm < 0.0);
 }
 
-/* Number of discretized states of edge qa->qb at per-joint resolution res (Sec. III-D). */
+/* Number of discretized states of edge qa->qb at per-joint resolution res (Sec. III-D).
+ * An edge with a non-finite endpoint is reduced to its two endpoints (it collides anyway). */
 int orc_edge_n_states(const double *qa, const double *qb, int dof, double res) {
     double L = 0.0;
     for (int j = 0; j < dof; ++j) {
         double d = fabs(qb[j] - qa[j]);
+        if (!isfinite(d)) return 2;
         if (d > L) L = d;
     }
     double n = ceil(L / res) + 1.0;
+    if (!(n < 2147483647.0)) return 2147483647;
     return n < 2.0 ? 2 : (int)n;
 }
 
@@ -490,6 +493,14 @@ static void *run_job(void *arg) {
             int n = jb->n_states ? jb->n_states[i] : orc_edge_n_states(qa, qb, dof, jb->res);
             int hit = 0, near = 0;
             double emin = INFINITY;
+            if (n < 2) n = 2;
+            if (!all_finite(qa, dof) || !all_finite(qb, dof)) {
+                /* a non-finite endpoint is a non-finite state of the edge: colliding */
+                jb->flag[i] = 1;
+                if (jb->cls) jb->cls[i] = 1;
+                if (jb->out) jb->out[i] = NAN;
+                continue;
+            }
             for (int k = 0; k < n; ++k) {
                 orc_edge_state(qa, qb, dof, n, k, q);
                 double cm = orc_state_min_clearance(jb->rb, jb->env, q);

@@ -92,6 +92,21 @@ def test_edge_state_count(orc, L, res, n):
     assert orc.edge_n_states(qa, qb, res) == n
 
 
+def test_non_finite_edges_collide(orc):
+    """A non-finite joint value makes a state colliding, so an edge with a non-finite endpoint
+    collides whatever its other joints do (including an infinite joint span)."""
+    w = workload("edges7_shelf", n=4)
+    qa, qb = w["qa"].astype(np.float64), w["qb"].astype(np.float64)
+    qa[0, 1] = np.nan
+    qb[1, 0] = np.inf
+    qa[2, 6] = -np.inf
+    qb[2, 6] = -np.inf
+    flag, cls, emin = orc.edges(w["robot"], w["env"], qa, qb)
+    assert list(flag[:3]) == [1, 1, 1] and list(cls[:3]) == [1, 1, 1]
+    assert np.isnan(emin[:3]).all()
+    assert orc.edge_n_states(qa[1], qb[1], 1 / 32) == 2
+
+
 def test_edge_states_endpoints_and_spacing(orc):
     g = np.random.default_rng(3)
     for _ in range(20):
