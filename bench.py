@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark: validated states/s of batched edge validation at 7-DoF on one MI355X.
+
+Workload (synthetic, seeded): the 7-DoF DH chain (42 spheres, 540 self pairs) in the shelf
+scene (100 oriented boxes + 50 capsules); 65,536 edges with endpoints uniform in the joint
+limits, discretised at 1/32 rad per joint (2..187 states per edge).  One step validates the
+whole batch in one persistent launch (`validate_edges`); the plain one-launch-per-edge path
+(`validate_edges_per_edge`) is timed on the same batch for comparison.
+
+`value` = nominal states (sum of the edges' state counts) per second of the batched step,
+inputs resident in HBM.  The roofline entry divides the FP32 operations the launch actually
+executes (counted by the instrumented variant of the same kernel) by the mean launch time
+measured with HIP events on the launch stream.  `cpu_baseline` is the FP64 oracle on a bounded
+sample of the same edges, on all host cores.
+
+Progress goes to stderr; stdout carries exactly one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12          # MI355X vector FP32, packed (published)
+PEAK_FP32_UNPACKED = 78.6e12  # without packed FP32 instructions (this build disables them)
+RES = 1.0 / 32.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def state_counts(qa, qb, res):
+    """Per-edge state count (the metric's denominator): max(2, ceil(L / res) + 1)."""
+    L = np.max(np.abs(qb.astype(np.float64) - qa.astype(np.float64)), axis=1)
+    return np.maximum(2, np.ceil(L / res) + 1).astype(np.int64)
+
+
+def cpu_baseline(w, budget_s=12.0):
+    from oracle import oracle as O
+    rb, ev = O.Robot(w["robot"]), O.Env(w["env"])
+    threads = O.threads(0)
+    n = 512
+    E = len(w["qa"])
+    while True:
+        idx = np.arange(min(n, E))
+        t0 = time.perf_counter()
+        O.edges(rb, ev, w["qa"][idx], w["qb"][idx], res=RES, early=True, n_threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 3 or len(idx) == E:
+            break
+        n *= 2
+    states = int(state_counts(w["qa"][idx], w["qb"][idx], RES).sum())
+    log(f"cpu oracle: {len(idx)} edges, {states} states in {dt:.2f}s on {threads} threads")
+    return {"value": states / dt, "unit": "states/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {len(idx)} of the {E} edges ({states} nominal states), FP64 scalar "
+                      f"oracle with first-hit stop per edge, {threads} threads, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--per-edge-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="edges7_shelf", choices=["edges7_shelf", "edges8_shelf"])
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the validation path shards into independent edge "
+              "ranges with no exchange, and this build runs and reports a single MI355X "
+              "(use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2309_14545_amd as vk
+    from synthetic import workload, robot_summary, scene_summary
+
+    torch.cuda.set_device(0)
+    w = workload(args.workload)
+    E = len(w["qa"])
+    counts = state_counts(w["qa"], w["qb"], RES)
+    nominal = int(counts.sum())
+    log(f"workload {args.workload}: {E} edges, {nominal} nominal states")
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa = torch.from_numpy(w["qa"]).cuda()
+    qb = torch.from_numpy(w["qb"]).cuda()
+    out = torch.empty(E, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    # executed FP32 work of one launch (instrumented variant, untimed)
+    flops_t = torch.zeros(1, dtype=torch.int64, device="cuda")
+    vk.validate_edges_counted(robot, env, qa, qb, flops_t, resolution=RES, out=out)
+    torch.cuda.synchronize()
+    flops = int(flops_t.item())
+    flags_counted = out.cpu().numpy().copy()
+
+    for _ in range(args.warmup):
+        vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launch_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = nominal * args.steps / (t1 - t0)
+    flags = out.cpu().numpy()
+    assert np.array_equal(flags, flags_counted), "counted and timed launches disagree"
+    log(f"batched: {ms_step:.3f} ms/step (launch {launch_ms:.3f} ms), {value:.3e} states/s, "
+        f"edge collision rate {flags.mean():.3f}")
+
+    # plain one-launch-per-edge baseline on the same batch
+    pe_out = torch.empty_like(out)
+    vk.validate_edges(robot, env, qa, qb, resolution=RES, out=pe_out, per_edge=True)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for _ in range(args.per_edge_steps):
+        vk.validate_edges(robot, env, qa, qb, resolution=RES, out=pe_out, per_edge=True)
+    torch.cuda.synchronize()
+    p1 = time.perf_counter()
+    pe_ms = (p1 - p0) * 1e3 / args.per_edge_steps
+    pe_value = nominal * args.per_edge_steps / (p1 - p0)
+    assert np.array_equal(pe_out.cpu().numpy(), flags), "per-edge and batched flags differ"
+    log(f"per-edge: {pe_ms:.1f} ms/step, {pe_value:.3e} states/s")
+
+    achieved = flops / (launch_ms * 1e-3)
+    result = {
+        "metric": "validated states/sec at 7-DoF (batched vs per-edge) + % FP32 peak",
+        "value": value,
+        "unit": "states/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "robot": robot_summary(w["robot"]),
+            "scene": scene_summary(w["env"]),
+            "edges": E,
+            "nominal_states": nominal,
+            "resolution_rad": RES,
+            "edge_collision_rate": float(flags.mean()),
+            "launch": list(vk.get_edge_launch()),
+        },
+        "per_edge": {"value": pe_value, "unit": "states/s", "ms_per_step": pe_ms,
+                     "launches_per_step": E, "steps": args.per_edge_steps},
+        "speedup_vs_per_edge": value / pe_value,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32,
+            "frac_of_unpacked": achieved / PEAK_FP32_UNPACKED,
+            "traffic": None,
+            "kernel": "k_validate_edges<LDS=true>",
+            "flop_per_launch": flops,
+            "launch_ms": launch_ms,
+        },
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

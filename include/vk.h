@@ -1,0 +1,210 @@
+/*
+ * vk.h -- C ABI of the MI355X vectorized motion-validation library (libvk.so).
+ *
+ * Implements the hot path of "Motions in Microseconds via Vectorized Sampling-Based Planning"
+ * (arXiv 2309.14545): forward kinematics (FK) of a revolute kinematic tree over many
+ * configurations at once (Sec. III-B), placement of the robot's collision spheres and
+ * sphere-vs-primitive plus self-collision tests (Sec. III-C), and motion (edge) validation by
+ * discretising a straight joint-space motion with a "rake" ordering and first-hit early exit
+ * (Sec. III-D).  Two extensions use the same kernels: a differentiable squared-penetration
+ * cost with a hand-written adjoint, and mixed-robot edge batches replayed from a HIP graph.
+ *
+ * Conventions shared by every entry point
+ *   - Plain C types only.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Batch arrays (q, qa, qb, collide, centres, cost, grad) are DEVICE pointers owned by the
+ *     caller; the call only enqueues work on `stream` and returns.  Results are valid once the
+ *     caller synchronises that stream.  Description structs are HOST memory, copied at create.
+ *   - Handles (vk_robot, vk_env, vk_edge_batch) are owned by the library; destroy them when no
+ *     enqueued work still uses them (after a stream sync).
+ *   - Configurations in a state batch are structure-of-arrays: q[j * ldq + i] is joint j of
+ *     state i (Sec. III-A, struct-of-arrays layout); edge endpoints are array-of-structs:
+ *     qa[e * dof + j].
+ *   - Output polarity: 1 = in collision (invalid), 0 = free.
+ *   - Arguments are checked when the call is made: NULL handles or pointers, n < 0, ld < n and
+ *     inconsistent sizes return an error and enqueue nothing; n == 0 is a no-op returning VK_OK.
+ *     An asynchronous device fault surfaces as VK_ERR_HIP from a later call or from the
+ *     caller's stream synchronisation.  vk_last_error() gives a text for the last error of the
+ *     calling thread.
+ *   - Joint limits are not checked (validity means collision-free, Sec. III-D).  A state with
+ *     a non-finite joint value is reported as colliding; its cost and gradient are NaN.
+ *   - A handle may be used from several streams at once; a vk_edge_batch may not.
+ */
+#ifndef VK_H
+#define VK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vk_status;
+#define VK_OK 0
+#define VK_ERR_INVALID_ARG (-1)  /* NULL pointer, negative size, bad index or value          */
+#define VK_ERR_SHAPE (-2)        /* leading dimension or size inconsistent with the handle  */
+#define VK_ERR_UNSUPPORTED (-3)  /* a description the kernels do not handle (see create)    */
+#define VK_ERR_HIP (-4)          /* a HIP runtime call failed                                */
+#define VK_ERR_OOM (-5)          /* device allocation failed                                 */
+
+typedef struct vk_robot_s *vk_robot;
+typedef struct vk_env_s *vk_env;
+typedef struct vk_edge_batch_s *vk_edge_batch;
+
+/*
+ * Robot: a revolute kinematic tree whose links carry collision spheres (Sec. III-C).
+ * Links are numbered 0..dof; link 0 is the fixed base at the world origin; joint j moves link
+ * j+1 and hangs off link parent_link[j] (0 <= parent_link[j] <= j).  Frames follow standard DH:
+ *   P_j = T_parent(j) * M_j,  T_{j+1} = P_j * Rz(q_j + theta_offset_j) Tz(d_j) Tx(a_j) Rx(alpha_j)
+ * and joint j turns about the z axis of P_j.
+ */
+typedef struct {
+    int32_t dof;                  /* 1..64                                                    */
+    const int32_t *parent_link;   /* [dof]; NULL = serial chain (parent_link[j] = j)          */
+    const float *mount;           /* [dof][12] row-major 3x4 fixed transforms; NULL = identity */
+    const float *dh;              /* [dof][5]: a, d, cos(alpha), sin(alpha), theta_offset      */
+    const float *q_lo;            /* [dof] informational, not checked; may be NULL             */
+    const float *q_hi;            /* [dof] informational, not checked; may be NULL             */
+    int32_t n_spheres;            /* S >= 0                                                    */
+    const int32_t *sphere_link;   /* [S] link of each sphere, 0..dof, non-decreasing           */
+    const float *sphere_xyzr;     /* [S][4] centre in the link frame, radius > 0               */
+    int32_t n_self_pairs;         /* P >= 0                                                    */
+    const int32_t *self_pairs;    /* [P][2] sphere indices on two different links              */
+} vk_robot_desc;
+
+/* Environment of primitives (Sec. III-C: spheres, cylinders, cuboids; capsules = swept
+ * spheres).  Counts may be zero (the matching pointer may then be NULL). */
+typedef struct {
+    int32_t n_spheres;   const float *spheres;    /* [n][4]  centre, radius                     */
+    int32_t n_capsules;  const float *capsules;   /* [n][7]  end p0, end p1, radius             */
+    int32_t n_cylinders; const float *cylinders;  /* [n][8]  centre, unit axis, half height, r  */
+    int32_t n_boxes;     const float *boxes;      /* [n][15] centre, row-major 3x3 rotation
+                                                   *         (its columns are the box axes),
+                                                   *         half extents                       */
+} vk_env_desc;
+
+/* Create / destroy a device-resident robot.  The library precomputes, per link, a bounding
+ * sphere of the link's spheres (the mid-phase of Sec. III-D) and orders the self pairs by
+ * their later link so each is tested right after that link is posed (interleaving,
+ * Sec. III-D).  Errors: VK_ERR_INVALID_ARG for a bad parent, link index, sphere order, radius
+ * <= 0 or a pair on one link; VK_ERR_UNSUPPORTED for dof > 64. */
+vk_status vk_robot_create(const vk_robot_desc *desc, vk_robot *out);
+vk_status vk_robot_destroy(vk_robot robot);
+int32_t vk_robot_dof(vk_robot robot);
+int32_t vk_robot_n_spheres(vk_robot robot);
+
+/* Create / destroy a device-resident environment.  Large point-cloud-like sets of spheres get
+ * a uniform grid index (broadphase) built here; queries are unchanged. */
+vk_status vk_env_create(const vk_env_desc *desc, vk_env *out);
+vk_status vk_env_destroy(vk_env env);
+
+/*
+ * Sphere centres of n states (Sec. III-B FK + Sec. III-C, positions only).
+ *   q       [dof][ldq] float, device, SoA
+ *   centres [S][3][ldc] float, device: centres[(s*3 + axis)*ldc + i]
+ * Requires ldq >= n, ldc >= n.
+ */
+vk_status fk_spheres(vk_robot robot, const float *q, int64_t n, int64_t ldq, float *centres,
+                     int64_t ldc, void *stream);
+
+/*
+ * Collision flag of n states (Sec. III-C): 1 if some robot sphere overlaps some primitive or
+ * some listed self pair overlaps (clearance < 0), else 0.
+ *   q       [dof][ldq] float, device, SoA; ldq >= n
+ *   collide [n] uint8, device
+ */
+vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n, int64_t ldq,
+                          uint8_t *collide, void *stream);
+
+/*
+ * Collision flag of n_edges straight joint-space motions (Sec. III-D).  Edge e from qa to qb is
+ * discretised into n_e states q_k = qa + k/(n_e-1) (qb - qa), k = 0..n_e-1, both endpoints
+ * included, with n_e = n_states[e] if n_states is given, else
+ *   n_e = max(2, ceil(max_j |qb_j - qa_j| / resolution) + 1)
+ * evaluated in double precision (so it is exact for FP32 inputs and a power-of-two
+ * resolution).  collide[e] = OR of the state flags.  States are visited in rake order (lane l
+ * of a 64-wide wavefront takes states l*ceil(n_e/64) + k at step k) and the edge stops at the
+ * first colliding state found; the flag does not depend on the order.  All edges run in one
+ * persistent launch that pulls edges from a device work queue.
+ *   qa, qb    [n_edges][dof] float, device
+ *   n_states  [n_edges] int32, device, each >= 2; or NULL
+ *   resolution > 0 (radians per step, per joint); ignored when n_states is given
+ *   collide   [n_edges] uint8, device
+ */
+vk_status validate_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                         const int32_t *n_states, int64_t n_edges, float resolution,
+                         uint8_t *collide, void *stream);
+
+/* Same contract as validate_edges, but one kernel launch per edge (the plain baseline the
+ * batched launch is measured against). */
+vk_status validate_edges_per_edge(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                                  const int32_t *n_states, int64_t n_edges, float resolution,
+                                  uint8_t *collide, void *stream);
+
+/* Measurement variant of validate_edges: the same flags from the same kernel code, which in
+ * addition adds to *flops (one device uint64, not cleared by the call) the FP32 operations the
+ * launch executed: per wave-uniform step the model's count (fused multiply-add = 2; revolute
+ * joint 30, mount 63, sphere placement 18, sphere-sphere and self pair 11, capsule 25, box 34,
+ * cylinder 35) times the 64 lanes that issue it.  Early exits and mid-phase skips are thereby
+ * excluded; masked lanes are included. */
+vk_status validate_edges_counted(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                                 const int32_t *n_states, int64_t n_edges, float resolution,
+                                 uint8_t *collide, uint64_t *flops, void *stream);
+
+/*
+ * Squared-penetration cost per state (differentiable extension):
+ *   cost = sum_{s,o} max(0, r_s - sd_o(c_s))^2 + sum_{(s,t) in pairs} max(0, r_s + r_t - |c_s - c_t|)^2
+ * over every robot sphere s and primitive o (sd = signed distance) and every listed self pair.
+ *   q [dof][ldq] float, device; cost [n] float, device
+ */
+vk_status penetration_cost_fwd(vk_robot robot, vk_env env, const float *q, int64_t n,
+                               int64_t ldq, float *cost, void *stream);
+
+/*
+ * Adjoint of penetration_cost_fwd: grad_q[j][i] = grad_cost[i] * d cost_i / d q_j.  The kernel
+ * recomputes FK, forms the force f_s = d cost / d c_s on every sphere and pulls it back through
+ * the joint axes (dq_j = z_j . sum over spheres beyond j of (c_s - o_j) x f_s).
+ *   grad_cost [n] float, device; grad_q [dof][ldg] float, device, ldg >= n
+ */
+vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64_t n,
+                               int64_t ldq, const float *grad_cost, float *grad_q, int64_t ldg,
+                               void *stream);
+
+/*
+ * Mixed-robot edge batches: several edge sets, each with its own robot and environment, run as
+ * one persistent launch; the launch is captured once in a HIP graph and replayed by
+ * vk_edge_batch_run.  Set k covers edges [edge_offset, edge_offset + n_edges) of the qa/qb
+ * arrays given to vk_edge_batch_create (AoS with that set's robot dof, offsets in floats) and
+ * writes collide[out_offset + i].  The arrays passed at create are device pointers that must
+ * stay valid for the batch's life; run replays on them.
+ */
+typedef struct {
+    int32_t robot;          /* index into robots[] */
+    int32_t env;            /* index into envs[]   */
+    int64_t qa_offset;      /* float offset of the set's first edge in qa and qb */
+    int64_t n_edges;
+    int64_t out_offset;     /* offset of the set's first flag in collide */
+} vk_edge_set;
+
+vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const vk_env *envs,
+                               int32_t n_envs, const vk_edge_set *sets, int32_t n_sets,
+                               float resolution, const float *qa, const float *qb,
+                               uint8_t *collide, void *stream, vk_edge_batch *out);
+vk_status vk_edge_batch_run(vk_edge_batch batch, void *stream);
+vk_status vk_edge_batch_destroy(vk_edge_batch batch);
+
+/*
+ * Launch configuration of the persistent edge launches (validate_edges and batches created
+ * afterwards): workgroup size (64, 128, 192 or 256) and workgroups per compute unit (1..64).  Both 0 restores the built-in default.  The
+ * project's autotuner (a Python helper next to the binding) times candidates and calls this.
+ */
+vk_status vk_set_edge_launch(int32_t block_threads, int32_t blocks_per_cu);
+vk_status vk_get_edge_launch(int32_t *block_threads, int32_t *blocks_per_cu);
+
+/* Text of the calling thread's last non-OK status ("" if none). */
+const char *vk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VK_H */

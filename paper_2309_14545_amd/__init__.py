@@ -1,0 +1,347 @@
+"""Python binding of libvk (the C ABI in include/vk.h): argument marshalling only.
+
+Every step of the validation path runs in the HIP kernels of libvk.so; PyTorch supplies device
+memory and the current stream.  Importing this module does not need a GPU, but every call
+that enqueues work needs the built library and a HIP device, and fails loudly otherwise.
+
+Layouts follow the C ABI: a batch of configurations is SoA ``[dof, N]`` float32; edge endpoints
+are ``[E, dof]`` float32; flags are uint8 (1 = in collision).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvk.so")
+
+VK_OK = 0
+_STATUS = {-1: "VK_ERR_INVALID_ARG", -2: "VK_ERR_SHAPE", -3: "VK_ERR_UNSUPPORTED",
+           -4: "VK_ERR_HIP", -5: "VK_ERR_OOM"}
+
+EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_spheres",
+           "vk_env_create", "vk_env_destroy", "fk_spheres", "validate_states", "validate_edges",
+           "validate_edges_per_edge", "validate_edges_counted", "penetration_cost_fwd", "penetration_cost_bwd",
+           "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_destroy",
+           "vk_set_edge_launch", "vk_get_edge_launch", "vk_last_error")
+
+
+class VkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _RobotDesc(C.Structure):
+    _fields_ = [("dof", C.c_int32), ("parent_link", C.POINTER(C.c_int32)),
+                ("mount", C.POINTER(C.c_float)), ("dh", C.POINTER(C.c_float)),
+                ("q_lo", C.POINTER(C.c_float)), ("q_hi", C.POINTER(C.c_float)),
+                ("n_spheres", C.c_int32), ("sphere_link", C.POINTER(C.c_int32)),
+                ("sphere_xyzr", C.POINTER(C.c_float)), ("n_self_pairs", C.c_int32),
+                ("self_pairs", C.POINTER(C.c_int32))]
+
+
+class _EnvDesc(C.Structure):
+    _fields_ = [("n_spheres", C.c_int32), ("spheres", C.POINTER(C.c_float)),
+                ("n_capsules", C.c_int32), ("capsules", C.POINTER(C.c_float)),
+                ("n_cylinders", C.c_int32), ("cylinders", C.POINTER(C.c_float)),
+                ("n_boxes", C.c_int32), ("boxes", C.POINTER(C.c_float))]
+
+
+class _EdgeSet(C.Structure):
+    _fields_ = [("robot", C.c_int32), ("env", C.c_int32), ("qa_offset", C.c_int64),
+                ("n_edges", C.c_int64), ("out_offset", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvk.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2309_14545_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, fp = C.c_void_p, C.c_int64, C.c_int32, C.c_float
+        L.vk_robot_create.argtypes = [C.POINTER(_RobotDesc), C.POINTER(vp)]
+        L.vk_robot_destroy.argtypes = [vp]
+        L.vk_robot_dof.argtypes = [vp]
+        L.vk_robot_dof.restype = i32
+        L.vk_robot_n_spheres.argtypes = [vp]
+        L.vk_robot_n_spheres.restype = i32
+        L.vk_env_create.argtypes = [C.POINTER(_EnvDesc), C.POINTER(vp)]
+        L.vk_env_destroy.argtypes = [vp]
+        L.fk_spheres.argtypes = [vp, vp, i64, i64, vp, i64, vp]
+        L.validate_states.argtypes = [vp, vp, vp, i64, i64, vp, vp]
+        L.validate_edges.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp]
+        L.validate_edges_per_edge.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp]
+        L.validate_edges_counted.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp, vp]
+        L.penetration_cost_fwd.argtypes = [vp, vp, vp, i64, i64, vp, vp]
+        L.penetration_cost_bwd.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
+        L.vk_edge_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), i32,
+                                           C.POINTER(_EdgeSet), i32, fp, vp, vp, vp, vp,
+                                           C.POINTER(vp)]
+        L.vk_edge_batch_run.argtypes = [vp, vp]
+        L.vk_edge_batch_destroy.argtypes = [vp]
+        L.vk_set_edge_launch.argtypes = [i32, i32]
+        L.vk_get_edge_launch.argtypes = [C.POINTER(i32), C.POINTER(i32)]
+        L.vk_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("vk_robot_dof", "vk_robot_n_spheres", "vk_last_error"):
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != VK_OK:
+        raise VkError(status, lib().vk_last_error().decode())
+
+
+def _f32(a, shape):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(shape))
+
+
+def _i32(a, shape):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(shape))
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+
+
+class Robot:
+    """Device-resident robot (see vk_robot_desc).  ``desc`` is a dict of numpy arrays."""
+
+    def __init__(self, desc: dict):
+        dof = int(desc["dof"])
+        keep = {
+            "parent_link": _i32(desc["parent_link"], (-1,)) if desc.get("parent_link") is not None else None,
+            "mount": _f32(desc["mount"], (-1, 12)) if desc.get("mount") is not None else None,
+            "dh": _f32(desc["dh"], (-1, 5)),
+            "sphere_link": _i32(desc["sphere_link"], (-1,)),
+            "sphere_xyzr": _f32(desc["sphere_xyzr"], (-1, 4)),
+            "self_pairs": _i32(desc.get("self_pairs", np.zeros((0, 2))), (-1, 2)),
+        }
+        d = _RobotDesc(dof, _ip(keep["parent_link"]), _fp(keep["mount"]), _fp(keep["dh"]), None,
+                       None, len(keep["sphere_link"]), _ip(keep["sphere_link"]),
+                       _fp(keep["sphere_xyzr"]), len(keep["self_pairs"]), _ip(keep["self_pairs"]))
+        h = C.c_void_p()
+        _check(lib().vk_robot_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.dof = dof
+        self.n_spheres = len(keep["sphere_link"])
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vk_robot_destroy(self.handle)
+            self.handle = None
+
+
+class Env:
+    """Device-resident environment (see vk_env_desc)."""
+
+    def __init__(self, desc: dict):
+        arrs = {}
+        for key, w in (("spheres", 4), ("capsules", 7), ("cylinders", 8), ("boxes", 15)):
+            a = desc.get(key)
+            arrs[key] = _f32(a if a is not None else np.zeros((0, w)), (-1, w))
+        d = _EnvDesc(len(arrs["spheres"]), _fp(arrs["spheres"]), len(arrs["capsules"]),
+                     _fp(arrs["capsules"]), len(arrs["cylinders"]), _fp(arrs["cylinders"]),
+                     len(arrs["boxes"]), _fp(arrs["boxes"]))
+        h = C.c_void_p()
+        _check(lib().vk_env_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.counts = {k: len(v) for k, v in arrs.items()}
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vk_env_destroy(self.handle)
+            self.handle = None
+
+
+# --- device tensors ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dev_f32(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError(f"{name} must be a float32 CUDA (HIP) tensor")
+    return t.contiguous()
+
+
+def _soa(robot, q, name="q"):
+    q = _dev_f32(q, name)
+    if q.dim() != 2 or q.shape[0] != robot.dof:
+        raise ValueError(f"{name} must be [dof={robot.dof}, N] (structure of arrays)")
+    return q
+
+
+def fk_spheres(robot: Robot, q):
+    """Sphere centres [S, 3, N] of the SoA batch q [dof, N]."""
+    torch = _torch()
+    q = _soa(robot, q)
+    n = q.shape[1]
+    out = torch.empty((robot.n_spheres, 3, n), dtype=torch.float32, device=q.device)
+    _check(lib().fk_spheres(robot.handle, q.data_ptr(), n, n, out.data_ptr(), n, _stream()))
+    return out
+
+
+def validate_states(robot: Robot, env: Env, q):
+    """Collision flags uint8 [N] of the SoA batch q [dof, N]."""
+    torch = _torch()
+    q = _soa(robot, q)
+    n = q.shape[1]
+    out = torch.empty(n, dtype=torch.uint8, device=q.device)
+    _check(lib().validate_states(robot.handle, env.handle, q.data_ptr(), n, n, out.data_ptr(),
+                                 _stream()))
+    return out
+
+
+def validate_edges(robot: Robot, env: Env, qa, qb, n_states=None, resolution: float = 1.0 / 32.0,
+                   per_edge: bool = False, out=None):
+    """Edge collision flags uint8 [E] for endpoints qa, qb [E, dof].
+
+    ``per_edge=True`` uses one kernel launch per edge (the baseline); otherwise all edges run
+    in one persistent launch."""
+    torch = _torch()
+    qa, qb = _dev_f32(qa, "qa"), _dev_f32(qb, "qb")
+    if qa.dim() != 2 or qa.shape != qb.shape or qa.shape[1] != robot.dof:
+        raise ValueError(f"qa and qb must both be [E, dof={robot.dof}]")
+    E = qa.shape[0]
+    ns_ptr = None
+    if n_states is not None:
+        if not (isinstance(n_states, torch.Tensor) and n_states.is_cuda and n_states.dtype == torch.int32
+                and n_states.shape == (E,)):
+            raise TypeError("n_states must be an int32 CUDA tensor [E]")
+        n_states = n_states.contiguous()
+        ns_ptr = n_states.data_ptr()
+    if out is None:
+        out = torch.empty(E, dtype=torch.uint8, device=qa.device)
+    fn = lib().validate_edges_per_edge if per_edge else lib().validate_edges
+    _check(fn(robot.handle, env.handle, qa.data_ptr(), qb.data_ptr(), ns_ptr, E, float(resolution),
+              out.data_ptr(), _stream()))
+    return out
+
+
+def validate_edges_counted(robot: Robot, env: Env, qa, qb, flops, n_states=None,
+                           resolution: float = 1.0 / 32.0, out=None):
+    """validate_edges plus executed-FLOP accounting into ``flops`` (int64 CUDA tensor [1])."""
+    torch = _torch()
+    qa, qb = _dev_f32(qa, "qa"), _dev_f32(qb, "qb")
+    if qa.dim() != 2 or qa.shape != qb.shape or qa.shape[1] != robot.dof:
+        raise ValueError(f"qa and qb must both be [E, dof={robot.dof}]")
+    if not (isinstance(flops, torch.Tensor) and flops.is_cuda and flops.dtype == torch.int64):
+        raise TypeError("flops must be an int64 CUDA tensor")
+    E = qa.shape[0]
+    ns_ptr = n_states.contiguous().data_ptr() if n_states is not None else None
+    if out is None:
+        out = torch.empty(E, dtype=torch.uint8, device=qa.device)
+    _check(lib().validate_edges_counted(robot.handle, env.handle, qa.data_ptr(), qb.data_ptr(),
+                                        ns_ptr, E, float(resolution), out.data_ptr(),
+                                        flops.data_ptr(), _stream()))
+    return out
+
+
+def penetration_cost_fwd(robot: Robot, env: Env, q):
+    """Squared-penetration cost float32 [N] of the SoA batch q [dof, N]."""
+    torch = _torch()
+    q = _soa(robot, q)
+    n = q.shape[1]
+    out = torch.empty(n, dtype=torch.float32, device=q.device)
+    _check(lib().penetration_cost_fwd(robot.handle, env.handle, q.data_ptr(), n, n,
+                                      out.data_ptr(), _stream()))
+    return out
+
+
+def penetration_cost_bwd(robot: Robot, env: Env, q, grad_cost):
+    """grad_q [dof, N] = grad_cost[i] * d cost_i / d q."""
+    torch = _torch()
+    q = _soa(robot, q)
+    n = q.shape[1]
+    g = _dev_f32(grad_cost, "grad_cost")
+    if g.shape != (n,):
+        raise ValueError("grad_cost must be [N]")
+    out = torch.empty((robot.dof, n), dtype=torch.float32, device=q.device)
+    _check(lib().penetration_cost_bwd(robot.handle, env.handle, q.data_ptr(), n, n, g.data_ptr(),
+                                      out.data_ptr(), n, _stream()))
+    return out
+
+
+def _make_cost_function():
+    torch = _torch()
+
+    class PenetrationCost(torch.autograd.Function):
+        """cost = PenetrationCost.apply(q, robot, env): differentiable in q ([dof, N])."""
+
+        @staticmethod
+        def forward(ctx, q, robot, env):
+            ctx.robot, ctx.env = robot, env
+            ctx.save_for_backward(q)
+            return penetration_cost_fwd(robot, env, q)
+
+        @staticmethod
+        def backward(ctx, grad_cost):
+            (q,) = ctx.saved_tensors
+            g = penetration_cost_bwd(ctx.robot, ctx.env, q, grad_cost.contiguous())
+            return g, None, None
+
+    return PenetrationCost
+
+
+_PC = None
+
+
+def penetration_cost(q, robot: Robot, env: Env):
+    """Autograd entry point: cost [N] whose backward runs the adjoint kernel."""
+    global _PC
+    if _PC is None:
+        _PC = _make_cost_function()
+    return _PC.apply(q, robot, env)
+
+
+class EdgeBatch:
+    """Mixed-robot edge batch replayed from a HIP graph (vk_edge_batch_*)."""
+
+    def __init__(self, robots, envs, sets, qa, qb, out, resolution: float = 1.0 / 32.0):
+        self._keep = (list(robots), list(envs), qa, qb, out)
+        rh = (C.c_void_p * len(robots))(*[r.handle.value for r in robots])
+        eh = (C.c_void_p * len(envs))(*[e.handle.value for e in envs])
+        st = (_EdgeSet * len(sets))(*[_EdgeSet(*s) for s in sets])
+        h = C.c_void_p()
+        _check(lib().vk_edge_batch_create(rh, len(robots), eh, len(envs), st, len(sets),
+                                          float(resolution), qa.data_ptr(), qb.data_ptr(),
+                                          out.data_ptr(), _stream(), C.byref(h)))
+        self.handle = h
+
+    def run(self):
+        _check(lib().vk_edge_batch_run(self.handle, _stream()))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vk_edge_batch_destroy(self.handle)
+            self.handle = None
+
+
+def set_edge_launch(block_threads: int = 0, blocks_per_cu: int = 0):
+    _check(lib().vk_set_edge_launch(int(block_threads), int(blocks_per_cu)))
+
+
+def get_edge_launch():
+    b, p = C.c_int32(), C.c_int32()
+    _check(lib().vk_get_edge_launch(C.byref(b), C.byref(p)))
+    return b.value, p.value

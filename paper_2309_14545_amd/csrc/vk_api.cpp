@@ -1,0 +1,752 @@
+// C-ABI layer of libvk: handle creation (robot program, environment records, point-cloud grid),
+// argument checks and kernel launches.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "vk.h"
+#include "vk_launch.hpp"
+#include "vk_types.hpp"
+
+using namespace vk;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct VkError : std::runtime_error {
+    vk_status code;
+    VkError(vk_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void raise(vk_status c, const std::string &m) { throw VkError(c, m); }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) raise(VK_ERR_OOM, std::string(what) + ": out of device memory");
+    raise(VK_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F>
+vk_status guarded(F &&f) {
+    try {
+        f();
+        return VK_OK;
+    } catch (const VkError &e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return VK_ERR_OOM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return VK_ERR_INVALID_ARG;
+    }
+}
+
+struct DeviceInfo {
+    int n_cu = 0;
+    size_t max_lds = 0;
+};
+
+std::mutex g_mu;
+std::map<int, DeviceInfo> g_dev;
+std::map<std::pair<int, hipStream_t>, unsigned long long *> g_queues;
+int g_edge_block = 256;
+int g_edge_bpc = 4;
+
+const DeviceInfo &device_info(int dev) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev.find(dev);
+    if (it != g_dev.end()) return it->second;
+    DeviceInfo d;
+    int v = 0;
+    hip_check(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev), "device CUs");
+    d.n_cu = v;
+    hip_check(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+              "device LDS");
+    d.max_lds = (size_t)v;
+    return g_dev[dev] = d;
+}
+
+int current_device() {
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    return dev;
+}
+
+// One counter per (device, stream) for the persistent launch's work queue: calls on different
+// streams never share a counter.  Allocated on a stream's first persistent launch.
+unsigned long long *queue_for(int dev, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, s);
+    auto it = g_queues.find(key);
+    if (it != g_queues.end()) return it->second;
+    void *p = nullptr;
+    hip_check(hipMalloc(&p, 256), "queue counter");
+    return g_queues[key] = static_cast<unsigned long long *>(p);
+}
+
+// Device blob: several host arrays copied into one allocation at 256-byte aligned offsets.
+struct Blob {
+    std::vector<char> host;
+    size_t add(const void *p, size_t bytes) {
+        size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + std::max<size_t>(bytes, 16));
+        if (bytes) std::memcpy(host.data() + off, p, bytes);
+        return off;
+    }
+    void *upload() {
+        void *d = nullptr;
+        hip_check(hipMalloc(&d, host.size()), "hipMalloc");
+        hip_check(hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice), "hipMemcpy");
+        return d;
+    }
+};
+
+bool finite_all(const float *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// Bounding sphere of a set of spheres (AABB centre, radius = farthest reach), rounded up and
+// padded by 1e-5 m so the FP32 mid-phase stays conservative.
+void bounding_sphere(const std::vector<const float *> &sph, float out[4]) {
+    if (sph.empty()) {
+        out[0] = out[1] = out[2] = 0.0f;
+        out[3] = -1.0f;
+        return;
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (const float *s : sph)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], (double)s[a] - s[3]);
+            hi[a] = std::max(hi[a], (double)s[a] + s[3]);
+        }
+    double c[3];
+    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
+    double R = 0.0;
+    for (const float *s : sph) {
+        const double dx = s[0] - c[0], dy = s[1] - c[1], dz = s[2] - c[2];
+        R = std::max(R, std::sqrt(dx * dx + dy * dy + dz * dz) + s[3]);
+    }
+    for (int a = 0; a < 3; ++a) out[a] = (float)c[a];
+    out[3] = std::nextafter((float)(R + 1e-5), INFINITY);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Robot
+// ---------------------------------------------------------------------------------------------
+struct vk_robot_s {
+    int device = 0;
+    void *blob = nullptr;
+    RobotDev dev{};
+    int dof = 0, n_spheres = 0;
+};
+
+struct vk_env_s {
+    int device = 0;
+    void *blob = nullptr;
+    EnvDev dev{};
+};
+
+struct vk_edge_batch_s {
+    int device = 0;
+    void *blob = nullptr;              // BatchSet records and set prefix sums
+    unsigned long long *queue = nullptr;  // the batch's own work-queue counter
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t total = 0;
+};
+
+namespace {
+
+void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
+    if (!d) raise(VK_ERR_INVALID_ARG, "robot desc is NULL");
+    const int dof = d->dof;
+    if (dof < 1) raise(VK_ERR_INVALID_ARG, "dof must be >= 1");
+    if (dof > kMaxDof) raise(VK_ERR_UNSUPPORTED, "dof > 64 is not supported");
+    if (!d->dh) raise(VK_ERR_INVALID_ARG, "dh is NULL");
+    if (!finite_all(d->dh, (size_t)dof * 5)) raise(VK_ERR_INVALID_ARG, "dh has non-finite values");
+    if (d->mount && !finite_all(d->mount, (size_t)dof * 12))
+        raise(VK_ERR_INVALID_ARG, "mount has non-finite values");
+    const int S = d->n_spheres, P = d->n_self_pairs;
+    if (S < 0 || P < 0) raise(VK_ERR_INVALID_ARG, "negative sphere or pair count");
+    if (S > 0 && (!d->sphere_link || !d->sphere_xyzr)) raise(VK_ERR_INVALID_ARG, "spheres are NULL");
+    if (P > 0 && !d->self_pairs) raise(VK_ERR_INVALID_ARG, "self_pairs is NULL");
+
+    std::vector<int> par(dof + 1, -1);      // parent link of every link
+    for (int j = 0; j < dof; ++j) {
+        const int p = d->parent_link ? d->parent_link[j] : j;
+        if (p < 0 || p > j) raise(VK_ERR_INVALID_ARG, "parent_link[j] must be in [0, j]");
+        par[j + 1] = p;
+    }
+    std::vector<int> first(dof + 2, 0), count(dof + 1, 0);
+    for (int s = 0; s < S; ++s) {
+        const int l = d->sphere_link[s];
+        if (l < 0 || l > dof) raise(VK_ERR_INVALID_ARG, "sphere_link out of range");
+        if (s > 0 && l < d->sphere_link[s - 1]) raise(VK_ERR_INVALID_ARG, "sphere_link must be non-decreasing");
+        const float *x = d->sphere_xyzr + 4 * s;
+        if (!finite_all(x, 4) || !(x[3] > 0.0f)) raise(VK_ERR_INVALID_ARG, "sphere radius must be finite and > 0");
+        count[l]++;
+    }
+    for (int l = 0; l <= dof; ++l) first[l + 1] = first[l] + count[l];
+
+    auto anc = [&](int link) {               // joints from the base to `link`, base-most first
+        std::vector<int> v;
+        while (link > 0) {
+            v.push_back(link - 1);
+            link = par[link];
+        }
+        std::reverse(v.begin(), v.end());
+        return v;
+    };
+    auto is_anc = [&](int a, int b) {         // a is b or an ancestor of b
+        while (b > 0 && b != a) b = par[b];
+        return b == a;
+    };
+
+    std::vector<JointRec> joints(dof);
+    for (int j = 0; j < dof; ++j) {
+        JointRec &J = joints[j];
+        std::memset(&J, 0, sizeof J);
+        const float *h = d->dh + 5 * j;
+        J.a = h[0];
+        J.d = h[1];
+        J.ca = h[2];
+        J.sa = h[3];
+        J.theta_off = h[4];
+        J.twist = (h[2] == 1.0f && h[3] == 0.0f)    ? kTwist0
+                  : (h[2] == 0.0f && h[3] == 1.0f)  ? kTwistP90
+                  : (h[2] == 0.0f && h[3] == -1.0f) ? kTwistM90
+                                                    : kTwistGeneral;
+        J.parent = par[j + 1];
+        static const float ident[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+        const float *m = d->mount ? d->mount + 12 * j : ident;
+        std::memcpy(J.m, m, sizeof J.m);
+        J.has_mount = std::memcmp(m, ident, sizeof ident) != 0;
+    }
+
+    // link steps in topological (index) order, spheres in chunks of at most kSpl
+    std::vector<StepRec> steps;
+    std::vector<int> paths;
+    std::vector<int> sphere_step(S, 0), sphere_k(S, 0);
+    int cur = 0;
+    for (int l = 0; l <= dof; ++l) {
+        const int nchunk = std::max(1, (count[l] + kSpl - 1) / kSpl);
+        for (int c = 0; c < nchunk; ++c) {
+            StepRec st;
+            std::memset(&st, 0, sizeof st);
+            st.link = l;
+            st.joint = -1;
+            st.restart_len = -1;
+            if (c == 0 && l > 0) {
+                st.joint = l - 1;
+                if (par[l] != cur) {
+                    std::vector<int> a = anc(par[l]);
+                    st.restart_off = (int)paths.size();
+                    st.restart_len = (int)a.size();
+                    paths.insert(paths.end(), a.begin(), a.end());
+                }
+                cur = l;
+            }
+            st.sph_first = first[l] + c * kSpl;
+            st.sph_count = std::min(kSpl, count[l] - c * kSpl);
+            if (st.sph_count < 0) st.sph_count = 0;
+            std::vector<const float *> sp;
+            for (int k = 0; k < st.sph_count; ++k) {
+                sp.push_back(d->sphere_xyzr + 4 * (st.sph_first + k));
+                sphere_step[st.sph_first + k] = (int)steps.size();
+                sphere_k[st.sph_first + k] = k;
+            }
+            bounding_sphere(sp, st.coarse);
+            steps.push_back(st);
+        }
+        if (l == 0 && count[0] == 0) steps.pop_back();   // nothing to do on an empty base
+    }
+
+    // self pairs: grouped by the step holding the later-link sphere, then by earlier link
+    std::vector<std::map<int, std::map<int, uint32_t>>> grp(steps.size());
+    for (int p = 0; p < P; ++p) {
+        int s = d->self_pairs[2 * p], t = d->self_pairs[2 * p + 1];
+        if (s < 0 || s >= S || t < 0 || t >= S) raise(VK_ERR_INVALID_ARG, "self pair index out of range");
+        int ls = d->sphere_link[s], lt = d->sphere_link[t];
+        if (ls == lt) raise(VK_ERR_INVALID_ARG, "self pair on a single link (rigid, not supported)");
+        if (ls < lt) {
+            std::swap(s, t);
+            std::swap(ls, lt);
+        }
+        grp[sphere_step[s]][lt][t] |= 1u << sphere_k[s];
+    }
+    std::vector<BlockRec> blocks;
+    std::vector<EntryRec> entries;
+    int cur_aux = -1;                         // link whose pose the block frame holds
+    for (size_t si = 0; si < steps.size(); ++si) {
+        steps[si].blk_first = (int)blocks.size();
+        for (auto &kv : grp[si]) {
+            const int A = kv.first;
+            BlockRec B;
+            std::memset(&B, 0, sizeof B);
+            B.link = A;
+            std::vector<int> path = anc(A);
+            if (cur_aux >= 0 && is_anc(cur_aux, A)) {
+                const size_t skip = anc(cur_aux).size();
+                path.erase(path.begin(), path.begin() + skip);
+                B.restart = 0;
+            } else {
+                B.restart = 1;
+            }
+            B.path_off = (int)paths.size();
+            B.path_len = (int)path.size();
+            paths.insert(paths.end(), path.begin(), path.end());
+            cur_aux = A;
+            B.ent_first = (int)entries.size();
+            std::vector<const float *> sp;
+            for (auto &tm : kv.second) {
+                EntryRec E;
+                std::memset(&E, 0, sizeof E);
+                const float *x = d->sphere_xyzr + 4 * tm.first;
+                E.x = x[0];
+                E.y = x[1];
+                E.z = x[2];
+                E.r = x[3];
+                E.mask = tm.second;
+                entries.push_back(E);
+                sp.push_back(x);
+            }
+            B.ent_count = (int)kv.second.size();
+            bounding_sphere(sp, B.coarse);
+            blocks.push_back(B);
+        }
+        steps[si].blk_count = (int)blocks.size() - steps[si].blk_first;
+    }
+
+    std::vector<float4> spheres(S);
+    for (int s = 0; s < S; ++s)
+        spheres[s] = make_float4(d->sphere_xyzr[4 * s], d->sphere_xyzr[4 * s + 1],
+                                 d->sphere_xyzr[4 * s + 2], d->sphere_xyzr[4 * s + 3]);
+    if (paths.empty()) paths.push_back(0);
+
+    Blob b;
+    const size_t o_j = b.add(joints.data(), joints.size() * sizeof(JointRec));
+    const size_t o_s = b.add(steps.data(), steps.size() * sizeof(StepRec));
+    const size_t o_b = b.add(blocks.data(), blocks.size() * sizeof(BlockRec));
+    const size_t o_e = b.add(entries.data(), entries.size() * sizeof(EntryRec));
+    const size_t o_p = b.add(paths.data(), paths.size() * sizeof(int));
+    const size_t o_sp = b.add(spheres.data(), spheres.size() * sizeof(float4));
+    const size_t o_ss = b.add(sphere_step.data(), sphere_step.size() * sizeof(int));
+    r->device = current_device();
+    r->blob = b.upload();
+    char *base = static_cast<char *>(r->blob);
+    r->dev.joints = reinterpret_cast<const JointRec *>(base + o_j);
+    r->dev.steps = reinterpret_cast<const StepRec *>(base + o_s);
+    r->dev.blocks = reinterpret_cast<const BlockRec *>(base + o_b);
+    r->dev.entries = reinterpret_cast<const EntryRec *>(base + o_e);
+    r->dev.paths = reinterpret_cast<const int32_t *>(base + o_p);
+    r->dev.spheres = reinterpret_cast<const float4 *>(base + o_sp);
+    r->dev.sphere_step = reinterpret_cast<const int32_t *>(base + o_ss);
+    r->dev.dof = dof;
+    r->dev.n_steps = (int)steps.size();
+    r->dev.n_spheres = S;
+    r->dev.n_links = dof + 1;
+    r->dof = dof;
+    r->n_spheres = S;
+}
+
+void build_env(const vk_env_desc *d, vk_env_s *e) {
+    if (!d) raise(VK_ERR_INVALID_ARG, "env desc is NULL");
+    const int ns = d->n_spheres, nc = d->n_capsules, ny = d->n_cylinders, nb = d->n_boxes;
+    if (ns < 0 || nc < 0 || ny < 0 || nb < 0) raise(VK_ERR_INVALID_ARG, "negative primitive count");
+    if ((ns && !d->spheres) || (nc && !d->capsules) || (ny && !d->cylinders) || (nb && !d->boxes))
+        raise(VK_ERR_INVALID_ARG, "primitive array is NULL");
+    if ((ns && !finite_all(d->spheres, (size_t)ns * 4)) ||
+        (nc && !finite_all(d->capsules, (size_t)nc * 7)) ||
+        (ny && !finite_all(d->cylinders, (size_t)ny * 8)) ||
+        (nb && !finite_all(d->boxes, (size_t)nb * 15)))
+        raise(VK_ERR_INVALID_ARG, "primitive values must be finite");
+    std::vector<float4> rec;
+    rec.reserve((size_t)ns + 2 * nc + 2 * ny + 4 * nb);
+    for (int i = 0; i < ns; ++i) {
+        const float *s = d->spheres + 4 * i;
+        if (s[3] < 0.0f) raise(VK_ERR_INVALID_ARG, "negative sphere radius");
+        rec.push_back(make_float4(s[0], s[1], s[2], s[3]));
+    }
+    for (int i = 0; i < nc; ++i) {
+        const float *c = d->capsules + 7 * i;
+        const float ux = c[3] - c[0], uy = c[4] - c[1], uz = c[5] - c[2];
+        const float uu = ux * ux + uy * uy + uz * uz;
+        rec.push_back(make_float4(c[0], c[1], c[2], c[6]));
+        rec.push_back(make_float4(ux, uy, uz, uu > 0.0f ? 1.0f / uu : 0.0f));
+    }
+    for (int i = 0; i < ny; ++i) {
+        const float *c = d->cylinders + 8 * i;
+        rec.push_back(make_float4(c[0], c[1], c[2], c[6]));
+        rec.push_back(make_float4(c[3], c[4], c[5], c[7]));
+    }
+    for (int i = 0; i < nb; ++i) {
+        const float *b = d->boxes + 15 * i;
+        const float *R = b + 3, *ext = b + 12;
+        for (int k = 0; k < 3; ++k) rec.push_back(make_float4(R[k], R[3 + k], R[6 + k], ext[k]));
+        rec.push_back(make_float4(b[0], b[1], b[2], 0.0f));
+    }
+    if (rec.empty()) rec.push_back(make_float4(0, 0, 0, 0));
+    Blob bl;
+    const size_t o_r = bl.add(rec.data(), rec.size() * sizeof(float4));
+    e->device = current_device();
+    e->blob = bl.upload();
+    char *base = static_cast<char *>(e->blob);
+    std::memset(&e->dev, 0, sizeof e->dev);
+    e->dev.rec = reinterpret_cast<const float4 *>(base + o_r);
+    e->dev.n_sph = ns;
+    e->dev.n_cap = nc;
+    e->dev.n_cyl = ny;
+    e->dev.n_box = nb;
+    e->dev.off_cap = ns;
+    e->dev.off_cyl = ns + 2 * nc;
+    e->dev.off_box = ns + 2 * nc + 2 * ny;
+    e->dev.n_rec = ns + 2 * nc + 2 * ny + 4 * nb;
+}
+
+bool env_in_lds(const vk_env_s *e, size_t extra = 0) {
+    const DeviceInfo &di = device_info(e->device);
+    const size_t bytes = (size_t)e->dev.n_rec * 16 + extra;
+    return e->dev.n_rec > 0 && bytes <= std::min<size_t>(di.max_lds, 64 * 1024);
+}
+
+void check_pair(vk_robot r, vk_env e) {
+    if (!r) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+    if (!e) raise(VK_ERR_INVALID_ARG, "env handle is NULL");
+}
+
+void check_batch(int64_t n, int64_t ld, const void *in, const void *out, const char *what) {
+    if (n < 0) raise(VK_ERR_INVALID_ARG, std::string(what) + ": n < 0");
+    if (n > 0 && (!in || !out)) raise(VK_ERR_INVALID_ARG, std::string(what) + ": NULL array");
+    if (ld < n) raise(VK_ERR_SHAPE, std::string(what) + ": leading dimension < n");
+    if (n >= (int64_t(1) << 40)) raise(VK_ERR_SHAPE, std::string(what) + ": n too large");
+}
+
+}  // namespace
+
+extern "C" {
+
+vk_status vk_robot_create(const vk_robot_desc *desc, vk_robot *out) {
+    return guarded([&] {
+        if (!out) raise(VK_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        auto *r = new vk_robot_s();
+        try {
+            build_robot(desc, r);
+        } catch (...) {
+            delete r;
+            throw;
+        }
+        *out = r;
+    });
+}
+
+vk_status vk_robot_destroy(vk_robot robot) {
+    return guarded([&] {
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        hipError_t err = hipFree(robot->blob);
+        delete robot;
+        hip_check(err, "hipFree");
+    });
+}
+
+int32_t vk_robot_dof(vk_robot robot) { return robot ? robot->dof : -1; }
+int32_t vk_robot_n_spheres(vk_robot robot) { return robot ? robot->n_spheres : -1; }
+
+vk_status vk_env_create(const vk_env_desc *desc, vk_env *out) {
+    return guarded([&] {
+        if (!out) raise(VK_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        auto *e = new vk_env_s();
+        try {
+            build_env(desc, e);
+        } catch (...) {
+            delete e;
+            throw;
+        }
+        *out = e;
+    });
+}
+
+vk_status vk_env_destroy(vk_env env) {
+    return guarded([&] {
+        if (!env) raise(VK_ERR_INVALID_ARG, "env handle is NULL");
+        hipError_t err = hipFree(env->blob);
+        delete env;
+        hip_check(err, "hipFree");
+    });
+}
+
+vk_status fk_spheres(vk_robot robot, const float *q, int64_t n, int64_t ldq, float *centres,
+                     int64_t ldc, void *stream) {
+    return guarded([&] {
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        check_batch(n, ldq, q, centres, "fk_spheres");
+        if (ldc < n) raise(VK_ERR_SHAPE, "fk_spheres: ldc < n");
+        if (n == 0 || robot->n_spheres == 0) return;
+        hip_check(launch_fk_spheres(robot->dev, q, n, ldq, centres, ldc, (hipStream_t)stream),
+                  "fk_spheres launch");
+    });
+}
+
+vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n, int64_t ldq,
+                          uint8_t *collide, void *stream) {
+    return guarded([&] {
+        check_pair(robot, env);
+        check_batch(n, ldq, q, collide, "validate_states");
+        if (n == 0) return;
+        hip_check(launch_validate_states(robot->dev, env->dev, env_in_lds(env), q, n, ldq, collide,
+                                         (hipStream_t)stream),
+                  "validate_states launch");
+    });
+}
+
+static void check_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                        const int32_t *n_states, int64_t n_edges, float resolution,
+                        uint8_t *collide) {
+    check_pair(robot, env);
+    if (n_edges < 0) raise(VK_ERR_INVALID_ARG, "n_edges < 0");
+    if (n_edges > 0 && (!qa || !qb || !collide)) raise(VK_ERR_INVALID_ARG, "NULL edge array");
+    if (n_edges >= (int64_t(1) << 31) - (int64_t(1) << 24)) raise(VK_ERR_SHAPE, "too many edges");
+    if (!n_states && !(resolution > 0.0f && std::isfinite(resolution)))
+        raise(VK_ERR_INVALID_ARG, "resolution must be finite and > 0");
+}
+
+static void run_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                      const int32_t *n_states, int64_t n_edges, float resolution,
+                      uint8_t *collide, unsigned long long *flops, void *stream) {
+    check_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide);
+    if (n_edges == 0) return;
+    hipStream_t s = (hipStream_t)stream;
+    const int dev = robot->device;
+    const DeviceInfo &di = device_info(dev);
+    unsigned long long *queue = queue_for(dev, s);
+    int block, bpc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        block = g_edge_block;
+        bpc = g_edge_bpc;
+    }
+    const int64_t want = (n_edges + block / kWave - 1) / (block / kWave);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
+    hip_check(launch_reset_queue(queue, s), "queue reset");
+    hip_check(launch_validate_edges(robot->dev, env->dev, env_in_lds(env), qa, qb, n_states,
+                                    n_edges, resolution, collide, queue, grid, block, s, flops),
+              "validate_edges launch");
+}
+
+vk_status validate_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                         const int32_t *n_states, int64_t n_edges, float resolution,
+                         uint8_t *collide, void *stream) {
+    return guarded([&] {
+        run_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide, nullptr, stream);
+    });
+}
+
+vk_status validate_edges_counted(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                                 const int32_t *n_states, int64_t n_edges, float resolution,
+                                 uint8_t *collide, uint64_t *flops, void *stream) {
+    return guarded([&] {
+        if (!flops) raise(VK_ERR_INVALID_ARG, "flops is NULL");
+        run_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide,
+                  reinterpret_cast<unsigned long long *>(flops), stream);
+    });
+}
+
+vk_status validate_edges_per_edge(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                                  const int32_t *n_states, int64_t n_edges, float resolution,
+                                  uint8_t *collide, void *stream) {
+    return guarded([&] {
+        check_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide);
+        hipStream_t s = (hipStream_t)stream;
+        const bool lds = env_in_lds(env);
+        for (int64_t e = 0; e < n_edges; ++e)
+            hip_check(launch_validate_edge_one(robot->dev, env->dev, lds, qa, qb, n_states, e,
+                                               resolution, collide, s),
+                      "validate_edges_per_edge launch");
+    });
+}
+
+vk_status penetration_cost_fwd(vk_robot robot, vk_env env, const float *q, int64_t n,
+                               int64_t ldq, float *cost, void *stream) {
+    return guarded([&] {
+        check_pair(robot, env);
+        check_batch(n, ldq, q, cost, "penetration_cost_fwd");
+        if (n == 0) return;
+        hip_check(launch_cost_fwd(robot->dev, env->dev, env_in_lds(env), q, n, ldq, cost,
+                                  (hipStream_t)stream),
+                  "penetration_cost_fwd launch");
+    });
+}
+
+vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64_t n,
+                               int64_t ldq, const float *grad_cost, float *grad_q, int64_t ldg,
+                               void *stream) {
+    return guarded([&] {
+        check_pair(robot, env);
+        check_batch(n, ldq, q, grad_q, "penetration_cost_bwd");
+        if (n > 0 && !grad_cost) raise(VK_ERR_INVALID_ARG, "grad_cost is NULL");
+        if (ldg < n) raise(VK_ERR_SHAPE, "penetration_cost_bwd: ldg < n");
+        if (n == 0) return;
+        const DeviceInfo &di = device_info(robot->device);
+        int block = 256;
+        while (block > 64 && cost_bwd_slot_bytes(robot->dev, block) > di.max_lds) block /= 2;
+        const size_t slots = cost_bwd_slot_bytes(robot->dev, block);
+        if (slots > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the backward kernel");
+        hip_check(launch_cost_bwd(robot->dev, env->dev, env_in_lds(env, slots), q, n, ldq, grad_cost,
+                                  grad_q, ldg, block, (hipStream_t)stream),
+                  "penetration_cost_bwd launch");
+    });
+}
+
+vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const vk_env *envs,
+                               int32_t n_envs, const vk_edge_set *sets, int32_t n_sets,
+                               float resolution, const float *qa, const float *qb,
+                               uint8_t *collide, void *stream, vk_edge_batch *out) {
+    (void)stream;
+    return guarded([&] {
+        if (!out) raise(VK_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (n_robots < 1 || n_envs < 1 || n_sets < 0 || !robots || !envs || (n_sets && !sets))
+            raise(VK_ERR_INVALID_ARG, "robots, envs and sets must be non-empty arrays");
+        if (!(resolution > 0.0f && std::isfinite(resolution)))
+            raise(VK_ERR_INVALID_ARG, "resolution must be finite and > 0");
+        for (int i = 0; i < n_robots; ++i)
+            if (!robots[i]) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        for (int i = 0; i < n_envs; ++i)
+            if (!envs[i]) raise(VK_ERR_INVALID_ARG, "env handle is NULL");
+        std::vector<BatchSet> recs;
+        std::vector<int64_t> prefix;
+        int64_t total = 0;
+        for (int k = 0; k < n_sets; ++k) {
+            const vk_edge_set &s = sets[k];
+            if (s.robot < 0 || s.robot >= n_robots || s.env < 0 || s.env >= n_envs)
+                raise(VK_ERR_INVALID_ARG, "edge set refers to a missing robot or env");
+            if (s.n_edges < 0 || s.qa_offset < 0 || s.out_offset < 0)
+                raise(VK_ERR_INVALID_ARG, "negative edge-set size or offset");
+            if (s.n_edges == 0) continue;
+            BatchSet b;
+            std::memset(&b, 0, sizeof b);
+            b.rb = robots[s.robot]->dev;
+            b.env = envs[s.env]->dev;
+            b.qa_offset = s.qa_offset;
+            b.n_edges = s.n_edges;
+            b.out_offset = s.out_offset;
+            recs.push_back(b);
+            prefix.push_back(total);
+            total += s.n_edges;
+        }
+        if (total > 0 && (!qa || !qb || !collide)) raise(VK_ERR_INVALID_ARG, "NULL edge array");
+        if (total >= (int64_t(1) << 31) - (int64_t(1) << 24)) raise(VK_ERR_SHAPE, "too many edges");
+        auto *bt = new vk_edge_batch_s();
+        try {
+            bt->device = current_device();
+            bt->total = total;
+            if (recs.empty()) {
+                recs.push_back(BatchSet{});
+                prefix.push_back(0);
+            }
+            Blob bl;
+            const size_t o_s = bl.add(recs.data(), recs.size() * sizeof(BatchSet));
+            const size_t o_p = bl.add(prefix.data(), prefix.size() * sizeof(int64_t));
+            bt->blob = bl.upload();
+            void *q = nullptr;
+            hip_check(hipMalloc(&q, 256), "batch queue");
+            bt->queue = static_cast<unsigned long long *>(q);
+            const BatchSet *d_sets = reinterpret_cast<const BatchSet *>(static_cast<char *>(bt->blob) + o_s);
+            const int64_t *d_pre = reinterpret_cast<const int64_t *>(static_cast<char *>(bt->blob) + o_p);
+            const DeviceInfo &di = device_info(bt->device);
+            int block, bpc;
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                block = g_edge_block;
+                bpc = g_edge_bpc;
+            }
+            const int64_t want = (total + block / kWave - 1) / (block / kWave);
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
+            // capture {queue reset, persistent launch} once; vk_edge_batch_run replays it
+            hipStream_t cs = nullptr;
+            hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+            hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (err == hipSuccess) err = launch_reset_queue(bt->queue, cs);
+            if (err == hipSuccess && total > 0)
+                err = launch_validate_edge_batch(d_sets, d_pre, (int)recs.size(), total, resolution,
+                                                 qa, qb, collide, bt->queue, grid, block, cs);
+            hipGraph_t g = nullptr;
+            hipError_t err2 = hipStreamEndCapture(cs, &g);
+            (void)hipStreamDestroy(cs);
+            hip_check(err, "batch capture");
+            hip_check(err2, "hipStreamEndCapture");
+            bt->graph = g;
+            hip_check(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+        } catch (...) {
+            if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+            if (bt->graph) (void)hipGraphDestroy(bt->graph);
+            if (bt->queue) (void)hipFree(bt->queue);
+            if (bt->blob) (void)hipFree(bt->blob);
+            delete bt;
+            throw;
+        }
+        *out = bt;
+    });
+}
+
+vk_status vk_edge_batch_run(vk_edge_batch batch, void *stream) {
+    return guarded([&] {
+        if (!batch) raise(VK_ERR_INVALID_ARG, "batch handle is NULL");
+        hip_check(hipGraphLaunch(batch->exec, (hipStream_t)stream), "hipGraphLaunch");
+    });
+}
+
+vk_status vk_edge_batch_destroy(vk_edge_batch batch) {
+    return guarded([&] {
+        if (!batch) raise(VK_ERR_INVALID_ARG, "batch handle is NULL");
+        (void)hipGraphExecDestroy(batch->exec);
+        (void)hipGraphDestroy(batch->graph);
+        (void)hipFree(batch->queue);
+        hipError_t err = hipFree(batch->blob);
+        delete batch;
+        hip_check(err, "hipFree");
+    });
+}
+
+vk_status vk_set_edge_launch(int32_t block_threads, int32_t blocks_per_cu) {
+    return guarded([&] {
+        if (block_threads == 0 && blocks_per_cu == 0) {
+            block_threads = 256;
+            blocks_per_cu = 4;
+        }
+        if (block_threads < 64 || block_threads > 256 || block_threads % 64)
+            raise(VK_ERR_INVALID_ARG, "block_threads must be 64, 128, 192 or 256");
+        if (blocks_per_cu < 1 || blocks_per_cu > 64) raise(VK_ERR_INVALID_ARG, "blocks_per_cu must be in [1, 64]");
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_edge_block = block_threads;
+        g_edge_bpc = blocks_per_cu;
+    });
+}
+
+vk_status vk_get_edge_launch(int32_t *block_threads, int32_t *blocks_per_cu) {
+    return guarded([&] {
+        if (!block_threads || !blocks_per_cu) raise(VK_ERR_INVALID_ARG, "NULL output");
+        std::lock_guard<std::mutex> lk(g_mu);
+        *block_threads = g_edge_block;
+        *blocks_per_cu = g_edge_bpc;
+    });
+}
+
+const char *vk_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

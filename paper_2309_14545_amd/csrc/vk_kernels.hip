@@ -1,0 +1,748 @@
+// HIP kernels for gfx950: sphere FK, state validation, rake-ordered edge validation (persistent
+// work queue and one-launch-per-edge), and the squared-penetration cost with its adjoint.
+//
+// Mapping (Sec. III-A..D of the paper, re-designed for 64-wide CDNA wavefronts):
+//   * one lane = one configuration; a wavefront is the "vector" of configurations;
+//   * configurations are SoA in HBM, so lane i's load of joint j is one coalesced access;
+//   * the robot program (link steps, self-pair blocks) and the environment are wave-uniform:
+//     the robot through scalar loads, the environment staged once per workgroup in LDS;
+//   * per link: pose it, place its spheres, test them against the environment behind the
+//     link's bounding sphere (mid-phase, Sec. III-D), then test the self pairs it completes --
+//     checks are interleaved into FK and the walk stops at the first hit (Sec. III-D);
+//   * edges use the rake: lane l takes state l*ceil(n/64) + k at step k, so the first step
+//     samples the whole motion (Sec. III-D, Fig. 2) and a wave ballot ends the edge early.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "vk_device.hpp"
+#include "vk_launch.hpp"
+
+namespace vk {
+
+// Joint value sources ------------------------------------------------------------------------
+struct QEdge {                 // state on a straight edge: qa + t (qb - qa), qa/qb uniform
+    const float *a;            // (t = 1 gives qb exactly, so both endpoints are the inputs)
+    const float *b;
+    float t;
+    __device__ __forceinline__ float operator()(int j) const {
+        const float x = a[j], y = b[j];
+        return t == 1.0f ? y : fmaf(t, y - x, x);
+    }
+};
+
+struct QState {                // SoA state batch: q[j * ldq + i]
+    const float *q;
+    int64_t ldq;
+    int64_t i;
+    __device__ __forceinline__ float operator()(int j) const { return q[j * ldq + i]; }
+};
+
+// Environment view (records in LDS or global memory) -----------------------------------------
+struct EnvView {
+    const float4 *rec;
+    int n_sph, n_cap, n_cyl, n_box, off_cap, off_cyl, off_box;
+};
+
+__device__ __forceinline__ EnvView make_view(const EnvDev &e, const float4 *rec) {
+    EnvView v;
+    v.rec = rec;
+    v.n_sph = e.n_sph;
+    v.n_cap = e.n_cap;
+    v.n_cyl = e.n_cyl;
+    v.n_box = e.n_box;
+    v.off_cap = e.off_cap;
+    v.off_cyl = e.off_cyl;
+    v.off_box = e.off_box;
+    return v;
+}
+
+// Copy the environment records into LDS once per workgroup.
+__device__ __forceinline__ void stage_env(float4 *lds, const float4 *__restrict__ g, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = g[i];
+    __syncthreads();
+}
+
+// Executed-work accounting (FLOP model, FMA = 2): every wave-uniform operation below adds its
+// per-lane FLOP count; the instrumented kernel multiplies by the 64 lanes that issue it.
+// NoWork compiles to nothing, so the timed kernels carry no accounting.
+namespace flop {
+constexpr uint32_t kJoint = 30, kMount = 63, kPlace = 18, kSphere = 11, kCapsule = 25,
+                   kCylinder = 35, kBox = 34, kPair = 11;
+}
+struct NoWork {
+    __device__ __forceinline__ void add(uint32_t) {}
+};
+struct Work {
+    uint64_t f = 0;
+    __device__ __forceinline__ void add(uint32_t x) { f += x; }
+};
+
+// Pose the link of step S into T (rebuilding a tree branch from the base when needed).
+template <class Q, class W = NoWork>
+__device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, Frame &T,
+                                          const Q &q, W &&w = W()) {
+    if (S.joint < 0) return;
+    if (S.restart_len >= 0) {
+        frame_identity(T);
+        for (int k = 0; k < S.restart_len; ++k) {
+            const int j = rb.paths[S.restart_off + k];
+            frame_joint(T, rb.joints[j], q(j));
+            w.add(flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
+        }
+    }
+    frame_joint(T, rb.joints[S.joint], q(S.joint));
+    w.add(flop::kJoint + (rb.joints[S.joint].has_mount ? flop::kMount : 0));
+}
+
+// Pose the earlier link of self block B into Ta.
+template <class Q, class W = NoWork>
+__device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B, Frame &Ta,
+                                           const Q &q, W &&w = W()) {
+    if (B.restart) frame_identity(Ta);
+    for (int k = 0; k < B.path_len; ++k) {
+        const int j = rb.paths[B.path_off + k];
+        frame_joint(Ta, rb.joints[j], q(j));
+        w.add(flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
+    }
+}
+
+// Grid broadphase over a large sphere set: test one robot sphere against the points of the
+// 3x3x3 cells around its own cell (cell size >= largest robot radius + largest point radius).
+__device__ __forceinline__ bool grid_hit(const EnvDev &g, float cx, float cy, float cz, float r) {
+    const int ix = (int)floorf((cx - g.gorg[0]) * g.ginv);
+    const int iy = (int)floorf((cy - g.gorg[1]) * g.ginv);
+    const int iz = (int)floorf((cz - g.gorg[2]) * g.ginv);
+    bool hit = false;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const int z = iz + dz;
+        if (z < 0 || z >= g.gdim[2]) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int y = iy + dy;
+            if (y < 0 || y >= g.gdim[1]) continue;
+            const int row = (z * g.gdim[1] + y) * g.gdim[0];
+            const int x0 = max(ix - 1, 0), x1 = min(ix + 1, g.gdim[0] - 1);
+            if (x0 > x1) continue;
+            // the three cells of a row are contiguous in the sorted point array
+            const int b = g.cell_start[row + x0], e = g.cell_start[row + x1 + 1];
+            for (int p = b; p < e && !hit; ++p) hit = hit_sphere(cx, cy, cz, r, g.grid_pts[p]);
+        }
+    }
+    return hit;
+}
+
+// Gated fine test: the step's bounding sphere (coarse) must touch the primitive in some live
+// lane before the step's spheres are tested against it; then the exit test.
+#define VK_GATE(KFLOP, COARSE, FINE)                                                \
+    work.add(KFLOP);                                                                \
+    if (wave_ballot(live && (COARSE))) {                                            \
+        work.add((KFLOP) * cnt);                                                    \
+        _Pragma("unroll") for (int k = 0; k < kSpl; ++k) if (k < cnt) col |= (FINE); \
+        if (EDGE) {                                                                 \
+            if (wave_ballot(col)) return true;                                      \
+        } else {                                                                    \
+            live = !col;                                                            \
+            if (!wave_ballot(live)) return col;                                     \
+        }                                                                           \
+    }
+
+// The interleaved FK + collision walk of one configuration per lane.
+//   EDGE = true : returns as soon as any lane of the wave collides (the edge is invalid);
+//                 the return value is then wave-uniform.
+//   EDGE = false: per-lane result; lanes that collided stop contributing, and the walk ends
+//                 when every lane has collided.  `col` on entry marks lanes already decided.
+template <bool EDGE, class Q, class W = NoWork>
+__device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev &ed, const Q &q,
+                             bool col, W &&work = W()) {
+    Frame Tm, Ta;
+    frame_identity(Tm);
+    frame_identity(Ta);
+    bool live = !col;
+    if (!EDGE && !wave_ballot(live)) return col;
+    for (int st = 0; st < rb.n_steps; ++st) {
+        const StepRec &S = rb.steps[st];
+        pose_step(rb, S, Tm, q, work);
+        const int cnt = S.sph_count;
+        if (cnt == 0) continue;
+        work.add(flop::kPlace * (cnt + 1));
+        float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl];
+#pragma unroll
+        for (int k = 0; k < kSpl; ++k) {
+            cx[k] = cy[k] = cz[k] = cr[k] = 0.0f;
+            if (k < cnt) {
+                const float4 s = rb.spheres[S.sph_first + k];
+                frame_point(Tm, s.x, s.y, s.z, cx[k], cy[k], cz[k]);
+                cr[k] = s.w;
+            }
+        }
+        float Cx, Cy, Cz;
+        frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
+        const float CR = S.coarse[3];
+
+        for (int i = 0; i < ev.n_sph; ++i) {
+            const float4 o = ev.rec[i];
+            VK_GATE(flop::kSphere, hit_sphere(Cx, Cy, Cz, CR, o), hit_sphere(cx[k], cy[k], cz[k], cr[k], o))
+        }
+        for (int i = 0; i < ev.n_cap; ++i) {
+            const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
+            VK_GATE(flop::kCapsule, hit_capsule(Cx, Cy, Cz, CR, A, B),
+                    hit_capsule(cx[k], cy[k], cz[k], cr[k], A, B))
+        }
+        for (int i = 0; i < ev.n_cyl; ++i) {
+            const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
+            VK_GATE(flop::kCylinder, hit_cylinder(Cx, Cy, Cz, CR, A, B),
+                    hit_cylinder(cx[k], cy[k], cz[k], cr[k], A, B))
+        }
+        for (int i = 0; i < ev.n_box; ++i) {
+            const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
+                         Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
+            VK_GATE(flop::kBox, hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
+                    hit_box(cx[k], cy[k], cz[k], cr[k], X, Y, Z, O))
+        }
+        if (ed.n_cells > 0) {
+#pragma unroll
+            for (int k = 0; k < kSpl; ++k)
+                if (k < cnt && live && !col) col |= grid_hit(ed, cx[k], cy[k], cz[k], cr[k]);
+            if (EDGE) {
+                if (wave_ballot(col)) return true;
+            } else {
+                live = !col;
+                if (!wave_ballot(live)) return col;
+            }
+        }
+
+        // self pairs completed by this step (earlier link posed into Ta)
+        for (int b = 0; b < S.blk_count; ++b) {
+            const BlockRec &B = rb.blocks[S.blk_first + b];
+            pose_block(rb, B, Ta, q, work);
+            float Ax, Ay, Az;
+            frame_point(Ta, B.coarse[0], B.coarse[1], B.coarse[2], Ax, Ay, Az);
+            const float dx = Ax - Cx, dy = Ay - Cy, dz = Az - Cz, rr = B.coarse[3] + CR;
+            work.add(flop::kPlace + flop::kPair);
+            if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
+            for (int e = 0; e < B.ent_count; ++e) {
+                const EntryRec &E = rb.entries[B.ent_first + e];
+                float tx, ty, tz;
+                frame_point(Ta, E.x, E.y, E.z, tx, ty, tz);
+                work.add(flop::kPlace + flop::kPair * __builtin_popcount(E.mask));
+#pragma unroll
+                for (int k = 0; k < kSpl; ++k) {
+                    if ((E.mask >> k) & 1u) {
+                        const float ex = tx - cx[k], ey = ty - cy[k], ez = tz - cz[k];
+                        const float s = E.r + cr[k];
+                        col |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < s * s;
+                    }
+                }
+            }
+            if (EDGE) {
+                if (wave_ballot(col)) return true;
+            } else {
+                live = !col;
+                if (!wave_ballot(live)) return col;
+            }
+        }
+    }
+    return EDGE ? false : col;
+}
+
+// ---------------------------------------------------------------------------------------------
+// fk_spheres: one lane per state; writes [S][3][ldc].
+// ---------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_fk_spheres(RobotDev rb, const float *__restrict__ q,
+                                                    int64_t n, int64_t ldq,
+                                                    float *__restrict__ out, int64_t ldc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    QState qs{q, ldq, active ? i : 0};
+    Frame T;
+    frame_identity(T);
+    for (int st = 0; st < rb.n_steps; ++st) {
+        const StepRec &S = rb.steps[st];
+        pose_step(rb, S, T, qs);
+        for (int k = 0; k < S.sph_count; ++k) {
+            const int s = S.sph_first + k;
+            const float4 l = rb.spheres[s];
+            float x, y, z;
+            frame_point(T, l.x, l.y, l.z, x, y, z);
+            if (active) {
+                out[(3 * (int64_t)s + 0) * ldc + i] = x;
+                out[(3 * (int64_t)s + 1) * ldc + i] = y;
+                out[(3 * (int64_t)s + 2) * ldc + i] = z;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// validate_states: one lane per state.
+// ---------------------------------------------------------------------------------------------
+template <bool LDS>
+__global__ void __launch_bounds__(256)
+    k_validate_states(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+                      const float *__restrict__ q, int64_t n, int64_t ldq,
+                      uint8_t *__restrict__ out) {
+    extern __shared__ float4 lds_env[];
+    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
+    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    QState qs{q, ldq, active ? i : 0};
+    bool col = !active;                       // inactive lanes count as decided
+    if (active)
+        for (int j = 0; j < rb.dof; ++j) col |= !isfinite(qs(j));
+    col = walk_collide<false>(rb, ev, ed, qs, col);
+    if (active) out[i] = col ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Edge validation.  One wave validates one edge: states in rake order, first hit ends it.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ int edge_count(const float *a, const float *b, int dof, float res) {
+    // n = max(2, ceil(L / res) + 1), L = max_j |b_j - a_j| in double: the difference of two
+    // floats is exact in double, so this matches a double-precision evaluation bit for bit.
+    double L = 0.0;
+    for (int j = 0; j < dof; ++j) L = fmax(L, fabs((double)b[j] - (double)a[j]));
+    const double n = ceil(L / (double)res) + 1.0;
+    return n < 2.0 ? 2 : (n > 2147483647.0 ? 2147483647 : (int)n);
+}
+
+template <class V, class W = NoWork>
+__device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, const EnvDev &ed,
+                                             const float *a, const float *b, int n,
+                                             W &&work = W()) {
+    bool bad = false;
+    for (int j = 0; j < rb.dof; ++j) bad |= !isfinite(a[j]) || !isfinite(b[j]);
+    if (bad) return 1;
+    if (n < 2) n = 2;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int stride = (n + kWave - 1) / kWave;
+    const float inv = 1.0f / (float)(n - 1);
+    for (int k = 0; k < stride; ++k) {
+        int idx = lane * stride + k;
+        idx = idx < n ? idx : n - 1;          // surplus lanes repeat the last state
+        const float t = idx == n - 1 ? 1.0f : (float)idx * inv;
+        QEdge qs{a, b, t};
+        if (walk_collide<true>(rb, ev, ed, qs, false, work)) return 1;
+    }
+    return 0;
+}
+
+// Work-queue pull with no lane-dependent branch: every lane executes the atomic, lane 0 adds 1
+// and the others add 0, so lane 0's returned ticket is the wave's item and the first active
+// lane (lane 0; the whole wave is active here) broadcasts it.  Keeping lane-dependent control
+// flow out of the persistent loop matters: a lane-0-only `if` around the atomic can be
+// threaded by the compiler across iterations, after which the broadcast reads a lane that
+// never took a ticket.
+__device__ __forceinline__ int64_t next_item(unsigned long long *queue, int lane) {
+    const unsigned long long t = atomicAdd(queue, lane == 0 ? 1ull : 0ull);
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)t);
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)(t >> 32));
+    return (int64_t)(((unsigned long long)hi << 32) | lo);
+}
+
+template <bool LDS, bool COUNT>
+__global__ void __launch_bounds__(256)
+    k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+                     const float *__restrict__ qa, const float *__restrict__ qb,
+                     const int32_t *__restrict__ nst, int64_t n_edges, float res,
+                     uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
+                     unsigned long long *__restrict__ flops) {
+    extern __shared__ float4 lds_env[];
+    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
+    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    const int lane = threadIdx.x & (kWave - 1);
+    typename std::conditional<COUNT, Work, NoWork>::type work;
+    for (;;) {
+        const int64_t e = next_item(queue, lane);
+        if (e >= n_edges) break;
+        const float *a = qa + e * rb.dof;
+        const float *b = qb + e * rb.dof;
+        const int n = nst ? nst[e] : edge_count(a, b, rb.dof, res);
+        const uint8_t hit = edge_body(rb, ev, ed, a, b, n, work);
+        out[e] = hit;                         // wave-uniform value, same address in every lane
+    }
+    if constexpr (COUNT) {
+        atomicAdd(flops, lane == 0 ? (unsigned long long)work.f * kWave : 0ull);
+    }
+}
+
+template <bool LDS>
+__global__ void __launch_bounds__(64)
+    k_validate_edge_one(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+                        const float *__restrict__ qa, const float *__restrict__ qb,
+                        const int32_t *__restrict__ nst, int64_t e, float res,
+                        uint8_t *__restrict__ out) {
+    extern __shared__ float4 lds_env[];
+    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
+    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    const float *a = qa + e * rb.dof;
+    const float *b = qb + e * rb.dof;
+    const int n = nst ? nst[e] : edge_count(a, b, rb.dof, res);
+    const uint8_t hit = edge_body(rb, ev, ed, a, b, n);
+    if ((threadIdx.x & (kWave - 1)) == 0) out[e] = hit;
+}
+
+// Mixed-robot batch: every edge set has its own robot and environment; one persistent launch
+// pulls edges from a single queue across all sets.  The environment is read from global
+// memory with wave-uniform loads (it changes from item to item, so it is not staged in LDS).
+__global__ void __launch_bounds__(256)
+    k_validate_edge_batch(const BatchSet *__restrict__ sets, const int64_t *__restrict__ prefix,
+                          int n_sets, int64_t total, float res, const float *__restrict__ qa,
+                          const float *__restrict__ qb, uint8_t *__restrict__ out,
+                          unsigned long long *__restrict__ queue) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        const int64_t e = next_item(queue, lane);
+        if (e >= total) break;
+        int lo = 0, hi = n_sets - 1;          // last set whose first edge is <= e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        const BatchSet &S = sets[lo];
+        const int64_t local = e - prefix[lo];
+        const float *a = qa + S.qa_offset + local * S.rb.dof;
+        const float *b = qb + S.qa_offset + local * S.rb.dof;
+        const int n = edge_count(a, b, S.rb.dof, res);
+        const EnvView ev = make_view(S.env, S.env.rec);
+        const uint8_t hit = edge_body(S.rb, ev, S.env, a, b, n);
+        out[S.out_offset + local] = hit;      // wave-uniform value
+    }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Squared-penetration cost.  Every pair contributes max(0, -clearance)^2; the per-step
+// bounding sphere still gates the fine tests (no penetration of the bound implies none of the
+// fine spheres), but there is no early exit.
+// ---------------------------------------------------------------------------------------------
+template <bool GRAD>
+struct CostAcc;
+
+// Penetration of sphere k against a primitive with signed distance sd and gradient g;
+// accumulates the cost and (GRAD) the force d cost / d c = -2 p g.
+#define VK_PEN(SDEXPR)                                                                \
+    {                                                                                 \
+        float gx, gy, gz;                                                             \
+        const float sd = (SDEXPR);                                                    \
+        const float p = cr[k] - sd;                                                   \
+        if (p > 0.0f) {                                                               \
+            cost = fmaf(p, p, cost);                                                  \
+            if (GRAD) {                                                               \
+                fx[k] = fmaf(-2.0f * p, gx, fx[k]);                                   \
+                fy[k] = fmaf(-2.0f * p, gy, fy[k]);                                   \
+                fz[k] = fmaf(-2.0f * p, gz, fz[k]);                                   \
+            }                                                                         \
+        }                                                                             \
+    }
+
+#define VK_COST_GATE(COARSE, SDEXPR)                                                  \
+    if (wave_ballot(live && (COARSE))) {                                              \
+        _Pragma("unroll") for (int k = 0; k < kSpl; ++k) if (k < cnt) VK_PEN(SDEXPR) \
+    }
+
+// Per-link force/moment slots live in LDS: slot (link, component) for each lane of the wave.
+struct LinkSlots {
+    float *base;               // [n_links][6][64] for this wave
+    int lane;
+    __device__ __forceinline__ float &at(int link, int c) const {
+        return base[(link * 6 + c) * kWave + lane];
+    }
+    __device__ __forceinline__ void add(int link, float px, float py, float pz, float fx,
+                                        float fy, float fz) const {
+        at(link, 0) += fx;
+        at(link, 1) += fy;
+        at(link, 2) += fz;
+        at(link, 3) += py * fz - pz * fy;      // moment about the world origin: p x f
+        at(link, 4) += pz * fx - px * fz;
+        at(link, 5) += px * fy - py * fx;
+    }
+};
+
+template <bool GRAD, class Q>
+__device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &ed, const Q &q,
+                           bool live, const LinkSlots &slots) {
+    Frame Tm, Ta;
+    frame_identity(Tm);
+    frame_identity(Ta);
+    float cost = 0.0f;
+    for (int st = 0; st < rb.n_steps; ++st) {
+        const StepRec &S = rb.steps[st];
+        pose_step(rb, S, Tm, q);
+        const int cnt = S.sph_count;
+        if (cnt == 0) continue;
+        float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl], fx[kSpl], fy[kSpl], fz[kSpl];
+#pragma unroll
+        for (int k = 0; k < kSpl; ++k) {
+            cx[k] = cy[k] = cz[k] = cr[k] = 0.0f;
+            fx[k] = fy[k] = fz[k] = 0.0f;
+            if (k < cnt) {
+                const float4 s = rb.spheres[S.sph_first + k];
+                frame_point(Tm, s.x, s.y, s.z, cx[k], cy[k], cz[k]);
+                cr[k] = s.w;
+            }
+        }
+        float Cx, Cy, Cz;
+        frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
+        const float CR = S.coarse[3];
+        for (int i = 0; i < ev.n_sph; ++i) {
+            const float4 o = ev.rec[i];
+            VK_COST_GATE(hit_sphere(Cx, Cy, Cz, CR, o), sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
+        }
+        for (int i = 0; i < ev.n_cap; ++i) {
+            const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
+            VK_COST_GATE(hit_capsule(Cx, Cy, Cz, CR, A, B),
+                         sd_capsule(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
+        }
+        for (int i = 0; i < ev.n_cyl; ++i) {
+            const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
+            VK_COST_GATE(hit_cylinder(Cx, Cy, Cz, CR, A, B),
+                         sd_cylinder(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
+        }
+        for (int i = 0; i < ev.n_box; ++i) {
+            const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
+                         Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
+            VK_COST_GATE(hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
+                         sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
+        }
+        for (int b = 0; b < S.blk_count; ++b) {
+            const BlockRec &B = rb.blocks[S.blk_first + b];
+            pose_block(rb, B, Ta, q);
+            float Ax, Ay, Az;
+            frame_point(Ta, B.coarse[0], B.coarse[1], B.coarse[2], Ax, Ay, Az);
+            const float dx = Ax - Cx, dy = Ay - Cy, dz = Az - Cz, rr = B.coarse[3] + CR;
+            if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
+            for (int e = 0; e < B.ent_count; ++e) {
+                const EntryRec &E = rb.entries[B.ent_first + e];
+                float tx, ty, tz;
+                frame_point(Ta, E.x, E.y, E.z, tx, ty, tz);
+                float gtx = 0.0f, gty = 0.0f, gtz = 0.0f;
+#pragma unroll
+                for (int k = 0; k < kSpl; ++k) {
+                    if ((E.mask >> k) & 1u) {
+                        float ux, uy, uz;
+                        const float d = sd_grad_point(cx[k], cy[k], cz[k], tx, ty, tz, ux, uy, uz);
+                        const float p = E.r + cr[k] - d;
+                        if (p > 0.0f) {
+                            cost = fmaf(p, p, cost);
+                            if (GRAD) {
+                                const float w = -2.0f * p;
+                                fx[k] = fmaf(w, ux, fx[k]);
+                                fy[k] = fmaf(w, uy, fy[k]);
+                                fz[k] = fmaf(w, uz, fz[k]);
+                                gtx = fmaf(-w, ux, gtx);
+                                gty = fmaf(-w, uy, gty);
+                                gtz = fmaf(-w, uz, gtz);
+                            }
+                        }
+                    }
+                }
+                if (GRAD) slots.add(B.link, tx, ty, tz, gtx, gty, gtz);
+            }
+        }
+        if (GRAD) {
+#pragma unroll
+            for (int k = 0; k < kSpl; ++k)
+                if (k < cnt) slots.add(S.link, cx[k], cy[k], cz[k], fx[k], fy[k], fz[k]);
+        }
+    }
+    return cost;
+}
+
+template <bool LDS>
+__global__ void __launch_bounds__(256)
+    k_cost_fwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+               const float *__restrict__ q, int64_t n, int64_t ldq, float *__restrict__ cost) {
+    extern __shared__ float4 lds_env[];
+    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
+    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    QState qs{q, ldq, active ? i : 0};
+    bool finite = true;
+    for (int j = 0; j < rb.dof; ++j) finite &= isfinite(qs(j));
+    LinkSlots none{nullptr, 0};
+    const float c = cost_walk<false>(rb, ev, ed, qs, active && finite, none);
+    if (active) cost[i] = finite ? c : __builtin_nanf("");
+}
+
+// Backward: forces per link accumulated in LDS, suffix sums over the tree, then
+// dq_j = z_j . (M_j - o_j x F_j) with (F_j, M_j) the force and moment (about the origin) of
+// everything joint j moves and (z_j, o_j) the axis and origin of joint j's frame.
+template <bool LDS>
+__global__ void __launch_bounds__(256)
+    k_cost_bwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+               const float *__restrict__ q, int64_t n, int64_t ldq,
+               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg) {
+    extern __shared__ float4 lds_dyn[];
+    // layout: [slots for every wave of the block][env records]
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int slot_floats = rb.n_links * 6 * kWave;
+    float *slot_base = reinterpret_cast<float *>(lds_dyn);
+    float4 *lds_env = lds_dyn + (slot_floats * (blockDim.x / kWave)) / 4;
+    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
+    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    LinkSlots slots{slot_base + wave * slot_floats, lane};
+    for (int l = 0; l < rb.n_links; ++l)
+        for (int c = 0; c < 6; ++c) slots.at(l, c) = 0.0f;
+
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    QState qs{q, ldq, active ? i : 0};
+    bool finite = true;
+    for (int j = 0; j < rb.dof; ++j) finite &= isfinite(qs(j));
+    cost_walk<true>(rb, ev, ed, qs, active && finite, slots);
+
+    // suffix sums: child link totals into the parent (parents have smaller indices)
+    for (int l = rb.n_links - 1; l >= 1; --l) {
+        const int p = rb.joints[l - 1].parent;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) slots.at(p, c) += slots.at(l, c);
+    }
+    const float gc = active ? gcost[i] : 0.0f;
+    // one more forward pass for the joint frames P_j = T_parent(j) * M_j
+    Frame T;
+    frame_identity(T);
+    int cur = 0;                               // link whose pose T holds
+    for (int j = 0; j < rb.dof; ++j) {
+        const JointRec &J = rb.joints[j];
+        if (J.parent != cur) {
+            // rebuild the parent's pose from the base along the restart path of the step
+            // that poses link j+1 (stored with that step)
+            frame_identity(T);
+            for (int s = 0; s < rb.n_steps; ++s) {
+                const StepRec &S = rb.steps[s];
+                if (S.joint == j) {
+                    for (int k = 0; k < S.restart_len; ++k) {
+                        const int jj = rb.paths[S.restart_off + k];
+                        frame_joint(T, rb.joints[jj], qs(jj));
+                    }
+                    break;
+                }
+            }
+        }
+        if (J.has_mount) frame_mount(T, J.m);
+        const float zx = T.r[2], zy = T.r[5], zz = T.r[8];
+        const float ox = T.p[0], oy = T.p[1], oz = T.p[2];
+        const int l = j + 1;
+        const float Fx = slots.at(l, 0), Fy = slots.at(l, 1), Fz = slots.at(l, 2);
+        const float Mx = slots.at(l, 3) - (oy * Fz - oz * Fy);
+        const float My = slots.at(l, 4) - (oz * Fx - ox * Fz);
+        const float Mz = slots.at(l, 5) - (ox * Fy - oy * Fx);
+        const float g = fmaf(zx, Mx, fmaf(zy, My, zz * Mz));
+        if (active) grad[j * ldg + i] = finite ? gc * g : __builtin_nanf("");
+        frame_dh(T, J, qs(j));
+        cur = l;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host-side launchers (called from the C-ABI layer).
+// ---------------------------------------------------------------------------------------------
+hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int64_t ldq,
+                             float *out, int64_t ldc, hipStream_t s) {
+    const int bs = 256;
+    const int64_t grid = (n + bs - 1) / bs;
+    hipLaunchKernelGGL(k_fk_spheres, dim3((unsigned)grid), dim3(bs), 0, s, rb, q, n, ldq, out, ldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
+                                  int64_t n, int64_t ldq, uint8_t *out, hipStream_t s) {
+    const int bs = 256;
+    const int64_t grid = (n + bs - 1) / bs;
+    if (lds)
+        hipLaunchKernelGGL(k_validate_states<true>, dim3((unsigned)grid), dim3(bs),
+                           (size_t)ed.n_rec * 16, s, rb, ed, ed.rec, q, n, ldq, out);
+    else
+        hipLaunchKernelGGL(k_validate_states<false>, dim3((unsigned)grid), dim3(bs), 0, s, rb, ed,
+                           ed.rec, q, n, ldq, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, queue, 0ull, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, bool lds, const float *qa,
+                                 const float *qb, const int32_t *nst, int64_t n_edges, float res,
+                                 uint8_t *out, unsigned long long *queue, int grid, int block,
+                                 hipStream_t s, unsigned long long *flops) {
+    const size_t sh = lds ? (size_t)ed.n_rec * 16 : 0;
+    if (flops) {
+        if (lds)
+            hipLaunchKernelGGL((k_validate_edges<true, true>), dim3(grid), dim3(block), sh, s, rb,
+                               ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops);
+        else
+            hipLaunchKernelGGL((k_validate_edges<false, true>), dim3(grid), dim3(block), sh, s, rb,
+                               ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops);
+    } else {
+        if (lds)
+            hipLaunchKernelGGL((k_validate_edges<true, false>), dim3(grid), dim3(block), sh, s, rb,
+                               ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops);
+        else
+            hipLaunchKernelGGL((k_validate_edges<false, false>), dim3(grid), dim3(block), sh, s, rb,
+                               ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed, bool lds,
+                                    const float *qa, const float *qb, const int32_t *nst,
+                                    int64_t e, float res, uint8_t *out, hipStream_t s) {
+    if (lds)
+        hipLaunchKernelGGL(k_validate_edge_one<true>, dim3(1), dim3(kWave), (size_t)ed.n_rec * 16,
+                           s, rb, ed, ed.rec, qa, qb, nst, e, res, out);
+    else
+        hipLaunchKernelGGL(k_validate_edge_one<false>, dim3(1), dim3(kWave), 0, s, rb, ed, ed.rec,
+                           qa, qb, nst, e, res, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
+                           int64_t n, int64_t ldq, float *cost, hipStream_t s) {
+    const int bs = 256;
+    const int64_t grid = (n + bs - 1) / bs;
+    if (lds)
+        hipLaunchKernelGGL(k_cost_fwd<true>, dim3((unsigned)grid), dim3(bs), (size_t)ed.n_rec * 16,
+                           s, rb, ed, ed.rec, q, n, ldq, cost);
+    else
+        hipLaunchKernelGGL(k_cost_fwd<false>, dim3((unsigned)grid), dim3(bs), 0, s, rb, ed, ed.rec,
+                           q, n, ldq, cost);
+    return hipGetLastError();
+}
+
+size_t cost_bwd_slot_bytes(const RobotDev &rb, int block) {
+    return (size_t)rb.n_links * 6 * kWave * sizeof(float) * (block / kWave);
+}
+
+hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
+                           int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
+                           int block, hipStream_t s) {
+    const int64_t grid = (n + block - 1) / block;
+    const size_t slots = cost_bwd_slot_bytes(rb, block);
+    if (lds)
+        hipLaunchKernelGGL(k_cost_bwd<true>, dim3((unsigned)grid), dim3(block),
+                           slots + (size_t)ed.n_rec * 16, s, rb, ed, ed.rec, q, n, ldq, gcost, grad,
+                           ldg);
+    else
+        hipLaunchKernelGGL(k_cost_bwd<false>, dim3((unsigned)grid), dim3(block), slots, s, rb, ed,
+                           ed.rec, q, n, ldq, gcost, grad, ldg);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
+                                      int64_t total, float res, const float *qa, const float *qb,
+                                      uint8_t *out, unsigned long long *queue, int grid, int block,
+                                      hipStream_t s) {
+    hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block), 0, s, sets, prefix, n_sets,
+                       total, res, qa, qb, out, queue);
+    return hipGetLastError();
+}
+
+}  // namespace vk

@@ -1,0 +1,106 @@
+// Device-resident records shared by the host runtime (vk_api.cpp) and the kernels.
+//
+// The host turns a robot description into a small uniform "program" that every lane of a
+// wavefront walks in lock-step: a list of link steps in topological order (pose a link,
+// place its spheres, test them, then test the self pairs that this link completes).  This
+// is the GPU counterpart of the straight-line, topologically reordered FK + collision code
+// the paper generates per robot (Sec. III-B tracing compiler, Sec. III-D interleaving): the
+// control flow depends only on the robot, so it is identical in every lane and all of its
+// data is read with wave-uniform (scalar) loads.
+#pragma once
+#include <stdint.h>
+
+namespace vk {
+
+constexpr int kWave = 64;          // CDNA wavefront width: one lane per configuration
+constexpr int kSpl = 8;            // spheres held in registers per link step
+constexpr int kMaxDof = 64;
+
+// Twist codes: the paper's tracing compiler folds constant sin/cos of the DH twist; the
+// common twists 0 and +-90 degrees are folded the same way here (a uniform branch picks the
+// specialised update).
+enum Twist : int32_t { kTwist0 = 0, kTwistP90 = 1, kTwistM90 = 2, kTwistGeneral = 3 };
+
+struct JointRec {                  // 80 bytes
+    float a, d, ca, sa;            // DH length, offset, cos/sin of twist
+    float theta_off;
+    int32_t twist;                 // Twist
+    int32_t has_mount;             // 0: mount is identity
+    int32_t parent;                // link the joint hangs off
+    float m[12];                   // mount, row-major 3x4
+};
+
+// One link step.  If `joint` >= 0 the step first poses link joint+1: when `restart_len` >= 0
+// the parent's pose is rebuilt from the base by applying the `restart_len` joints listed at
+// paths[restart_off...] (a tree branch), otherwise the step continues from the previous
+// step's pose (serial chain).  A link with more than kSpl spheres is split into several steps;
+// the later ones have joint = -1 and reuse the pose.
+struct StepRec {                   // 48 bytes
+    int32_t joint;
+    int32_t restart_off, restart_len;
+    int32_t sph_first, sph_count;  // fine spheres of this step (<= kSpl)
+    int32_t blk_first, blk_count;  // self-collision blocks completed by this step
+    int32_t link;
+    float coarse[4];               // bounding sphere of the step's spheres, link frame
+};
+
+// Self pairs between this step's spheres and the spheres of one earlier link A.  The pose of
+// A is rebuilt into a second register frame by applying path joints (from identity when
+// `restart`, else continuing from the previous block's link, an ancestor of A).
+struct BlockRec {                  // 48 bytes
+    int32_t restart;
+    int32_t path_off, path_len;
+    int32_t ent_first, ent_count;
+    int32_t link;
+    int32_t pad0, pad1;
+    float coarse[4];               // bounding sphere of the block's earlier spheres, A's frame
+};
+
+// One earlier sphere t of a block and the mask of this step's spheres it is paired with.
+struct EntryRec {                  // 32 bytes
+    float x, y, z, r;              // centre in A's frame, radius
+    uint32_t mask;                 // bit k: paired with the step's k-th sphere
+    uint32_t pad[3];
+};
+
+struct RobotDev {
+    const JointRec *joints;
+    const StepRec *steps;
+    const BlockRec *blocks;
+    const EntryRec *entries;
+    const int32_t *paths;
+    const float4 *spheres;         // [S] centre (link frame), radius
+    const int32_t *sphere_step;    // [S] step index of each sphere (cost backward)
+    int32_t dof, n_steps, n_spheres, n_links;
+};
+
+// Environment, packed as float4 records in one buffer:
+//   spheres   1 x float4: (centre, radius)
+//   capsules  2 x float4: (p0, radius), (u = p1 - p0, 1 / (u . u) or 0)
+//   cylinders 2 x float4: (centre, half height), (unit axis, radius)
+//   boxes     4 x float4: (col_0 of R, e_0), (col_1, e_1), (col_2, e_2), (centre, 0)
+struct EnvDev {
+    const float4 *rec;
+    int32_t n_sph, n_cap, n_cyl, n_box;
+    int32_t off_cap, off_cyl, off_box, n_rec;    // offsets / total in float4 records
+    // uniform grid over a large sphere set (point clouds); n_cells == 0 when absent
+    const float4 *grid_pts;        // points sorted by cell (centre, radius)
+    const int32_t *cell_start;     // [n_cells + 1]
+    int32_t gdim[3];
+    int32_t n_cells;
+    float gorg[3];
+    float ginv;                    // 1 / cell size
+    float gcell;
+    float gmax_r;                  // largest radius stored in the grid
+};
+
+// One edge set of a mixed-robot batch.
+struct BatchSet {
+    RobotDev rb;
+    EnvDev env;
+    int64_t qa_offset;             // float offset of the set's first edge in qa / qb
+    int64_t n_edges;
+    int64_t out_offset;
+};
+
+}  // namespace vk

@@ -1,0 +1,104 @@
+"""GPU parity of the squared-penetration cost and its adjoint against the FP64 oracle.
+
+Tolerances.  The FP32 sphere centres carry errors of order 1e-6 m; a penetration p shifts by
+about that much, so each term p^2 moves by ~2 p * 1e-6, i.e. relatively by 2e-6 / p.  With
+penetrations of 1e-2 m and more dominating the sum, the forward check allows an absolute 1e-6
+plus a relative 2e-4.  The gradient metric is the per-trajectory relative Frobenius error over
+trajectories whose oracle maximum penetration is at least 1e-3 m (there a 1e-6 m centre error
+is a small fraction of the penetration); the bound is 1e-4.
+"""
+import numpy as np
+import pytest
+
+from helpers import dev, host, say
+from synthetic import workload, rng, chain_robot, bimanual_robot, random_scene, uniform_states
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_14545_amd as vk
+    vk.lib()
+    return vk
+
+
+def _cases():
+    w = workload("cost7", n=96)                   # 96 trajectories x 64 waypoints
+    yield "cost7", w["robot"], w["env"], w["q"], 64
+    r14 = workload("states14_cloud", n=1)["robot"]
+    env = random_scene(rng("gpu-cost", "env"), mounts=((0, .25, .5), (0, -.25, .5)))
+    g = rng("gpu-cost", "cyl")
+    cyl = []
+    for _ in range(10):
+        w_ = g.normal(size=3)
+        w_ /= np.linalg.norm(w_)
+        cyl.append(np.concatenate([g.uniform(-1, 1, 3), w_, [g.uniform(.05, .3), g.uniform(.03, .15)]]))
+    env["cylinders"] = np.asarray(cyl, np.float32)
+    yield "bimanual14_mixed", r14, env, uniform_states(rng("gpu-cost", "q14"), 14, 64 * 24), 64
+
+
+@pytest.mark.parametrize("case", list(_cases()), ids=lambda c: c[0])
+def test_cost_forward(vk, orc, case):
+    name, robot, env, q, _ = case
+    say("cost fwd", name, q.shape)
+    c = host(vk.penetration_cost_fwd(vk.Robot(robot), vk.Env(env), dev(q))).astype(np.float64)
+    ref = orc.costs(robot, env, q)
+    err = np.abs(c - ref)
+    say("  max abs err", err.max(), "max cost", ref.max(), "active", (ref > 0).mean())
+    assert np.all(err <= 1e-6 + 2e-4 * ref)
+    cmin, _ = orc.states(robot, env, q)
+    assert np.all(c[cmin > 1e-4] == 0.0)         # clearly free states have exactly zero cost
+
+
+@pytest.mark.parametrize("case", list(_cases()), ids=lambda c: c[0])
+def test_cost_gradient(vk, orc, case):
+    name, robot, env, q, per = case
+    import torch
+    n = q.shape[1]
+    gc = np.random.default_rng(4).uniform(0.5, 2.0, n).astype(np.float32)
+    say("cost bwd", name, q.shape)
+    g = host(vk.penetration_cost_bwd(vk.Robot(robot), vk.Env(env), dev(q), dev(gc))).astype(np.float64)
+    ref = orc.cost_grads(robot, env, q) * gc[None, :].astype(np.float64)
+    cmin, _ = orc.states(robot, env, q)
+    # per trajectory (groups of `per` consecutive states)
+    checked = 0
+    worst = 0.0
+    for t in range(n // per):
+        sl = slice(t * per, (t + 1) * per)
+        if -np.nanmin(cmin[sl]) < 1e-3:
+            continue
+        rel = np.linalg.norm(g[:, sl] - ref[:, sl]) / np.linalg.norm(ref[:, sl])
+        worst = max(worst, rel)
+        checked += 1
+    glob = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+    say(f"  trajectories checked {checked}, worst rel {worst:.2e}, global rel {glob:.2e}")
+    assert checked > 0
+    assert worst <= 1e-4
+    assert glob <= 1e-4
+    free = cmin > 1e-4
+    assert np.all(g[:, free] == 0.0)
+
+
+def test_autograd_function(vk):
+    import torch
+    w = workload("cost7", n=8)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    q = dev(w["q"]).requires_grad_(True)
+    cost = vk.penetration_cost(q, r, e)
+    (2.0 * cost).sum().backward()
+    direct = vk.penetration_cost_bwd(r, e, q.detach(), torch.full_like(cost, 2.0))
+    torch.testing.assert_close(q.grad, direct, rtol=0, atol=0)
+
+
+def test_cost_non_finite(vk):
+    w = workload("cost7", n=2)
+    q = w["q"].copy()
+    q[2, 5] = np.nan
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    c = host(vk.penetration_cost_fwd(r, e, dev(q)))
+    assert np.isnan(c[5]) and np.isfinite(np.delete(c, 5)).all()
+    g = host(vk.penetration_cost_bwd(r, e, dev(q), dev(np.ones(q.shape[1], np.float32))))
+    assert np.isnan(g[:, 5]).all() and np.isfinite(np.delete(g, 5, axis=1)).all()

@@ -1,0 +1,125 @@
+"""GPU parity of validate_edges (persistent batched launch) and validate_edges_per_edge
+against the FP64 oracle, plus schedule invariance and degenerate edges."""
+import numpy as np
+import pytest
+
+from helpers import dev, host, say, edge_mismatches, state_mismatches
+from synthetic import workload, rng, uniform_edges
+
+pytestmark = pytest.mark.gpu
+RES = 1.0 / 32.0
+
+
+@pytest.fixture(scope="module")
+def vk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_14545_amd as vk
+    vk.lib()
+    yield vk
+    vk.set_edge_launch(0, 0)
+
+
+@pytest.mark.parametrize("name", ["edges7_shelf", "edges8_shelf"])
+@pytest.mark.parametrize("per_edge", [False, True], ids=["batched", "per_edge"])
+def test_edges_parity(vk, orc, name, per_edge):
+    w = workload(name, n=1500)
+    say("validate_edges", name, "per_edge" if per_edge else "batched", "E", len(w["qa"]))
+    flags = host(vk.validate_edges(vk.Robot(w["robot"]), vk.Env(w["env"]), dev(w["qa"]),
+                                   dev(w["qb"]), resolution=RES, per_edge=per_edge))
+    _, cls, _ = orc.edges(w["robot"], w["env"], w["qa"], w["qb"], res=RES)
+    bad, near = edge_mismatches(flags, cls)
+    say(f"  mismatches outside band {bad}, near-contact {near}, collision rate {flags.mean():.3f}")
+    assert bad == 0
+
+
+def test_edges_full_size_sampled(vk, orc):
+    """The full 65,536-edge 7-DoF shelf batch in the default launch; the oracle checks a seeded
+    sample of 600 edges."""
+    w = workload("edges7_shelf")
+    E = len(w["qa"])
+    say("validate_edges full size", E)
+    flags = host(vk.validate_edges(vk.Robot(w["robot"]), vk.Env(w["env"]), dev(w["qa"]),
+                                   dev(w["qb"]), resolution=RES))
+    idx = np.sort(np.random.default_rng(11).choice(E, 600, replace=False))
+    _, cls, _ = orc.edges(w["robot"], w["env"], w["qa"][idx], w["qb"][idx], res=RES)
+    assert edge_mismatches(flags[idx], cls)[0] == 0
+
+
+def test_schedule_invariance(vk):
+    """Flags do not depend on the launch shape or on batching: bitwise equal across workgroup
+    sizes, workgroups per CU and the one-launch-per-edge path."""
+    w = workload("edges8_shelf", n=3000)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = dev(w["qa"]), dev(w["qb"])
+    ref = host(vk.validate_edges(r, e, qa, qb, per_edge=True))
+    for block, bpc in ((64, 1), (128, 3), (256, 8), (192, 2), (256, 1)):
+        say("launch", block, bpc)
+        vk.set_edge_launch(block, bpc)
+        np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb)), ref)
+    vk.set_edge_launch(0, 0)
+
+
+def test_explicit_state_counts(vk, orc):
+    import torch
+    w = workload("edges7_shelf", n=800)
+    g = np.random.default_rng(2)
+    ns = g.integers(2, 300, len(w["qa"])).astype(np.int32)
+    flags = host(vk.validate_edges(vk.Robot(w["robot"]), vk.Env(w["env"]), dev(w["qa"]),
+                                   dev(w["qb"]), n_states=dev(ns)))
+    _, cls, _ = orc.edges(w["robot"], w["env"], w["qa"], w["qb"], n_states=ns)
+    assert edge_mismatches(flags, cls)[0] == 0
+
+
+def test_endpoints_only_equals_states(vk):
+    """With two states per edge the edge flag is exactly the OR of the two endpoint states'
+    flags from validate_states (both paths evaluate the very same FP32 configurations)."""
+    w = workload("edges7_shelf", n=2000)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    ns = np.full(len(w["qa"]), 2, np.int32)
+    fe = host(vk.validate_edges(r, e, dev(w["qa"]), dev(w["qb"]), n_states=dev(ns)))
+    fa = host(vk.validate_states(r, e, dev(np.ascontiguousarray(w["qa"].T))))
+    fb = host(vk.validate_states(r, e, dev(np.ascontiguousarray(w["qb"].T))))
+    np.testing.assert_array_equal(fe, fa | fb)
+
+
+def test_fine_resolution_long_edges(vk, orc):
+    """Resolution 1/256 rad: up to ~1,500 states per edge, ~24 rake steps."""
+    w = workload("edges7_shelf", n=120)
+    flags = host(vk.validate_edges(vk.Robot(w["robot"]), vk.Env(w["env"]), dev(w["qa"]),
+                                   dev(w["qb"]), resolution=1.0 / 256.0))
+    _, cls, _ = orc.edges(w["robot"], w["env"], w["qa"], w["qb"], res=1.0 / 256.0)
+    assert edge_mismatches(flags, cls)[0] == 0
+
+
+def test_degenerate_edges(vk, orc):
+    import torch
+    w = workload("edges7_shelf", n=256)
+    qa, qb = w["qa"].copy(), w["qb"].copy()
+    qb[:40] = qa[:40]                       # zero length: two copies of one state
+    qa[40, 2] = np.nan                      # non-finite endpoint -> colliding
+    qb[41, 0] = np.inf
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    flags = host(vk.validate_edges(r, e, dev(qa), dev(qb)))
+    assert flags[40] == 1 and flags[41] == 1
+    _, cls, _ = orc.edges(w["robot"], w["env"], qa, qb)
+    assert edge_mismatches(flags, cls)[0] == 0
+    # zero-length edges agree with their single state
+    cm, _ = orc.states(w["robot"], w["env"], qa[:40].T)
+    assert state_mismatches(flags[:40], cm)[0] == 0
+    # empty batch is a no-op
+    out = vk.validate_edges(r, e, torch.zeros((0, 7), device="cuda"), torch.zeros((0, 7), device="cuda"))
+    assert out.numel() == 0
+
+
+def test_argument_errors(vk):
+    import torch
+    w = workload("edges7_shelf", n=4)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa = dev(w["qa"])
+    with pytest.raises(vk.VkError):
+        vk.validate_edges(r, e, qa, qa, resolution=0.0)
+    with pytest.raises(vk.VkError):
+        vk.validate_edges(r, e, qa, qa, resolution=float("nan"))
+    with pytest.raises(ValueError):
+        vk.validate_edges(r, e, qa, qa[:, :6].contiguous())

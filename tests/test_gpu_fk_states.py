@@ -1,0 +1,163 @@
+"""GPU parity of fk_spheres and validate_states against the FP64 oracle (through the C ABI)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from helpers import BAND, CENTRE_TOL, dev, host, say, state_mismatches
+from synthetic import (workload, chain_robot, bimanual_robot, cube_scene, shelf_scene,
+                       random_scene, rng, uniform_states)
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def vk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_14545_amd as vk
+    vk.lib()
+    return vk
+
+
+def _robots():
+    return {
+        "chain7": workload("states7", n=1)["robot"],
+        "chain8": workload("edges8_shelf", n=1)["robot"],
+        "bimanual14": workload("states14_cloud", n=1)["robot"],
+    }
+
+
+def _oracle_centres(orc, robot, q):
+    rb = orc.Robot(robot)
+    return np.stack([orc.sphere_centres(rb, q[:, i]) for i in range(q.shape[1])], axis=2)
+
+
+def test_fk_hand_values(vk, orc):
+    for case in json.load(open(os.path.join(GOLDEN, "fk_hand.json")))["cases"]:
+        if "centres" not in case:
+            continue
+        say("fk hand case", case["name"])
+        dh = np.asarray(case["dh"], np.float32)
+        sp = np.asarray(case["spheres"], np.float32).reshape(-1, 5)
+        robot = {"dof": len(dh), "parent_link": np.asarray(case.get("parent_link", range(len(dh)))),
+                 "mount": np.asarray(case["mount"], np.float32) if "mount" in case else None,
+                 "dh": dh, "sphere_link": sp[:, 0].astype(np.int32), "sphere_xyzr": sp[:, 1:]}
+        r = vk.Robot(robot)
+        c = host(vk.fk_spheres(r, dev(np.asarray(case["q"], np.float32).reshape(-1, 1))))
+        np.testing.assert_allclose(c[:, :, 0], np.asarray(case["centres"]), atol=CENTRE_TOL)
+
+
+@pytest.mark.parametrize("name", ["chain7", "chain8", "bimanual14"])
+def test_fk_spheres_parity(vk, orc, name):
+    robot = _robots()[name]
+    n = 1037                                  # several 256-lane blocks and a ragged tail
+    q = uniform_states(rng("gpu-fk", name), robot["dof"], n)
+    say("fk_spheres", name, "n", n)
+    c = host(vk.fk_spheres(vk.Robot(robot), dev(q)))
+    ref = _oracle_centres(orc, robot, q.astype(np.float64))
+    err = np.linalg.norm(c - ref, axis=1).max()
+    say("  max centre error", err)
+    assert err <= CENTRE_TOL
+
+
+def test_fk_spheres_full_size_sampled(vk, orc):
+    """2^20 states of the 14-DoF robot in the launch used for large batches; the oracle checks
+    a seeded sample of 512 states."""
+    robot = _robots()["bimanual14"]
+    n = 1 << 20
+    q = uniform_states(rng("gpu-fk", "full"), robot["dof"], n)
+    say("fk_spheres full size", n)
+    c = vk.fk_spheres(vk.Robot(robot), dev(q))
+    idx = np.sort(np.random.default_rng(5).choice(n, 512, replace=False))
+    sub = host(c[:, :, idx])
+    ref = _oracle_centres(orc, robot, q[:, idx].astype(np.float64))
+    assert np.linalg.norm(sub - ref, axis=1).max() <= CENTRE_TOL
+
+
+def test_fk_spheres_leading_dimensions(vk, orc):
+    import ctypes as C
+    import torch
+    robot = _robots()["chain7"]
+    r = vk.Robot(robot)
+    n, ldq, ldc = 300, 333, 301
+    q = np.zeros((robot["dof"], ldq), np.float32)
+    q[:, :n] = uniform_states(rng("gpu-fk", "ld"), robot["dof"], n)
+    qd = dev(q)
+    out = torch.full((r.n_spheres, 3, ldc), -7.0, device="cuda")
+    st = vk._stream()
+    vk._check(vk.lib().fk_spheres(r.handle, qd.data_ptr(), n, ldq, out.data_ptr(), ldc, st))
+    o = host(out)
+    ref = _oracle_centres(orc, robot, q[:, :n].astype(np.float64))
+    assert np.linalg.norm(o[:, :, :n] - ref, axis=1).max() <= CENTRE_TOL
+    assert np.all(o[:, :, n:] == -7.0)       # padding untouched
+    assert vk.lib().fk_spheres(r.handle, qd.data_ptr(), n, n - 1, out.data_ptr(), ldc, st) == -2
+
+
+def _state_case(name):
+    if name == "states7":
+        w = workload("states7")
+        return w["robot"], w["env"], w["q"]
+    if name == "chain8_shelf":
+        w = workload("edges8_shelf", n=1)
+        return w["robot"], w["env"], uniform_states(rng("gpu-st", name), 8, 2000)
+    if name == "bimanual14_cube":
+        r = workload("states14_cloud", n=1)["robot"]
+        env = cube_scene(rng("gpu-st", "env14"), mounts=((0, .25, .5), (0, -.25, .5)), sphere_r=(0.02, 0.06))
+        return r, env, uniform_states(rng("gpu-st", name), 14, 1037)
+    if name == "chain7_mixed_kinds":
+        r = workload("states7", n=1)["robot"]
+        env = random_scene(rng("gpu-st", "mixed-env"))
+        g = rng("gpu-st", "cyl")
+        cyl = []
+        for _ in range(12):
+            w = g.normal(size=3)
+            w /= np.linalg.norm(w)
+            cyl.append(np.concatenate([g.uniform(-1, 1, 3), w, [g.uniform(.05, .3), g.uniform(.03, .15)]]))
+        env["cylinders"] = np.asarray(cyl, np.float32)
+        return r, env, uniform_states(rng("gpu-st", name), 7, 1500)
+    if name == "chain7_big_env":
+        # more records than fit the per-workgroup LDS budget: the global-memory variant runs
+        r = workload("states7", n=1)["robot"]
+        env = cube_scene(rng("gpu-st", "big"), n_spheres=5000, n_boxes=0, sphere_r=(0.005, 0.02))
+        return r, env, uniform_states(rng("gpu-st", name), 7, 700)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["states7", "chain8_shelf", "bimanual14_cube",
+                                  "chain7_mixed_kinds", "chain7_big_env"])
+def test_validate_states_parity(vk, orc, name):
+    robot, env, q = _state_case(name)
+    say("validate_states", name, "n", q.shape[1])
+    flags = host(vk.validate_states(vk.Robot(robot), vk.Env(env), dev(q)))
+    cmin, _ = orc.states(robot, env, q)
+    bad, near = state_mismatches(flags, cmin)
+    say(f"  mismatches outside band {bad}, near-contact {near}, collision rate {flags.mean():.3f}")
+    assert bad == 0
+
+
+def test_validate_states_non_finite(vk, orc):
+    w = workload("states7", n=512)
+    q = w["q"].copy()
+    q[3, 10] = np.nan
+    q[0, 200] = np.inf
+    q[6, 511] = -np.inf
+    flags = host(vk.validate_states(vk.Robot(w["robot"]), vk.Env(w["env"]), dev(q)))
+    assert flags[10] == 1 and flags[200] == 1 and flags[511] == 1
+    cmin, _ = orc.states(w["robot"], w["env"], q)
+    assert state_mismatches(flags, cmin)[0] == 0
+
+
+def test_validate_states_empty_and_free(vk):
+    import torch
+    w = workload("states7", n=64)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    out = vk.validate_states(r, e, torch.zeros((7, 0), device="cuda"))
+    assert out.numel() == 0
+    # no obstacles and no self pairs: every state is free
+    bare = dict(w["robot"])
+    bare["self_pairs"] = np.zeros((0, 2), np.int32)
+    flags = host(vk.validate_states(vk.Robot(bare), vk.Env({}), dev(w["q"])))
+    assert not flags.any()
