@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--per-edge-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="edges7_shelf", choices=["edges7_shelf", "edges8_shelf"])
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -84,6 +86,16 @@ def main():
     from synthetic import workload, robot_summary, scene_summary
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.calibrate_copy} MiB three times (read {args.calibrate_copy} MiB, "
+            f"write {args.calibrate_copy} MiB per copy)")
+        return
     w = workload(args.workload)
     E = len(w["qa"])
     counts = state_counts(w["qa"], w["qb"], RES)
@@ -123,18 +135,20 @@ def main():
         f"edge collision rate {flags.mean():.3f}")
 
     # plain one-launch-per-edge baseline on the same batch
-    pe_out = torch.empty_like(out)
-    vk.validate_edges(robot, env, qa, qb, resolution=RES, out=pe_out, per_edge=True)
-    torch.cuda.synchronize()
-    p0 = time.perf_counter()
-    for _ in range(args.per_edge_steps):
+    pe_value = pe_ms = None
+    if args.per_edge_steps > 0:
+        pe_out = torch.empty_like(out)
         vk.validate_edges(robot, env, qa, qb, resolution=RES, out=pe_out, per_edge=True)
-    torch.cuda.synchronize()
-    p1 = time.perf_counter()
-    pe_ms = (p1 - p0) * 1e3 / args.per_edge_steps
-    pe_value = nominal * args.per_edge_steps / (p1 - p0)
-    assert np.array_equal(pe_out.cpu().numpy(), flags), "per-edge and batched flags differ"
-    log(f"per-edge: {pe_ms:.1f} ms/step, {pe_value:.3e} states/s")
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for _ in range(args.per_edge_steps):
+            vk.validate_edges(robot, env, qa, qb, resolution=RES, out=pe_out, per_edge=True)
+        torch.cuda.synchronize()
+        p1 = time.perf_counter()
+        pe_ms = (p1 - p0) * 1e3 / args.per_edge_steps
+        pe_value = nominal * args.per_edge_steps / (p1 - p0)
+        assert np.array_equal(pe_out.cpu().numpy(), flags), "per-edge and batched flags differ"
+        log(f"per-edge: {pe_ms:.1f} ms/step, {pe_value:.3e} states/s")
 
     achieved = flops / (launch_ms * 1e-3)
     result = {
@@ -162,7 +176,7 @@ def main():
         },
         "per_edge": {"value": pe_value, "unit": "states/s", "ms_per_step": pe_ms,
                      "launches_per_step": E, "steps": args.per_edge_steps},
-        "speedup_vs_per_edge": value / pe_value,
+        "speedup_vs_per_edge": value / pe_value if pe_value else None,
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,

@@ -105,7 +105,8 @@ def _state_case(name):
         return w["robot"], w["env"], uniform_states(rng("gpu-st", name), 8, 2000)
     if name == "bimanual14_cube":
         r = workload("states14_cloud", n=1)["robot"]
-        env = cube_scene(rng("gpu-st", "env14"), mounts=((0, .25, .5), (0, -.25, .5)), sphere_r=(0.02, 0.06))
+        env = cube_scene(rng("gpu-st", "env14"), n_spheres=6, n_boxes=1,
+                         mounts=((0, .25, .5), (0, -.25, .5)), sphere_r=(0.02, 0.06))
         return r, env, uniform_states(rng("gpu-st", name), 14, 1037)
     if name == "chain7_mixed_kinds":
         r = workload("states7", n=1)["robot"]
@@ -121,7 +122,9 @@ def _state_case(name):
     if name == "chain7_big_env":
         # more records than fit the per-workgroup LDS budget: the global-memory variant runs
         r = workload("states7", n=1)["robot"]
-        env = cube_scene(rng("gpu-st", "big"), n_spheres=5000, n_boxes=0, sphere_r=(0.005, 0.02))
+        g = rng("gpu-st", "big")
+        c = g.uniform(-4.0, 4.0, (4200, 3))
+        env = {"spheres": np.concatenate([c, g.uniform(0.005, 0.02, (4200, 1))], 1).astype(np.float32)}
         return r, env, uniform_states(rng("gpu-st", name), 7, 700)
     raise KeyError(name)
 
