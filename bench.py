@@ -108,10 +108,14 @@ def main():
     stream = torch.cuda.current_stream()
 
     # executed FP32 work of one launch (instrumented variant, untimed)
-    flops_t = torch.zeros(1, dtype=torch.int64, device="cuda")
+    flops_t = torch.zeros(5, dtype=torch.int64, device="cuda")
     vk.validate_edges_counted(robot, env, qa, qb, flops_t, resolution=RES, out=out)
     torch.cuda.synchronize()
-    flops = int(flops_t.item())
+    fl = [int(x) for x in flops_t.cpu().tolist()]
+    flops = fl[0]
+    breakdown = dict(zip(("fk", "cull", "fine", "self"), fl[1:]))
+    log(f"executed FLOP per launch {flops:.4e}: " +
+        ", ".join(f"{k} {100.0 * v / max(flops, 1):.1f}%" for k, v in breakdown.items()))
     flags_counted = out.cpu().numpy().copy()
 
     for _ in range(args.warmup):
@@ -187,6 +191,7 @@ def main():
             "traffic": None,
             "kernel": "k_validate_edges<LDS=true>",
             "flop_per_launch": flops,
+            "flop_breakdown": breakdown,
             "launch_ms": launch_ms,
         },
     }

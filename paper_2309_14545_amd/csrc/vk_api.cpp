@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -363,6 +364,44 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
     r->n_spheres = S;
 }
 
+// Bounding sphere (AABB centre, farthest reach) of a set of spheres, rounded up and padded by
+// 1e-5 m so the FP32 culling tests stay conservative.
+float4 bound_of(const std::vector<std::array<double, 4>> &sph) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (const auto &s : sph)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], s[a] - s[3]);
+            hi[a] = std::max(hi[a], s[a] + s[3]);
+        }
+    double c[3], R = 0.0;
+    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
+    for (const auto &s : sph) {
+        const double dx = s[0] - c[0], dy = s[1] - c[1], dz = s[2] - c[2];
+        R = std::max(R, std::sqrt(dx * dx + dy * dy + dz * dz) + s[3]);
+    }
+    return make_float4((float)c[0], (float)c[1], (float)c[2],
+                       std::nextafter((float)(R + 1e-5), INFINITY));
+}
+
+float int_bits(int v) {
+    float f;
+    std::memcpy(&f, &v, sizeof f);
+    return f;
+}
+
+uint64_t spread_bits(uint64_t v) {       // 21-bit value -> every third bit
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
+constexpr int kClusterSize = 8;   // primitives per cluster
+constexpr int kGroupSize = 8;     // clusters per group
+
 void build_env(const vk_env_desc *d, vk_env_s *e) {
     if (!d) raise(VK_ERR_INVALID_ARG, "env desc is NULL");
     const int ns = d->n_spheres, nc = d->n_capsules, ny = d->n_cylinders, nb = d->n_boxes;
@@ -374,47 +413,133 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
         (ny && !finite_all(d->cylinders, (size_t)ny * 8)) ||
         (nb && !finite_all(d->boxes, (size_t)nb * 15)))
         raise(VK_ERR_INVALID_ARG, "primitive values must be finite");
-    std::vector<float4> rec;
-    rec.reserve((size_t)ns + 2 * nc + 2 * ny + 4 * nb);
+    for (int i = 0; i < ns; ++i)
+        if (d->spheres[4 * i + 3] < 0.0f) raise(VK_ERR_INVALID_ARG, "negative sphere radius");
+
+    // every primitive with its bounding sphere
+    struct Prim {
+        int type, idx;
+        std::array<double, 4> bs;
+        uint64_t key;
+    };
+    std::vector<Prim> prims;
+    prims.reserve((size_t)ns + nc + ny + nb);
     for (int i = 0; i < ns; ++i) {
         const float *s = d->spheres + 4 * i;
-        if (s[3] < 0.0f) raise(VK_ERR_INVALID_ARG, "negative sphere radius");
-        rec.push_back(make_float4(s[0], s[1], s[2], s[3]));
+        prims.push_back({0, i, {s[0], s[1], s[2], s[3]}, 0});
     }
     for (int i = 0; i < nc; ++i) {
         const float *c = d->capsules + 7 * i;
-        const float ux = c[3] - c[0], uy = c[4] - c[1], uz = c[5] - c[2];
-        const float uu = ux * ux + uy * uy + uz * uz;
-        rec.push_back(make_float4(c[0], c[1], c[2], c[6]));
-        rec.push_back(make_float4(ux, uy, uz, uu > 0.0f ? 1.0f / uu : 0.0f));
+        const double hx = 0.5 * ((double)c[3] - c[0]), hy = 0.5 * ((double)c[4] - c[1]),
+                     hz = 0.5 * ((double)c[5] - c[2]);
+        prims.push_back({1, i, {c[0] + hx, c[1] + hy, c[2] + hz,
+                                std::sqrt(hx * hx + hy * hy + hz * hz) + c[6]}, 0});
     }
     for (int i = 0; i < ny; ++i) {
         const float *c = d->cylinders + 8 * i;
-        rec.push_back(make_float4(c[0], c[1], c[2], c[6]));
-        rec.push_back(make_float4(c[3], c[4], c[5], c[7]));
+        prims.push_back({2, i, {c[0], c[1], c[2], std::hypot((double)c[6], (double)c[7])}, 0});
     }
     for (int i = 0; i < nb; ++i) {
         const float *b = d->boxes + 15 * i;
-        const float *R = b + 3, *ext = b + 12;
-        for (int k = 0; k < 3; ++k) rec.push_back(make_float4(R[k], R[3 + k], R[6 + k], ext[k]));
-        rec.push_back(make_float4(b[0], b[1], b[2], 0.0f));
+        const double r = std::sqrt((double)b[12] * b[12] + (double)b[13] * b[13] + (double)b[14] * b[14]);
+        prims.push_back({3, i, {b[0], b[1], b[2], r}, 0});
     }
+    // Morton order of the centres, then runs of kClusterSize primitives form clusters
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (const Prim &p : prims)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = std::min(lo[a], p.bs[a]);
+            hi[a] = std::max(hi[a], p.bs[a]);
+        }
+    for (Prim &p : prims) {
+        uint64_t k = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double span = hi[a] > lo[a] ? hi[a] - lo[a] : 1.0;
+            const uint64_t q = (uint64_t)std::min(2097151.0, (p.bs[a] - lo[a]) / span * 2097151.0);
+            k |= spread_bits(q) << a;
+        }
+        p.key = k;
+    }
+    std::stable_sort(prims.begin(), prims.end(),
+                     [](const Prim &a, const Prim &b) { return a.key < b.key; });
+    const int n_prim = (int)prims.size();
+    const int n_clu = (n_prim + kClusterSize - 1) / kClusterSize;
+    const int n_sup = (n_clu + kGroupSize - 1) / kGroupSize;
+
+    std::vector<float4> sph, cap, cyl, box, csph, cbeg, ssph, sbeg;
+    std::vector<std::array<double, 4>> cluster_bs;
+    for (int c = 0; c < n_clu; ++c) {
+        cbeg.push_back(make_float4(int_bits((int)sph.size()), int_bits((int)(cap.size() / 2)),
+                                   int_bits((int)(cyl.size() / 2)), int_bits((int)(box.size() / 4))));
+        std::vector<std::array<double, 4>> members;
+        const int p0 = c * kClusterSize, p1 = std::min(n_prim, p0 + kClusterSize);
+        for (int type = 0; type < 4; ++type)
+            for (int p = p0; p < p1; ++p) {
+                if (prims[p].type != type) continue;
+                members.push_back(prims[p].bs);
+                const int i = prims[p].idx;
+                if (type == 0) {
+                    const float *s = d->spheres + 4 * i;
+                    sph.push_back(make_float4(s[0], s[1], s[2], s[3]));
+                } else if (type == 1) {
+                    const float *q = d->capsules + 7 * i;
+                    const float ux = q[3] - q[0], uy = q[4] - q[1], uz = q[5] - q[2];
+                    const float uu = ux * ux + uy * uy + uz * uz;
+                    cap.push_back(make_float4(q[0], q[1], q[2], q[6]));
+                    cap.push_back(make_float4(ux, uy, uz, uu > 0.0f ? 1.0f / uu : 0.0f));
+                } else if (type == 2) {
+                    const float *q = d->cylinders + 8 * i;
+                    cyl.push_back(make_float4(q[0], q[1], q[2], q[6]));
+                    cyl.push_back(make_float4(q[3], q[4], q[5], q[7]));
+                } else {
+                    const float *b = d->boxes + 15 * i;
+                    const float *R = b + 3, *ext = b + 12;
+                    for (int k = 0; k < 3; ++k) box.push_back(make_float4(R[k], R[3 + k], R[6 + k], ext[k]));
+                    box.push_back(make_float4(b[0], b[1], b[2], 0.0f));
+                }
+            }
+        const float4 bsf = bound_of(members);
+        csph.push_back(bsf);
+        cluster_bs.push_back({bsf.x, bsf.y, bsf.z, bsf.w});
+    }
+    cbeg.push_back(make_float4(int_bits((int)sph.size()), int_bits((int)(cap.size() / 2)),
+                               int_bits((int)(cyl.size() / 2)), int_bits((int)(box.size() / 4))));
+    for (int g = 0; g < n_sup; ++g) {
+        const int c0 = g * kGroupSize, c1 = std::min(n_clu, c0 + kGroupSize);
+        sbeg.push_back(make_float4(int_bits(c0), 0.0f, 0.0f, 0.0f));
+        std::vector<std::array<double, 4>> members(cluster_bs.begin() + c0, cluster_bs.begin() + c1);
+        ssph.push_back(bound_of(members));
+    }
+    sbeg.push_back(make_float4(int_bits(n_clu), 0.0f, 0.0f, 0.0f));
+
+    std::vector<float4> rec;
+    std::memset(&e->dev, 0, sizeof e->dev);
+    auto put = [&](const std::vector<float4> &v) {
+        const int off = (int)rec.size();
+        rec.insert(rec.end(), v.begin(), v.end());
+        return off;
+    };
+    put(ssph);
+    e->dev.off_sbeg = put(sbeg);
+    e->dev.off_csph = put(csph);
+    e->dev.off_cbeg = put(cbeg);
+    e->dev.off_sph = put(sph);
+    e->dev.off_cap = put(cap);
+    e->dev.off_cyl = put(cyl);
+    e->dev.off_box = put(box);
+    e->dev.n_rec = (int)rec.size();
+    e->dev.n_sup = n_sup;
+    e->dev.n_clu = n_clu;
+    e->dev.n_sph = ns;
+    e->dev.n_cap = nc;
+    e->dev.n_cyl = ny;
+    e->dev.n_box = nb;
     if (rec.empty()) rec.push_back(make_float4(0, 0, 0, 0));
     Blob bl;
     const size_t o_r = bl.add(rec.data(), rec.size() * sizeof(float4));
     e->device = current_device();
     e->blob = bl.upload();
-    char *base = static_cast<char *>(e->blob);
-    std::memset(&e->dev, 0, sizeof e->dev);
-    e->dev.rec = reinterpret_cast<const float4 *>(base + o_r);
-    e->dev.n_sph = ns;
-    e->dev.n_cap = nc;
-    e->dev.n_cyl = ny;
-    e->dev.n_box = nb;
-    e->dev.off_cap = ns;
-    e->dev.off_cyl = ns + 2 * nc;
-    e->dev.off_box = ns + 2 * nc + 2 * ny;
-    e->dev.n_rec = ns + 2 * nc + 2 * ny + 4 * nb;
+    e->dev.rec = reinterpret_cast<const float4 *>(static_cast<char *>(e->blob) + o_r);
 }
 
 bool env_in_lds(const vk_env_s *e, size_t extra = 0) {

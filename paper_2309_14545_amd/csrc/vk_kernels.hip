@@ -41,20 +41,27 @@ struct QState {                // SoA state batch: q[j * ldq + i]
 // Environment view (records in LDS or global memory) -----------------------------------------
 struct EnvView {
     const float4 *rec;
-    int n_sph, n_cap, n_cyl, n_box, off_cap, off_cyl, off_box;
+    int n_sup, off_sbeg, off_csph, off_cbeg, off_sph, off_cap, off_cyl, off_box;
 };
 
 __device__ __forceinline__ EnvView make_view(const EnvDev &e, const float4 *rec) {
     EnvView v;
     v.rec = rec;
-    v.n_sph = e.n_sph;
-    v.n_cap = e.n_cap;
-    v.n_cyl = e.n_cyl;
-    v.n_box = e.n_box;
+    v.n_sup = e.n_sup;
+    v.off_sbeg = e.off_sbeg;
+    v.off_csph = e.off_csph;
+    v.off_cbeg = e.off_cbeg;
+    v.off_sph = e.off_sph;
     v.off_cap = e.off_cap;
     v.off_cyl = e.off_cyl;
     v.off_box = e.off_box;
     return v;
+}
+
+// An index stored as float bits in a record; every lane read the same record, so the first
+// lane's value is the wave's value (kept in a scalar register).
+__device__ __forceinline__ int rec_index(float x) {
+    return __builtin_amdgcn_readfirstlane(__float_as_int(x));
 }
 
 // Copy the environment records into LDS once per workgroup.
@@ -66,16 +73,19 @@ __device__ __forceinline__ void stage_env(float4 *lds, const float4 *__restrict_
 // Executed-work accounting (FLOP model, FMA = 2): every wave-uniform operation below adds its
 // per-lane FLOP count; the instrumented kernel multiplies by the 64 lanes that issue it.
 // NoWork compiles to nothing, so the timed kernels carry no accounting.
+// Work is split in four categories: FK and sphere placement, culling (hierarchy and per-link
+// bounding-sphere tests), fine environment tests, self pairs (including re-posing links).
 namespace flop {
 constexpr uint32_t kJoint = 30, kMount = 63, kPlace = 18, kSphere = 11, kCapsule = 25,
                    kCylinder = 35, kBox = 34, kPair = 11;
+enum Cat { kFk = 0, kCull = 1, kFine = 2, kSelf = 3 };
 }
 struct NoWork {
-    __device__ __forceinline__ void add(uint32_t) {}
+    __device__ __forceinline__ void add(int, uint32_t) {}
 };
 struct Work {
-    uint64_t f = 0;
-    __device__ __forceinline__ void add(uint32_t x) { f += x; }
+    uint64_t f[4] = {0, 0, 0, 0};
+    __device__ __forceinline__ void add(int c, uint32_t x) { f[c] += x; }
 };
 
 // Pose the link of step S into T (rebuilding a tree branch from the base when needed).
@@ -88,11 +98,11 @@ __device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, 
         for (int k = 0; k < S.restart_len; ++k) {
             const int j = rb.paths[S.restart_off + k];
             frame_joint(T, rb.joints[j], q(j));
-            w.add(flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
+            w.add(flop::kFk, flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
         }
     }
     frame_joint(T, rb.joints[S.joint], q(S.joint));
-    w.add(flop::kJoint + (rb.joints[S.joint].has_mount ? flop::kMount : 0));
+    w.add(flop::kFk, flop::kJoint + (rb.joints[S.joint].has_mount ? flop::kMount : 0));
 }
 
 // Pose the earlier link of self block B into Ta.
@@ -103,7 +113,7 @@ __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B
     for (int k = 0; k < B.path_len; ++k) {
         const int j = rb.paths[B.path_off + k];
         frame_joint(Ta, rb.joints[j], q(j));
-        w.add(flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
+        w.add(flop::kSelf, flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
     }
 }
 
@@ -134,9 +144,9 @@ __device__ __forceinline__ bool grid_hit(const EnvDev &g, float cx, float cy, fl
 // Gated fine test: the step's bounding sphere (coarse) must touch the primitive in some live
 // lane before the step's spheres are tested against it; then the exit test.
 #define VK_GATE(KFLOP, COARSE, FINE)                                                \
-    work.add(KFLOP);                                                                \
+    work.add(flop::kCull, KFLOP);                                                   \
     if (wave_ballot(live && (COARSE))) {                                            \
-        work.add((KFLOP) * cnt);                                                    \
+        work.add(flop::kFine, (KFLOP) * cnt);                                       \
         _Pragma("unroll") for (int k = 0; k < kSpl; ++k) if (k < cnt) col |= (FINE); \
         if (EDGE) {                                                                 \
             if (wave_ballot(col)) return true;                                      \
@@ -164,7 +174,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         pose_step(rb, S, Tm, q, work);
         const int cnt = S.sph_count;
         if (cnt == 0) continue;
-        work.add(flop::kPlace * (cnt + 1));
+        work.add(flop::kFk, flop::kPlace * (cnt + 1));
         float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl];
 #pragma unroll
         for (int k = 0; k < kSpl; ++k) {
@@ -179,25 +189,40 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
 
-        for (int i = 0; i < ev.n_sph; ++i) {
-            const float4 o = ev.rec[i];
-            VK_GATE(flop::kSphere, hit_sphere(Cx, Cy, Cz, CR, o), hit_sphere(cx[k], cy[k], cz[k], cr[k], o))
-        }
-        for (int i = 0; i < ev.n_cap; ++i) {
-            const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
-            VK_GATE(flop::kCapsule, hit_capsule(Cx, Cy, Cz, CR, A, B),
-                    hit_capsule(cx[k], cy[k], cz[k], cr[k], A, B))
-        }
-        for (int i = 0; i < ev.n_cyl; ++i) {
-            const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
-            VK_GATE(flop::kCylinder, hit_cylinder(Cx, Cy, Cz, CR, A, B),
-                    hit_cylinder(cx[k], cy[k], cz[k], cr[k], A, B))
-        }
-        for (int i = 0; i < ev.n_box; ++i) {
-            const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
-                         Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
-            VK_GATE(flop::kBox, hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
-                    hit_box(cx[k], cy[k], cz[k], cr[k], X, Y, Z, O))
+        // environment: hierarchy of bounding spheres (groups, then clusters), then the
+        // per-primitive gate (link bounding sphere) and the link's fine spheres
+        for (int g = 0; g < ev.n_sup; ++g) {
+            work.add(flop::kCull, flop::kSphere);
+            if (!wave_ballot(live && hit_sphere(Cx, Cy, Cz, CR, ev.rec[g]))) continue;
+            const int c0 = rec_index(ev.rec[ev.off_sbeg + g].x);
+            const int c1 = rec_index(ev.rec[ev.off_sbeg + g + 1].x);
+            for (int c = c0; c < c1; ++c) {
+                work.add(flop::kCull, flop::kSphere);
+                if (!wave_ballot(live && hit_sphere(Cx, Cy, Cz, CR, ev.rec[ev.off_csph + c])))
+                    continue;
+                const float4 b0 = ev.rec[ev.off_cbeg + c], b1 = ev.rec[ev.off_cbeg + c + 1];
+                for (int i = rec_index(b0.x), e = rec_index(b1.x); i < e; ++i) {
+                    const float4 o = ev.rec[ev.off_sph + i];
+                    VK_GATE(flop::kSphere, hit_sphere(Cx, Cy, Cz, CR, o),
+                            hit_sphere(cx[k], cy[k], cz[k], cr[k], o))
+                }
+                for (int i = rec_index(b0.y), e = rec_index(b1.y); i < e; ++i) {
+                    const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
+                    VK_GATE(flop::kCapsule, hit_capsule(Cx, Cy, Cz, CR, A, B),
+                            hit_capsule(cx[k], cy[k], cz[k], cr[k], A, B))
+                }
+                for (int i = rec_index(b0.z), e = rec_index(b1.z); i < e; ++i) {
+                    const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
+                    VK_GATE(flop::kCylinder, hit_cylinder(Cx, Cy, Cz, CR, A, B),
+                            hit_cylinder(cx[k], cy[k], cz[k], cr[k], A, B))
+                }
+                for (int i = rec_index(b0.w), e = rec_index(b1.w); i < e; ++i) {
+                    const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
+                                 Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
+                    VK_GATE(flop::kBox, hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
+                            hit_box(cx[k], cy[k], cz[k], cr[k], X, Y, Z, O))
+                }
+            }
         }
         if (ed.n_cells > 0) {
 #pragma unroll
@@ -218,13 +243,13 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
             float Ax, Ay, Az;
             frame_point(Ta, B.coarse[0], B.coarse[1], B.coarse[2], Ax, Ay, Az);
             const float dx = Ax - Cx, dy = Ay - Cy, dz = Az - Cz, rr = B.coarse[3] + CR;
-            work.add(flop::kPlace + flop::kPair);
+            work.add(flop::kSelf, flop::kPlace + flop::kPair);
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
             for (int e = 0; e < B.ent_count; ++e) {
                 const EntryRec &E = rb.entries[B.ent_first + e];
                 float tx, ty, tz;
                 frame_point(Ta, E.x, E.y, E.z, tx, ty, tz);
-                work.add(flop::kPlace + flop::kPair * __builtin_popcount(E.mask));
+                work.add(flop::kSelf, flop::kPlace + flop::kPair * __builtin_popcount(E.mask));
 #pragma unroll
                 for (int k = 0; k < kSpl; ++k) {
                     if ((E.mask >> k) & 1u) {
@@ -362,7 +387,10 @@ __global__ void __launch_bounds__(256)
         out[e] = hit;                         // wave-uniform value, same address in every lane
     }
     if constexpr (COUNT) {
-        atomicAdd(flops, lane == 0 ? (unsigned long long)work.f * kWave : 0ull);
+        const unsigned long long tot = work.f[0] + work.f[1] + work.f[2] + work.f[3];
+        atomicAdd(flops + 0, lane == 0 ? tot * kWave : 0ull);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) atomicAdd(flops + 1 + c, lane == 0 ? work.f[c] * kWave : 0ull);
     }
 }
 
@@ -489,25 +517,36 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
         float Cx, Cy, Cz;
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
-        for (int i = 0; i < ev.n_sph; ++i) {
-            const float4 o = ev.rec[i];
-            VK_COST_GATE(hit_sphere(Cx, Cy, Cz, CR, o), sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
-        }
-        for (int i = 0; i < ev.n_cap; ++i) {
-            const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
-            VK_COST_GATE(hit_capsule(Cx, Cy, Cz, CR, A, B),
-                         sd_capsule(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
-        }
-        for (int i = 0; i < ev.n_cyl; ++i) {
-            const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
-            VK_COST_GATE(hit_cylinder(Cx, Cy, Cz, CR, A, B),
-                         sd_cylinder(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
-        }
-        for (int i = 0; i < ev.n_box; ++i) {
-            const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
-                         Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
-            VK_COST_GATE(hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
-                         sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
+        for (int g = 0; g < ev.n_sup; ++g) {
+            if (!wave_ballot(live && hit_sphere(Cx, Cy, Cz, CR, ev.rec[g]))) continue;
+            const int c0 = rec_index(ev.rec[ev.off_sbeg + g].x);
+            const int c1 = rec_index(ev.rec[ev.off_sbeg + g + 1].x);
+            for (int c = c0; c < c1; ++c) {
+                if (!wave_ballot(live && hit_sphere(Cx, Cy, Cz, CR, ev.rec[ev.off_csph + c])))
+                    continue;
+                const float4 b0 = ev.rec[ev.off_cbeg + c], b1 = ev.rec[ev.off_cbeg + c + 1];
+                for (int i = rec_index(b0.x), e = rec_index(b1.x); i < e; ++i) {
+                    const float4 o = ev.rec[ev.off_sph + i];
+                    VK_COST_GATE(hit_sphere(Cx, Cy, Cz, CR, o),
+                                 sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
+                }
+                for (int i = rec_index(b0.y), e = rec_index(b1.y); i < e; ++i) {
+                    const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
+                    VK_COST_GATE(hit_capsule(Cx, Cy, Cz, CR, A, B),
+                                 sd_capsule(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
+                }
+                for (int i = rec_index(b0.z), e = rec_index(b1.z); i < e; ++i) {
+                    const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
+                    VK_COST_GATE(hit_cylinder(Cx, Cy, Cz, CR, A, B),
+                                 sd_cylinder(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
+                }
+                for (int i = rec_index(b0.w), e = rec_index(b1.w); i < e; ++i) {
+                    const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
+                                 Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
+                    VK_COST_GATE(hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
+                                 sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
+                }
+            }
         }
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec &B = rb.blocks[S.blk_first + b];

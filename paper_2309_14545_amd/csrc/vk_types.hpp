@@ -74,15 +74,26 @@ struct RobotDev {
     int32_t dof, n_steps, n_spheres, n_links;
 };
 
-// Environment, packed as float4 records in one buffer:
-//   spheres   1 x float4: (centre, radius)
-//   capsules  2 x float4: (p0, radius), (u = p1 - p0, 1 / (u . u) or 0)
-//   cylinders 2 x float4: (centre, half height), (unit axis, radius)
-//   boxes     4 x float4: (col_0 of R, e_0), (col_1, e_1), (col_2, e_2), (centre, 0)
+// Environment, packed as float4 records in one buffer, preceded by a two-level hierarchy of
+// bounding spheres (wave-uniform culling):
+//   [0, n_sup)                 group bounding spheres (centre, radius)
+//   off_sbeg + [0, n_sup]      group g covers clusters [x(g), x(g+1)) (int bits in .x)
+//   off_csph + [0, n_clu)      cluster bounding spheres
+//   off_cbeg + [0, n_clu]      cluster c covers, per primitive type, records
+//                              [v(c), v(c+1)) with v = (.x spheres, .y capsules, .z cylinders,
+//                              .w boxes) as int bits, counted in primitives of that type
+//   off_sph   spheres   1 x float4: (centre, radius)
+//   off_cap   capsules  2 x float4: (p0, radius), (u = p1 - p0, 1 / (u . u) or 0)
+//   off_cyl   cylinders 2 x float4: (centre, half height), (unit axis, radius)
+//   off_box   boxes     4 x float4: (col_0 of R, e_0), (col_1, e_1), (col_2, e_2), (centre, 0)
+// Primitives are ordered by cluster (clusters are runs of spatially close primitives along a
+// Morton curve), so a cluster's primitives of one type are contiguous.
 struct EnvDev {
     const float4 *rec;
+    int32_t n_sup, n_clu;
+    int32_t off_sbeg, off_csph, off_cbeg;
+    int32_t off_sph, off_cap, off_cyl, off_box, n_rec;   // offsets / total in float4 records
     int32_t n_sph, n_cap, n_cyl, n_box;
-    int32_t off_cap, off_cyl, off_box, n_rec;    // offsets / total in float4 records
     // uniform grid over a large sphere set (point clouds); n_cells == 0 when absent
     const float4 *grid_pts;        // points sorted by cell (centre, radius)
     const int32_t *cell_start;     // [n_cells + 1]
