@@ -63,6 +63,107 @@ def cpu_baseline(w, budget_s=12.0):
                       f"oracle with first-hit stop per edge, {threads} threads, {dt:.2f} s"}
 
 
+def _events_ms(fn, steps):
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record()
+        fn()
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def extra_edges(vk, name, steps):
+    import torch
+    from synthetic import workload
+    from paper_2309_14545_amd import autotune
+    w = workload(name)
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = torch.from_numpy(w["qa"]).cuda(), torch.from_numpy(w["qb"]).cuda()
+    out = torch.empty(len(w["qa"]), dtype=torch.uint8, device="cuda")
+    tune = autotune.tune_edges(robot, env, qa, qb, resolution=RES, cache=None)
+    flops_t = torch.zeros(5, dtype=torch.int64, device="cuda")
+    vk.validate_edges_counted(robot, env, qa, qb, flops_t, resolution=RES, out=out)
+    vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out)
+    torch.cuda.synchronize()
+    ms = _events_ms(lambda: vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out), steps)
+    nominal = int(state_counts(w["qa"], w["qb"], RES).sum())
+    m = float(np.mean(ms))
+    flops = int(flops_t[0].item())
+    vk.set_edge_launch(0, 0)
+    return {"workload": name, "states_per_s": nominal / (m * 1e-3), "launch_ms": m,
+            "nominal_states": nominal, "edge_collision_rate": float(out.float().mean().item()),
+            "executed_tflops": flops / (m * 1e-3) / 1e12,
+            "frac_fp32_peak": flops / (m * 1e-3) / PEAK_FP32,
+            "launch": [tune["block"], tune["per_cu"]]}
+
+
+def extra_states(vk, name, n, steps):
+    import torch
+    from synthetic import workload
+    w = workload(name, n=n)
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    q = torch.from_numpy(w["q"]).cuda()
+    out = vk.validate_states(robot, env, q)
+    torch.cuda.synchronize()
+    ms = _events_ms(lambda: vk.validate_states(robot, env, q), steps)
+    m = float(np.median(ms))
+    return {"workload": name, "states": q.shape[1], "states_per_s": q.shape[1] / (m * 1e-3),
+            "median_ms": m, "collision_rate": float(out.float().mean().item())}
+
+
+def extra_cost(vk, steps):
+    import torch
+    from synthetic import workload
+    w = workload("cost7")
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    q = torch.from_numpy(w["q"]).cuda()
+    n = q.shape[1]
+    gc = torch.ones(n, device="cuda")
+    vk.penetration_cost_bwd(robot, env, q, gc)
+    torch.cuda.synchronize()
+    fwd = _events_ms(lambda: vk.penetration_cost_fwd(robot, env, q), steps)
+    bwd = _events_ms(lambda: vk.penetration_cost_bwd(robot, env, q, gc), steps)
+    f, b = float(np.median(fwd)), float(np.median(bwd))
+    return {"workload": "cost7", "states": n, "fwd_ms": f, "bwd_ms": b,
+            "fwd_bwd_states_per_s": n / ((f + b) * 1e-3)}
+
+
+def extra_mixed(vk, n_batches, reps):
+    import torch
+    from synthetic import workload, pack_edge_sets
+    from paper_2309_14545_amd import autotune
+    lat, edges, states, tuned = [], 0, 0, None
+    for b in range(n_batches):
+        w = workload("mixed", variant=b)
+        robots = [vk.Robot(r) for r in w["robots"]]
+        envs = [vk.Env(e) for e in w["envs"]]
+        qa_h, qb_h, sets, total = pack_edge_sets(w)
+        qa, qb = torch.from_numpy(qa_h).cuda(), torch.from_numpy(qb_h).cuda()
+        out = torch.empty(total, dtype=torch.uint8, device="cuda")
+        if tuned is None:
+            batch, tuned = autotune.tune_batch(
+                lambda: vk.EdgeBatch(robots, envs, sets, qa, qb, out, resolution=RES))
+        else:
+            batch = vk.EdgeBatch(robots, envs, sets, qa, qb, out, resolution=RES)
+        batch.run()
+        torch.cuda.synchronize()
+        lat += _events_ms(batch.run, reps)
+        edges += total
+        states += sum(int(state_counts(w["qa"][k], w["qb"][k], RES).sum())
+                      for k in range(len(w["sets"])))
+        del batch
+    vk.set_edge_launch(0, 0)
+    lat = np.asarray(lat)
+    return {"workload": "mixed", "batches": n_batches, "replays_per_batch": reps,
+            "sets_per_batch": 1024, "mean_edges_per_batch": edges / n_batches,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "states_per_s_at_p50": states / n_batches / (np.percentile(lat, 50) * 1e-3),
+            "launch": [tuned["block"], tuned["per_cu"]]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +172,8 @@ def main():
     ap.add_argument("--per-edge-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="edges7_shelf", choices=["edges7_shelf", "edges8_shelf"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (8-DoF edges, states, point cloud, cost, mixed)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -106,6 +209,12 @@ def main():
     qb = torch.from_numpy(w["qb"]).cuda()
     out = torch.empty(E, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
+
+    # launch shape from the project's autotuner (untimed setup)
+    from paper_2309_14545_amd import autotune
+    tune = autotune.tune_edges(robot, env, qa, qb, resolution=RES, cache=None)
+    log(f"autotuned launch: block {tune['block']}, {tune['per_cu']} per CU "
+        f"({tune['ms']:.3f} ms while tuning)")
 
     # executed FP32 work of one launch (instrumented variant, untimed)
     flops_t = torch.zeros(5, dtype=torch.int64, device="cuda")
@@ -195,6 +304,18 @@ def main():
             "launch_ms": launch_ms,
         },
     }
+    if not args.no_extras:
+        extra = {}
+        for key, fn in (("edges8_shelf", lambda: extra_edges(vk, "edges8_shelf", 10)),
+                        ("states7", lambda: extra_states(vk, "states7", None, 20)),
+                        ("states7_1M", lambda: extra_states(vk, "states7", 1 << 20, 10)),
+                        ("states14_cloud", lambda: extra_states(vk, "states14_cloud", None, 5)),
+                        ("cost7", lambda: extra_cost(vk, 10)),
+                        ("mixed", lambda: extra_mixed(vk, 3, 20))):
+            t0 = time.perf_counter()
+            extra[key] = fn()
+            log(f"extra {key}: {extra[key]} ({time.perf_counter() - t0:.1f}s)")
+        result["extra"] = extra
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(result), flush=True)

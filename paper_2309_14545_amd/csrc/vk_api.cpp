@@ -400,6 +400,8 @@ uint64_t spread_bits(uint64_t v) {       // 21-bit value -> every third bit
 }
 
 constexpr int kClusterSize = 8;   // primitives per cluster
+constexpr int kGridMinSpheres = 1024;
+constexpr double kGridRobotR = 0.08;   // robot radius the grid cell size is tuned for
 constexpr int kGroupSize = 8;     // clusters per group
 
 void build_env(const vk_env_desc *d, vk_env_s *e) {
@@ -416,6 +418,24 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     for (int i = 0; i < ns; ++i)
         if (d->spheres[4 * i + 3] < 0.0f) raise(VK_ERR_INVALID_ARG, "negative sphere radius");
 
+    // Large sets of small spheres (point clouds) go to a uniform grid: when there are more than
+    // kGridMinSpheres spheres, those with a radius at most twice the median radius.
+    std::vector<char> in_grid(ns, 0);
+    std::vector<int> grid_idx;
+    float gmax_r = 0.0f;
+    if (ns > kGridMinSpheres) {
+        std::vector<float> radii(ns);
+        for (int i = 0; i < ns; ++i) radii[i] = d->spheres[4 * i + 3];
+        std::nth_element(radii.begin(), radii.begin() + ns / 2, radii.end());
+        const float lim = 2.0f * radii[ns / 2];
+        for (int i = 0; i < ns; ++i)
+            if (d->spheres[4 * i + 3] <= lim) {
+                in_grid[i] = 1;
+                grid_idx.push_back(i);
+                gmax_r = std::max(gmax_r, d->spheres[4 * i + 3]);
+            }
+    }
+
     // every primitive with its bounding sphere
     struct Prim {
         int type, idx;
@@ -425,6 +445,7 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     std::vector<Prim> prims;
     prims.reserve((size_t)ns + nc + ny + nb);
     for (int i = 0; i < ns; ++i) {
+        if (in_grid[i]) continue;
         const float *s = d->spheres + 4 * i;
         prims.push_back({0, i, {s[0], s[1], s[2], s[3]}, 0});
     }
@@ -527,6 +548,54 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     e->dev.off_cap = put(cap);
     e->dev.off_cyl = put(cyl);
     e->dev.off_box = put(box);
+
+    // grid: cell size sized so robot spheres up to kGridRobotR scan a 3x3x3 neighbourhood
+    std::vector<float4> pts;
+    if (!grid_idx.empty()) {
+        const double h = kGridRobotR + gmax_r;
+        double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300};
+        for (int i : grid_idx)
+            for (int a = 0; a < 3; ++a) {
+                glo[a] = std::min(glo[a], (double)d->spheres[4 * i + a]);
+                ghi[a] = std::max(ghi[a], (double)d->spheres[4 * i + a]);
+            }
+        int dim[3];
+        for (int a = 0; a < 3; ++a) {
+            glo[a] -= 1e-3;
+            dim[a] = (int)std::floor((ghi[a] - glo[a]) / h) + 1;
+        }
+        const int64_t ncell = (int64_t)dim[0] * dim[1] * dim[2];
+        if (ncell > (int64_t(1) << 24)) raise(VK_ERR_UNSUPPORTED, "point cloud grid too large");
+        const float inv = (float)(1.0 / h);
+        auto cell_of = [&](int i) {
+            int c[3];
+            for (int a = 0; a < 3; ++a) {
+                int v = (int)std::floor(((double)d->spheres[4 * i + a] - glo[a]) / h);
+                c[a] = std::min(std::max(v, 0), dim[a] - 1);
+            }
+            return ((int64_t)c[2] * dim[1] + c[1]) * dim[0] + c[0];
+        };
+        std::vector<int> start(ncell + 1, 0);
+        for (int i : grid_idx) start[cell_of(i) + 1]++;
+        for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        pts.resize(grid_idx.size());
+        for (int i : grid_idx) {
+            const float *q = d->spheres + 4 * i;
+            pts[fill[cell_of(i)]++] = make_float4(q[0], q[1], q[2], q[3]);
+        }
+        std::vector<float4> cells((ncell + 1 + 3) / 4, make_float4(0, 0, 0, 0));
+        std::memcpy(cells.data(), start.data(), start.size() * sizeof(int));
+        e->dev.off_cell = put(cells);
+        e->dev.n_cells = (int)ncell;
+        e->dev.n_pts = (int)pts.size();
+        for (int a = 0; a < 3; ++a) {
+            e->dev.gdim[a] = dim[a];
+            e->dev.gorg[a] = (float)glo[a];
+        }
+        e->dev.ginv = inv;
+        e->dev.gmax_r = gmax_r;
+    }
     e->dev.n_rec = (int)rec.size();
     e->dev.n_sup = n_sup;
     e->dev.n_clu = n_clu;
@@ -537,9 +606,11 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     if (rec.empty()) rec.push_back(make_float4(0, 0, 0, 0));
     Blob bl;
     const size_t o_r = bl.add(rec.data(), rec.size() * sizeof(float4));
+    const size_t o_p = bl.add(pts.data(), pts.size() * sizeof(float4));
     e->device = current_device();
     e->blob = bl.upload();
     e->dev.rec = reinterpret_cast<const float4 *>(static_cast<char *>(e->blob) + o_r);
+    e->dev.grid_pts = reinterpret_cast<const float4 *>(static_cast<char *>(e->blob) + o_p);
 }
 
 bool env_in_lds(const vk_env_s *e, size_t extra = 0) {

@@ -41,7 +41,7 @@ struct QState {                // SoA state batch: q[j * ldq + i]
 // Environment view (records in LDS or global memory) -----------------------------------------
 struct EnvView {
     const float4 *rec;
-    int n_sup, off_sbeg, off_csph, off_cbeg, off_sph, off_cap, off_cyl, off_box;
+    int n_sup, off_sbeg, off_csph, off_cbeg, off_sph, off_cap, off_cyl, off_box, off_cell;
 };
 
 __device__ __forceinline__ EnvView make_view(const EnvDev &e, const float4 *rec) {
@@ -55,6 +55,7 @@ __device__ __forceinline__ EnvView make_view(const EnvDev &e, const float4 *rec)
     v.off_cap = e.off_cap;
     v.off_cyl = e.off_cyl;
     v.off_box = e.off_box;
+    v.off_cell = e.off_cell;
     return v;
 }
 
@@ -117,27 +118,40 @@ __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B
     }
 }
 
-// Grid broadphase over a large sphere set: test one robot sphere against the points of the
-// 3x3x3 cells around its own cell (cell size >= largest robot radius + largest point radius).
-__device__ __forceinline__ bool grid_hit(const EnvDev &g, float cx, float cy, float cz, float r) {
-    const int ix = (int)floorf((cx - g.gorg[0]) * g.ginv);
-    const int iy = (int)floorf((cy - g.gorg[1]) * g.ginv);
-    const int iz = (int)floorf((cz - g.gorg[2]) * g.ginv);
-    bool hit = false;
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int z = iz + dz;
-        if (z < 0 || z >= g.gdim[2]) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int y = iy + dy;
-            if (y < 0 || y >= g.gdim[1]) continue;
+// Grid broadphase over a large set of small spheres.  A point of radius <= gmax_r can touch a
+// robot sphere (c, r) only if it lies within r + gmax_r of c, i.e. in a cell at most
+// R = ceil((r + gmax_r) / h) cells away along each axis; the cells of one row are contiguous
+// in the sorted point array, so each (z, y) row is one contiguous range.  Per lane (the cells
+// differ between configurations); `visit(p)` returns true to stop.
+template <class F>
+__device__ __forceinline__ void grid_scan(const EnvView &ev, const EnvDev &g, float cx, float cy,
+                                          float cz, float r, F &&visit) {
+    const float *cell = reinterpret_cast<const float *>(ev.rec + ev.off_cell);
+    const int R = (int)ceilf((r + g.gmax_r) * g.ginv * 1.00001f + 1e-5f);
+    const float lim = 1.0e6f;
+    const int ix = (int)fminf(fmaxf(floorf((cx - g.gorg[0]) * g.ginv), -lim), lim);
+    const int iy = (int)fminf(fmaxf(floorf((cy - g.gorg[1]) * g.ginv), -lim), lim);
+    const int iz = (int)fminf(fmaxf(floorf((cz - g.gorg[2]) * g.ginv), -lim), lim);
+    const int x0 = max(ix - R, 0), x1 = min(ix + R, g.gdim[0] - 1);
+    const int y0 = max(iy - R, 0), y1 = min(iy + R, g.gdim[1] - 1);
+    const int z0 = max(iz - R, 0), z1 = min(iz + R, g.gdim[2] - 1);
+    if (x0 > x1) return;
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y) {
             const int row = (z * g.gdim[1] + y) * g.gdim[0];
-            const int x0 = max(ix - 1, 0), x1 = min(ix + 1, g.gdim[0] - 1);
-            if (x0 > x1) continue;
-            // the three cells of a row are contiguous in the sorted point array
-            const int b = g.cell_start[row + x0], e = g.cell_start[row + x1 + 1];
-            for (int p = b; p < e && !hit; ++p) hit = hit_sphere(cx, cy, cz, r, g.grid_pts[p]);
+            const int b = __float_as_int(cell[row + x0]), e = __float_as_int(cell[row + x1 + 1]);
+            for (int p = b; p < e; ++p)
+                if (visit(g.grid_pts[p])) return;
         }
-    }
+}
+
+__device__ __forceinline__ bool grid_hit(const EnvView &ev, const EnvDev &g, float cx, float cy,
+                                         float cz, float r) {
+    bool hit = false;
+    grid_scan(ev, g, cx, cy, cz, r, [&](const float4 &p) {
+        hit = hit_sphere(cx, cy, cz, r, p);
+        return hit;
+    });
     return hit;
 }
 
@@ -227,7 +241,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         if (ed.n_cells > 0) {
 #pragma unroll
             for (int k = 0; k < kSpl; ++k)
-                if (k < cnt && live && !col) col |= grid_hit(ed, cx[k], cy[k], cz[k], cr[k]);
+                if (k < cnt && live && !col) col |= grid_hit(ev, ed, cx[k], cy[k], cz[k], cr[k]);
             if (EDGE) {
                 if (wave_ballot(col)) return true;
             } else {
@@ -546,6 +560,16 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
                     VK_COST_GATE(hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
                                  sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
                 }
+            }
+        }
+        if (ed.n_cells > 0 && live) {
+#pragma unroll
+            for (int k = 0; k < kSpl; ++k) {
+                if (k >= cnt) continue;
+                grid_scan(ev, ed, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
+                    VK_PEN(sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
+                    return false;
+                });
             }
         }
         for (int b = 0; b < S.blk_count; ++b) {

@@ -94,15 +94,17 @@ struct EnvDev {
     int32_t off_sbeg, off_csph, off_cbeg;
     int32_t off_sph, off_cap, off_cyl, off_box, n_rec;   // offsets / total in float4 records
     int32_t n_sph, n_cap, n_cyl, n_box;
-    // uniform grid over a large sphere set (point clouds); n_cells == 0 when absent
-    const float4 *grid_pts;        // points sorted by cell (centre, radius)
-    const int32_t *cell_start;     // [n_cells + 1]
+    // Uniform grid over a large set of small spheres (point clouds); n_cells == 0 when absent.
+    // The cell index (cell_start, n_cells + 1 ints, four per record) is part of the record
+    // buffer at off_cell, so it is staged in LDS with the rest; the points themselves, sorted by
+    // cell, stay in global memory (L2).
+    const float4 *grid_pts;        // [n_pts] centre, radius
+    int32_t off_cell;
+    int32_t n_cells, n_pts;
     int32_t gdim[3];
-    int32_t n_cells;
     float gorg[3];
     float ginv;                    // 1 / cell size
-    float gcell;
-    float gmax_r;                  // largest radius stored in the grid
+    float gmax_r;                  // largest point radius
 };
 
 // One edge set of a mixed-robot batch.

@@ -11,11 +11,11 @@ from .robots import (chain_robot, bimanual_robot, robot_summary, link_parents,
 from .scenes import (cube_scene, shelf_scene, point_cloud_scene, random_scene,
                      empty_scene, scene_summary)
 from .workloads import (ROOT_SEED, rng, uniform_states, uniform_edges, trajectories,
-                        workload)
+                        workload, pack_edge_sets)
 
 __all__ = [
     "chain_robot", "bimanual_robot", "robot_summary", "link_parents", "candidate_pairs",
     "cube_scene", "shelf_scene", "point_cloud_scene", "random_scene", "empty_scene",
     "scene_summary", "ROOT_SEED", "rng", "uniform_states", "uniform_edges", "trajectories",
-    "workload",
+    "workload", "pack_edge_sets",
 ]

@@ -152,7 +152,7 @@ def shelf_scene(g: np.random.Generator, n_units: int = 12, n_loose: int = 4,
 
 def point_cloud_scene(g: np.random.Generator, n_spheres: int = 300, n_points: int = 20000,
                       point_r: float = 0.01, mounts=((0.0, 0.0, 0.0),),
-                      sphere_r=(0.02, 0.08)) -> dict:
+                      sphere_r=(0.01, 0.04)) -> dict:
     """Random spheres plus a noisy table top (z = 0.4) and three walls sampled as points."""
     m = np.asarray(mounts, dtype=np.float64).reshape(-1, 3)
     spheres = [_sphere(g, m, *sphere_r) for _ in range(n_spheres)]

@@ -81,10 +81,31 @@ def _lognormal_counts(g, n_sets, mu=4.0, sigma=1.0):
     return np.maximum(1, np.floor(np.exp(g.normal(mu, sigma, n_sets)))).astype(np.int64)
 
 
-def workload(name: str, n: int | None = None) -> dict:
+def pack_edge_sets(w: dict, max_edges: int | None = None):
+    """Concatenate a mixed workload's edge sets into flat FP32 qa / qb arrays.
+
+    Returns (qa, qb, sets, total) with sets as (robot, env, float offset, n_edges, out offset)
+    tuples in the layout of the mixed-batch C interface."""
+    qa_parts, qb_parts, sets, off, out_off = [], [], [], 0, 0
+    for k, (ri, ei, _) in enumerate(w["sets"]):
+        a, b = w["qa"][k], w["qb"][k]
+        if max_edges:
+            a, b = a[:max_edges], b[:max_edges]
+        qa_parts.append(a.reshape(-1))
+        qb_parts.append(b.reshape(-1))
+        sets.append((ri, ei, off, len(a), out_off))
+        off += a.size
+        out_off += len(a)
+    qa = np.concatenate(qa_parts).astype(np.float32) if qa_parts else np.zeros(1, np.float32)
+    qb = np.concatenate(qb_parts).astype(np.float32) if qb_parts else np.zeros(1, np.float32)
+    return qa, qb, sets, out_off
+
+
+def workload(name: str, n: int | None = None, variant: int = 0) -> dict:
     """Return a dict with the robot(s), scene(s) and batch of the named workload.
 
-    ``n`` overrides the batch size (states, edges, trajectories or edge sets).
+    ``n`` overrides the batch size (states, edges, trajectories or edge sets); ``variant``
+    selects another seeded draw of the batch (used for repeated mixed batches).
     """
     if name == "states7":
         robot = robot7()
@@ -115,15 +136,16 @@ def workload(name: str, n: int | None = None) -> dict:
     if name == "mixed":
         robots = [robot7(), robot8(), robot14()]
         n_sets = n or 1024
-        g = rng("mixed", "sets")
+        tag = "mixed" if variant == 0 else f"mixed{variant}"
+        g = rng(tag, "sets")
         which = g.integers(0, 3, n_sets)
         counts = _lognormal_counts(g, n_sets)
         envs, sets, qa, qb = [], [], [], []
         for k in range(n_sets):
             r = robots[which[k]]
             mounts = TORSO_MOUNTS if r["dof"] == 14 else ((0.0, 0.0, 0.0),)
-            envs.append(random_scene(rng("mixed", f"env{k}"), mounts=mounts))
-            a, b = uniform_edges(rng("mixed", f"edges{k}"), r["dof"], int(counts[k]))
+            envs.append(random_scene(rng(tag, f"env{k}"), mounts=mounts))
+            a, b = uniform_edges(rng(tag, f"edges{k}"), r["dof"], int(counts[k]))
             qa.append(a)
             qb.append(b)
             sets.append((int(which[k]), k, int(counts[k])))

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from helpers import dev, host, say, edge_mismatches
-from synthetic import workload
+from synthetic import workload, pack_edge_sets
 
 pytestmark = pytest.mark.gpu
 
@@ -18,24 +18,10 @@ def vk():
 
 
 def _pack(vk, w, max_edges=None):
-    """Concatenate every set's edges, padded to 16 joints per edge so one qa/qb array serves
-    all robots (offsets are in floats)."""
     robots = [vk.Robot(r) for r in w["robots"]]
     envs = [vk.Env(e) for e in w["envs"]]
-    qa_parts, qb_parts, sets, out_off, off = [], [], [], 0, 0
-    for k, (ri, ei, ne) in enumerate(w["sets"]):
-        a, b = w["qa"][k], w["qb"][k]
-        if max_edges:
-            a, b = a[:max_edges], b[:max_edges]
-        ne = len(a)
-        qa_parts.append(a.reshape(-1))
-        qb_parts.append(b.reshape(-1))
-        sets.append((ri, ei, off, ne, out_off))
-        off += a.size
-        out_off += ne
-    qa = dev(np.concatenate(qa_parts).astype(np.float32))
-    qb = dev(np.concatenate(qb_parts).astype(np.float32))
-    return robots, envs, sets, qa, qb, out_off
+    qa, qb, sets, total = pack_edge_sets(w, max_edges)
+    return robots, envs, sets, dev(qa), dev(qb), total
 
 
 def test_batch_parity_and_replays(vk, orc):

@@ -1,0 +1,85 @@
+"""GPU parity of the point-cloud workload: two 7-DoF arms on a torso, 300 spheres and a
+20,000-point cloud (the cloud goes to the uniform-grid broadphase)."""
+import numpy as np
+import pytest
+
+from helpers import dev, host, say, state_mismatches
+from synthetic import workload, rng, uniform_states, point_cloud_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_14545_amd as vk
+    vk.lib()
+    return vk
+
+
+@pytest.fixture(scope="module")
+def cloud():
+    return workload("states14_cloud", n=2048)
+
+
+def test_cloud_states_parity(vk, orc, cloud):
+    w = cloud
+    say("validate_states cloud n", w["q"].shape[1], "env spheres", len(w["env"]["spheres"]))
+    flags = host(vk.validate_states(vk.Robot(w["robot"]), vk.Env(w["env"]), dev(w["q"])))
+    cmin, _ = orc.states(w["robot"], w["env"], w["q"])
+    bad, near = state_mismatches(flags, cmin)
+    say(f"  mismatches outside band {bad}, near-contact {near}, collision rate {flags.mean():.3f}")
+    assert bad == 0
+
+
+def test_cloud_only_parity(vk, orc, cloud):
+    """The cloud alone (no large spheres), so the grid decides most flags."""
+    w = cloud
+    env = {"spheres": w["env"]["spheres"][300:]}
+    q = uniform_states(rng("gpu-cloud", "q"), 14, 3000)
+    flags = host(vk.validate_states(vk.Robot(w["robot"]), vk.Env(env), dev(q)))
+    cmin, _ = orc.states(w["robot"], env, q)
+    bad, near = state_mismatches(flags, cmin)
+    say(f"  cloud only: mismatches {bad}, near {near}, rate {flags.mean():.3f}")
+    assert bad == 0
+    assert 0.05 < flags.mean() < 0.995
+
+
+def test_cloud_full_size_sampled(vk, orc):
+    w = workload("states14_cloud")
+    n = w["q"].shape[1]
+    say("validate_states cloud full size", n)
+    flags = host(vk.validate_states(vk.Robot(w["robot"]), vk.Env(w["env"]), dev(w["q"])))
+    idx = np.sort(np.random.default_rng(9).choice(n, 384, replace=False))
+    cmin, _ = orc.states(w["robot"], w["env"], w["q"][:, idx])
+    assert state_mismatches(flags[idx], cmin)[0] == 0
+
+
+def test_cloud_cost(vk, orc, cloud):
+    w = cloud
+    env = {"spheres": w["env"]["spheres"]}
+    q = w["q"][:, :256]
+    c = host(vk.penetration_cost_fwd(vk.Robot(w["robot"]), vk.Env(env), dev(q))).astype(np.float64)
+    ref = orc.costs(w["robot"], env, q)
+    assert np.all(np.abs(c - ref) <= 1e-6 + 2e-4 * ref)
+    g = host(vk.penetration_cost_bwd(vk.Robot(w["robot"]), vk.Env(env), dev(q),
+                                     dev(np.ones(q.shape[1], np.float32)))).astype(np.float64)
+    gr = orc.cost_grads(w["robot"], env, q)
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    say("  cloud cost gradient rel", rel)
+    assert rel <= 1e-4
+
+
+def test_small_sphere_sets_stay_flat(vk, orc):
+    """A sphere set just above the grid threshold with mixed radii (some go to the grid, some
+    to the hierarchy) agrees with the oracle."""
+    g = rng("gpu-cloud", "mixed")
+    c = g.uniform(-1.5, 1.5, (1100, 3))
+    r = np.where(g.uniform(size=1100) < 0.8, 0.01, g.uniform(0.02, 0.06, 1100))
+    env = {"spheres": np.concatenate([c, r[:, None]], 1).astype(np.float32)}
+    w = workload("states7", n=1)
+    q = uniform_states(rng("gpu-cloud", "q7"), 7, 1500)
+    flags = host(vk.validate_states(vk.Robot(w["robot"]), vk.Env(env), dev(q)))
+    cmin, _ = orc.states(w["robot"], env, q)
+    assert state_mismatches(flags, cmin)[0] == 0
