@@ -364,45 +364,60 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
     r->n_spheres = S;
 }
 
-// Bounding sphere (AABB centre, farthest reach) of a set of spheres, rounded up and padded by
-// 1e-5 m so the FP32 culling tests stay conservative.
-float4 bound_of(const std::vector<std::array<double, 4>> &sph) {
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (const auto &s : sph)
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = std::min(lo[a], s[a] - s[3]);
-            hi[a] = std::max(hi[a], s[a] + s[3]);
-        }
-    double c[3], R = 0.0;
-    for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
-    for (const auto &s : sph) {
-        const double dx = s[0] - c[0], dy = s[1] - c[1], dz = s[2] - c[2];
-        R = std::max(R, std::sqrt(dx * dx + dy * dy + dz * dz) + s[3]);
-    }
-    return make_float4((float)c[0], (float)c[1], (float)c[2],
-                       std::nextafter((float)(R + 1e-5), INFINITY));
-}
-
 float int_bits(int v) {
     float f;
     std::memcpy(&f, &v, sizeof f);
     return f;
 }
 
-uint64_t spread_bits(uint64_t v) {       // 21-bit value -> every third bit
-    v &= 0x1fffff;
-    v = (v | v << 32) & 0x1f00000000ffffull;
-    v = (v | v << 16) & 0x1f0000ff0000ffull;
-    v = (v | v << 8) & 0x100f00f00f00f00full;
-    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
-    v = (v | v << 2) & 0x1249249249249249ull;
-    return v;
-}
-
-constexpr int kClusterSize = 8;   // primitives per cluster
 constexpr int kGridMinSpheres = 1024;
-constexpr double kGridRobotR = 0.08;   // robot radius the grid cell size is tuned for
-constexpr int kGroupSize = 8;     // clusters per group
+constexpr double kGridRobotR = 0.08;   // robot radius the point-grid cell size is tuned for
+constexpr double kVoxCap = 0.5;        // voxel lists cover link bounding spheres up to 0.5 m
+constexpr double kVoxMinCell = 0.05;
+constexpr double kVoxMaxCells = 49152; // byte field of at most 48 KiB (fits LDS with records)
+
+// Host-side signed distances (double) used only to build the voxel lists.
+struct HostPrim {
+    int type, idx;
+    double v[15];
+    double bc[3], br;              // bounding sphere
+};
+
+double host_sd(const HostPrim &p, const double *x) {
+    const double *v = p.v;
+    auto nrm = [](double a, double b, double c) { return std::sqrt(a * a + b * b + c * c); };
+    switch (p.type) {
+    case 0:
+        return nrm(x[0] - v[0], x[1] - v[1], x[2] - v[2]) - v[3];
+    case 1: {
+        const double u[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+        const double w[3] = {x[0] - v[0], x[1] - v[1], x[2] - v[2]};
+        const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        double t = uu > 0.0 ? (w[0] * u[0] + w[1] * u[1] + w[2] * u[2]) / uu : 0.0;
+        t = std::min(1.0, std::max(0.0, t));
+        return nrm(w[0] - t * u[0], w[1] - t * u[1], w[2] - t * u[2]) - v[6];
+    }
+    case 2: {
+        const double r[3] = {x[0] - v[0], x[1] - v[1], x[2] - v[2]};
+        const double h = r[0] * v[3] + r[1] * v[4] + r[2] * v[5];
+        const double rho = nrm(r[0] - h * v[3], r[1] - h * v[4], r[2] - h * v[5]);
+        const double a = std::fabs(h) - v[6], b = rho - v[7];
+        if (a <= 0.0 && b <= 0.0) return std::max(a, b);
+        return nrm(std::max(a, 0.0), std::max(b, 0.0), 0.0);
+    }
+    default: {
+        const double r[3] = {x[0] - v[0], x[1] - v[1], x[2] - v[2]};
+        double q[3], o = 0.0, m = -1e300;
+        for (int k = 0; k < 3; ++k) {
+            const double pk = v[3 + k] * r[0] + v[6 + k] * r[1] + v[9 + k] * r[2];
+            q[k] = std::fabs(pk) - v[12 + k];
+            o += std::max(q[k], 0.0) * std::max(q[k], 0.0);
+            m = std::max(m, q[k]);
+        }
+        return std::sqrt(o) + std::min(m, 0.0);
+    }
+    }
+}
 
 void build_env(const vk_env_desc *d, vk_env_s *e) {
     if (!d) raise(VK_ERR_INVALID_ARG, "env desc is NULL");
@@ -436,120 +451,133 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
             }
     }
 
-    // every primitive with its bounding sphere
-    struct Prim {
-        int type, idx;
-        std::array<double, 4> bs;
-        uint64_t key;
-    };
-    std::vector<Prim> prims;
-    prims.reserve((size_t)ns + nc + ny + nb);
+    // primitive records (the voxel lists refer to them by type and index)
+    std::vector<float4> sph, cap, cyl, box;
+    std::vector<HostPrim> prims;
     for (int i = 0; i < ns; ++i) {
         if (in_grid[i]) continue;
-        const float *s = d->spheres + 4 * i;
-        prims.push_back({0, i, {s[0], s[1], s[2], s[3]}, 0});
+        const float *q = d->spheres + 4 * i;
+        HostPrim p{0, (int)sph.size(), {}, {q[0], q[1], q[2]}, q[3]};
+        for (int k = 0; k < 4; ++k) p.v[k] = q[k];
+        prims.push_back(p);
+        sph.push_back(make_float4(q[0], q[1], q[2], q[3]));
     }
     for (int i = 0; i < nc; ++i) {
-        const float *c = d->capsules + 7 * i;
-        const double hx = 0.5 * ((double)c[3] - c[0]), hy = 0.5 * ((double)c[4] - c[1]),
-                     hz = 0.5 * ((double)c[5] - c[2]);
-        prims.push_back({1, i, {c[0] + hx, c[1] + hy, c[2] + hz,
-                                std::sqrt(hx * hx + hy * hy + hz * hz) + c[6]}, 0});
+        const float *q = d->capsules + 7 * i;
+        HostPrim p{1, i, {}, {}, 0.0};
+        for (int k = 0; k < 7; ++k) p.v[k] = q[k];
+        double hl = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            p.bc[a] = 0.5 * ((double)q[a] + q[3 + a]);
+            hl += 0.25 * ((double)q[3 + a] - q[a]) * ((double)q[3 + a] - q[a]);
+        }
+        p.br = std::sqrt(hl) + q[6];
+        prims.push_back(p);
+        const float ux = q[3] - q[0], uy = q[4] - q[1], uz = q[5] - q[2];
+        const float uu = ux * ux + uy * uy + uz * uz;
+        cap.push_back(make_float4(q[0], q[1], q[2], q[6]));
+        cap.push_back(make_float4(ux, uy, uz, uu > 0.0f ? 1.0f / uu : 0.0f));
     }
     for (int i = 0; i < ny; ++i) {
-        const float *c = d->cylinders + 8 * i;
-        prims.push_back({2, i, {c[0], c[1], c[2], std::hypot((double)c[6], (double)c[7])}, 0});
+        const float *q = d->cylinders + 8 * i;
+        HostPrim p{2, i, {}, {q[0], q[1], q[2]}, std::hypot((double)q[6], (double)q[7])};
+        for (int k = 0; k < 8; ++k) p.v[k] = q[k];
+        prims.push_back(p);
+        cyl.push_back(make_float4(q[0], q[1], q[2], q[6]));
+        cyl.push_back(make_float4(q[3], q[4], q[5], q[7]));
     }
     for (int i = 0; i < nb; ++i) {
         const float *b = d->boxes + 15 * i;
-        const double r = std::sqrt((double)b[12] * b[12] + (double)b[13] * b[13] + (double)b[14] * b[14]);
-        prims.push_back({3, i, {b[0], b[1], b[2], r}, 0});
+        HostPrim p{3, i, {}, {b[0], b[1], b[2]},
+                   std::sqrt((double)b[12] * b[12] + (double)b[13] * b[13] + (double)b[14] * b[14])};
+        for (int k = 0; k < 15; ++k) p.v[k] = b[k];
+        prims.push_back(p);
+        const float *R = b + 3, *ext = b + 12;
+        for (int k = 0; k < 3; ++k) box.push_back(make_float4(R[k], R[3 + k], R[6 + k], ext[k]));
+        box.push_back(make_float4(b[0], b[1], b[2], 0.0f));
     }
-    // Morton order of the centres, then runs of kClusterSize primitives form clusters
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-    for (const Prim &p : prims)
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = std::min(lo[a], p.bs[a]);
-            hi[a] = std::max(hi[a], p.bs[a]);
-        }
-    for (Prim &p : prims) {
-        uint64_t k = 0;
-        for (int a = 0; a < 3; ++a) {
-            const double span = hi[a] > lo[a] ? hi[a] - lo[a] : 1.0;
-            const uint64_t q = (uint64_t)std::min(2097151.0, (p.bs[a] - lo[a]) / span * 2097151.0);
-            k |= spread_bits(q) << a;
-        }
-        p.key = k;
-    }
-    std::stable_sort(prims.begin(), prims.end(),
-                     [](const Prim &a, const Prim &b) { return a.key < b.key; });
-    const int n_prim = (int)prims.size();
-    const int n_clu = (n_prim + kClusterSize - 1) / kClusterSize;
-    const int n_sup = (n_clu + kGroupSize - 1) / kGroupSize;
 
-    std::vector<float4> sph, cap, cyl, box, csph, cbeg, ssph, sbeg;
-    std::vector<std::array<double, 4>> cluster_bs;
-    for (int c = 0; c < n_clu; ++c) {
-        cbeg.push_back(make_float4(int_bits((int)sph.size()), int_bits((int)(cap.size() / 2)),
-                                   int_bits((int)(cyl.size() / 2)), int_bits((int)(box.size() / 4))));
-        std::vector<std::array<double, 4>> members;
-        const int p0 = c * kClusterSize, p1 = std::min(n_prim, p0 + kClusterSize);
-        for (int type = 0; type < 4; ++type)
-            for (int p = p0; p < p1; ++p) {
-                if (prims[p].type != type) continue;
-                members.push_back(prims[p].bs);
-                const int i = prims[p].idx;
-                if (type == 0) {
-                    const float *s = d->spheres + 4 * i;
-                    sph.push_back(make_float4(s[0], s[1], s[2], s[3]));
-                } else if (type == 1) {
-                    const float *q = d->capsules + 7 * i;
-                    const float ux = q[3] - q[0], uy = q[4] - q[1], uz = q[5] - q[2];
-                    const float uu = ux * ux + uy * uy + uz * uz;
-                    cap.push_back(make_float4(q[0], q[1], q[2], q[6]));
-                    cap.push_back(make_float4(ux, uy, uz, uu > 0.0f ? 1.0f / uu : 0.0f));
-                } else if (type == 2) {
-                    const float *q = d->cylinders + 8 * i;
-                    cyl.push_back(make_float4(q[0], q[1], q[2], q[6]));
-                    cyl.push_back(make_float4(q[3], q[4], q[5], q[7]));
-                } else {
-                    const float *b = d->boxes + 15 * i;
-                    const float *R = b + 3, *ext = b + 12;
-                    for (int k = 0; k < 3; ++k) box.push_back(make_float4(R[k], R[3 + k], R[6 + k], ext[k]));
-                    box.push_back(make_float4(b[0], b[1], b[2], 0.0f));
-                }
+    // voxel broadphase: grid over everything within kVoxCap of a primitive
+    std::memset(&e->dev, 0, sizeof e->dev);
+    std::vector<int> vstart(1, 0);
+    std::vector<int2> vlist;
+    std::vector<unsigned char> vdist;
+    if (!prims.empty()) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (const HostPrim &p : prims)
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], p.bc[a] - p.br - kVoxCap);
+                hi[a] = std::max(hi[a], p.bc[a] + p.br + kVoxCap);
             }
-        const float4 bsf = bound_of(members);
-        csph.push_back(bsf);
-        cluster_bs.push_back({bsf.x, bsf.y, bsf.z, bsf.w});
+        const double vol = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+        const double h = std::max(kVoxMinCell, std::cbrt(vol / kVoxMaxCells) * 1.0001);
+        int dim[3];
+        for (int a = 0; a < 3; ++a) dim[a] = std::max(1, (int)std::ceil((hi[a] - lo[a]) / h));
+        const int64_t nvox = (int64_t)dim[0] * dim[1] * dim[2];
+        const double hd = 0.5 * h * std::sqrt(3.0);
+        std::vector<std::vector<std::pair<float, int>>> cells(nvox);
+        for (size_t pi = 0; pi < prims.size(); ++pi) {
+            const HostPrim &p = prims[pi];
+            int c0[3], c1[3];
+            for (int a = 0; a < 3; ++a) {
+                c0[a] = std::max(0, (int)std::floor((p.bc[a] - p.br - kVoxCap - hd - lo[a]) / h));
+                c1[a] = std::min(dim[a] - 1, (int)std::floor((p.bc[a] + p.br + kVoxCap + hd - lo[a]) / h));
+            }
+            for (int z = c0[2]; z <= c1[2]; ++z)
+                for (int y = c0[1]; y <= c1[1]; ++y)
+                    for (int x = c0[0]; x <= c1[0]; ++x) {
+                        const double ctr[3] = {lo[0] + (x + 0.5) * h, lo[1] + (y + 0.5) * h,
+                                               lo[2] + (z + 0.5) * h};
+                        // every point of the cell is within hd of its centre (1-Lipschitz sd)
+                        const double lb = host_sd(p, ctr) - hd - 1e-5;
+                        if (lb < kVoxCap)
+                            cells[((int64_t)z * dim[1] + y) * dim[0] + x].push_back(
+                                {(float)std::nextafter((float)lb, -INFINITY),
+                                 (p.type << 28) | p.idx});
+                    }
+        }
+        const double q = kVoxCap / 255.0;
+        vdist.resize((size_t)nvox);
+        for (int64_t c = 0; c < nvox; ++c) {
+            auto &L = cells[c];
+            std::sort(L.begin(), L.end());
+            for (auto &it : L) vlist.push_back(make_int2(it.second, 0));
+            for (size_t k = 0; k < L.size(); ++k) {
+                float f = L[k].first;
+                std::memcpy(&vlist[vlist.size() - L.size() + k].y, &f, sizeof f);
+            }
+            vstart.push_back((int)vlist.size());
+            const double m = L.empty() ? kVoxCap : std::max(0.0, (double)L[0].first);
+            vdist[c] = (unsigned char)std::min(255.0, std::floor(m / q));
+        }
+        if (vlist.size() >= (size_t(1) << 31)) raise(VK_ERR_UNSUPPORTED, "voxel lists too large");
+        for (int a = 0; a < 3; ++a) {
+            e->dev.vdim[a] = dim[a];
+            e->dev.vorg[a] = (float)lo[a];
+        }
+        e->dev.n_vox = (int)nvox;
+        e->dev.vinv = (float)(1.0 / h);
+        e->dev.vq = (float)q;
+        e->dev.vcap = (float)kVoxCap;
     }
-    cbeg.push_back(make_float4(int_bits((int)sph.size()), int_bits((int)(cap.size() / 2)),
-                               int_bits((int)(cyl.size() / 2)), int_bits((int)(box.size() / 4))));
-    for (int g = 0; g < n_sup; ++g) {
-        const int c0 = g * kGroupSize, c1 = std::min(n_clu, c0 + kGroupSize);
-        sbeg.push_back(make_float4(int_bits(c0), 0.0f, 0.0f, 0.0f));
-        std::vector<std::array<double, 4>> members(cluster_bs.begin() + c0, cluster_bs.begin() + c1);
-        ssph.push_back(bound_of(members));
-    }
-    sbeg.push_back(make_float4(int_bits(n_clu), 0.0f, 0.0f, 0.0f));
 
     std::vector<float4> rec;
-    std::memset(&e->dev, 0, sizeof e->dev);
     auto put = [&](const std::vector<float4> &v) {
         const int off = (int)rec.size();
         rec.insert(rec.end(), v.begin(), v.end());
         return off;
     };
-    put(ssph);
-    e->dev.off_sbeg = put(sbeg);
-    e->dev.off_csph = put(csph);
-    e->dev.off_cbeg = put(cbeg);
     e->dev.off_sph = put(sph);
     e->dev.off_cap = put(cap);
     e->dev.off_cyl = put(cyl);
     e->dev.off_box = put(box);
+    {
+        std::vector<float4> packed((vdist.size() + 15) / 16, make_float4(0, 0, 0, 0));
+        if (!vdist.empty()) std::memcpy(packed.data(), vdist.data(), vdist.size());
+        e->dev.off_vdist = put(packed);
+    }
 
-    // grid: cell size sized so robot spheres up to kGridRobotR scan a 3x3x3 neighbourhood
+    // point grid: cell size sized so robot spheres up to kGridRobotR scan a 3x3x3 neighbourhood
     std::vector<float4> pts;
     if (!grid_idx.empty()) {
         const double h = kGridRobotR + gmax_r;
@@ -566,7 +594,6 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
         }
         const int64_t ncell = (int64_t)dim[0] * dim[1] * dim[2];
         if (ncell > (int64_t(1) << 24)) raise(VK_ERR_UNSUPPORTED, "point cloud grid too large");
-        const float inv = (float)(1.0 / h);
         auto cell_of = [&](int i) {
             int c[3];
             for (int a = 0; a < 3; ++a) {
@@ -593,13 +620,11 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
             e->dev.gdim[a] = dim[a];
             e->dev.gorg[a] = (float)glo[a];
         }
-        e->dev.ginv = inv;
+        e->dev.ginv = (float)(1.0 / h);
         e->dev.gmax_r = gmax_r;
     }
     e->dev.n_rec = (int)rec.size();
-    e->dev.n_sup = n_sup;
-    e->dev.n_clu = n_clu;
-    e->dev.n_sph = ns;
+    e->dev.n_sph = (int)sph.size();
     e->dev.n_cap = nc;
     e->dev.n_cyl = ny;
     e->dev.n_box = nb;
@@ -607,10 +632,15 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     Blob bl;
     const size_t o_r = bl.add(rec.data(), rec.size() * sizeof(float4));
     const size_t o_p = bl.add(pts.data(), pts.size() * sizeof(float4));
+    const size_t o_s = bl.add(vstart.data(), vstart.size() * sizeof(int));
+    const size_t o_l = bl.add(vlist.data(), vlist.size() * sizeof(int2));
     e->device = current_device();
     e->blob = bl.upload();
-    e->dev.rec = reinterpret_cast<const float4 *>(static_cast<char *>(e->blob) + o_r);
-    e->dev.grid_pts = reinterpret_cast<const float4 *>(static_cast<char *>(e->blob) + o_p);
+    char *base = static_cast<char *>(e->blob);
+    e->dev.rec = reinterpret_cast<const float4 *>(base + o_r);
+    e->dev.grid_pts = reinterpret_cast<const float4 *>(base + o_p);
+    e->dev.vstart = reinterpret_cast<const int32_t *>(base + o_s);
+    e->dev.vlist = reinterpret_cast<const int2 *>(base + o_l);
 }
 
 bool env_in_lds(const vk_env_s *e, size_t extra = 0) {

@@ -41,28 +41,76 @@ struct QState {                // SoA state batch: q[j * ldq + i]
 // Environment view (records in LDS or global memory) -----------------------------------------
 struct EnvView {
     const float4 *rec;
-    int n_sup, off_sbeg, off_csph, off_cbeg, off_sph, off_cap, off_cyl, off_box, off_cell;
+    int off_sph, off_cap, off_cyl, off_box, off_vdist, off_cell;
+    int n_sph, n_cap, n_cyl, n_box;
 };
 
 __device__ __forceinline__ EnvView make_view(const EnvDev &e, const float4 *rec) {
     EnvView v;
     v.rec = rec;
-    v.n_sup = e.n_sup;
-    v.off_sbeg = e.off_sbeg;
-    v.off_csph = e.off_csph;
-    v.off_cbeg = e.off_cbeg;
     v.off_sph = e.off_sph;
     v.off_cap = e.off_cap;
     v.off_cyl = e.off_cyl;
     v.off_box = e.off_box;
+    v.off_vdist = e.off_vdist;
     v.off_cell = e.off_cell;
+    v.n_sph = e.n_sph;
+    v.n_cap = e.n_cap;
+    v.n_cyl = e.n_cyl;
+    v.n_box = e.n_box;
     return v;
 }
 
-// An index stored as float bits in a record; every lane read the same record, so the first
-// lane's value is the wave's value (kept in a scalar register).
-__device__ __forceinline__ int rec_index(float x) {
-    return __builtin_amdgcn_readfirstlane(__float_as_int(x));
+// Overlap of sphere (x, y, z, r) with primitive `i` of type `t` (0 sphere, 1 capsule,
+// 2 cylinder, 3 box), records read from the view.
+__device__ __forceinline__ bool hit_any(const EnvView &ev, int t, int i, float x, float y,
+                                        float z, float r) {
+    if (t == 3) {
+        const float4 *b = ev.rec + ev.off_box + 4 * i;
+        return hit_box(x, y, z, r, b[0], b[1], b[2], b[3]);
+    }
+    if (t == 1) {
+        const float4 *c = ev.rec + ev.off_cap + 2 * i;
+        return hit_capsule(x, y, z, r, c[0], c[1]);
+    }
+    if (t == 0) return hit_sphere(x, y, z, r, ev.rec[ev.off_sph + i]);
+    const float4 *c = ev.rec + ev.off_cyl + 2 * i;
+    return hit_cylinder(x, y, z, r, c[0], c[1]);
+}
+
+// Signed distance and gradient to primitive `i` of type `t`.
+__device__ __forceinline__ float sd_any(const EnvView &ev, int t, int i, float x, float y, float z,
+                                        float &gx, float &gy, float &gz) {
+    if (t == 3) {
+        const float4 *b = ev.rec + ev.off_box + 4 * i;
+        return sd_box(x, y, z, b[0], b[1], b[2], b[3], gx, gy, gz);
+    }
+    if (t == 1) {
+        const float4 *c = ev.rec + ev.off_cap + 2 * i;
+        return sd_capsule(x, y, z, c[0], c[1], gx, gy, gz);
+    }
+    if (t == 0) return sd_sphere(x, y, z, ev.rec[ev.off_sph + i], gx, gy, gz);
+    const float4 *c = ev.rec + ev.off_cyl + 2 * i;
+    return sd_cylinder(x, y, z, c[0], c[1], gx, gy, gz);
+}
+
+// Voxel broadphase lookup for a link bounding sphere (C, CR <= vcap): the candidate range
+// [b, e) of the cell holding C, empty when the cell's smallest lower bound is >= CR or C lies
+// outside the grid (then nothing is within vcap of C).
+__device__ __forceinline__ void voxel_range(const EnvView &ev, const EnvDev &ed, float Cx,
+                                            float Cy, float Cz, float CR, int &b, int &e) {
+    b = e = 0;
+    const float fx = floorf((Cx - ed.vorg[0]) * ed.vinv);
+    const float fy = floorf((Cy - ed.vorg[1]) * ed.vinv);
+    const float fz = floorf((Cz - ed.vorg[2]) * ed.vinv);
+    if (!(fx >= 0.0f && fy >= 0.0f && fz >= 0.0f && fx < (float)ed.vdim[0] &&
+          fy < (float)ed.vdim[1] && fz < (float)ed.vdim[2]))
+        return;
+    const int cell = ((int)fz * ed.vdim[1] + (int)fy) * ed.vdim[0] + (int)fx;
+    const unsigned char *dist = reinterpret_cast<const unsigned char *>(ev.rec + ev.off_vdist);
+    if ((float)dist[cell] * ed.vq >= CR) return;
+    b = ed.vstart[cell];
+    e = ed.vstart[cell + 1];
 }
 
 // Copy the environment records into LDS once per workgroup.
@@ -74,8 +122,10 @@ __device__ __forceinline__ void stage_env(float4 *lds, const float4 *__restrict_
 // Executed-work accounting (FLOP model, FMA = 2): every wave-uniform operation below adds its
 // per-lane FLOP count; the instrumented kernel multiplies by the 64 lanes that issue it.
 // NoWork compiles to nothing, so the timed kernels carry no accounting.
-// Work is split in four categories: FK and sphere placement, culling (hierarchy and per-link
-// bounding-sphere tests), fine environment tests, self pairs (including re-posing links).
+// Work is split in four categories: FK and sphere placement, culling (voxel lookups and
+// per-link bounding-sphere tests), fine environment tests, self pairs (including re-posing
+// links).  Every lane counts the operations it executes (lanes masked off by divergent
+// control flow add nothing); the instrumented kernel sums the lanes.
 namespace flop {
 constexpr uint32_t kJoint = 30, kMount = 63, kPlace = 18, kSphere = 11, kCapsule = 25,
                    kCylinder = 35, kBox = 34, kPair = 11;
@@ -203,39 +253,56 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
 
-        // environment: hierarchy of bounding spheres (groups, then clusters), then the
-        // per-primitive gate (link bounding sphere) and the link's fine spheres
-        for (int g = 0; g < ev.n_sup; ++g) {
-            work.add(flop::kCull, flop::kSphere);
-            if (!wave_ballot(live && hit_sphere(Cx, Cy, Cz, CR, ev.rec[g]))) continue;
-            const int c0 = rec_index(ev.rec[ev.off_sbeg + g].x);
-            const int c1 = rec_index(ev.rec[ev.off_sbeg + g + 1].x);
-            for (int c = c0; c < c1; ++c) {
-                work.add(flop::kCull, flop::kSphere);
-                if (!wave_ballot(live && hit_sphere(Cx, Cy, Cz, CR, ev.rec[ev.off_csph + c])))
-                    continue;
-                const float4 b0 = ev.rec[ev.off_cbeg + c], b1 = ev.rec[ev.off_cbeg + c + 1];
-                for (int i = rec_index(b0.x), e = rec_index(b1.x); i < e; ++i) {
-                    const float4 o = ev.rec[ev.off_sph + i];
-                    VK_GATE(flop::kSphere, hit_sphere(Cx, Cy, Cz, CR, o),
-                            hit_sphere(cx[k], cy[k], cz[k], cr[k], o))
+        // environment: voxel broadphase per lane (candidates sorted by a lower bound of their
+        // distance to the cell; stop at the first bound >= CR), then the exact link-sphere
+        // test (mid-phase) and the link's fine spheres
+        if (CR <= ed.vcap) {
+            int b, e;
+            work.add(flop::kCull, 6);
+            voxel_range(ev, ed, Cx, Cy, Cz, CR, b, e);
+            if (!live) e = b;
+            if (wave_ballot(b < e)) {
+                for (int p = b; p < e; ++p) {
+                    const int2 ent = ed.vlist[p];
+                    if (__int_as_float(ent.y) >= CR) break;
+                    const int t = ent.x >> 28, i = ent.x & 0x0fffffff;
+                    work.add(flop::kCull, flop::kBox);
+                    if (hit_any(ev, t, i, Cx, Cy, Cz, CR)) {
+                        work.add(flop::kFine, flop::kBox * cnt);
+#pragma unroll
+                        for (int k = 0; k < kSpl; ++k)
+                            if (k < cnt) col |= hit_any(ev, t, i, cx[k], cy[k], cz[k], cr[k]);
+                    }
                 }
-                for (int i = rec_index(b0.y), e = rec_index(b1.y); i < e; ++i) {
-                    const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
-                    VK_GATE(flop::kCapsule, hit_capsule(Cx, Cy, Cz, CR, A, B),
-                            hit_capsule(cx[k], cy[k], cz[k], cr[k], A, B))
+                if (EDGE) {
+                    if (wave_ballot(col)) return true;
+                } else {
+                    live = !col;
+                    if (!wave_ballot(live)) return col;
                 }
-                for (int i = rec_index(b0.z), e = rec_index(b1.z); i < e; ++i) {
-                    const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
-                    VK_GATE(flop::kCylinder, hit_cylinder(Cx, Cy, Cz, CR, A, B),
-                            hit_cylinder(cx[k], cy[k], cz[k], cr[k], A, B))
-                }
-                for (int i = rec_index(b0.w), e = rec_index(b1.w); i < e; ++i) {
-                    const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
-                                 Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
-                    VK_GATE(flop::kBox, hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
-                            hit_box(cx[k], cy[k], cz[k], cr[k], X, Y, Z, O))
-                }
+            }
+        } else {
+            // a link bounding sphere larger than the voxel lists cover: every primitive
+            for (int i = 0; i < ev.n_sph; ++i) {
+                const float4 o = ev.rec[ev.off_sph + i];
+                VK_GATE(flop::kSphere, hit_sphere(Cx, Cy, Cz, CR, o),
+                        hit_sphere(cx[k], cy[k], cz[k], cr[k], o))
+            }
+            for (int i = 0; i < ev.n_cap; ++i) {
+                const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
+                VK_GATE(flop::kCapsule, hit_capsule(Cx, Cy, Cz, CR, A, B),
+                        hit_capsule(cx[k], cy[k], cz[k], cr[k], A, B))
+            }
+            for (int i = 0; i < ev.n_cyl; ++i) {
+                const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
+                VK_GATE(flop::kCylinder, hit_cylinder(Cx, Cy, Cz, CR, A, B),
+                        hit_cylinder(cx[k], cy[k], cz[k], cr[k], A, B))
+            }
+            for (int i = 0; i < ev.n_box; ++i) {
+                const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
+                             Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
+                VK_GATE(flop::kBox, hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
+                        hit_box(cx[k], cy[k], cz[k], cr[k], X, Y, Z, O))
             }
         }
         if (ed.n_cells > 0) {
@@ -401,10 +468,13 @@ __global__ void __launch_bounds__(256)
         out[e] = hit;                         // wave-uniform value, same address in every lane
     }
     if constexpr (COUNT) {
-        const unsigned long long tot = work.f[0] + work.f[1] + work.f[2] + work.f[3];
-        atomicAdd(flops + 0, lane == 0 ? tot * kWave : 0ull);
+        unsigned long long v[4] = {work.f[0], work.f[1], work.f[2], work.f[3]};
 #pragma unroll
-        for (int c = 0; c < 4; ++c) atomicAdd(flops + 1 + c, lane == 0 ? work.f[c] * kWave : 0ull);
+        for (int c = 0; c < 4; ++c)
+            for (int m = 1; m < kWave; m <<= 1) v[c] += __shfl_xor(v[c], m);
+        atomicAdd(flops + 0, lane == 0 ? v[0] + v[1] + v[2] + v[3] : 0ull);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) atomicAdd(flops + 1 + c, lane == 0 ? v[c] : 0ull);
     }
 }
 
@@ -531,35 +601,39 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
         float Cx, Cy, Cz;
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
-        for (int g = 0; g < ev.n_sup; ++g) {
-            if (!wave_ballot(live && hit_sphere(Cx, Cy, Cz, CR, ev.rec[g]))) continue;
-            const int c0 = rec_index(ev.rec[ev.off_sbeg + g].x);
-            const int c1 = rec_index(ev.rec[ev.off_sbeg + g + 1].x);
-            for (int c = c0; c < c1; ++c) {
-                if (!wave_ballot(live && hit_sphere(Cx, Cy, Cz, CR, ev.rec[ev.off_csph + c])))
-                    continue;
-                const float4 b0 = ev.rec[ev.off_cbeg + c], b1 = ev.rec[ev.off_cbeg + c + 1];
-                for (int i = rec_index(b0.x), e = rec_index(b1.x); i < e; ++i) {
-                    const float4 o = ev.rec[ev.off_sph + i];
-                    VK_COST_GATE(hit_sphere(Cx, Cy, Cz, CR, o),
-                                 sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
-                }
-                for (int i = rec_index(b0.y), e = rec_index(b1.y); i < e; ++i) {
-                    const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
-                    VK_COST_GATE(hit_capsule(Cx, Cy, Cz, CR, A, B),
-                                 sd_capsule(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
-                }
-                for (int i = rec_index(b0.z), e = rec_index(b1.z); i < e; ++i) {
-                    const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
-                    VK_COST_GATE(hit_cylinder(Cx, Cy, Cz, CR, A, B),
-                                 sd_cylinder(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
-                }
-                for (int i = rec_index(b0.w), e = rec_index(b1.w); i < e; ++i) {
-                    const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
-                                 Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
-                    VK_COST_GATE(hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
-                                 sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
-                }
+        if (CR <= ed.vcap) {
+            int b, e;
+            voxel_range(ev, ed, Cx, Cy, Cz, CR, b, e);
+            if (!live) e = b;
+            for (int p = b; p < e; ++p) {
+                const int2 ent = ed.vlist[p];
+                if (__int_as_float(ent.y) >= CR) break;
+                const int t = ent.x >> 28, i = ent.x & 0x0fffffff;
+                if (!hit_any(ev, t, i, Cx, Cy, Cz, CR)) continue;
+#pragma unroll
+                for (int k = 0; k < kSpl; ++k)
+                    if (k < cnt) VK_PEN(sd_any(ev, t, i, cx[k], cy[k], cz[k], gx, gy, gz))
+            }
+        } else {
+            for (int i = 0; i < ev.n_sph; ++i) {
+                const float4 o = ev.rec[ev.off_sph + i];
+                VK_COST_GATE(hit_sphere(Cx, Cy, Cz, CR, o), sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
+            }
+            for (int i = 0; i < ev.n_cap; ++i) {
+                const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
+                VK_COST_GATE(hit_capsule(Cx, Cy, Cz, CR, A, B),
+                             sd_capsule(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
+            }
+            for (int i = 0; i < ev.n_cyl; ++i) {
+                const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
+                VK_COST_GATE(hit_cylinder(Cx, Cy, Cz, CR, A, B),
+                             sd_cylinder(cx[k], cy[k], cz[k], A, B, gx, gy, gz))
+            }
+            for (int i = 0; i < ev.n_box; ++i) {
+                const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
+                             Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
+                VK_COST_GATE(hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
+                             sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
             }
         }
         if (ed.n_cells > 0 && live) {

@@ -74,26 +74,27 @@ struct RobotDev {
     int32_t dof, n_steps, n_spheres, n_links;
 };
 
-// Environment, packed as float4 records in one buffer, preceded by a two-level hierarchy of
-// bounding spheres (wave-uniform culling):
-//   [0, n_sup)                 group bounding spheres (centre, radius)
-//   off_sbeg + [0, n_sup]      group g covers clusters [x(g), x(g+1)) (int bits in .x)
-//   off_csph + [0, n_clu)      cluster bounding spheres
-//   off_cbeg + [0, n_clu]      cluster c covers, per primitive type, records
-//                              [v(c), v(c+1)) with v = (.x spheres, .y capsules, .z cylinders,
-//                              .w boxes) as int bits, counted in primitives of that type
+// Environment.  Primitive records, packed as float4 in one buffer:
 //   off_sph   spheres   1 x float4: (centre, radius)
 //   off_cap   capsules  2 x float4: (p0, radius), (u = p1 - p0, 1 / (u . u) or 0)
 //   off_cyl   cylinders 2 x float4: (centre, half height), (unit axis, radius)
 //   off_box   boxes     4 x float4: (col_0 of R, e_0), (col_1, e_1), (col_2, e_2), (centre, 0)
-// Primitives are ordered by cluster (clusters are runs of spatially close primitives along a
-// Morton curve), so a cluster's primitives of one type are contiguous.
+//   off_vdist voxel distance bytes (16 per record), then the point-grid cell index
+// The record buffer is what a workgroup stages in LDS.
+//
+// Voxel broadphase over the primitives: a uniform grid covering every point within `vcap` of
+// a primitive.  For each cell, vlist[vstart[c] .. vstart[c+1]) lists every primitive whose
+// distance to some point of the cell may be below vcap, as (type << 28 | index, lower bound
+// of that distance over the cell), sorted by the bound; the byte field holds the smallest
+// bound of the cell, rounded down to multiples of vq (255 = nothing closer than vcap).
 struct EnvDev {
     const float4 *rec;
-    int32_t n_sup, n_clu;
-    int32_t off_sbeg, off_csph, off_cbeg;
-    int32_t off_sph, off_cap, off_cyl, off_box, n_rec;   // offsets / total in float4 records
+    int32_t off_sph, off_cap, off_cyl, off_box, off_vdist, n_rec;
     int32_t n_sph, n_cap, n_cyl, n_box;
+    const int32_t *vstart;         // [n_vox + 1]
+    const int2 *vlist;
+    int32_t vdim[3], n_vox;
+    float vorg[3], vinv, vq, vcap;
     // Uniform grid over a large set of small spheres (point clouds); n_cells == 0 when absent.
     // The cell index (cell_start, n_cells + 1 ints, four per record) is part of the record
     // buffer at off_cell, so it is staged in LDS with the rest; the points themselves, sorted by
