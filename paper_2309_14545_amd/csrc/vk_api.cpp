@@ -212,10 +212,6 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
         std::reverse(v.begin(), v.end());
         return v;
     };
-    auto is_anc = [&](int a, int b) {         // a is b or an ancestor of b
-        while (b > 0 && b != a) b = par[b];
-        return b == a;
-    };
 
     std::vector<JointRec> joints(dof);
     for (int j = 0; j < dof; ++j) {
@@ -276,7 +272,9 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
         if (l == 0 && count[0] == 0) steps.pop_back();   // nothing to do on an empty base
     }
 
-    // self pairs: grouped by the step holding the later-link sphere, then by earlier link
+    // self pairs: grouped by the step holding the later-link sphere, then by the step holding
+    // the earlier sphere (blocks ordered by that step, so consecutive blocks tend to walk down
+    // one branch and can continue from the previous block's pose)
     std::vector<std::map<int, std::map<int, uint32_t>>> grp(steps.size());
     for (int p = 0; p < P; ++p) {
         int s = d->self_pairs[2 * p], t = d->self_pairs[2 * p + 1];
@@ -287,30 +285,27 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
             std::swap(s, t);
             std::swap(ls, lt);
         }
-        grp[sphere_step[s]][lt][t] |= 1u << sphere_k[s];
+        grp[sphere_step[s]][sphere_step[t]][t] |= 1u << sphere_k[s];
     }
     std::vector<BlockRec> blocks;
     std::vector<EntryRec> entries;
-    int cur_aux = -1;                         // link whose pose the block frame holds
     for (size_t si = 0; si < steps.size(); ++si) {
         steps[si].blk_first = (int)blocks.size();
         for (auto &kv : grp[si]) {
-            const int A = kv.first;
+            const int sa = kv.first;
+            const int A = steps[sa].link;
             BlockRec B;
             std::memset(&B, 0, sizeof B);
+            B.step_a = sa;
             B.link = A;
-            std::vector<int> path = anc(A);
-            if (cur_aux >= 0 && is_anc(cur_aux, A)) {
-                const size_t skip = anc(cur_aux).size();
-                path.erase(path.begin(), path.begin() + skip);
-                B.restart = 0;
-            } else {
-                B.restart = 1;
-            }
+            const std::vector<int> path = anc(A);
             B.path_off = (int)paths.size();
             B.path_len = (int)path.size();
             paths.insert(paths.end(), path.begin(), path.end());
-            cur_aux = A;
+            uint64_t mask = 0;
+            for (int l = par[A]; l > 0; l = par[l]) mask |= 1ull << (l - 1);
+            B.anc_lo = (uint32_t)mask;
+            B.anc_hi = (uint32_t)(mask >> 32);
             B.ent_first = (int)entries.size();
             std::vector<const float *> sp;
             for (auto &tm : kv.second) {
@@ -571,11 +566,6 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     e->dev.off_cap = put(cap);
     e->dev.off_cyl = put(cyl);
     e->dev.off_box = put(box);
-    {
-        std::vector<float4> packed((vdist.size() + 15) / 16, make_float4(0, 0, 0, 0));
-        if (!vdist.empty()) std::memcpy(packed.data(), vdist.data(), vdist.size());
-        e->dev.off_vdist = put(packed);
-    }
 
     // point grid: cell size sized so robot spheres up to kGridRobotR scan a 3x3x3 neighbourhood
     std::vector<float4> pts;
@@ -622,6 +612,15 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
         }
         e->dev.ginv = (float)(1.0 / h);
         e->dev.gmax_r = gmax_r;
+    } else {
+        e->dev.off_cell = (int)rec.size();
+    }
+    // the voxel byte field goes last: it is read from global memory (one byte per lane and
+    // link), so it never competes for LDS with the primitives and the cell index
+    {
+        std::vector<float4> packed((vdist.size() + 15) / 16, make_float4(0, 0, 0, 0));
+        if (!vdist.empty()) std::memcpy(packed.data(), vdist.data(), vdist.size());
+        e->dev.off_vdist = put(packed);
     }
     e->dev.n_rec = (int)rec.size();
     e->dev.n_sph = (int)sph.size();
@@ -643,10 +642,20 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     e->dev.vlist = reinterpret_cast<const int2 *>(base + o_l);
 }
 
-bool env_in_lds(const vk_env_s *e, size_t extra = 0) {
+// Environment for one launch, with the number of leading records staged in LDS: the
+// primitives and the point-grid cell index when both fit, else the primitives alone, else none
+// (everything read from global memory).  `extra` is the kernel's other dynamic LDS (step
+// caches, adjoint slots) and must fit on its own.
+EnvDev env_for_launch(const vk_env_s *e, size_t extra) {
     const DeviceInfo &di = device_info(e->device);
-    const size_t bytes = (size_t)e->dev.n_rec * 16 + extra;
-    return e->dev.n_rec > 0 && bytes <= std::min<size_t>(di.max_lds, 64 * 1024);
+    if (extra > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the LDS step cache");
+    EnvDev d = e->dev;
+    auto fits = [&](int n) {
+        const size_t b = (size_t)n * 16;
+        return n > 0 && b <= 64 * 1024 && b + extra <= di.max_lds;
+    };
+    d.n_stage = fits(d.off_vdist) ? d.off_vdist : fits(d.off_cell) ? d.off_cell : 0;
+    return d;
 }
 
 void check_pair(vk_robot r, vk_env e) {
@@ -734,7 +743,9 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
         check_pair(robot, env);
         check_batch(n, ldq, q, collide, "validate_states");
         if (n == 0) return;
-        hip_check(launch_validate_states(robot->dev, env->dev, env_in_lds(env), q, n, ldq, collide,
+        hip_check(launch_validate_states(robot->dev,
+                                         env_for_launch(env, walk_lds_bytes(robot->dev, 256)), q, n,
+                                         ldq, collide,
                                          (hipStream_t)stream),
                   "validate_states launch");
     });
@@ -769,7 +780,8 @@ static void run_edges(vk_robot robot, vk_env env, const float *qa, const float *
     const int64_t want = (n_edges + block / kWave - 1) / (block / kWave);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
     hip_check(launch_reset_queue(queue, s), "queue reset");
-    hip_check(launch_validate_edges(robot->dev, env->dev, env_in_lds(env), qa, qb, n_states,
+    hip_check(launch_validate_edges(robot->dev, env_for_launch(env, walk_lds_bytes(robot->dev, block)),
+                                    qa, qb, n_states,
                                     n_edges, resolution, collide, queue, grid, block, s, flops),
               "validate_edges launch");
 }
@@ -798,9 +810,9 @@ vk_status validate_edges_per_edge(vk_robot robot, vk_env env, const float *qa, c
     return guarded([&] {
         check_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide);
         hipStream_t s = (hipStream_t)stream;
-        const bool lds = env_in_lds(env);
+        const EnvDev ed = env_for_launch(env, walk_lds_bytes(robot->dev, kWave));
         for (int64_t e = 0; e < n_edges; ++e)
-            hip_check(launch_validate_edge_one(robot->dev, env->dev, lds, qa, qb, n_states, e,
+            hip_check(launch_validate_edge_one(robot->dev, ed, qa, qb, n_states, e,
                                                resolution, collide, s),
                       "validate_edges_per_edge launch");
     });
@@ -812,7 +824,8 @@ vk_status penetration_cost_fwd(vk_robot robot, vk_env env, const float *q, int64
         check_pair(robot, env);
         check_batch(n, ldq, q, cost, "penetration_cost_fwd");
         if (n == 0) return;
-        hip_check(launch_cost_fwd(robot->dev, env->dev, env_in_lds(env), q, n, ldq, cost,
+        hip_check(launch_cost_fwd(robot->dev, env_for_launch(env, walk_lds_bytes(robot->dev, 256)),
+                                  q, n, ldq, cost,
                                   (hipStream_t)stream),
                   "penetration_cost_fwd launch");
     });
@@ -832,7 +845,7 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
         while (block > 64 && cost_bwd_slot_bytes(robot->dev, block) > di.max_lds) block /= 2;
         const size_t slots = cost_bwd_slot_bytes(robot->dev, block);
         if (slots > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the backward kernel");
-        hip_check(launch_cost_bwd(robot->dev, env->dev, env_in_lds(env, slots), q, n, ldq, grad_cost,
+        hip_check(launch_cost_bwd(robot->dev, env_for_launch(env, slots), q, n, ldq, grad_cost,
                                   grad_q, ldg, block, (hipStream_t)stream),
                   "penetration_cost_bwd launch");
     });
@@ -903,6 +916,10 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             }
             const int64_t want = (total + block / kWave - 1) / (block / kWave);
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
+            int cache_steps = 0;
+            for (const BatchSet &b : recs) cache_steps = std::max(cache_steps, b.rb.n_steps);
+            if ((size_t)(block / kWave) * cache_steps * 3 * kWave * sizeof(float) > di.max_lds)
+                raise(VK_ERR_UNSUPPORTED, "robots too large for the LDS step cache");
             // capture {queue reset, persistent launch} once; vk_edge_batch_run replays it
             hipStream_t cs = nullptr;
             hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
@@ -910,7 +927,8 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             if (err == hipSuccess) err = launch_reset_queue(bt->queue, cs);
             if (err == hipSuccess && total > 0)
                 err = launch_validate_edge_batch(d_sets, d_pre, (int)recs.size(), total, resolution,
-                                                 qa, qb, collide, bt->queue, grid, block, cs);
+                                                 qa, qb, collide, bt->queue, grid, block,
+                                                 cache_steps, cs);
             hipGraph_t g = nullptr;
             hipError_t err2 = hipStreamEndCapture(cs, &g);
             (void)hipStreamDestroy(cs);

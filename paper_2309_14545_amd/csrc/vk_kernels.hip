@@ -13,6 +13,9 @@
 //     samples the whole motion (Sec. III-D, Fig. 2) and a wave ballot ends the edge early.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "vk_device.hpp"
@@ -40,20 +43,24 @@ struct QState {                // SoA state batch: q[j * ldq + i]
 
 // Environment view (records in LDS or global memory) -----------------------------------------
 struct EnvView {
-    const float4 *rec;
-    int off_sph, off_cap, off_cyl, off_box, off_vdist, off_cell;
+    const float4 *rec;             // primitive records
+    const float *cell;             // point-grid cell index (int bits)
+    int off_sph, off_cap, off_cyl, off_box;
     int n_sph, n_cap, n_cyl, n_box;
 };
 
-__device__ __forceinline__ EnvView make_view(const EnvDev &e, const float4 *rec) {
+// Staging modes of the record buffer: 0 nothing in LDS, 1 the primitives, 2 the primitives and
+// the point-grid cell index.  `lds` holds the staged prefix.  The mode is a template constant so
+// that every record access compiles to an LDS or a global load, never a generic one.
+template <int STAGE>
+__device__ __forceinline__ EnvView make_view(const EnvDev &e, const float4 *lds) {
     EnvView v;
-    v.rec = rec;
+    v.rec = STAGE ? lds : e.rec;
+    v.cell = reinterpret_cast<const float *>((STAGE == 2 ? lds : e.rec) + e.off_cell);
     v.off_sph = e.off_sph;
     v.off_cap = e.off_cap;
     v.off_cyl = e.off_cyl;
     v.off_box = e.off_box;
-    v.off_vdist = e.off_vdist;
-    v.off_cell = e.off_cell;
     v.n_sph = e.n_sph;
     v.n_cap = e.n_cap;
     v.n_cyl = e.n_cyl;
@@ -107,7 +114,7 @@ __device__ __forceinline__ void voxel_range(const EnvView &ev, const EnvDev &ed,
           fy < (float)ed.vdim[1] && fz < (float)ed.vdim[2]))
         return;
     const int cell = ((int)fz * ed.vdim[1] + (int)fy) * ed.vdim[0] + (int)fx;
-    const unsigned char *dist = reinterpret_cast<const unsigned char *>(ev.rec + ev.off_vdist);
+    const unsigned char *dist = reinterpret_cast<const unsigned char *>(ed.rec + ed.off_vdist);
     if ((float)dist[cell] * ed.vq >= CR) return;
     b = ed.vstart[cell];
     e = ed.vstart[cell + 1];
@@ -156,16 +163,71 @@ __device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, 
     w.add(flop::kFk, flop::kJoint + (rb.joints[S.joint].has_mount ? flop::kMount : 0));
 }
 
-// Pose the earlier link of self block B into Ta.
+// Pose the earlier link A of self block B into Ta.  Ta holds link `ta_link` (depth `ta_depth`
+// joints from the base): when that link is A nothing is done; when it is the base or a proper
+// ancestor of A the remaining joints of A's path are applied; otherwise Ta restarts from the
+// base.
 template <class Q, class W = NoWork>
 __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B, Frame &Ta,
-                                           const Q &q, W &&w = W()) {
-    if (B.restart) frame_identity(Ta);
-    for (int k = 0; k < B.path_len; ++k) {
+                                           int &ta_link, int &ta_depth, const Q &q,
+                                           W &&w = W()) {
+    if (ta_link == B.link) return;
+    const unsigned long long anc = ((unsigned long long)B.anc_hi << 32) | B.anc_lo;
+    int k0 = ta_depth;
+    if (!(ta_link == 0 || (ta_link > 0 && ((anc >> (ta_link - 1)) & 1ull)))) {
+        frame_identity(Ta);
+        k0 = 0;
+    }
+    for (int k = k0; k < B.path_len; ++k) {
         const int j = rb.paths[B.path_off + k];
         frame_joint(Ta, rb.joints[j], q(j));
         w.add(flop::kSelf, flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
     }
+    ta_link = B.link;
+    ta_depth = B.path_len;
+}
+
+// Sphere centres of a step from its link frame (placed lazily, when a test needs them).
+__device__ __forceinline__ void place_step(const RobotDev &rb, const StepRec &S, const Frame &T,
+                                           float (&cx)[kSpl], float (&cy)[kSpl],
+                                           float (&cz)[kSpl], float (&cr)[kSpl]) {
+#pragma unroll
+    for (int k = 0; k < kSpl; ++k) {
+        cx[k] = cy[k] = cz[k] = cr[k] = 0.0f;
+        if (k < S.sph_count) {
+            const float4 s = rb.spheres[S.sph_first + k];
+            frame_point(T, s.x, s.y, s.z, cx[k], cy[k], cz[k]);
+            cr[k] = s.w;
+        }
+    }
+}
+
+// Per-wave LDS cache of every step's link bounding-sphere centre, [step][axis][lane].
+struct StepCache {
+    float *base;
+    int lane;
+    __device__ __forceinline__ void put(int st, float x, float y, float z) const {
+        base[(st * 3 + 0) * kWave + lane] = x;
+        base[(st * 3 + 1) * kWave + lane] = y;
+        base[(st * 3 + 2) * kWave + lane] = z;
+    }
+    __device__ __forceinline__ void get(int st, float &x, float &y, float &z) const {
+        x = base[(st * 3 + 0) * kWave + lane];
+        y = base[(st * 3 + 1) * kWave + lane];
+        z = base[(st * 3 + 2) * kWave + lane];
+    }
+};
+
+// Floats of LDS per wave for the step cache.
+__host__ __device__ constexpr int step_cache_floats(int n_steps) { return n_steps * 3 * kWave; }
+
+// Dynamic LDS of the walks: [step cache of every wave of the block][environment records].
+__device__ __forceinline__ StepCache step_cache(float *lds, int n_steps) {
+    return StepCache{lds + (threadIdx.x / kWave) * step_cache_floats(n_steps),
+                     (int)(threadIdx.x & (kWave - 1))};
+}
+__device__ __forceinline__ float4 *after_caches(float *lds, int n_steps) {
+    return reinterpret_cast<float4 *>(lds + (blockDim.x / kWave) * step_cache_floats(n_steps));
 }
 
 // Grid broadphase over a large set of small spheres.  A point of radius <= gmax_r can touch a
@@ -176,7 +238,7 @@ __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B
 template <class F>
 __device__ __forceinline__ void grid_scan(const EnvView &ev, const EnvDev &g, float cx, float cy,
                                           float cz, float r, F &&visit) {
-    const float *cell = reinterpret_cast<const float *>(ev.rec + ev.off_cell);
+    const float *cell = ev.cell;
     const int R = (int)ceilf((r + g.gmax_r) * g.ginv * 1.00001f + 1e-5f);
     const float lim = 1.0e6f;
     const int ix = (int)fminf(fmaxf(floorf((cx - g.gorg[0]) * g.ginv), -lim), lim);
@@ -227,10 +289,11 @@ __device__ __forceinline__ bool grid_hit(const EnvView &ev, const EnvDev &g, flo
 //                 when every lane has collided.  `col` on entry marks lanes already decided.
 template <bool EDGE, class Q, class W = NoWork>
 __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev &ed, const Q &q,
-                             bool col, W &&work = W()) {
+                             const StepCache &sc, bool col, W &&work = W()) {
     Frame Tm, Ta;
     frame_identity(Tm);
     frame_identity(Ta);
+    int ta_link = 0, ta_depth = 0;
     bool live = !col;
     if (!EDGE && !wave_ballot(live)) return col;
     for (int st = 0; st < rb.n_steps; ++st) {
@@ -238,20 +301,20 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         pose_step(rb, S, Tm, q, work);
         const int cnt = S.sph_count;
         if (cnt == 0) continue;
-        work.add(flop::kFk, flop::kPlace * (cnt + 1));
-        float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl];
-#pragma unroll
-        for (int k = 0; k < kSpl; ++k) {
-            cx[k] = cy[k] = cz[k] = cr[k] = 0.0f;
-            if (k < cnt) {
-                const float4 s = rb.spheres[S.sph_first + k];
-                frame_point(Tm, s.x, s.y, s.z, cx[k], cy[k], cz[k]);
-                cr[k] = s.w;
-            }
-        }
+        work.add(flop::kFk, flop::kPlace);
         float Cx, Cy, Cz;
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
+        sc.put(st, Cx, Cy, Cz);
+        // the step's fine spheres, placed on first use (uniform decision)
+        float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl];
+        bool placed = false;
+#define VK_PLACE()                                                                  \
+    if (!placed) {                                                                  \
+        place_step(rb, S, Tm, cx, cy, cz, cr);                                      \
+        work.add(flop::kFk, flop::kPlace * cnt);                                    \
+        placed = true;                                                              \
+    }
 
         // environment: voxel broadphase per lane (candidates sorted by a lower bound of their
         // distance to the cell; stop at the first bound >= CR), then the exact link-sphere
@@ -262,6 +325,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
             voxel_range(ev, ed, Cx, Cy, Cz, CR, b, e);
             if (!live) e = b;
             if (wave_ballot(b < e)) {
+                VK_PLACE()
                 for (int p = b; p < e; ++p) {
                     const int2 ent = ed.vlist[p];
                     if (__int_as_float(ent.y) >= CR) break;
@@ -283,6 +347,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
             }
         } else {
             // a link bounding sphere larger than the voxel lists cover: every primitive
+            VK_PLACE()
             for (int i = 0; i < ev.n_sph; ++i) {
                 const float4 o = ev.rec[ev.off_sph + i];
                 VK_GATE(flop::kSphere, hit_sphere(Cx, Cy, Cz, CR, o),
@@ -306,6 +371,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
             }
         }
         if (ed.n_cells > 0) {
+            VK_PLACE()
 #pragma unroll
             for (int k = 0; k < kSpl; ++k)
                 if (k < cnt && live && !col) col |= grid_hit(ev, ed, cx[k], cy[k], cz[k], cr[k]);
@@ -317,15 +383,18 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
             }
         }
 
-        // self pairs completed by this step (earlier link posed into Ta)
+        // self pairs completed by this step: gate each block with the earlier step's link
+        // bounding sphere (cached centre), then pose its link into Ta and test the pairs
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec &B = rb.blocks[S.blk_first + b];
-            pose_block(rb, B, Ta, q, work);
-            float Ax, Ay, Az;
-            frame_point(Ta, B.coarse[0], B.coarse[1], B.coarse[2], Ax, Ay, Az);
-            const float dx = Ax - Cx, dy = Ay - Cy, dz = Az - Cz, rr = B.coarse[3] + CR;
-            work.add(flop::kSelf, flop::kPlace + flop::kPair);
+            float ax, ay, az;
+            sc.get(B.step_a, ax, ay, az);
+            const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
+            const float rr = rb.steps[B.step_a].coarse[3] + CR;
+            work.add(flop::kSelf, flop::kPair);
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
+            VK_PLACE()
+            pose_block(rb, B, Ta, ta_link, ta_depth, q, work);
             for (int e = 0; e < B.ent_count; ++e) {
                 const EntryRec &E = rb.entries[B.ent_first + e];
                 float tx, ty, tz;
@@ -347,6 +416,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
                 if (!wave_ballot(live)) return col;
             }
         }
+#undef VK_PLACE
     }
     return EDGE ? false : col;
 }
@@ -382,21 +452,24 @@ __global__ void __launch_bounds__(256) k_fk_spheres(RobotDev rb, const float *__
 // ---------------------------------------------------------------------------------------------
 // validate_states: one lane per state.
 // ---------------------------------------------------------------------------------------------
-template <bool LDS>
+template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_validate_states(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                       const float *__restrict__ q, int64_t n, int64_t ldq,
                       uint8_t *__restrict__ out) {
-    extern __shared__ float4 lds_env[];
-    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
-    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    extern __shared__ float4 lds_dyn[];
+    float *lf = reinterpret_cast<float *>(lds_dyn);
+    const StepCache sc = step_cache(lf, rb.n_steps);
+    float4 *lds_env = after_caches(lf, rb.n_steps);
+    if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
+    const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = i < n;
     QState qs{q, ldq, active ? i : 0};
     bool col = !active;                       // inactive lanes count as decided
     if (active)
         for (int j = 0; j < rb.dof; ++j) col |= !isfinite(qs(j));
-    col = walk_collide<false>(rb, ev, ed, qs, col);
+    col = walk_collide<false>(rb, ev, ed, qs, sc, col);
     if (active) out[i] = col ? 1 : 0;
 }
 
@@ -414,8 +487,8 @@ __device__ __forceinline__ int edge_count(const float *a, const float *b, int do
 
 template <class V, class W = NoWork>
 __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, const EnvDev &ed,
-                                             const float *a, const float *b, int n,
-                                             W &&work = W()) {
+                                             const StepCache &sc, const float *a, const float *b,
+                                             int n, W &&work = W()) {
     bool bad = false;
     for (int j = 0; j < rb.dof; ++j) bad |= !isfinite(a[j]) || !isfinite(b[j]);
     if (bad) return 1;
@@ -428,7 +501,7 @@ __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, co
         idx = idx < n ? idx : n - 1;          // surplus lanes repeat the last state
         const float t = idx == n - 1 ? 1.0f : (float)idx * inv;
         QEdge qs{a, b, t};
-        if (walk_collide<true>(rb, ev, ed, qs, false, work)) return 1;
+        if (walk_collide<true>(rb, ev, ed, qs, sc, false, work)) return 1;
     }
     return 0;
 }
@@ -446,16 +519,19 @@ __device__ __forceinline__ int64_t next_item(unsigned long long *queue, int lane
     return (int64_t)(((unsigned long long)hi << 32) | lo);
 }
 
-template <bool LDS, bool COUNT>
+template <int STAGE, bool COUNT>
 __global__ void __launch_bounds__(256)
     k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                      const float *__restrict__ qa, const float *__restrict__ qb,
                      const int32_t *__restrict__ nst, int64_t n_edges, float res,
                      uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
                      unsigned long long *__restrict__ flops) {
-    extern __shared__ float4 lds_env[];
-    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
-    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    extern __shared__ float4 lds_dyn[];
+    float *lf = reinterpret_cast<float *>(lds_dyn);
+    const StepCache sc = step_cache(lf, rb.n_steps);
+    float4 *lds_env = after_caches(lf, rb.n_steps);
+    if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
+    const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int lane = threadIdx.x & (kWave - 1);
     typename std::conditional<COUNT, Work, NoWork>::type work;
     for (;;) {
@@ -464,7 +540,7 @@ __global__ void __launch_bounds__(256)
         const float *a = qa + e * rb.dof;
         const float *b = qb + e * rb.dof;
         const int n = nst ? nst[e] : edge_count(a, b, rb.dof, res);
-        const uint8_t hit = edge_body(rb, ev, ed, a, b, n, work);
+        const uint8_t hit = edge_body(rb, ev, ed, sc, a, b, n, work);
         out[e] = hit;                         // wave-uniform value, same address in every lane
     }
     if constexpr (COUNT) {
@@ -478,20 +554,23 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-template <bool LDS>
+template <int STAGE>
 __global__ void __launch_bounds__(64)
     k_validate_edge_one(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                         const float *__restrict__ qa, const float *__restrict__ qb,
                         const int32_t *__restrict__ nst, int64_t e, float res,
                         uint8_t *__restrict__ out) {
-    extern __shared__ float4 lds_env[];
-    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
-    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    extern __shared__ float4 lds_dyn[];
+    float *lf = reinterpret_cast<float *>(lds_dyn);
+    const StepCache sc = step_cache(lf, rb.n_steps);
+    float4 *lds_env = after_caches(lf, rb.n_steps);
+    if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
+    const EnvView ev = make_view<STAGE>(ed, lds_env);
     const float *a = qa + e * rb.dof;
     const float *b = qb + e * rb.dof;
     const int n = nst ? nst[e] : edge_count(a, b, rb.dof, res);
-    const uint8_t hit = edge_body(rb, ev, ed, a, b, n);
-    if ((threadIdx.x & (kWave - 1)) == 0) out[e] = hit;
+    const uint8_t hit = edge_body(rb, ev, ed, sc, a, b, n);
+    out[e] = hit;                             // wave-uniform value
 }
 
 // Mixed-robot batch: every edge set has its own robot and environment; one persistent launch
@@ -501,7 +580,9 @@ __global__ void __launch_bounds__(256)
     k_validate_edge_batch(const BatchSet *__restrict__ sets, const int64_t *__restrict__ prefix,
                           int n_sets, int64_t total, float res, const float *__restrict__ qa,
                           const float *__restrict__ qb, uint8_t *__restrict__ out,
-                          unsigned long long *__restrict__ queue) {
+                          unsigned long long *__restrict__ queue, int cache_steps) {
+    extern __shared__ float4 lds_dyn[];
+    const StepCache sc = step_cache(reinterpret_cast<float *>(lds_dyn), cache_steps);
     const int lane = threadIdx.x & (kWave - 1);
     for (;;) {
         const int64_t e = next_item(queue, lane);
@@ -516,8 +597,8 @@ __global__ void __launch_bounds__(256)
         const float *a = qa + S.qa_offset + local * S.rb.dof;
         const float *b = qb + S.qa_offset + local * S.rb.dof;
         const int n = edge_count(a, b, S.rb.dof, res);
-        const EnvView ev = make_view(S.env, S.env.rec);
-        const uint8_t hit = edge_body(S.rb, ev, S.env, a, b, n);
+        const EnvView ev = make_view<0>(S.env, nullptr);
+        const uint8_t hit = edge_body(S.rb, ev, S.env, sc, a, b, n);
         out[S.out_offset + local] = hit;      // wave-uniform value
     }
 }
@@ -577,10 +658,11 @@ struct LinkSlots {
 
 template <bool GRAD, class Q>
 __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &ed, const Q &q,
-                           bool live, const LinkSlots &slots) {
+                           const StepCache &sc, bool live, const LinkSlots &slots) {
     Frame Tm, Ta;
     frame_identity(Tm);
     frame_identity(Ta);
+    int ta_link = 0, ta_depth = 0;
     float cost = 0.0f;
     for (int st = 0; st < rb.n_steps; ++st) {
         const StepRec &S = rb.steps[st];
@@ -601,6 +683,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
         float Cx, Cy, Cz;
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
+        sc.put(st, Cx, Cy, Cz);
         if (CR <= ed.vcap) {
             int b, e;
             voxel_range(ev, ed, Cx, Cy, Cz, CR, b, e);
@@ -648,11 +731,12 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
         }
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec &B = rb.blocks[S.blk_first + b];
-            pose_block(rb, B, Ta, q);
-            float Ax, Ay, Az;
-            frame_point(Ta, B.coarse[0], B.coarse[1], B.coarse[2], Ax, Ay, Az);
-            const float dx = Ax - Cx, dy = Ay - Cy, dz = Az - Cz, rr = B.coarse[3] + CR;
+            float ax, ay, az;
+            sc.get(B.step_a, ax, ay, az);
+            const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
+            const float rr = rb.steps[B.step_a].coarse[3] + CR;
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
+            pose_block(rb, B, Ta, ta_link, ta_depth, q);
             for (int e = 0; e < B.ent_count; ++e) {
                 const EntryRec &E = rb.entries[B.ent_first + e];
                 float tx, ty, tz;
@@ -690,27 +774,30 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
     return cost;
 }
 
-template <bool LDS>
+template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_cost_fwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                const float *__restrict__ q, int64_t n, int64_t ldq, float *__restrict__ cost) {
-    extern __shared__ float4 lds_env[];
-    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
-    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    extern __shared__ float4 lds_dyn[];
+    float *lf = reinterpret_cast<float *>(lds_dyn);
+    const StepCache sc = step_cache(lf, rb.n_steps);
+    float4 *lds_env = after_caches(lf, rb.n_steps);
+    if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
+    const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = i < n;
     QState qs{q, ldq, active ? i : 0};
     bool finite = true;
     for (int j = 0; j < rb.dof; ++j) finite &= isfinite(qs(j));
     LinkSlots none{nullptr, 0};
-    const float c = cost_walk<false>(rb, ev, ed, qs, active && finite, none);
+    const float c = cost_walk<false>(rb, ev, ed, qs, sc, active && finite, none);
     if (active) cost[i] = finite ? c : __builtin_nanf("");
 }
 
 // Backward: forces per link accumulated in LDS, suffix sums over the tree, then
 // dq_j = z_j . (M_j - o_j x F_j) with (F_j, M_j) the force and moment (about the origin) of
 // everything joint j moves and (z_j, o_j) the axis and origin of joint j's frame.
-template <bool LDS>
+template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_cost_bwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                const float *__restrict__ q, int64_t n, int64_t ldq,
@@ -720,9 +807,11 @@ __global__ void __launch_bounds__(256)
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const int slot_floats = rb.n_links * 6 * kWave;
     float *slot_base = reinterpret_cast<float *>(lds_dyn);
-    float4 *lds_env = lds_dyn + (slot_floats * (blockDim.x / kWave)) / 4;
-    if (LDS) stage_env(lds_env, env_rec, ed.n_rec);
-    const EnvView ev = make_view(ed, LDS ? lds_env : env_rec);
+    float *lf = slot_base + slot_floats * (blockDim.x / kWave);
+    const StepCache sc = step_cache(lf, rb.n_steps);
+    float4 *lds_env = after_caches(lf, rb.n_steps);
+    if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
+    const EnvView ev = make_view<STAGE>(ed, lds_env);
     LinkSlots slots{slot_base + wave * slot_floats, lane};
     for (int l = 0; l < rb.n_links; ++l)
         for (int c = 0; c < 6; ++c) slots.at(l, c) = 0.0f;
@@ -732,7 +821,7 @@ __global__ void __launch_bounds__(256)
     QState qs{q, ldq, active ? i : 0};
     bool finite = true;
     for (int j = 0; j < rb.dof; ++j) finite &= isfinite(qs(j));
-    cost_walk<true>(rb, ev, ed, qs, active && finite, slots);
+    cost_walk<true>(rb, ev, ed, qs, sc, active && finite, slots);
 
     // suffix sums: child link totals into the parent (parents have smaller indices)
     for (int l = rb.n_links - 1; l >= 1; --l) {
@@ -788,16 +877,70 @@ hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int6
     return hipGetLastError();
 }
 
-hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
-                                  int64_t n, int64_t ldq, uint8_t *out, hipStream_t s) {
+size_t walk_lds_bytes(const RobotDev &rb, int block) {
+    return (size_t)(block / kWave) * step_cache_floats(rb.n_steps) * sizeof(float);
+}
+
+// Resident workgroups per CU of a kernel at a block size and dynamic LDS (memoised: the
+// runtime query is not free and launches repeat with the same shapes).
+static int resident_blocks(const void *kernel, int block, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, size_t>, int> memo;
+    const auto key = std::make_tuple(kernel, block, lds);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, lds) != hipSuccess) n = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    memo[key] = n;
+    return n;
+}
+
+// Staging mode of a launch (see make_view).  ed.n_stage arrives as the largest prefix that fits
+// the LDS; a prefix is staged only if it costs no resident workgroups against reading every
+// record from global memory: when the per-wave step caches already fill the LDS, staging the
+// records would trade occupancy for latency, and occupancy matters more here.  On return
+// ed.n_stage is the prefix the chosen mode stages.
+static int pick_stage(EnvDev &ed, const void *k0, const void *k1, const void *k2, int block,
+                      size_t base) {
+    const int occ0 = resident_blocks(k0, block, base);
+    if (ed.n_stage > ed.off_cell && resident_blocks(k2, block, base + (size_t)ed.n_stage * 16) >= occ0)
+        return 2;
+    if (ed.off_cell > 0 && ed.n_stage >= ed.off_cell &&
+        resident_blocks(k1, block, base + (size_t)ed.off_cell * 16) >= occ0) {
+        ed.n_stage = ed.off_cell;
+        return 1;
+    }
+    ed.n_stage = 0;
+    return 0;
+}
+
+#define VK_STAGED(KERNEL, ...)                                                                  \
+    {                                                                                           \
+        EnvDev ed = ed_in;                                                                      \
+        const int mode = pick_stage(ed, reinterpret_cast<const void *>(&KERNEL<0 __VA_ARGS__>), \
+                                    reinterpret_cast<const void *>(&KERNEL<1 __VA_ARGS__>),     \
+                                    reinterpret_cast<const void *>(&KERNEL<2 __VA_ARGS__>),     \
+                                    (int)block_.x, base_);                                      \
+        const size_t sh_ = base_ + (size_t)ed.n_stage * 16;                                     \
+        switch (mode) {                                                                         \
+        case 0: hipLaunchKernelGGL((KERNEL<0 __VA_ARGS__>), grid_, block_, sh_, s, ARGS_); break; \
+        case 1: hipLaunchKernelGGL((KERNEL<1 __VA_ARGS__>), grid_, block_, sh_, s, ARGS_); break; \
+        default: hipLaunchKernelGGL((KERNEL<2 __VA_ARGS__>), grid_, block_, sh_, s, ARGS_); break; \
+        }                                                                                       \
+    }
+
+hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
+                                  int64_t ldq, uint8_t *out, hipStream_t s) {
     const int bs = 256;
-    const int64_t grid = (n + bs - 1) / bs;
-    if (lds)
-        hipLaunchKernelGGL(k_validate_states<true>, dim3((unsigned)grid), dim3(bs),
-                           (size_t)ed.n_rec * 16, s, rb, ed, ed.rec, q, n, ldq, out);
-    else
-        hipLaunchKernelGGL(k_validate_states<false>, dim3((unsigned)grid), dim3(bs), 0, s, rb, ed,
-                           ed.rec, q, n, ldq, out);
+    const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
+    const size_t base_ = walk_lds_bytes(rb, bs);
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, out
+    VK_STAGED(k_validate_states)
+#undef ARGS_
     return hipGetLastError();
 }
 
@@ -806,79 +949,68 @@ hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, bool lds, const float *qa,
+hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const float *qa,
                                  const float *qb, const int32_t *nst, int64_t n_edges, float res,
                                  uint8_t *out, unsigned long long *queue, int grid, int block,
                                  hipStream_t s, unsigned long long *flops) {
-    const size_t sh = lds ? (size_t)ed.n_rec * 16 : 0;
+    const dim3 grid_(grid), block_(block);
+    const size_t base_ = walk_lds_bytes(rb, block);
+#define ARGS_ rb, ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops
     if (flops) {
-        if (lds)
-            hipLaunchKernelGGL((k_validate_edges<true, true>), dim3(grid), dim3(block), sh, s, rb,
-                               ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops);
-        else
-            hipLaunchKernelGGL((k_validate_edges<false, true>), dim3(grid), dim3(block), sh, s, rb,
-                               ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops);
+        VK_STAGED(k_validate_edges, , true)
     } else {
-        if (lds)
-            hipLaunchKernelGGL((k_validate_edges<true, false>), dim3(grid), dim3(block), sh, s, rb,
-                               ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops);
-        else
-            hipLaunchKernelGGL((k_validate_edges<false, false>), dim3(grid), dim3(block), sh, s, rb,
-                               ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops);
+        VK_STAGED(k_validate_edges, , false)
     }
+#undef ARGS_
     return hipGetLastError();
 }
 
-hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed, bool lds,
-                                    const float *qa, const float *qb, const int32_t *nst,
-                                    int64_t e, float res, uint8_t *out, hipStream_t s) {
-    if (lds)
-        hipLaunchKernelGGL(k_validate_edge_one<true>, dim3(1), dim3(kWave), (size_t)ed.n_rec * 16,
-                           s, rb, ed, ed.rec, qa, qb, nst, e, res, out);
-    else
-        hipLaunchKernelGGL(k_validate_edge_one<false>, dim3(1), dim3(kWave), 0, s, rb, ed, ed.rec,
-                           qa, qb, nst, e, res, out);
+hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed_in, const float *qa,
+                                    const float *qb, const int32_t *nst, int64_t e, float res,
+                                    uint8_t *out, hipStream_t s) {
+    const dim3 grid_(1), block_(kWave);
+    const size_t base_ = walk_lds_bytes(rb, kWave);
+#define ARGS_ rb, ed, ed.rec, qa, qb, nst, e, res, out
+    VK_STAGED(k_validate_edge_one)
+#undef ARGS_
     return hipGetLastError();
 }
 
-hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
-                           int64_t n, int64_t ldq, float *cost, hipStream_t s) {
+hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
+                           int64_t ldq, float *cost, hipStream_t s) {
     const int bs = 256;
-    const int64_t grid = (n + bs - 1) / bs;
-    if (lds)
-        hipLaunchKernelGGL(k_cost_fwd<true>, dim3((unsigned)grid), dim3(bs), (size_t)ed.n_rec * 16,
-                           s, rb, ed, ed.rec, q, n, ldq, cost);
-    else
-        hipLaunchKernelGGL(k_cost_fwd<false>, dim3((unsigned)grid), dim3(bs), 0, s, rb, ed, ed.rec,
-                           q, n, ldq, cost);
+    const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
+    const size_t base_ = walk_lds_bytes(rb, bs);
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, cost
+    VK_STAGED(k_cost_fwd)
+#undef ARGS_
     return hipGetLastError();
 }
 
 size_t cost_bwd_slot_bytes(const RobotDev &rb, int block) {
-    return (size_t)rb.n_links * 6 * kWave * sizeof(float) * (block / kWave);
+    return (size_t)rb.n_links * 6 * kWave * sizeof(float) * (block / kWave) +
+           walk_lds_bytes(rb, block);
 }
 
-hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
-                           int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
-                           int block, hipStream_t s) {
-    const int64_t grid = (n + block - 1) / block;
-    const size_t slots = cost_bwd_slot_bytes(rb, block);
-    if (lds)
-        hipLaunchKernelGGL(k_cost_bwd<true>, dim3((unsigned)grid), dim3(block),
-                           slots + (size_t)ed.n_rec * 16, s, rb, ed, ed.rec, q, n, ldq, gcost, grad,
-                           ldg);
-    else
-        hipLaunchKernelGGL(k_cost_bwd<false>, dim3((unsigned)grid), dim3(block), slots, s, rb, ed,
-                           ed.rec, q, n, ldq, gcost, grad, ldg);
+hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
+                           int64_t ldq, const float *gcost, float *grad, int64_t ldg, int block,
+                           hipStream_t s) {
+    const dim3 grid_((unsigned)((n + block - 1) / block)), block_(block);
+    const size_t base_ = cost_bwd_slot_bytes(rb, block);
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg
+    VK_STAGED(k_cost_bwd)
+#undef ARGS_
     return hipGetLastError();
 }
+#undef VK_STAGED
 
 hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
                                       int64_t total, float res, const float *qa, const float *qb,
                                       uint8_t *out, unsigned long long *queue, int grid, int block,
-                                      hipStream_t s) {
-    hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block), 0, s, sets, prefix, n_sets,
-                       total, res, qa, qb, out, queue);
+                                      int cache_steps, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block),
+                       (size_t)(block / kWave) * step_cache_floats(cache_steps) * sizeof(float), s,
+                       sets, prefix, n_sets, total, res, qa, qb, out, queue, cache_steps);
     return hipGetLastError();
 }
 

@@ -1,4 +1,5 @@
-// Kernel launchers shared between the kernel translation unit and the C-ABI layer.
+// Kernel launchers shared between the kernel translation unit and the C-ABI layer.  The
+// EnvDev passed to a launcher carries in n_stage the number of leading records to stage in LDS.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -8,26 +9,28 @@ namespace vk {
 
 hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int64_t ldq,
                              float *out, int64_t ldc, hipStream_t s);
-hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
+hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const float *q,
                                   int64_t n, int64_t ldq, uint8_t *out, hipStream_t s);
 hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s);
-hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, bool lds, const float *qa,
+hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const float *qa,
                                  const float *qb, const int32_t *nst, int64_t n_edges, float res,
                                  uint8_t *out, unsigned long long *queue, int grid, int block,
                                  hipStream_t s, unsigned long long *flops = nullptr);
-hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed, bool lds,
+hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed,
                                     const float *qa, const float *qb, const int32_t *nst,
                                     int64_t e, float res, uint8_t *out, hipStream_t s);
-hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
+hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, float *cost, hipStream_t s);
 size_t cost_bwd_slot_bytes(const RobotDev &rb, int block);
-hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, bool lds, const float *q,
+// Per-workgroup LDS of the step caches (world centre of every link bound, per wave).
+size_t walk_lds_bytes(const RobotDev &rb, int block);
+hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
                            int block, hipStream_t s);
 
 hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
                                       int64_t total, float res, const float *qa, const float *qb,
                                       uint8_t *out, unsigned long long *queue, int grid, int block,
-                                      hipStream_t s);
+                                      int cache_steps, hipStream_t s);
 
 }  // namespace vk

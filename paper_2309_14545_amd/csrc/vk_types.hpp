@@ -44,15 +44,17 @@ struct StepRec {                   // 48 bytes
     float coarse[4];               // bounding sphere of the step's spheres, link frame
 };
 
-// Self pairs between this step's spheres and the spheres of one earlier link A.  The pose of
-// A is rebuilt into a second register frame by applying path joints (from identity when
-// `restart`, else continuing from the previous block's link, an ancestor of A).
+// Self pairs between this step's spheres and the spheres of one earlier step (on link A).  The
+// earlier step's link bounding sphere (its world centre is kept per lane in LDS) gates the
+// block; only then is A posed into a second register frame, continuing from the frame's
+// current link when that link is an ancestor of A (anc bits), else from the base along the
+// full path of joints.
 struct BlockRec {                  // 48 bytes
-    int32_t restart;
-    int32_t path_off, path_len;
+    int32_t step_a;                // earlier step
+    int32_t path_off, path_len;    // joints from the base to link A, base-most first
     int32_t ent_first, ent_count;
-    int32_t link;
-    int32_t pad0, pad1;
+    int32_t link;                  // A
+    uint32_t anc_lo, anc_hi;       // bit l-1: link l (>= 1) is a proper ancestor of A
     float coarse[4];               // bounding sphere of the block's earlier spheres, A's frame
 };
 
@@ -79,8 +81,11 @@ struct RobotDev {
 //   off_cap   capsules  2 x float4: (p0, radius), (u = p1 - p0, 1 / (u . u) or 0)
 //   off_cyl   cylinders 2 x float4: (centre, half height), (unit axis, radius)
 //   off_box   boxes     4 x float4: (col_0 of R, e_0), (col_1, e_1), (col_2, e_2), (centre, 0)
-//   off_vdist voxel distance bytes (16 per record), then the point-grid cell index
-// The record buffer is what a workgroup stages in LDS.
+//   off_cell  point-grid cell index (cell_start, n_cells + 1 ints, four per record)
+//   off_vdist voxel distance bytes (16 per record)
+// A launch stages a prefix of the buffer in LDS: the primitives and the cell index when they
+// fit, else the primitives alone.  The byte field is always read from global memory: one byte
+// per lane and link is not worth the LDS (and so the occupancy) it would take.
 //
 // Voxel broadphase over the primitives: a uniform grid covering every point within `vcap` of
 // a primitive.  For each cell, vlist[vstart[c] .. vstart[c+1]) lists every primitive whose
@@ -89,18 +94,17 @@ struct RobotDev {
 // bound of the cell, rounded down to multiples of vq (255 = nothing closer than vcap).
 struct EnvDev {
     const float4 *rec;
-    int32_t off_sph, off_cap, off_cyl, off_box, off_vdist, n_rec;
+    int32_t off_sph, off_cap, off_cyl, off_box, off_cell, off_vdist, n_rec;
+    int32_t n_stage;               // leading records a launch stages in LDS (set per launch)
     int32_t n_sph, n_cap, n_cyl, n_box;
     const int32_t *vstart;         // [n_vox + 1]
     const int2 *vlist;
     int32_t vdim[3], n_vox;
     float vorg[3], vinv, vq, vcap;
     // Uniform grid over a large set of small spheres (point clouds); n_cells == 0 when absent.
-    // The cell index (cell_start, n_cells + 1 ints, four per record) is part of the record
-    // buffer at off_cell, so it is staged in LDS with the rest; the points themselves, sorted by
+    // The cell index is part of the record buffer at off_cell; the points themselves, sorted by
     // cell, stay in global memory (L2).
     const float4 *grid_pts;        // [n_pts] centre, radius
-    int32_t off_cell;
     int32_t n_cells, n_pts;
     int32_t gdim[3];
     float gorg[3];
