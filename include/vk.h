@@ -142,12 +142,12 @@ vk_status validate_edges_per_edge(vk_robot robot, vk_env env, const float *qa, c
 
 /* Measurement variant of validate_edges: the same flags from the same kernel code, which in
  * addition adds to flops[0..4] (five device uint64, not cleared by the call) the FP32
- * operations the launch executed: per wave-uniform step the model's count (fused multiply-add
- * = 2; revolute joint 30, mount 63, sphere placement 18, sphere-sphere and self pair 11,
- * capsule 25, box 34, cylinder 35) times the 64 lanes that issue it.  flops[0] is the total;
- * flops[1..4] split it into FK and sphere placement, culling (bounding-sphere tests), fine
- * environment tests and self pairs.  Early exits and skipped tests are thereby excluded; masked
- * lanes are included. */
+ * operations the launch executed, by the model's count per operation (fused multiply-add = 2;
+ * revolute joint 30, mount 63, sphere placement 18, sphere-sphere and self pair 11, capsule 25,
+ * box 34, cylinder 35), summed over the lanes that execute it.  flops[0] is the total;
+ * flops[1..4] split it into FK and sphere placement, culling (voxel lookups and link
+ * bounding-sphere tests), fine environment tests and self pairs (with re-posing).  Early exits,
+ * skipped tests and lanes masked off by divergent control flow add nothing. */
 vk_status validate_edges_counted(vk_robot robot, vk_env env, const float *qa, const float *qb,
                                  const int32_t *n_states, int64_t n_edges, float resolution,
                                  uint8_t *collide, uint64_t *flops, void *stream);

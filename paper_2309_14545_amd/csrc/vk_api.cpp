@@ -317,6 +317,15 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
                 E.z = x[2];
                 E.r = x[3];
                 E.mask = tm.second;
+                // entry gate against this step's bound, and the pair constants (see the self
+                // test of the walk): r r_k for paired spheres, -inf for the others
+                const double g = (double)x[3] + (double)steps[si].coarse[3];
+                E.gate2 = std::nextafter((float)(g * g), INFINITY);
+                E.nhr2 = (float)(-0.5 * (double)x[3] * (double)x[3]);
+                for (int k = 0; k < kSpl; ++k)
+                    E.rr[k] = (k < steps[si].sph_count && ((tm.second >> k) & 1u))
+                                  ? x[3] * d->sphere_xyzr[4 * (steps[si].sph_first + k) + 3]
+                                  : -INFINITY;
                 entries.push_back(E);
                 sp.push_back(x);
             }

@@ -384,7 +384,16 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         }
 
         // self pairs completed by this step: gate each block with the earlier step's link
-        // bounding sphere (cached centre), then pose its link into Ta and test the pairs
+        // bounding sphere (cached centre), then pose its link into Ta, gate each of its spheres
+        // with this step's bounding sphere, and test the pairs of those that pass.  The pair
+        // test runs relative to this step's bound centre C: with u_k = c_k - C and t' = t - C,
+        //   |t' - u_k| < r_t + r_k  <=>  t'.u_k + al_k + r_t r_k > (|t'|^2 - r_t^2) / 2,
+        //   al_k = (r_k^2 - |u_k|^2) / 2,
+        // so a pair costs three FMAs, an add and a max; r_t r_k comes with the entry (-inf for
+        // pairs not in its mask).  |t'| and |u_k| are at most a few link lengths, so the
+        // rounding of the expanded form stays near 1e-7 m^2.
+        bool rel = false;
+        float al[kSpl];
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec &B = rb.blocks[S.blk_first + b];
             float ax, ay, az;
@@ -394,21 +403,37 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
             work.add(flop::kSelf, flop::kPair);
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
             VK_PLACE()
-            pose_block(rb, B, Ta, ta_link, ta_depth, q, work);
-            for (int e = 0; e < B.ent_count; ++e) {
-                const EntryRec &E = rb.entries[B.ent_first + e];
-                float tx, ty, tz;
-                frame_point(Ta, E.x, E.y, E.z, tx, ty, tz);
-                work.add(flop::kSelf, flop::kPlace + flop::kPair * __builtin_popcount(E.mask));
+            if (!rel) {
 #pragma unroll
                 for (int k = 0; k < kSpl; ++k) {
-                    if ((E.mask >> k) & 1u) {
-                        const float ex = tx - cx[k], ey = ty - cy[k], ez = tz - cz[k];
-                        const float s = E.r + cr[k];
-                        col |= fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < s * s;
-                    }
+                    cx[k] -= Cx;
+                    cy[k] -= Cy;
+                    cz[k] -= Cz;
+                    al[k] = fmaf(-0.5f, fmaf(cx[k], cx[k], fmaf(cy[k], cy[k], cz[k] * cz[k])),
+                                 0.5f * cr[k] * cr[k]);
                 }
+                rel = true;
             }
+            pose_block(rb, B, Ta, ta_link, ta_depth, q, work);
+            const float ox = Ta.p[0] - Cx, oy = Ta.p[1] - Cy, oz = Ta.p[2] - Cz;
+            float D = -INFINITY;
+            for (int e = 0; e < B.ent_count; ++e) {
+                const EntryRec &E = rb.entries[B.ent_first + e];
+                const float tx = fmaf(Ta.r[0], E.x, fmaf(Ta.r[1], E.y, fmaf(Ta.r[2], E.z, ox)));
+                const float ty = fmaf(Ta.r[3], E.x, fmaf(Ta.r[4], E.y, fmaf(Ta.r[5], E.z, oy)));
+                const float tz = fmaf(Ta.r[6], E.x, fmaf(Ta.r[7], E.y, fmaf(Ta.r[8], E.z, oz)));
+                const float t2 = fmaf(tx, tx, fmaf(ty, ty, tz * tz));
+                work.add(flop::kSelf, flop::kPlace + flop::kPair);
+                if (!wave_ballot(live && t2 < E.gate2)) continue;
+                float M = -INFINITY;
+#pragma unroll
+                for (int k = 0; k < kSpl; ++k)
+                    if (k < cnt)
+                        M = fmaxf(M, fmaf(tx, cx[k], fmaf(ty, cy[k], fmaf(tz, cz[k], al[k]))) + E.rr[k]);
+                work.add(flop::kSelf, flop::kPair * __builtin_popcount(E.mask));
+                D = fmaxf(D, M - fmaf(0.5f, t2, E.nhr2));
+            }
+            col |= D > 0.0f;
             if (EDGE) {
                 if (wave_ballot(col)) return true;
             } else {

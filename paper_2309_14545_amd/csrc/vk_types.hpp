@@ -59,10 +59,13 @@ struct BlockRec {                  // 48 bytes
 };
 
 // One earlier sphere t of a block and the mask of this step's spheres it is paired with.
-struct EntryRec {                  // 32 bytes
+struct EntryRec {                  // 64 bytes (one scalar load)
     float x, y, z, r;              // centre in A's frame, radius
     uint32_t mask;                 // bit k: paired with the step's k-th sphere
-    uint32_t pad[3];
+    float gate2;                   // (r + R)^2, R the step's link bounding radius (rounded up)
+    float nhr2;                    // -r^2 / 2
+    float pad;
+    float rr[kSpl];                // r * r_k for paired spheres k, -inf otherwise
 };
 
 struct RobotDev {
