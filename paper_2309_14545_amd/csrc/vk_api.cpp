@@ -336,7 +336,7 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
         steps[si].blk_count = (int)blocks.size() - steps[si].blk_first;
     }
 
-    std::vector<float4> spheres(S);
+    std::vector<float4> spheres(S + kSpl, make_float4(0, 0, 0, 0));   // kSpl padding records
     for (int s = 0; s < S; ++s)
         spheres[s] = make_float4(d->sphere_xyzr[4 * s], d->sphere_xyzr[4 * s + 1],
                                  d->sphere_xyzr[4 * s + 2], d->sphere_xyzr[4 * s + 3]);

@@ -23,13 +23,29 @@
 
 namespace vk {
 
+// The robot program and the batch descriptors are never written while a kernel runs.  Reading
+// them through the constant address space lets every wave-uniform access compile to a scalar
+// load; through a generic pointer the stores elsewhere in a kernel (flags, queue) can force
+// vector loads of uniform data.  A record is copied word by word and unused words fold away.
+template <class T>
+__device__ __forceinline__ T ld(const T *p, int64_t i) {
+    static_assert(sizeof(T) % 4 == 0, "records are whole words");
+    T out;
+    const __attribute__((address_space(4))) uint32_t *src =
+        (const __attribute__((address_space(4))) uint32_t *)(p + i);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(T) / 4); ++w) dst[w] = src[w];
+    return out;
+}
+
 // Joint value sources ------------------------------------------------------------------------
 struct QEdge {                 // state on a straight edge: qa + t (qb - qa), qa/qb uniform
     const float *a;            // (t = 1 gives qb exactly, so both endpoints are the inputs)
     const float *b;
     float t;
     __device__ __forceinline__ float operator()(int j) const {
-        const float x = a[j], y = b[j];
+        const float x = ld(a, j), y = ld(b, j);
         return t == 1.0f ? y : fmaf(t, y - x, x);
     }
 };
@@ -154,13 +170,15 @@ __device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, 
     if (S.restart_len >= 0) {
         frame_identity(T);
         for (int k = 0; k < S.restart_len; ++k) {
-            const int j = rb.paths[S.restart_off + k];
-            frame_joint(T, rb.joints[j], q(j));
-            w.add(flop::kFk, flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
+            const int j = ld(rb.paths, S.restart_off + k);
+            const JointRec J = ld(rb.joints, j);
+            frame_joint(T, J, q(j));
+            w.add(flop::kFk, flop::kJoint + (J.has_mount ? flop::kMount : 0));
         }
     }
-    frame_joint(T, rb.joints[S.joint], q(S.joint));
-    w.add(flop::kFk, flop::kJoint + (rb.joints[S.joint].has_mount ? flop::kMount : 0));
+    const JointRec J = ld(rb.joints, S.joint);
+    frame_joint(T, J, q(S.joint));
+    w.add(flop::kFk, flop::kJoint + (J.has_mount ? flop::kMount : 0));
 }
 
 // Pose the earlier link A of self block B into Ta.  Ta holds link `ta_link` (depth `ta_depth`
@@ -179,26 +197,30 @@ __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B
         k0 = 0;
     }
     for (int k = k0; k < B.path_len; ++k) {
-        const int j = rb.paths[B.path_off + k];
-        frame_joint(Ta, rb.joints[j], q(j));
-        w.add(flop::kSelf, flop::kJoint + (rb.joints[j].has_mount ? flop::kMount : 0));
+        const int j = ld(rb.paths, B.path_off + k);
+        const JointRec J = ld(rb.joints, j);
+        frame_joint(Ta, J, q(j));
+        w.add(flop::kSelf, flop::kJoint + (J.has_mount ? flop::kMount : 0));
     }
     ta_link = B.link;
     ta_depth = B.path_len;
 }
 
-// Sphere centres of a step from its link frame (placed lazily, when a test needs them).
+// Sphere centres of a step from its link frame (placed lazily, when a test needs them).  All
+// kSpl slots are loaded and placed without branches (the sphere array carries kSpl records of
+// padding): slots k >= sph_count hold finite values with radius 0 and every consumer either
+// skips them or, in the self test, neutralises them with a -inf pair constant.
 __device__ __forceinline__ void place_step(const RobotDev &rb, const StepRec &S, const Frame &T,
                                            float (&cx)[kSpl], float (&cy)[kSpl],
                                            float (&cz)[kSpl], float (&cr)[kSpl]) {
+    const float4 *sp = rb.spheres + S.sph_first;
+    float4 sv[kSpl];
+#pragma unroll
+    for (int k = 0; k < kSpl; ++k) sv[k] = ld(sp, k);
 #pragma unroll
     for (int k = 0; k < kSpl; ++k) {
-        cx[k] = cy[k] = cz[k] = cr[k] = 0.0f;
-        if (k < S.sph_count) {
-            const float4 s = rb.spheres[S.sph_first + k];
-            frame_point(T, s.x, s.y, s.z, cx[k], cy[k], cz[k]);
-            cr[k] = s.w;
-        }
+        frame_point(T, sv[k].x, sv[k].y, sv[k].z, cx[k], cy[k], cz[k]);
+        cr[k] = k < S.sph_count ? sv[k].w : 0.0f;
     }
 }
 
@@ -297,7 +319,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
     bool live = !col;
     if (!EDGE && !wave_ballot(live)) return col;
     for (int st = 0; st < rb.n_steps; ++st) {
-        const StepRec &S = rb.steps[st];
+        const StepRec S = ld(rb.steps, st);
         pose_step(rb, S, Tm, q, work);
         const int cnt = S.sph_count;
         if (cnt == 0) continue;
@@ -395,41 +417,42 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         bool rel = false;
         float al[kSpl];
         for (int b = 0; b < S.blk_count; ++b) {
-            const BlockRec &B = rb.blocks[S.blk_first + b];
+            const BlockRec B = ld(rb.blocks, S.blk_first + b);
             float ax, ay, az;
             sc.get(B.step_a, ax, ay, az);
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
-            const float rr = rb.steps[B.step_a].coarse[3] + CR;
+            const float rr = ld(rb.steps, B.step_a).coarse[3] + CR;
             work.add(flop::kSelf, flop::kPair);
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
-            VK_PLACE()
-            if (!rel) {
-#pragma unroll
-                for (int k = 0; k < kSpl; ++k) {
-                    cx[k] -= Cx;
-                    cy[k] -= Cy;
-                    cz[k] -= Cz;
-                    al[k] = fmaf(-0.5f, fmaf(cx[k], cx[k], fmaf(cy[k], cy[k], cz[k] * cz[k])),
-                                 0.5f * cr[k] * cr[k]);
-                }
-                rel = true;
-            }
             pose_block(rb, B, Ta, ta_link, ta_depth, q, work);
             const float ox = Ta.p[0] - Cx, oy = Ta.p[1] - Cy, oz = Ta.p[2] - Cz;
             float D = -INFINITY;
+            const EntryRec *ep = rb.entries + B.ent_first;
             for (int e = 0; e < B.ent_count; ++e) {
-                const EntryRec &E = rb.entries[B.ent_first + e];
+                const EntryRec E = ld(ep, e);
                 const float tx = fmaf(Ta.r[0], E.x, fmaf(Ta.r[1], E.y, fmaf(Ta.r[2], E.z, ox)));
                 const float ty = fmaf(Ta.r[3], E.x, fmaf(Ta.r[4], E.y, fmaf(Ta.r[5], E.z, oy)));
                 const float tz = fmaf(Ta.r[6], E.x, fmaf(Ta.r[7], E.y, fmaf(Ta.r[8], E.z, oz)));
                 const float t2 = fmaf(tx, tx, fmaf(ty, ty, tz * tz));
                 work.add(flop::kSelf, flop::kPlace + flop::kPair);
                 if (!wave_ballot(live && t2 < E.gate2)) continue;
+                if (!rel) {                      // this step's spheres, relative to C
+                    VK_PLACE()
+#pragma unroll
+                    for (int k = 0; k < kSpl; ++k) {
+                        cx[k] -= Cx;
+                        cy[k] -= Cy;
+                        cz[k] -= Cz;
+                        al[k] = fmaf(-0.5f, fmaf(cx[k], cx[k], fmaf(cy[k], cy[k], cz[k] * cz[k])),
+                                     0.5f * cr[k] * cr[k]);
+                    }
+                    rel = true;
+                }
+                // every slot: unpaired and unused ones carry rr = -inf
                 float M = -INFINITY;
 #pragma unroll
                 for (int k = 0; k < kSpl; ++k)
-                    if (k < cnt)
-                        M = fmaxf(M, fmaf(tx, cx[k], fmaf(ty, cy[k], fmaf(tz, cz[k], al[k]))) + E.rr[k]);
+                    M = fmaxf(M, fmaf(tx, cx[k], fmaf(ty, cy[k], fmaf(tz, cz[k], al[k]))) + E.rr[k]);
                 work.add(flop::kSelf, flop::kPair * __builtin_popcount(E.mask));
                 D = fmaxf(D, M - fmaf(0.5f, t2, E.nhr2));
             }
@@ -458,11 +481,11 @@ __global__ void __launch_bounds__(256) k_fk_spheres(RobotDev rb, const float *__
     Frame T;
     frame_identity(T);
     for (int st = 0; st < rb.n_steps; ++st) {
-        const StepRec &S = rb.steps[st];
+        const StepRec S = ld(rb.steps, st);
         pose_step(rb, S, T, qs);
         for (int k = 0; k < S.sph_count; ++k) {
             const int s = S.sph_first + k;
-            const float4 l = rb.spheres[s];
+            const float4 l = ld(rb.spheres, s);
             float x, y, z;
             frame_point(T, l.x, l.y, l.z, x, y, z);
             if (active) {
@@ -505,7 +528,7 @@ __device__ __forceinline__ int edge_count(const float *a, const float *b, int do
     // n = max(2, ceil(L / res) + 1), L = max_j |b_j - a_j| in double: the difference of two
     // floats is exact in double, so this matches a double-precision evaluation bit for bit.
     double L = 0.0;
-    for (int j = 0; j < dof; ++j) L = fmax(L, fabs((double)b[j] - (double)a[j]));
+    for (int j = 0; j < dof; ++j) L = fmax(L, fabs((double)ld(b, j) - (double)ld(a, j)));
     const double n = ceil(L / (double)res) + 1.0;
     return n < 2.0 ? 2 : (n > 2147483647.0 ? 2147483647 : (int)n);
 }
@@ -515,7 +538,7 @@ __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, co
                                              const StepCache &sc, const float *a, const float *b,
                                              int n, W &&work = W()) {
     bool bad = false;
-    for (int j = 0; j < rb.dof; ++j) bad |= !isfinite(a[j]) || !isfinite(b[j]);
+    for (int j = 0; j < rb.dof; ++j) bad |= !isfinite(ld(a, j)) || !isfinite(ld(b, j));
     if (bad) return 1;
     if (n < 2) n = 2;
     const int lane = threadIdx.x & (kWave - 1);
@@ -564,7 +587,7 @@ __global__ void __launch_bounds__(256)
         if (e >= n_edges) break;
         const float *a = qa + e * rb.dof;
         const float *b = qb + e * rb.dof;
-        const int n = nst ? nst[e] : edge_count(a, b, rb.dof, res);
+        const int n = nst ? ld(nst, e) : edge_count(a, b, rb.dof, res);
         const uint8_t hit = edge_body(rb, ev, ed, sc, a, b, n, work);
         out[e] = hit;                         // wave-uniform value, same address in every lane
     }
@@ -593,7 +616,7 @@ __global__ void __launch_bounds__(64)
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const float *a = qa + e * rb.dof;
     const float *b = qb + e * rb.dof;
-    const int n = nst ? nst[e] : edge_count(a, b, rb.dof, res);
+    const int n = nst ? ld(nst, e) : edge_count(a, b, rb.dof, res);
     const uint8_t hit = edge_body(rb, ev, ed, sc, a, b, n);
     out[e] = hit;                             // wave-uniform value
 }
@@ -615,10 +638,10 @@ __global__ void __launch_bounds__(256)
         int lo = 0, hi = n_sets - 1;          // last set whose first edge is <= e
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (prefix[mid] <= e) lo = mid; else hi = mid - 1;
+            if (ld(prefix, mid) <= e) lo = mid; else hi = mid - 1;
         }
-        const BatchSet &S = sets[lo];
-        const int64_t local = e - prefix[lo];
+        const BatchSet S = ld(sets, lo);
+        const int64_t local = e - ld(prefix, lo);
         const float *a = qa + S.qa_offset + local * S.rb.dof;
         const float *b = qb + S.qa_offset + local * S.rb.dof;
         const int n = edge_count(a, b, S.rb.dof, res);
@@ -690,7 +713,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
     int ta_link = 0, ta_depth = 0;
     float cost = 0.0f;
     for (int st = 0; st < rb.n_steps; ++st) {
-        const StepRec &S = rb.steps[st];
+        const StepRec S = ld(rb.steps, st);
         pose_step(rb, S, Tm, q);
         const int cnt = S.sph_count;
         if (cnt == 0) continue;
@@ -700,7 +723,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
             cx[k] = cy[k] = cz[k] = cr[k] = 0.0f;
             fx[k] = fy[k] = fz[k] = 0.0f;
             if (k < cnt) {
-                const float4 s = rb.spheres[S.sph_first + k];
+                const float4 s = ld(rb.spheres, S.sph_first + k);
                 frame_point(Tm, s.x, s.y, s.z, cx[k], cy[k], cz[k]);
                 cr[k] = s.w;
             }
@@ -755,15 +778,15 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
             }
         }
         for (int b = 0; b < S.blk_count; ++b) {
-            const BlockRec &B = rb.blocks[S.blk_first + b];
+            const BlockRec B = ld(rb.blocks, S.blk_first + b);
             float ax, ay, az;
             sc.get(B.step_a, ax, ay, az);
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
-            const float rr = rb.steps[B.step_a].coarse[3] + CR;
+            const float rr = ld(rb.steps, B.step_a).coarse[3] + CR;
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
             pose_block(rb, B, Ta, ta_link, ta_depth, q);
             for (int e = 0; e < B.ent_count; ++e) {
-                const EntryRec &E = rb.entries[B.ent_first + e];
+                const EntryRec E = ld(rb.entries, B.ent_first + e);
                 float tx, ty, tz;
                 frame_point(Ta, E.x, E.y, E.z, tx, ty, tz);
                 float gtx = 0.0f, gty = 0.0f, gtz = 0.0f;
@@ -850,7 +873,7 @@ __global__ void __launch_bounds__(256)
 
     // suffix sums: child link totals into the parent (parents have smaller indices)
     for (int l = rb.n_links - 1; l >= 1; --l) {
-        const int p = rb.joints[l - 1].parent;
+        const int p = ld(rb.joints, l - 1).parent;
 #pragma unroll
         for (int c = 0; c < 6; ++c) slots.at(p, c) += slots.at(l, c);
     }
@@ -860,17 +883,17 @@ __global__ void __launch_bounds__(256)
     frame_identity(T);
     int cur = 0;                               // link whose pose T holds
     for (int j = 0; j < rb.dof; ++j) {
-        const JointRec &J = rb.joints[j];
+        const JointRec J = ld(rb.joints, j);
         if (J.parent != cur) {
             // rebuild the parent's pose from the base along the restart path of the step
             // that poses link j+1 (stored with that step)
             frame_identity(T);
             for (int s = 0; s < rb.n_steps; ++s) {
-                const StepRec &S = rb.steps[s];
+                const StepRec S = ld(rb.steps, s);
                 if (S.joint == j) {
                     for (int k = 0; k < S.restart_len; ++k) {
-                        const int jj = rb.paths[S.restart_off + k];
-                        frame_joint(T, rb.joints[jj], qs(jj));
+                        const int jj = ld(rb.paths, S.restart_off + k);
+                        frame_joint(T, ld(rb.joints, jj), qs(jj));
                     }
                     break;
                 }
