@@ -15,6 +15,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # wave-level atomics (queue tickets, work counters) reduce across lanes with DPP instead of
+    # a per-lane scan loop
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -91,7 +91,7 @@ unsigned long long *queue_for(int dev, hipStream_t s) {
     auto it = g_queues.find(key);
     if (it != g_queues.end()) return it->second;
     void *p = nullptr;
-    hip_check(hipMalloc(&p, 256), "queue counter");
+    hip_check(hipMalloc(&p, kQueueBytes), "queue counters");
     return g_queues[key] = static_cast<unsigned long long *>(p);
 }
 
@@ -141,6 +141,106 @@ void bounding_sphere(const std::vector<const float *> &sph, float out[4]) {
     }
     for (int a = 0; a < 3; ++a) out[a] = (float)c[a];
     out[3] = std::nextafter((float)(R + 1e-5), INFINITY);
+}
+
+// Distance from point x to the segment p + s u, s in [0, 1] (double).
+double point_segment(const double x[3], const double p[3], const double u[3]) {
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double s = 0.0;
+    if (uu > 0.0) s = std::min(1.0, std::max(0.0, ((x[0] - p[0]) * u[0] + (x[1] - p[1]) * u[1] +
+                                                  (x[2] - p[2]) * u[2]) / uu));
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double v = x[a] - p[a] - s * u[a];
+        d2 += v * v;
+    }
+    return std::sqrt(d2);
+}
+
+// Bounding capsule of a set of spheres: the axis is the principal direction of the centres
+// (power iteration on their covariance) or, if tighter, the line through the two farthest
+// centres; the segment spans the centres' projections.  Written to a StepRec.
+void bounding_capsule(const std::vector<const float *> &sph, StepRec &st) {
+    const size_t n = sph.size();
+    auto fit = [&](const double axis[3], double p[3], double u[3]) {
+        double c[3] = {0, 0, 0};
+        for (const float *s : sph)
+            for (int a = 0; a < 3; ++a) c[a] += s[a] / (double)n;
+        double lo = 1e300, hi = -1e300;
+        for (const float *s : sph) {
+            const double t = (s[0] - c[0]) * axis[0] + (s[1] - c[1]) * axis[1] + (s[2] - c[2]) * axis[2];
+            lo = std::min(lo, t);
+            hi = std::max(hi, t);
+        }
+        double r = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            p[a] = c[a] + lo * axis[a];
+            u[a] = (hi - lo) * axis[a];
+        }
+        for (const float *s : sph) {
+            const double x[3] = {s[0], s[1], s[2]};
+            r = std::max(r, point_segment(x, p, u) + s[3]);
+        }
+        return r;
+    };
+    double best_p[3] = {0, 0, 0}, best_u[3] = {0, 0, 0}, best_r = 1e300;
+    std::vector<std::array<double, 3>> axes;
+    {   // principal direction
+        double c[3] = {0, 0, 0}, C[3][3] = {{0}};
+        for (const float *s : sph)
+            for (int a = 0; a < 3; ++a) c[a] += s[a] / (double)n;
+        for (const float *s : sph)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) C[a][b] += (s[a] - c[a]) * (s[b] - c[b]);
+        double v[3] = {1.0, 0.7, 0.3};
+        for (int it = 0; it < 200; ++it) {
+            double w[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) w[a] += C[a][b] * v[b];
+            const double nw = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+            if (!(nw > 0.0)) break;
+            for (int a = 0; a < 3; ++a) v[a] = w[a] / nw;
+        }
+        const double nv = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        axes.push_back({v[0] / nv, v[1] / nv, v[2] / nv});
+    }
+    {   // farthest pair of centres
+        double best = 0.0, ax[3] = {1, 0, 0};
+        for (size_t i = 0; i < n; ++i)
+            for (size_t j = i + 1; j < n; ++j) {
+                double d[3], dd = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    d[a] = (double)sph[j][a] - sph[i][a];
+                    dd += d[a] * d[a];
+                }
+                if (dd > best) {
+                    best = dd;
+                    for (int a = 0; a < 3; ++a) ax[a] = d[a] / std::sqrt(dd);
+                }
+            }
+        axes.push_back({ax[0], ax[1], ax[2]});
+    }
+    for (const auto &ax : axes) {
+        double p[3], u[3];
+        const double r = fit(ax.data(), p, u);
+        if (r < best_r) {
+            best_r = r;
+            for (int a = 0; a < 3; ++a) {
+                best_p[a] = p[a];
+                best_u[a] = u[a];
+            }
+        }
+    }
+    double uu = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        st.cap_p[a] = (float)best_p[a];
+        st.cap_u[a] = (float)best_u[a];
+        uu += (double)st.cap_u[a] * st.cap_u[a];
+    }
+    // the float-rounded segment moves by at most a few 1e-8 m; the 1 mm padding covers it
+    st.cap_r = std::nextafter((float)(best_r + 1e-3), INFINITY);
+    st.cap_uu = (float)uu;
+    st.cap_inv = uu > 0.0 ? (float)(1.0 / uu) : 0.0f;
 }
 
 }  // namespace
@@ -267,6 +367,7 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
                 sphere_k[st.sph_first + k] = k;
             }
             bounding_sphere(sp, st.coarse);
+            if (!sp.empty()) bounding_capsule(sp, st);
             steps.push_back(st);
         }
         if (l == 0 && count[0] == 0) steps.pop_back();   // nothing to do on an empty base
@@ -912,7 +1013,7 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             const size_t o_p = bl.add(prefix.data(), prefix.size() * sizeof(int64_t));
             bt->blob = bl.upload();
             void *q = nullptr;
-            hip_check(hipMalloc(&q, 256), "batch queue");
+            hip_check(hipMalloc(&q, kQueueBytes), "batch queue");
             bt->queue = static_cast<unsigned long long *>(q);
             const BatchSet *d_sets = reinterpret_cast<const BatchSet *>(static_cast<char *>(bt->blob) + o_s);
             const int64_t *d_pre = reinterpret_cast<const int64_t *>(static_cast<char *>(bt->blob) + o_p);

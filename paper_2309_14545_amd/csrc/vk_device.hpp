@@ -79,6 +79,13 @@ __device__ __forceinline__ void frame_point(const Frame &T, float x, float y, fl
     oz = fmaf(T.r[6], x, fmaf(T.r[7], y, fmaf(T.r[8], z, T.p[2])));
 }
 
+__device__ __forceinline__ void frame_rotate(const Frame &T, float x, float y, float z, float &ox,
+                                             float &oy, float &oz) {
+    ox = fmaf(T.r[0], x, fmaf(T.r[1], y, T.r[2] * z));
+    oy = fmaf(T.r[3], x, fmaf(T.r[4], y, T.r[5] * z));
+    oz = fmaf(T.r[6], x, fmaf(T.r[7], y, T.r[8] * z));
+}
+
 // ---------------------------------------------------------------------------------------
 // Overlap tests of a robot sphere (centre c, radius r > 0) with one primitive.  Collision
 // means clearance sd(c) - r < 0; each test is that inequality rewritten without a square

@@ -152,6 +152,8 @@ __device__ __forceinline__ void stage_env(float4 *lds, const float4 *__restrict_
 namespace flop {
 constexpr uint32_t kJoint = 30, kMount = 63, kPlace = 18, kSphere = 11, kCapsule = 25,
                    kCylinder = 35, kBox = 34, kPair = 11;
+// sphere against a segment-swept sphere (capsule) bound, and placing a capsule bound's segment
+constexpr uint32_t kSphereCapsule = 25, kPlaceSegment = 33;
 enum Cat { kFk = 0, kCull = 1, kFine = 2, kSelf = 3 };
 }
 struct NoWork {
@@ -414,16 +416,34 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         // so a pair costs three FMAs, an add and a max; r_t r_k comes with the entry (-inf for
         // pairs not in its mask).  |t'| and |u_k| are at most a few link lengths, so the
         // rounding of the expanded form stays near 1e-7 m^2.
-        bool rel = false;
+        bool rel = false, seg = false;
         float al[kSpl];
+        float px = 0.0f, py = 0.0f, pz = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f;
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec B = ld(rb.blocks, S.blk_first + b);
             float ax, ay, az;
             sc.get(B.step_a, ax, ay, az);
+            const float RA = ld(rb.steps, B.step_a).coarse[3];
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
-            const float rr = ld(rb.steps, B.step_a).coarse[3] + CR;
+            const float rr = RA + CR;
             work.add(flop::kSelf, flop::kPair);
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
+            // second gate, still without posing A: A's bounding sphere against this step's
+            // bounding capsule (segment placed once per step)
+            if (!seg) {
+                frame_point(Tm, S.cap_p[0], S.cap_p[1], S.cap_p[2], px, py, pz);
+                frame_rotate(Tm, S.cap_u[0], S.cap_u[1], S.cap_u[2], ux, uy, uz);
+                work.add(flop::kSelf, flop::kPlaceSegment);
+                seg = true;
+            }
+            {
+                const float rx = ax - px, ry = ay - py, rz = az - pz;
+                const float t = fminf(fmaxf(fmaf(rx, ux, fmaf(ry, uy, rz * uz)) * S.cap_inv, 0.0f), 1.0f);
+                const float ex = fmaf(-t, ux, rx), ey = fmaf(-t, uy, ry), ez = fmaf(-t, uz, rz);
+                const float rc = RA + S.cap_r;
+                work.add(flop::kSelf, flop::kSphereCapsule);
+                if (!wave_ballot(live && fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rc * rc)) continue;
+            }
             pose_block(rb, B, Ta, ta_link, ta_depth, q, work);
             const float ox = Ta.p[0] - Cx, oy = Ta.p[1] - Cy, oz = Ta.p[2] - Cz;
             float D = -INFINITY;
@@ -554,26 +574,75 @@ __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, co
     return 0;
 }
 
-// Work-queue pull with no lane-dependent branch: every lane executes the atomic, lane 0 adds 1
-// and the others add 0, so lane 0's returned ticket is the wave's item and the first active
-// lane (lane 0; the whole wave is active here) broadcasts it.  Keeping lane-dependent control
-// flow out of the persistent loop matters: a lane-0-only `if` around the atomic can be
-// threaded by the compiler across iterations, after which the broadcast reads a lane that
-// never took a ticket.
-__device__ __forceinline__ int64_t next_item(unsigned long long *queue, int lane) {
-    const unsigned long long t = atomicAdd(queue, lane == 0 ? 1ull : 0ull);
-    const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)t);
-    const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)(t >> 32));
-    return (int64_t)(((unsigned long long)hi << 32) | lo);
+// Ticket from a counter with no lane-dependent branch: every lane executes the atomic, lane 0
+// adds 1 and the others add 0, so lane 0's returned value is the wave's ticket, broadcast from
+// the first active lane (lane 0; the whole wave is active here).  Keeping lane-dependent control
+// flow out of the persistent loop matters: a lane-0-only `if` around the atomic can be threaded
+// by the compiler across iterations, after which the broadcast reads a lane that never took a
+// ticket.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)v);
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
 }
 
+__device__ __forceinline__ unsigned long long take_ticket(unsigned long long *ctr, int lane) {
+    return uniform_u64(atomicAdd(ctr, lane == 0 ? 1ull : 0ull));
+}
+
+// Persistent work distribution.  The items [0, n) are split into kQueues equal parts; part p is
+// handed out in chunks of `chunk` items by the counter at queue[p * kQueueWords].  A wave starts
+// at part (workgroup index mod kQueues) -- consecutive workgroups are placed on different XCDs,
+// so the waves of one XCD mostly share a counter and no counter serialises the whole chip -- and
+// moves to the next part once its part is drained.  A part visited after the home part is first
+// read with a plain atomic load, so drained parts cost no read-modify-write.  A wave leaves each
+// part at most once, so the loop ends after at most kQueues drained parts.
+struct Puller {
+    unsigned long long *queue;
+    int64_t n;
+    int chunk, part, left;
+};
+
+__device__ __forceinline__ Puller make_puller(unsigned long long *queue, int64_t n, int chunk) {
+    return Puller{queue, n, chunk, (int)(blockIdx.x % kQueues), kQueues};
+}
+
+__device__ __forceinline__ bool pull(Puller &p, int lane, int64_t &first, int64_t &count) {
+    while (p.left > 0) {
+        const int64_t lo = p.n * p.part / kQueues, hi = p.n * (p.part + 1) / kQueues;
+        unsigned long long *ctr = p.queue + (size_t)p.part * kQueueWords;
+        bool open = true;
+        if (p.left < kQueues) {
+            const unsigned long long seen =
+                uniform_u64(__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            open = (int64_t)seen * p.chunk < hi - lo;
+        }
+        if (open) {
+            const int64_t f = (int64_t)take_ticket(ctr, lane) * p.chunk;
+            if (f < hi - lo) {
+                first = lo + f;
+                count = hi - lo - f < p.chunk ? hi - lo - f : p.chunk;
+                return true;
+            }
+        }
+        p.part = p.part + 1 == kQueues ? 0 : p.part + 1;
+        --p.left;
+    }
+    return false;
+}
+
+// Waves per SIMD the persistent edge kernel is compiled for (register budget 512 / waves).
+#ifndef VK_EDGE_WAVES
+#define VK_EDGE_WAVES 4
+#endif
+
 template <int STAGE, bool COUNT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VK_EDGE_WAVES, 8)))
     k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                      const float *__restrict__ qa, const float *__restrict__ qb,
                      const int32_t *__restrict__ nst, int64_t n_edges, float res,
                      uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
-                     unsigned long long *__restrict__ flops) {
+                     int chunk, unsigned long long *__restrict__ flops) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
     const StepCache sc = step_cache(lf, rb.n_steps);
@@ -582,14 +651,16 @@ __global__ void __launch_bounds__(256)
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int lane = threadIdx.x & (kWave - 1);
     typename std::conditional<COUNT, Work, NoWork>::type work;
-    for (;;) {
-        const int64_t e = next_item(queue, lane);
-        if (e >= n_edges) break;
-        const float *a = qa + e * rb.dof;
-        const float *b = qb + e * rb.dof;
-        const int n = nst ? ld(nst, e) : edge_count(a, b, rb.dof, res);
-        const uint8_t hit = edge_body(rb, ev, ed, sc, a, b, n, work);
-        out[e] = hit;                         // wave-uniform value, same address in every lane
+    Puller pl = make_puller(queue, n_edges, chunk);
+    int64_t first, count;
+    while (pull(pl, lane, first, count)) {
+        for (int64_t e = first; e < first + count; ++e) {
+            const float *a = qa + e * rb.dof;
+            const float *b = qb + e * rb.dof;
+            const int n = nst ? ld(nst, e) : edge_count(a, b, rb.dof, res);
+            const uint8_t hit = edge_body(rb, ev, ed, sc, a, b, n, work);
+            out[e] = hit;                     // wave-uniform value, same address in every lane
+        }
     }
     if constexpr (COUNT) {
         unsigned long long v[4] = {work.f[0], work.f[1], work.f[2], work.f[3]};
@@ -628,13 +699,14 @@ __global__ void __launch_bounds__(256)
     k_validate_edge_batch(const BatchSet *__restrict__ sets, const int64_t *__restrict__ prefix,
                           int n_sets, int64_t total, float res, const float *__restrict__ qa,
                           const float *__restrict__ qb, uint8_t *__restrict__ out,
-                          unsigned long long *__restrict__ queue, int cache_steps) {
+                          unsigned long long *__restrict__ queue, int chunk, int cache_steps) {
     extern __shared__ float4 lds_dyn[];
     const StepCache sc = step_cache(reinterpret_cast<float *>(lds_dyn), cache_steps);
     const int lane = threadIdx.x & (kWave - 1);
-    for (;;) {
-        const int64_t e = next_item(queue, lane);
-        if (e >= total) break;
+    Puller pl = make_puller(queue, total, chunk);
+    int64_t first, count;
+    while (pull(pl, lane, first, count))
+    for (int64_t e = first; e < first + count; ++e) {
         int lo = 0, hi = n_sets - 1;          // last set whose first edge is <= e
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -651,9 +723,9 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n) {
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n, int stride) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    if (i < n) p[(size_t)i * stride] = v;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -993,8 +1065,19 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const
 }
 
 hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, queue, 0ull, 1);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, queue, 0ull, kQueues, kQueueWords);
     return hipGetLastError();
+}
+
+// Items per ticket of a persistent launch: about VK_TICKETS_PER_WAVE tickets per wave keeps the
+// dynamic balance fine while bounding the number of queue atomics.
+#ifndef VK_TICKETS_PER_WAVE
+#define VK_TICKETS_PER_WAVE 8
+#endif
+static int work_chunk(int64_t n_items, int grid, int block) {
+    const int64_t waves = (int64_t)grid * (block / kWave);
+    const int64_t c = n_items / (waves * VK_TICKETS_PER_WAVE);
+    return (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
 }
 
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const float *qa,
@@ -1003,7 +1086,8 @@ hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const 
                                  hipStream_t s, unsigned long long *flops) {
     const dim3 grid_(grid), block_(block);
     const size_t base_ = walk_lds_bytes(rb, block);
-#define ARGS_ rb, ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, flops
+    const int chunk = work_chunk(n_edges, grid, block);
+#define ARGS_ rb, ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, chunk, flops
     if (flops) {
         VK_STAGED(k_validate_edges, , true)
     } else {
@@ -1058,7 +1142,8 @@ hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefi
                                       int cache_steps, hipStream_t s) {
     hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block),
                        (size_t)(block / kWave) * step_cache_floats(cache_steps) * sizeof(float), s,
-                       sets, prefix, n_sets, total, res, qa, qb, out, queue, cache_steps);
+                       sets, prefix, n_sets, total, res, qa, qb, out, queue,
+                       work_chunk(total, grid, block), cache_steps);
     return hipGetLastError();
 }
 

@@ -14,6 +14,11 @@ namespace vk {
 
 constexpr int kWave = 64;          // CDNA wavefront width: one lane per configuration
 constexpr int kSpl = 8;            // spheres held in registers per link step
+// Work queues of the persistent launches: kQueues 64-bit counters, kQueueWords words apart
+// (4 KiB, so the counters sit in different memory channels).
+constexpr int kQueues = 8;
+constexpr int kQueueWords = 512;
+constexpr size_t kQueueBytes = (size_t)kQueues * kQueueWords * 8;
 constexpr int kMaxDof = 64;
 
 // Twist codes: the paper's tracing compiler folds constant sin/cos of the DH twist; the
@@ -35,13 +40,19 @@ struct JointRec {                  // 80 bytes
 // paths[restart_off...] (a tree branch), otherwise the step continues from the previous
 // step's pose (serial chain).  A link with more than kSpl spheres is split into several steps;
 // the later ones have joint = -1 and reuse the pose.
-struct StepRec {                   // 48 bytes
+struct StepRec {                   // 80 bytes
     int32_t joint;
     int32_t restart_off, restart_len;
     int32_t sph_first, sph_count;  // fine spheres of this step (<= kSpl)
     int32_t blk_first, blk_count;  // self-collision blocks completed by this step
     int32_t link;
     float coarse[4];               // bounding sphere of the step's spheres, link frame
+    // Bounding capsule of the step's spheres (link frame): segment p + s u, s in [0, 1], and
+    // radius cap_r (padded by 1 mm: it only gates self blocks, and the padding covers the FP32
+    // rounding of the segment distance).  cap_uu = u.u and cap_inv = 1 / u.u (0 if u = 0).
+    float cap_p[3], cap_u[3];
+    float cap_r, cap_uu, cap_inv;
+    float pad[3];
 };
 
 // Self pairs between this step's spheres and the spheres of one earlier step (on link A).  The
