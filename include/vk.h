@@ -196,8 +196,11 @@ vk_status vk_edge_batch_destroy(vk_edge_batch batch);
 
 /*
  * Launch configuration of the persistent edge launches (validate_edges and batches created
- * afterwards): workgroup size (64, 128, 192 or 256) and workgroups per compute unit (1..64).  Both 0 restores the built-in default.  The
- * project's autotuner (a Python helper next to the binding) times candidates and calls this.
+ * afterwards): workgroup size (a multiple of 64 up to 1024) and workgroups per compute unit
+ * (1..64).  Both 0 restores the built-in default (256, 4).  A launch whose per-wave LDS caches
+ * (3 floats per link step and 2 per joint, per lane) would not fit the workgroup's LDS uses the
+ * largest smaller workgroup that fits.  The project's autotuner (a Python helper next to the
+ * binding) times candidates and calls this.  Invalid values: VK_ERR_INVALID_ARG.
  */
 vk_status vk_set_edge_launch(int32_t block_threads, int32_t blocks_per_cu);
 vk_status vk_get_edge_launch(int32_t *block_threads, int32_t *blocks_per_cu);

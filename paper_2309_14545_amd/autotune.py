@@ -15,7 +15,7 @@ import time
 
 from . import get_edge_launch, set_edge_launch, validate_edges
 
-BLOCKS = (64, 128, 256)
+BLOCKS = (64, 128, 256, 512, 1024)
 PER_CU = (1, 2, 4, 8)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "vk_autotune.json")
 

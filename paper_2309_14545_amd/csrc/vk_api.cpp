@@ -887,6 +887,8 @@ static void run_edges(vk_robot robot, vk_env env, const float *qa, const float *
         block = g_edge_block;
         bpc = g_edge_bpc;
     }
+    // a workgroup's per-wave caches must fit the LDS: smaller workgroups for large robots
+    while (block > kWave && walk_lds_bytes(robot->dev, block) > di.max_lds) block -= kWave;
     const int64_t want = (n_edges + block / kWave - 1) / (block / kWave);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
     hip_check(launch_reset_queue(queue, s), "queue reset");
@@ -952,8 +954,8 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
         if (n == 0) return;
         const DeviceInfo &di = device_info(robot->device);
         int block = 256;
-        while (block > 64 && cost_bwd_slot_bytes(robot->dev, block) > di.max_lds) block /= 2;
-        const size_t slots = cost_bwd_slot_bytes(robot->dev, block);
+        while (block > 64 && cost_bwd_slot_bytes(robot->dev, block, false) > di.max_lds) block /= 2;
+        const size_t slots = cost_bwd_slot_bytes(robot->dev, block, false);
         if (slots > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the backward kernel");
         hip_check(launch_cost_bwd(robot->dev, env_for_launch(env, slots), q, n, ldq, grad_cost,
                                   grad_q, ldg, block, (hipStream_t)stream),
@@ -1024,12 +1026,18 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
                 block = g_edge_block;
                 bpc = g_edge_bpc;
             }
+            // per wave: link bound centres, and optionally the joint sines/cosines
+            int cache_floats = 0, cache_floats_jc = 0;
+            for (const BatchSet &b : recs) {
+                cache_floats = std::max(cache_floats, b.rb.n_steps * 3 * kWave);
+                cache_floats_jc = std::max(cache_floats_jc, (b.rb.n_steps * 3 + b.rb.dof * 2) * kWave);
+            }
+            while (block > kWave && (size_t)(block / kWave) * cache_floats * sizeof(float) > di.max_lds)
+                block -= kWave;
+            if ((size_t)(block / kWave) * cache_floats * sizeof(float) > di.max_lds)
+                raise(VK_ERR_UNSUPPORTED, "robots too large for the LDS step cache");
             const int64_t want = (total + block / kWave - 1) / (block / kWave);
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
-            int cache_steps = 0;
-            for (const BatchSet &b : recs) cache_steps = std::max(cache_steps, b.rb.n_steps);
-            if ((size_t)(block / kWave) * cache_steps * 3 * kWave * sizeof(float) > di.max_lds)
-                raise(VK_ERR_UNSUPPORTED, "robots too large for the LDS step cache");
             // capture {queue reset, persistent launch} once; vk_edge_batch_run replays it
             hipStream_t cs = nullptr;
             hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
@@ -1038,7 +1046,7 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             if (err == hipSuccess && total > 0)
                 err = launch_validate_edge_batch(d_sets, d_pre, (int)recs.size(), total, resolution,
                                                  qa, qb, collide, bt->queue, grid, block,
-                                                 cache_steps, cs);
+                                                 cache_floats, cache_floats_jc, cs);
             hipGraph_t g = nullptr;
             hipError_t err2 = hipStreamEndCapture(cs, &g);
             (void)hipStreamDestroy(cs);
@@ -1083,8 +1091,8 @@ vk_status vk_set_edge_launch(int32_t block_threads, int32_t blocks_per_cu) {
             block_threads = 256;
             blocks_per_cu = 4;
         }
-        if (block_threads < 64 || block_threads > 256 || block_threads % 64)
-            raise(VK_ERR_INVALID_ARG, "block_threads must be 64, 128, 192 or 256");
+        if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
+            raise(VK_ERR_INVALID_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
         if (blocks_per_cu < 1 || blocks_per_cu > 64) raise(VK_ERR_INVALID_ARG, "blocks_per_cu must be in [1, 64]");
         std::lock_guard<std::mutex> lk(g_mu);
         g_edge_block = block_threads;

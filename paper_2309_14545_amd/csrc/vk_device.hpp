@@ -40,9 +40,8 @@ __device__ __forceinline__ void frame_mount(Frame &T, const float *m) {
 // T <- T * Rz(theta) Tz(d) Tx(a) Rx(alpha): the standard DH link transform (Sec. III-B).
 // Column form: c0' = c c0 + s c1, c1' = -s c0 + c c1, p' = p + d c2 + a c0', then the twist
 // mixes c1' and c2.  Twists of 0 and +-90 degrees are folded (no multiplies).
-__device__ __forceinline__ void frame_dh(Frame &T, const JointRec &J, float theta) {
-    float s, c;
-    sincosf(theta + J.theta_off, &s, &c);
+// DH update with the joint angle given by its sine and cosine (theta + theta_off).
+__device__ __forceinline__ void frame_dh_sc(Frame &T, const JointRec &J, float s, float c) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const float c0 = T.r[3 * i], c1 = T.r[3 * i + 1], c2 = T.r[3 * i + 2];
@@ -65,10 +64,21 @@ __device__ __forceinline__ void frame_dh(Frame &T, const JointRec &J, float thet
     }
 }
 
+__device__ __forceinline__ void frame_dh(Frame &T, const JointRec &J, float theta) {
+    float s, c;
+    sincosf(theta + J.theta_off, &s, &c);
+    frame_dh_sc(T, J, s, c);
+}
+
 // Full joint update: optional mount, then the DH transform.
 __device__ __forceinline__ void frame_joint(Frame &T, const JointRec &J, float q) {
     if (J.has_mount) frame_mount(T, J.m);
     frame_dh(T, J, q);
+}
+
+__device__ __forceinline__ void frame_joint_sc(Frame &T, const JointRec &J, float s, float c) {
+    if (J.has_mount) frame_mount(T, J.m);
+    frame_dh_sc(T, J, s, c);
 }
 
 // World position of a point given in the frame's coordinates.

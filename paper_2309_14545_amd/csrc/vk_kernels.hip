@@ -164,33 +164,90 @@ struct Work {
     __device__ __forceinline__ void add(int c, uint32_t x) { f[c] += x; }
 };
 
-// Pose the link of step S into T (rebuilding a tree branch from the base when needed).
+// Per-wave LDS cache, per lane: the world centre of every step's link bounding sphere
+// ([step][axis][lane]) and the sine and cosine of every joint angle ([joint][2][lane]), both
+// written by the walk as it poses each link.  The centres gate self blocks without posing the
+// earlier link; the joint sines and cosines make re-posing an earlier link (and rebuilding a
+// tree branch) cost the DH products only.
+struct StepCache {
+    float *base;
+    int lane;
+    int joint_off;                 // n_steps * 3 * kWave, or -1 without the joint slots
+    __device__ __forceinline__ void put(int st, float x, float y, float z) const {
+        base[(st * 3 + 0) * kWave + lane] = x;
+        base[(st * 3 + 1) * kWave + lane] = y;
+        base[(st * 3 + 2) * kWave + lane] = z;
+    }
+    __device__ __forceinline__ void get(int st, float &x, float &y, float &z) const {
+        x = base[(st * 3 + 0) * kWave + lane];
+        y = base[(st * 3 + 1) * kWave + lane];
+        z = base[(st * 3 + 2) * kWave + lane];
+    }
+    __device__ __forceinline__ void put_sc(int j, float s, float c) const {
+        base[joint_off + (j * 2 + 0) * kWave + lane] = s;
+        base[joint_off + (j * 2 + 1) * kWave + lane] = c;
+    }
+    __device__ __forceinline__ void get_sc(int j, float &s, float &c) const {
+        s = base[joint_off + (j * 2 + 0) * kWave + lane];
+        c = base[joint_off + (j * 2 + 1) * kWave + lane];
+    }
+};
+
+// Floats of LDS per wave for the cache (jc: with the joint slots; a launch leaves them out when
+// their LDS would cost resident waves).
+__host__ __device__ constexpr int step_cache_floats(int n_steps, int dof, bool jc) {
+    return (n_steps * 3 + (jc ? dof * 2 : 0)) * kWave;
+}
+
+// Dynamic LDS of the walks: [cache of every wave of the block][environment records].
+__device__ __forceinline__ StepCache step_cache(float *lds, int n_steps, int dof, bool jc) {
+    return StepCache{lds + (threadIdx.x / kWave) * step_cache_floats(n_steps, dof, jc),
+                     (int)(threadIdx.x & (kWave - 1)), jc ? n_steps * 3 * kWave : -1};
+}
+__device__ __forceinline__ float4 *after_caches(float *lds, int n_steps, int dof, bool jc) {
+    return reinterpret_cast<float4 *>(lds + (blockDim.x / kWave) * step_cache_floats(n_steps, dof, jc));
+}
+
+// Pose the link of step S into T (rebuilding a tree branch from the base when needed).  With a
+// cache, the step's joint keeps its sine and cosine there and a rebuilt branch reads the
+// earlier joints' values back instead of evaluating them again.
 template <class Q, class W = NoWork>
 __device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, Frame &T,
-                                          const Q &q, W &&w = W()) {
+                                          const Q &q, W &&w = W(),
+                                          const StepCache *sc = nullptr) {
     if (S.joint < 0) return;
     if (S.restart_len >= 0) {
         frame_identity(T);
         for (int k = 0; k < S.restart_len; ++k) {
             const int j = ld(rb.paths, S.restart_off + k);
             const JointRec J = ld(rb.joints, j);
-            frame_joint(T, J, q(j));
+            if (sc && sc->joint_off >= 0) {
+                float sj, cj;
+                sc->get_sc(j, sj, cj);
+                frame_joint_sc(T, J, sj, cj);
+            } else {
+                frame_joint(T, J, q(j));
+            }
             w.add(flop::kFk, flop::kJoint + (J.has_mount ? flop::kMount : 0));
         }
     }
     const JointRec J = ld(rb.joints, S.joint);
-    frame_joint(T, J, q(S.joint));
+    float sj, cj;
+    sincosf(q(S.joint) + J.theta_off, &sj, &cj);
+    if (sc && sc->joint_off >= 0) sc->put_sc(S.joint, sj, cj);
+    frame_joint_sc(T, J, sj, cj);
     w.add(flop::kFk, flop::kJoint + (J.has_mount ? flop::kMount : 0));
 }
 
-// Pose the earlier link A of self block B into Ta.  Ta holds link `ta_link` (depth `ta_depth`
-// joints from the base): when that link is A nothing is done; when it is the base or a proper
-// ancestor of A the remaining joints of A's path are applied; otherwise Ta restarts from the
-// base.
+// Pose the earlier link A of self block B into Ta, from the cached joint sines and cosines when
+// the cache has them (every joint on A's path was evaluated by the walk before).  Ta holds link
+// `ta_link` (depth `ta_depth` joints from the base): when that link is A nothing is done; when
+// it is the base or a proper ancestor of A the remaining joints of A's path are applied;
+// otherwise Ta restarts from the base.
 template <class Q, class W = NoWork>
 __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B, Frame &Ta,
-                                           int &ta_link, int &ta_depth, const Q &q,
-                                           W &&w = W()) {
+                                           int &ta_link, int &ta_depth, const StepCache &sc,
+                                           const Q &q, W &&w = W()) {
     if (ta_link == B.link) return;
     const unsigned long long anc = ((unsigned long long)B.anc_hi << 32) | B.anc_lo;
     int k0 = ta_depth;
@@ -201,7 +258,13 @@ __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B
     for (int k = k0; k < B.path_len; ++k) {
         const int j = ld(rb.paths, B.path_off + k);
         const JointRec J = ld(rb.joints, j);
-        frame_joint(Ta, J, q(j));
+        if (sc.joint_off >= 0) {
+            float sj, cj;
+            sc.get_sc(j, sj, cj);
+            frame_joint_sc(Ta, J, sj, cj);
+        } else {
+            frame_joint(Ta, J, q(j));
+        }
         w.add(flop::kSelf, flop::kJoint + (J.has_mount ? flop::kMount : 0));
     }
     ta_link = B.link;
@@ -226,33 +289,6 @@ __device__ __forceinline__ void place_step(const RobotDev &rb, const StepRec &S,
     }
 }
 
-// Per-wave LDS cache of every step's link bounding-sphere centre, [step][axis][lane].
-struct StepCache {
-    float *base;
-    int lane;
-    __device__ __forceinline__ void put(int st, float x, float y, float z) const {
-        base[(st * 3 + 0) * kWave + lane] = x;
-        base[(st * 3 + 1) * kWave + lane] = y;
-        base[(st * 3 + 2) * kWave + lane] = z;
-    }
-    __device__ __forceinline__ void get(int st, float &x, float &y, float &z) const {
-        x = base[(st * 3 + 0) * kWave + lane];
-        y = base[(st * 3 + 1) * kWave + lane];
-        z = base[(st * 3 + 2) * kWave + lane];
-    }
-};
-
-// Floats of LDS per wave for the step cache.
-__host__ __device__ constexpr int step_cache_floats(int n_steps) { return n_steps * 3 * kWave; }
-
-// Dynamic LDS of the walks: [step cache of every wave of the block][environment records].
-__device__ __forceinline__ StepCache step_cache(float *lds, int n_steps) {
-    return StepCache{lds + (threadIdx.x / kWave) * step_cache_floats(n_steps),
-                     (int)(threadIdx.x & (kWave - 1))};
-}
-__device__ __forceinline__ float4 *after_caches(float *lds, int n_steps) {
-    return reinterpret_cast<float4 *>(lds + (blockDim.x / kWave) * step_cache_floats(n_steps));
-}
 
 // Grid broadphase over a large set of small spheres.  A point of radius <= gmax_r can touch a
 // robot sphere (c, r) only if it lies within r + gmax_r of c, i.e. in a cell at most
@@ -322,7 +358,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
     if (!EDGE && !wave_ballot(live)) return col;
     for (int st = 0; st < rb.n_steps; ++st) {
         const StepRec S = ld(rb.steps, st);
-        pose_step(rb, S, Tm, q, work);
+        pose_step(rb, S, Tm, q, work, &sc);
         const int cnt = S.sph_count;
         if (cnt == 0) continue;
         work.add(flop::kFk, flop::kPlace);
@@ -444,7 +480,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
                 work.add(flop::kSelf, flop::kSphereCapsule);
                 if (!wave_ballot(live && fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rc * rc)) continue;
             }
-            pose_block(rb, B, Ta, ta_link, ta_depth, q, work);
+            pose_block(rb, B, Ta, ta_link, ta_depth, sc, q, work);
             const float ox = Ta.p[0] - Cx, oy = Ta.p[1] - Cy, oz = Ta.p[2] - Cz;
             float D = -INFINITY;
             const EntryRec *ep = rb.entries + B.ent_first;
@@ -524,11 +560,11 @@ template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_validate_states(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                       const float *__restrict__ q, int64_t n, int64_t ldq,
-                      uint8_t *__restrict__ out) {
+                      uint8_t *__restrict__ out, int jc) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps);
-    float4 *lds_env = after_caches(lf, rb.n_steps);
+    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
+    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -637,16 +673,16 @@ __device__ __forceinline__ bool pull(Puller &p, int lane, int64_t &first, int64_
 #endif
 
 template <int STAGE, bool COUNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(VK_EDGE_WAVES, 8)))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_EDGE_WAVES, 8)))
     k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                      const float *__restrict__ qa, const float *__restrict__ qb,
                      const int32_t *__restrict__ nst, int64_t n_edges, float res,
                      uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
-                     int chunk, unsigned long long *__restrict__ flops) {
+                     int chunk, unsigned long long *__restrict__ flops, int jc) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps);
-    float4 *lds_env = after_caches(lf, rb.n_steps);
+    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
+    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int lane = threadIdx.x & (kWave - 1);
@@ -678,11 +714,11 @@ __global__ void __launch_bounds__(64)
     k_validate_edge_one(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                         const float *__restrict__ qa, const float *__restrict__ qb,
                         const int32_t *__restrict__ nst, int64_t e, float res,
-                        uint8_t *__restrict__ out) {
+                        uint8_t *__restrict__ out, int jc) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps);
-    float4 *lds_env = after_caches(lf, rb.n_steps);
+    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
+    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const float *a = qa + e * rb.dof;
@@ -695,13 +731,13 @@ __global__ void __launch_bounds__(64)
 // Mixed-robot batch: every edge set has its own robot and environment; one persistent launch
 // pulls edges from a single queue across all sets.  The environment is read from global
 // memory with wave-uniform loads (it changes from item to item, so it is not staged in LDS).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_EDGE_WAVES, 8)))
     k_validate_edge_batch(const BatchSet *__restrict__ sets, const int64_t *__restrict__ prefix,
                           int n_sets, int64_t total, float res, const float *__restrict__ qa,
                           const float *__restrict__ qb, uint8_t *__restrict__ out,
-                          unsigned long long *__restrict__ queue, int chunk, int cache_steps) {
+                          unsigned long long *__restrict__ queue, int chunk, int cache_floats, int jc) {
     extern __shared__ float4 lds_dyn[];
-    const StepCache sc = step_cache(reinterpret_cast<float *>(lds_dyn), cache_steps);
+    float *cache_base = reinterpret_cast<float *>(lds_dyn) + (threadIdx.x / kWave) * cache_floats;
     const int lane = threadIdx.x & (kWave - 1);
     Puller pl = make_puller(queue, total, chunk);
     int64_t first, count;
@@ -718,6 +754,7 @@ __global__ void __launch_bounds__(256)
         const float *b = qb + S.qa_offset + local * S.rb.dof;
         const int n = edge_count(a, b, S.rb.dof, res);
         const EnvView ev = make_view<0>(S.env, nullptr);
+        const StepCache sc{cache_base, lane, jc ? S.rb.n_steps * 3 * kWave : -1};
         const uint8_t hit = edge_body(S.rb, ev, S.env, sc, a, b, n);
         out[S.out_offset + local] = hit;      // wave-uniform value
     }
@@ -786,7 +823,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
     float cost = 0.0f;
     for (int st = 0; st < rb.n_steps; ++st) {
         const StepRec S = ld(rb.steps, st);
-        pose_step(rb, S, Tm, q);
+        pose_step(rb, S, Tm, q, NoWork(), &sc);
         const int cnt = S.sph_count;
         if (cnt == 0) continue;
         float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl], fx[kSpl], fy[kSpl], fz[kSpl];
@@ -856,7 +893,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
             const float rr = ld(rb.steps, B.step_a).coarse[3] + CR;
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
-            pose_block(rb, B, Ta, ta_link, ta_depth, q);
+            pose_block(rb, B, Ta, ta_link, ta_depth, sc, q);
             for (int e = 0; e < B.ent_count; ++e) {
                 const EntryRec E = ld(rb.entries, B.ent_first + e);
                 float tx, ty, tz;
@@ -897,11 +934,11 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
 template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_cost_fwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
-               const float *__restrict__ q, int64_t n, int64_t ldq, float *__restrict__ cost) {
+               const float *__restrict__ q, int64_t n, int64_t ldq, float *__restrict__ cost, int jc) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps);
-    float4 *lds_env = after_caches(lf, rb.n_steps);
+    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
+    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -921,15 +958,15 @@ template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_cost_bwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                const float *__restrict__ q, int64_t n, int64_t ldq,
-               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg) {
+               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg, int jc) {
     extern __shared__ float4 lds_dyn[];
     // layout: [slots for every wave of the block][env records]
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const int slot_floats = rb.n_links * 6 * kWave;
     float *slot_base = reinterpret_cast<float *>(lds_dyn);
     float *lf = slot_base + slot_floats * (blockDim.x / kWave);
-    const StepCache sc = step_cache(lf, rb.n_steps);
-    float4 *lds_env = after_caches(lf, rb.n_steps);
+    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
+    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     LinkSlots slots{slot_base + wave * slot_floats, lane};
@@ -997,8 +1034,8 @@ hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int6
     return hipGetLastError();
 }
 
-size_t walk_lds_bytes(const RobotDev &rb, int block) {
-    return (size_t)(block / kWave) * step_cache_floats(rb.n_steps) * sizeof(float);
+size_t walk_lds_bytes(const RobotDev &rb, int block, bool jc) {
+    return (size_t)(block / kWave) * step_cache_floats(rb.n_steps, rb.dof, jc) * sizeof(float);
 }
 
 // Resident workgroups per CU of a kernel at a block size and dynamic LDS (memoised: the
@@ -1038,11 +1075,40 @@ static int pick_stage(EnvDev &ed, const void *k0, const void *k1, const void *k2
     return 0;
 }
 
+// LDS a workgroup may use on the current device (memoised per device).
+static size_t device_max_lds() {
+    static std::mutex mu;
+    static std::map<int, size_t> memo;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = memo.find(dev);
+    if (it != memo.end()) return it->second;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 64 * 1024;
+    return memo[dev] = (size_t)v;
+}
+
+// Joint slots of the walk cache (see StepCache): kept when they cost no resident workgroups.
+#ifndef VK_JOINT_CACHE
+#define VK_JOINT_CACHE 1           // 0: never, 1: when it costs no resident workgroups, 2: always
+#endif
+static bool pick_joint_cache(const void *kernel, int block, size_t without, size_t with,
+                             size_t max_lds) {
+    if (VK_JOINT_CACHE == 0 || with > max_lds) return false;
+    if (VK_JOINT_CACHE == 2) return true;
+    return resident_blocks(kernel, block, with) >= resident_blocks(kernel, block, without);
+}
+
+// Launch KERNEL<stage, ...> with the joint-cache choice and the staging mode; the launcher
+// defines grid_, block_, base_nojc_, base_jc_ (dynamic LDS before staging) and ARGS_.
 #define VK_STAGED(KERNEL, ...)                                                                  \
     {                                                                                           \
         EnvDev ed = ed_in;                                                                      \
-        const int mode = pick_stage(ed, reinterpret_cast<const void *>(&KERNEL<0 __VA_ARGS__>), \
-                                    reinterpret_cast<const void *>(&KERNEL<1 __VA_ARGS__>),     \
+        const void *k0_ = reinterpret_cast<const void *>(&KERNEL<0 __VA_ARGS__>);              \
+        const int jc = pick_joint_cache(k0_, (int)block_.x, base_nojc_, base_jc_, max_lds_);   \
+        const size_t base_ = jc ? base_jc_ : base_nojc_;                                        \
+        const int mode = pick_stage(ed, k0_, reinterpret_cast<const void *>(&KERNEL<1 __VA_ARGS__>), \
                                     reinterpret_cast<const void *>(&KERNEL<2 __VA_ARGS__>),     \
                                     (int)block_.x, base_);                                      \
         const size_t sh_ = base_ + (size_t)ed.n_stage * 16;                                     \
@@ -1057,8 +1123,9 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const
                                   int64_t ldq, uint8_t *out, hipStream_t s) {
     const int bs = 256;
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
-    const size_t base_ = walk_lds_bytes(rb, bs);
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, out
+    const size_t base_nojc_ = walk_lds_bytes(rb, bs, false), base_jc_ = walk_lds_bytes(rb, bs, true);
+    const size_t max_lds_ = device_max_lds();
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, out, jc
     VK_STAGED(k_validate_states)
 #undef ARGS_
     return hipGetLastError();
@@ -1085,9 +1152,10 @@ hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const 
                                  uint8_t *out, unsigned long long *queue, int grid, int block,
                                  hipStream_t s, unsigned long long *flops) {
     const dim3 grid_(grid), block_(block);
-    const size_t base_ = walk_lds_bytes(rb, block);
+    const size_t base_nojc_ = walk_lds_bytes(rb, block, false), base_jc_ = walk_lds_bytes(rb, block, true);
+    const size_t max_lds_ = device_max_lds();
     const int chunk = work_chunk(n_edges, grid, block);
-#define ARGS_ rb, ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, chunk, flops
+#define ARGS_ rb, ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, chunk, flops, jc
     if (flops) {
         VK_STAGED(k_validate_edges, , true)
     } else {
@@ -1101,8 +1169,9 @@ hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed_in, con
                                     const float *qb, const int32_t *nst, int64_t e, float res,
                                     uint8_t *out, hipStream_t s) {
     const dim3 grid_(1), block_(kWave);
-    const size_t base_ = walk_lds_bytes(rb, kWave);
-#define ARGS_ rb, ed, ed.rec, qa, qb, nst, e, res, out
+    const size_t base_nojc_ = walk_lds_bytes(rb, kWave, false), base_jc_ = walk_lds_bytes(rb, kWave, true);
+    const size_t max_lds_ = device_max_lds();
+#define ARGS_ rb, ed, ed.rec, qa, qb, nst, e, res, out, jc
     VK_STAGED(k_validate_edge_one)
 #undef ARGS_
     return hipGetLastError();
@@ -1112,24 +1181,27 @@ hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed_in, const float 
                            int64_t ldq, float *cost, hipStream_t s) {
     const int bs = 256;
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
-    const size_t base_ = walk_lds_bytes(rb, bs);
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, cost
+    const size_t base_nojc_ = walk_lds_bytes(rb, bs, false), base_jc_ = walk_lds_bytes(rb, bs, true);
+    const size_t max_lds_ = device_max_lds();
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, cost, jc
     VK_STAGED(k_cost_fwd)
 #undef ARGS_
     return hipGetLastError();
 }
 
-size_t cost_bwd_slot_bytes(const RobotDev &rb, int block) {
+size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, bool jc) {
     return (size_t)rb.n_links * 6 * kWave * sizeof(float) * (block / kWave) +
-           walk_lds_bytes(rb, block);
+           walk_lds_bytes(rb, block, jc);
 }
 
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
                            int64_t ldq, const float *gcost, float *grad, int64_t ldg, int block,
                            hipStream_t s) {
     const dim3 grid_((unsigned)((n + block - 1) / block)), block_(block);
-    const size_t base_ = cost_bwd_slot_bytes(rb, block);
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg
+    const size_t base_nojc_ = cost_bwd_slot_bytes(rb, block, false),
+                 base_jc_ = cost_bwd_slot_bytes(rb, block, true);
+    const size_t max_lds_ = device_max_lds();
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg, jc
     VK_STAGED(k_cost_bwd)
 #undef ARGS_
     return hipGetLastError();
@@ -1139,11 +1211,15 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float 
 hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
                                       int64_t total, float res, const float *qa, const float *qb,
                                       uint8_t *out, unsigned long long *queue, int grid, int block,
-                                      int cache_steps, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block),
-                       (size_t)(block / kWave) * step_cache_floats(cache_steps) * sizeof(float), s,
+                                      int cache_floats_nojc, int cache_floats_jc, hipStream_t s) {
+    const size_t waves = (size_t)(block / kWave);
+    const size_t without = waves * cache_floats_nojc * sizeof(float);
+    const size_t with = waves * cache_floats_jc * sizeof(float);
+    const int jc = pick_joint_cache(reinterpret_cast<const void *>(&k_validate_edge_batch), block,
+                                    without, with, device_max_lds());
+    hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block), jc ? with : without, s,
                        sets, prefix, n_sets, total, res, qa, qb, out, queue,
-                       work_chunk(total, grid, block), cache_steps);
+                       work_chunk(total, grid, block), jc ? cache_floats_jc : cache_floats_nojc, jc);
     return hipGetLastError();
 }
 

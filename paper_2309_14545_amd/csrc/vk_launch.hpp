@@ -21,9 +21,11 @@ hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed,
                                     int64_t e, float res, uint8_t *out, hipStream_t s);
 hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, float *cost, hipStream_t s);
-size_t cost_bwd_slot_bytes(const RobotDev &rb, int block);
-// Per-workgroup LDS of the step caches (world centre of every link bound, per wave).
-size_t walk_lds_bytes(const RobotDev &rb, int block);
+size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, bool jc);
+// Per-workgroup LDS of the walk caches (link bound centres and joint sines/cosines, per wave).
+// With jc the joint sine/cosine slots are included; launchers add them only when they cost no
+// resident workgroups, so callers size their checks without them.
+size_t walk_lds_bytes(const RobotDev &rb, int block, bool jc = false);
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
                            int block, hipStream_t s);
@@ -31,6 +33,6 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
 hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
                                       int64_t total, float res, const float *qa, const float *qb,
                                       uint8_t *out, unsigned long long *queue, int grid, int block,
-                                      int cache_steps, hipStream_t s);
+                                      int cache_floats_nojc, int cache_floats_jc, hipStream_t s);
 
 }  // namespace vk

@@ -103,6 +103,9 @@ def test_launch_configuration_checks(vk):
     lib = vk.lib()
     assert lib.vk_set_edge_launch(100, 4) == -1
     assert lib.vk_set_edge_launch(128, 0) == -1
+    assert lib.vk_set_edge_launch(1088, 1) == -1
+    assert lib.vk_set_edge_launch(1024, 2) == 0
+    assert vk.get_edge_launch() == (1024, 2)
     assert lib.vk_set_edge_launch(128, 3) == 0
     assert vk.get_edge_launch() == (128, 3)
     assert lib.vk_set_edge_launch(0, 0) == 0
