@@ -154,6 +154,52 @@ def extra_cost(vk, steps):
             "fwd_bwd_states_per_s": n / ((f + b) * 1e-3)}
 
 
+def extra_prm(vk, steps):
+    """PRM roadmap step: k nearest neighbours of 8,192 samples, the undirected pair list, and
+    every roadmap edge validated in one persistent launch (all three timed together)."""
+    import torch
+    from synthetic import workload
+    w = workload("prm7_shelf")
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    nodes = torch.from_numpy(w["nodes"]).cuda()
+
+    def step():
+        idx, _ = vk.knn(nodes, w["k"])
+        return vk.validate_edges_indexed(robot, env, nodes, vk.knn_pairs(idx), resolution=RES)
+
+    flags = step()
+    torch.cuda.synchronize()
+    idx, _ = vk.knn(nodes, w["k"])
+    pairs = vk.knn_pairs(idx).cpu().numpy()
+    real = pairs[:, 0] >= 0
+    n_states = int(state_counts(w["nodes"][pairs[real, 0]], w["nodes"][pairs[real, 1]], RES).sum())
+    knn_ms = float(np.median(_events_ms(lambda: vk.knn(nodes, w["k"]), steps)))
+    m = float(np.median(_events_ms(step, steps)))
+    f = flags.cpu().numpy()[real]
+    return {"workload": "prm7_shelf", "samples": len(w["nodes"]), "k": w["k"],
+            "edges": int(real.sum()), "nominal_states": n_states, "step_ms": m, "knn_ms": knn_ms,
+            "edge_collision_rate": float(f.mean()), "states_per_s": n_states / (m * 1e-3)}
+
+
+def extra_shortcut(vk, steps):
+    """Shortcut candidates: 8 random waypoint pairs on each of 4,096 paths, one launch."""
+    import torch
+    from synthetic import workload
+    w = workload("shortcut7_shelf")
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    nodes = torch.from_numpy(w["nodes"]).cuda()
+    pairs = torch.from_numpy(w["pairs"]).cuda()
+    out = vk.validate_edges_indexed(robot, env, nodes, pairs, resolution=RES)
+    torch.cuda.synchronize()
+    p = w["pairs"]
+    n_states = int(state_counts(w["nodes"][p[:, 0]], w["nodes"][p[:, 1]], RES).sum())
+    m = float(np.median(_events_ms(
+        lambda: vk.validate_edges_indexed(robot, env, nodes, pairs, resolution=RES, out=out), steps)))
+    return {"workload": "shortcut7_shelf", "edges": len(p), "nominal_states": n_states,
+            "launch_ms": m, "edge_collision_rate": float(out.float().mean().item()),
+            "states_per_s": n_states / (m * 1e-3)}
+
+
 def extra_mixed(vk, n_batches, reps):
     import torch
     from synthetic import workload, pack_edge_sets
@@ -342,6 +388,8 @@ def main():
                         ("states7_1M", lambda: extra_states(vk, "states7", 1 << 20, 10)),
                         ("states14_cloud", lambda: extra_states(vk, "states14_cloud", None, 5)),
                         ("cost7", lambda: extra_cost(vk, 10)),
+                        ("prm7_shelf", lambda: extra_prm(vk, 10)),
+                        ("shortcut7_shelf", lambda: extra_shortcut(vk, 10)),
                         ("mixed", lambda: extra_mixed(vk, 3, 20))):
             t0 = time.perf_counter()
             extra[key] = fn()

@@ -140,6 +140,35 @@ vk_status validate_edges_per_edge(vk_robot robot, vk_env env, const float *qa, c
                                   const int32_t *n_states, int64_t n_edges, float resolution,
                                   uint8_t *collide, void *stream);
 
+/* Edge validation with endpoints given by index: edge e runs from node pairs[2e] to node
+ * pairs[2e+1] of `nodes` (device, AoS [n_nodes][dof]); otherwise exactly validate_edges (same
+ * discretisation, rake and early exit, same kernel).  This is the form a PRM roadmap or a batch
+ * of shortcut candidates takes (Sec. III-E: the planners built on the edge validator).  A pair
+ * with a negative entry is a hole: no edge, flag 0 (vk_knn_pairs writes (-1, -1) for
+ * duplicates).  An index >= n_nodes makes the edge's flag 1.  pairs: device int32 [n_edges][2].
+ * Errors as validate_edges. */
+vk_status validate_edges_indexed(vk_robot robot, vk_env env, const float *nodes, int64_t n_nodes,
+                                 const int32_t *pairs, const int32_t *n_states, int64_t n_edges,
+                                 float resolution, uint8_t *collide, void *stream);
+
+/* k nearest neighbours of each of n samples (device, AoS [n][dim]) among the others, by the
+ * Euclidean norm of the configuration difference (the roadmap neighbourhoods of a PRM,
+ * Sec. III-E).  Writes idx [n][k] (int32) and dist2 [n][k] (FP32 squared distances), each row
+ * ascending.  The squared distance is accumulated in dimension order with separately rounded
+ * FP32 products and sums (no fused multiply-add); equal distances go to the lower index.
+ * Samples at a non-finite distance are skipped; a row with fewer than k neighbours ends in
+ * index -1 and distance +inf.  1 <= dim <= 64, 1 <= k <= 32 (else VK_ERR_UNSUPPORTED /
+ * VK_ERR_INVALID_ARG).  Brute force: O(n^2 dim) work, meant for roadmaps of up to ~10^5
+ * samples. */
+vk_status vk_knn(const float *x, int64_t n, int32_t dim, int32_t k, int32_t *idx, float *dist2,
+                 void *stream);
+
+/* Undirected roadmap edges from kNN lists (device idx [n][k]): slot i*k+m of pairs ([n*k][2],
+ * device int32) holds (i, j) for j = idx[i][m] when i < j or when i is not in j's list, else
+ * the hole (-1, -1), so each undirected edge is listed once, at a fixed slot.  Entries outside
+ * [0, n) or equal to i become holes. */
+vk_status vk_knn_pairs(const int32_t *idx, int64_t n, int32_t k, int32_t *pairs, void *stream);
+
 /* Measurement variant of validate_edges: the same flags from the same kernel code, which in
  * addition adds to flops[0..4] (five device uint64, not cleared by the call) the FP32
  * operations the launch executed, by the model's count per operation (fused multiply-add = 2;

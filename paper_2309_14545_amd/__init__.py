@@ -23,7 +23,8 @@ _STATUS = {-1: "VK_ERR_INVALID_ARG", -2: "VK_ERR_SHAPE", -3: "VK_ERR_UNSUPPORTED
 
 EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_spheres",
            "vk_env_create", "vk_env_destroy", "fk_spheres", "validate_states", "validate_edges",
-           "validate_edges_per_edge", "validate_edges_counted", "penetration_cost_fwd", "penetration_cost_bwd",
+           "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
+           "vk_knn", "vk_knn_pairs", "penetration_cost_fwd", "penetration_cost_bwd",
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_destroy",
            "vk_set_edge_launch", "vk_get_edge_launch", "vk_last_error")
 
@@ -79,6 +80,9 @@ def lib():
         L.validate_edges.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp]
         L.validate_edges_per_edge.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp]
         L.validate_edges_counted.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp, vp]
+        L.validate_edges_indexed.argtypes = [vp, vp, vp, i64, vp, vp, i64, fp, vp, vp]
+        L.vk_knn.argtypes = [vp, i64, i32, i32, vp, vp, vp]
+        L.vk_knn_pairs.argtypes = [vp, i64, i32, vp, vp]
         L.penetration_cost_fwd.argtypes = [vp, vp, vp, i64, i64, vp, vp]
         L.penetration_cost_bwd.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
         L.vk_edge_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), i32,
@@ -257,6 +261,59 @@ def validate_edges_counted(robot: Robot, env: Env, qa, qb, flops, n_states=None,
                                         ns_ptr, E, float(resolution), out.data_ptr(),
                                         flops.data_ptr(), _stream()))
     return out
+
+
+def validate_edges_indexed(robot: Robot, env: Env, nodes, pairs, n_states=None,
+                           resolution: float = 1.0 / 32.0, out=None):
+    """Edge flags uint8 [E] for edges between rows of ``nodes`` [N, dof] given by ``pairs``
+    (int32 [E, 2]; a pair with a negative entry is a hole, flag 0)."""
+    torch = _torch()
+    nodes = _dev_f32(nodes, "nodes")
+    if nodes.dim() != 2 or nodes.shape[1] != robot.dof:
+        raise ValueError(f"nodes must be [N, dof={robot.dof}]")
+    if not (isinstance(pairs, torch.Tensor) and pairs.is_cuda and pairs.dtype == torch.int32
+            and pairs.dim() == 2 and pairs.shape[1] == 2):
+        raise TypeError("pairs must be an int32 CUDA tensor [E, 2]")
+    pairs = pairs.contiguous()
+    E = pairs.shape[0]
+    ns_ptr = None
+    if n_states is not None:
+        if not (isinstance(n_states, torch.Tensor) and n_states.is_cuda and n_states.dtype == torch.int32
+                and n_states.shape == (E,)):
+            raise TypeError("n_states must be an int32 CUDA tensor [E]")
+        n_states = n_states.contiguous()
+        ns_ptr = n_states.data_ptr()
+    if out is None:
+        out = torch.empty(E, dtype=torch.uint8, device=nodes.device)
+    _check(lib().validate_edges_indexed(robot.handle, env.handle, nodes.data_ptr(), nodes.shape[0],
+                                        pairs.data_ptr(), ns_ptr, E, float(resolution),
+                                        out.data_ptr(), _stream()))
+    return out
+
+
+def knn(x, k: int):
+    """(idx int32 [N, k], dist2 float32 [N, k]): the k nearest other rows of x [N, dim]."""
+    torch = _torch()
+    x = _dev_f32(x, "x")
+    if x.dim() != 2:
+        raise ValueError("x must be [N, dim]")
+    n, d = x.shape
+    idx = torch.empty((n, k), dtype=torch.int32, device=x.device)
+    d2 = torch.empty((n, k), dtype=torch.float32, device=x.device)
+    _check(lib().vk_knn(x.data_ptr(), n, d, k, idx.data_ptr(), d2.data_ptr(), _stream()))
+    return idx, d2
+
+
+def knn_pairs(idx):
+    """Undirected roadmap edges int32 [N*k, 2] from kNN lists (holes are (-1, -1))."""
+    torch = _torch()
+    if not (isinstance(idx, torch.Tensor) and idx.is_cuda and idx.dtype == torch.int32 and idx.dim() == 2):
+        raise TypeError("idx must be an int32 CUDA tensor [N, k]")
+    idx = idx.contiguous()
+    n, k = idx.shape
+    pairs = torch.empty((n * k, 2), dtype=torch.int32, device=idx.device)
+    _check(lib().vk_knn_pairs(idx.data_ptr(), n, k, pairs.data_ptr(), _stream()))
+    return pairs
 
 
 def penetration_cost_fwd(robot: Robot, env: Env, q):

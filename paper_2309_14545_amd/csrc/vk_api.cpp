@@ -95,6 +95,29 @@ unsigned long long *queue_for(int dev, hipStream_t s) {
     return g_queues[key] = static_cast<unsigned long long *>(p);
 }
 
+// Scratch of the kNN partial lists, per (device, stream), grown on demand and kept until the
+// process ends (calls on one stream are ordered, so they may share it).
+std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_knn_ws;
+
+void *knn_workspace(int dev, hipStream_t s, size_t bytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto &w = g_knn_ws[std::make_pair(dev, s)];
+    if (w.second < bytes) {
+        if (w.first) {
+            // the previous buffer may still be in use by work queued on this stream
+            hip_check(hipStreamSynchronize(s), "kNN workspace sync");
+            (void)hipFree(w.first);
+            w.first = nullptr;
+            w.second = 0;
+        }
+        void *p = nullptr;
+        hip_check(hipMalloc(&p, bytes), "kNN workspace");
+        w.first = p;
+        w.second = bytes;
+    }
+    return w.first;
+}
+
 // Device blob: several host arrays copied into one allocation at 256-byte aligned offsets.
 struct Blob {
     std::vector<char> host;
@@ -872,10 +895,9 @@ static void check_edges(vk_robot robot, vk_env env, const float *qa, const float
         raise(VK_ERR_INVALID_ARG, "resolution must be finite and > 0");
 }
 
-static void run_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
-                      const int32_t *n_states, int64_t n_edges, float resolution,
-                      uint8_t *collide, unsigned long long *flops, void *stream) {
-    check_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide);
+static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_edges,
+                      float resolution, uint8_t *collide, unsigned long long *flops,
+                      void *stream) {
     if (n_edges == 0) return;
     hipStream_t s = (hipStream_t)stream;
     const int dev = robot->device;
@@ -893,8 +915,7 @@ static void run_edges(vk_robot robot, vk_env env, const float *qa, const float *
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
     hip_check(launch_reset_queue(queue, s), "queue reset");
     hip_check(launch_validate_edges(robot->dev, env_for_launch(env, walk_lds_bytes(robot->dev, block)),
-                                    qa, qb, n_states,
-                                    n_edges, resolution, collide, queue, grid, block, s, flops),
+                                    src, n_edges, resolution, collide, queue, grid, block, s, flops),
               "validate_edges launch");
 }
 
@@ -902,7 +923,25 @@ vk_status validate_edges(vk_robot robot, vk_env env, const float *qa, const floa
                          const int32_t *n_states, int64_t n_edges, float resolution,
                          uint8_t *collide, void *stream) {
     return guarded([&] {
-        run_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide, nullptr, stream);
+        check_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide);
+        run_edges(robot, env, EdgeSrc{qa, qb, nullptr, 0, n_states}, n_edges, resolution, collide,
+                  nullptr, stream);
+    });
+}
+
+vk_status validate_edges_indexed(vk_robot robot, vk_env env, const float *nodes, int64_t n_nodes,
+                                 const int32_t *pairs, const int32_t *n_states, int64_t n_edges,
+                                 float resolution, uint8_t *collide, void *stream) {
+    return guarded([&] {
+        check_pair(robot, env);
+        if (n_nodes < 0 || n_edges < 0) raise(VK_ERR_INVALID_ARG, "n_nodes or n_edges < 0");
+        if (n_edges > 0 && (!pairs || !collide)) raise(VK_ERR_INVALID_ARG, "NULL pair or flag array");
+        if (n_edges > 0 && n_nodes > 0 && !nodes) raise(VK_ERR_INVALID_ARG, "NULL node array");
+        if (n_edges >= (int64_t(1) << 31) - (int64_t(1) << 24)) raise(VK_ERR_SHAPE, "too many edges");
+        if (!n_states && !(resolution > 0.0f && std::isfinite(resolution)))
+            raise(VK_ERR_INVALID_ARG, "resolution must be finite and > 0");
+        run_edges(robot, env, EdgeSrc{nodes, nodes, pairs, n_nodes, n_states}, n_edges, resolution,
+                  collide, nullptr, stream);
     });
 }
 
@@ -911,7 +950,8 @@ vk_status validate_edges_counted(vk_robot robot, vk_env env, const float *qa, co
                                  uint8_t *collide, uint64_t *flops, void *stream) {
     return guarded([&] {
         if (!flops) raise(VK_ERR_INVALID_ARG, "flops is NULL");
-        run_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide,
+        check_edges(robot, env, qa, qb, n_states, n_edges, resolution, collide);
+        run_edges(robot, env, EdgeSrc{qa, qb, nullptr, 0, n_states}, n_edges, resolution, collide,
                   reinterpret_cast<unsigned long long *>(flops), stream);
     });
 }
@@ -924,9 +964,33 @@ vk_status validate_edges_per_edge(vk_robot robot, vk_env env, const float *qa, c
         hipStream_t s = (hipStream_t)stream;
         const EnvDev ed = env_for_launch(env, walk_lds_bytes(robot->dev, kWave));
         for (int64_t e = 0; e < n_edges; ++e)
-            hip_check(launch_validate_edge_one(robot->dev, ed, qa, qb, n_states, e,
-                                               resolution, collide, s),
+            hip_check(launch_validate_edge_one(robot->dev, ed, EdgeSrc{qa, qb, nullptr, 0, n_states},
+                                               e, resolution, collide, s),
                       "validate_edges_per_edge launch");
+    });
+}
+
+vk_status vk_knn(const float *x, int64_t n, int32_t dim, int32_t k, int32_t *idx, float *dist2,
+                 void *stream) {
+    return guarded([&] {
+        if (n < 0 || dim < 1 || dim > kMaxDof) raise(VK_ERR_INVALID_ARG, "vk_knn: bad n or dim");
+        if (k < 1 || k > 32) raise(VK_ERR_UNSUPPORTED, "vk_knn: k must be in [1, 32]");
+        if (n == 0) return;
+        if (!x || !idx || !dist2) raise(VK_ERR_INVALID_ARG, "vk_knn: NULL array");
+        if (n >= (int64_t(1) << 31) / 32) raise(VK_ERR_SHAPE, "vk_knn: too many samples");
+        hipStream_t s = (hipStream_t)stream;
+        void *ws = knn_workspace(current_device(), s, knn_workspace_bytes(n, k));
+        hip_check(launch_knn(x, n, dim, k, idx, dist2, ws, s), "vk_knn launch");
+    });
+}
+
+vk_status vk_knn_pairs(const int32_t *idx, int64_t n, int32_t k, int32_t *pairs, void *stream) {
+    return guarded([&] {
+        if (n < 0 || k < 1) raise(VK_ERR_INVALID_ARG, "vk_knn_pairs: bad n or k");
+        if (n == 0) return;
+        if (!idx || !pairs) raise(VK_ERR_INVALID_ARG, "vk_knn_pairs: NULL array");
+        if (n >= (int64_t(1) << 31) / k) raise(VK_ERR_SHAPE, "vk_knn_pairs: too many slots");
+        hip_check(launch_knn_pairs(idx, n, k, pairs, (hipStream_t)stream), "vk_knn_pairs launch");
     });
 }
 

@@ -13,6 +13,7 @@
 //     samples the whole motion (Sec. III-D, Fig. 2) and a wave ballot ends the edge early.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -589,6 +590,23 @@ __device__ __forceinline__ int edge_count(const float *a, const float *b, int do
     return n < 2.0 ? 2 : (n > 2147483647.0 ? 2147483647 : (int)n);
 }
 
+// Endpoints of edge e.  Returns 0 for an edge to validate, 1 for a hole (an index pair with a
+// negative entry: no edge, flag 0) and 2 for an index past the node array (flag 1).
+__device__ __forceinline__ int edge_ends(const EdgeSrc &src, int dof, int64_t e, const float *&a,
+                                         const float *&b) {
+    if (!src.pairs) {
+        a = src.qa + e * dof;
+        b = src.qb + e * dof;
+        return 0;
+    }
+    const int64_t i = ld(src.pairs, 2 * e), j = ld(src.pairs, 2 * e + 1);
+    if (i < 0 || j < 0) return 1;
+    if (i >= src.n_nodes || j >= src.n_nodes) return 2;
+    a = src.qa + i * dof;
+    b = src.qa + j * dof;
+    return 0;
+}
+
 template <class V, class W = NoWork>
 __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, const EnvDev &ed,
                                              const StepCache &sc, const float *a, const float *b,
@@ -675,8 +693,7 @@ __device__ __forceinline__ bool pull(Puller &p, int lane, int64_t &first, int64_
 template <int STAGE, bool COUNT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_EDGE_WAVES, 8)))
     k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
-                     const float *__restrict__ qa, const float *__restrict__ qb,
-                     const int32_t *__restrict__ nst, int64_t n_edges, float res,
+                     EdgeSrc src, int64_t n_edges, float res,
                      uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
                      int chunk, unsigned long long *__restrict__ flops, int jc) {
     extern __shared__ float4 lds_dyn[];
@@ -691,10 +708,13 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
     int64_t first, count;
     while (pull(pl, lane, first, count)) {
         for (int64_t e = first; e < first + count; ++e) {
-            const float *a = qa + e * rb.dof;
-            const float *b = qb + e * rb.dof;
-            const int n = nst ? ld(nst, e) : edge_count(a, b, rb.dof, res);
-            const uint8_t hit = edge_body(rb, ev, ed, sc, a, b, n, work);
+            const float *a = nullptr, *b = nullptr;
+            const int kind = edge_ends(src, rb.dof, e, a, b);
+            uint8_t hit = kind == 2 ? 1 : 0;
+            if (kind == 0) {
+                const int n = src.nst ? ld(src.nst, e) : edge_count(a, b, rb.dof, res);
+                hit = edge_body(rb, ev, ed, sc, a, b, n, work);
+            }
             out[e] = hit;                     // wave-uniform value, same address in every lane
         }
     }
@@ -712,19 +732,20 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
 template <int STAGE>
 __global__ void __launch_bounds__(64)
     k_validate_edge_one(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
-                        const float *__restrict__ qa, const float *__restrict__ qb,
-                        const int32_t *__restrict__ nst, int64_t e, float res,
-                        uint8_t *__restrict__ out, int jc) {
+                        EdgeSrc src, int64_t e, float res, uint8_t *__restrict__ out, int jc) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
     const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
     float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
-    const float *a = qa + e * rb.dof;
-    const float *b = qb + e * rb.dof;
-    const int n = nst ? ld(nst, e) : edge_count(a, b, rb.dof, res);
-    const uint8_t hit = edge_body(rb, ev, ed, sc, a, b, n);
+    const float *a = nullptr, *b = nullptr;
+    const int kind = edge_ends(src, rb.dof, e, a, b);
+    uint8_t hit = kind == 2 ? 1 : 0;
+    if (kind == 0) {
+        const int n = src.nst ? ld(src.nst, e) : edge_count(a, b, rb.dof, res);
+        hit = edge_body(rb, ev, ed, sc, a, b, n);
+    }
     out[e] = hit;                             // wave-uniform value
 }
 
@@ -1024,6 +1045,147 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------------------------
+// k nearest neighbours of samples in configuration space (the roadmap of a PRM, Sec. III-E:
+// neighbours by the Euclidean norm).  One lane per query sample keeps a sorted top-K list in
+// registers; candidate samples stream through LDS in tiles shared by the workgroup.  The
+// squared distance is accumulated in joint order with separately rounded products and sums
+// (no fused multiply-add), so the neighbour order is a well-defined FP32 result; equal
+// distances go to the lower index.  Candidates with a non-finite distance are skipped; list
+// slots left without a neighbour hold index -1 and distance +inf.
+// ---------------------------------------------------------------------------------------------
+constexpr int kKnnTile = 128;
+
+__device__ __forceinline__ bool knn_less(float d, int i, float e, int j) {
+    return d < e || (d == e && i < j);
+}
+
+// Insert (s, c) into the sorted list (bd, bi) of length K if it beats the last entry.
+template <int K>
+__device__ __forceinline__ void knn_insert(float (&bd)[K], int (&bi)[K], float s, int c) {
+    if (!knn_less(s, c, bd[K - 1], bi[K - 1])) return;
+    bool done = false;
+#pragma unroll
+    for (int m = K - 1; m > 0; --m) {
+        if (!done) {
+            if (knn_less(s, c, bd[m - 1], bi[m - 1])) {
+                bd[m] = bd[m - 1];
+                bi[m] = bi[m - 1];
+            } else {
+                bd[m] = s;
+                bi[m] = c;
+                done = true;
+            }
+        }
+    }
+    if (!done) {
+        bd[0] = s;
+        bi[0] = c;
+    }
+}
+
+// Partial lists: workgroup (tile, p) holds 64 queries (one wave) and scans the candidates of
+// part p, [p n / parts, (p+1) n / parts), through LDS; each lane keeps the best K of that part
+// in registers and writes them to part lists [parts][n][K] (index 0x7fffffff = none).  Splitting
+// the candidates over parts gives the launch parts x n / 64 waves instead of n / 64.
+template <int K, int MAXD>
+__global__ void __launch_bounds__(64) k_knn_part(const float *__restrict__ x, int64_t n, int dim,
+                                                 int parts, int32_t *__restrict__ pidx,
+                                                 float *__restrict__ pd2) {
+#pragma clang fp contract(off)                 // products and sums rounded separately
+    extern __shared__ float tile[];            // [dim][kKnnTile]
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    const int p = blockIdx.y;
+    const int64_t c0 = n * p / parts, c1 = n * (p + 1) / parts;
+    float xi[MAXD];
+#pragma unroll
+    for (int j = 0; j < MAXD; ++j) xi[j] = (active && j < dim) ? x[i * dim + j] : 0.0f;
+    float bd[K];
+    int bi[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        bd[m] = INFINITY;
+        bi[m] = 0x7fffffff;
+    }
+    for (int64_t t0 = c0; t0 < c1; t0 += kKnnTile) {
+        const int tn = (int)(c1 - t0 < kKnnTile ? c1 - t0 : kKnnTile);
+        __syncthreads();
+        for (int v = threadIdx.x; v < tn * dim; v += blockDim.x) {
+            const int t = v / dim, j = v - t * dim;
+            tile[j * kKnnTile + t] = x[(t0 + t) * dim + j];
+        }
+        __syncthreads();
+        for (int t = 0; t < tn; ++t) {
+            float s = 0.0f;
+#pragma unroll
+            for (int j = 0; j < MAXD; ++j)
+                if (j < dim) {                 // plain operators: the pragma above keeps them apart
+                    const float d = xi[j] - tile[j * kKnnTile + t];
+                    const float dd = d * d;
+                    s = s + dd;
+                }
+            const int c = (int)(t0 + t);
+            if (active && c != i && isfinite(s)) knn_insert<K>(bd, bi, s, c);
+        }
+    }
+    if (!active) return;
+    const int64_t o = ((int64_t)p * n + i) * K;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        pidx[o + m] = bi[m];
+        pd2[o + m] = bd[m];
+    }
+}
+
+// Merge the parts' lists of each query into its k nearest (same order: distance, then index).
+template <int K>
+__global__ void __launch_bounds__(256) k_knn_merge(const int32_t *__restrict__ pidx,
+                                                   const float *__restrict__ pd2, int64_t n,
+                                                   int parts, int k, int32_t *__restrict__ idx,
+                                                   float *__restrict__ d2out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float bd[K];
+    int bi[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        bd[m] = INFINITY;
+        bi[m] = 0x7fffffff;
+    }
+    for (int p = 0; p < parts; ++p) {
+        const int64_t o = ((int64_t)p * n + i) * K;
+        for (int m = 0; m < K; ++m) {
+            const int c = pidx[o + m];
+            if (c == 0x7fffffff) break;        // the part's list is sorted: the rest is empty
+            knn_insert<K>(bd, bi, pd2[o + m], c);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        if (m < k) {
+            const bool ok = bi[m] != 0x7fffffff;
+            idx[i * k + m] = ok ? bi[m] : -1;
+            d2out[i * k + m] = ok ? bd[m] : INFINITY;
+        }
+}
+
+// Undirected roadmap edges from kNN lists, one slot per (i, m): (i, j) for j = idx[i][m] when
+// i < j or when i is not in j's list, else the hole (-1, -1); each edge appears exactly once.
+__global__ void k_knn_pairs(const int32_t *__restrict__ idx, int64_t n, int k,
+                            int32_t *__restrict__ pairs) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n * k) return;
+    const int64_t i = s / k;
+    const int32_t j = idx[s];
+    bool keep = j >= 0 && j < n && j != i;
+    if (keep && j < i)
+        for (int m = 0; m < k; ++m)
+            if (idx[(int64_t)j * k + m] == i) keep = false;
+    pairs[2 * s] = keep ? (int32_t)i : -1;
+    pairs[2 * s + 1] = keep ? j : -1;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Host-side launchers (called from the C-ABI layer).
 // ---------------------------------------------------------------------------------------------
 hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int64_t ldq,
@@ -1131,6 +1293,53 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const
     return hipGetLastError();
 }
 
+int knn_parts(int64_t n) {
+    const int64_t tiles = (n + kWave - 1) / kWave;
+    int64_t p = (2048 + tiles - 1) / tiles;    // aim at ~2,048 waves
+    p = std::min<int64_t>(p, std::max<int64_t>(1, n / kWave));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(p, 64));
+}
+
+static int knn_list_len(int k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32; }
+
+size_t knn_workspace_bytes(int64_t n, int k) {
+    return (size_t)knn_parts(n) * n * knn_list_len(k) * (sizeof(int32_t) + sizeof(float));
+}
+
+hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, float *d2,
+                      void *workspace, hipStream_t s) {
+    const int parts = knn_parts(n), K = knn_list_len(k);
+    int32_t *pidx = static_cast<int32_t *>(workspace);
+    float *pd2 = reinterpret_cast<float *>(pidx + (size_t)parts * n * K);
+    const dim3 grid_((unsigned)((n + kWave - 1) / kWave), (unsigned)parts), block_(kWave);
+    const size_t sh = (size_t)dim * kKnnTile * sizeof(float);
+    const dim3 mgrid((unsigned)((n + 255) / 256)), mblock(256);
+#define VK_KNN(KK, D)                                                                              \
+    do {                                                                                           \
+        hipLaunchKernelGGL((k_knn_part<KK, D>), grid_, block_, sh, s, x, n, dim, parts, pidx, pd2); \
+        hipLaunchKernelGGL((k_knn_merge<KK>), mgrid, mblock, 0, s, pidx, pd2, n, parts, k, idx, d2); \
+    } while (0)
+    if (dim <= 16) {
+        if (K == 4) VK_KNN(4, 16);
+        else if (K == 8) VK_KNN(8, 16);
+        else if (K == 16) VK_KNN(16, 16);
+        else VK_KNN(32, 16);
+    } else {
+        if (K <= 8) VK_KNN(8, 64);
+        else if (K == 16) VK_KNN(16, 64);
+        else VK_KNN(32, 64);
+    }
+#undef VK_KNN
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_pairs(const int32_t *idx, int64_t n, int k, int32_t *pairs, hipStream_t s) {
+    const int bs = 256;
+    hipLaunchKernelGGL(k_knn_pairs, dim3((unsigned)((n * k + bs - 1) / bs)), dim3(bs), 0, s, idx,
+                       n, k, pairs);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, queue, 0ull, kQueues, kQueueWords);
     return hipGetLastError();
@@ -1147,15 +1356,15 @@ static int work_chunk(int64_t n_items, int grid, int block) {
     return (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
 }
 
-hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const float *qa,
-                                 const float *qb, const int32_t *nst, int64_t n_edges, float res,
-                                 uint8_t *out, unsigned long long *queue, int grid, int block,
-                                 hipStream_t s, unsigned long long *flops) {
+hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const EdgeSrc &src,
+                                 int64_t n_edges, float res, uint8_t *out,
+                                 unsigned long long *queue, int grid, int block, hipStream_t s,
+                                 unsigned long long *flops) {
     const dim3 grid_(grid), block_(block);
     const size_t base_nojc_ = walk_lds_bytes(rb, block, false), base_jc_ = walk_lds_bytes(rb, block, true);
     const size_t max_lds_ = device_max_lds();
     const int chunk = work_chunk(n_edges, grid, block);
-#define ARGS_ rb, ed, ed.rec, qa, qb, nst, n_edges, res, out, queue, chunk, flops, jc
+#define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, jc
     if (flops) {
         VK_STAGED(k_validate_edges, , true)
     } else {
@@ -1165,13 +1374,12 @@ hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const 
     return hipGetLastError();
 }
 
-hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed_in, const float *qa,
-                                    const float *qb, const int32_t *nst, int64_t e, float res,
-                                    uint8_t *out, hipStream_t s) {
+hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed_in, const EdgeSrc &src,
+                                    int64_t e, float res, uint8_t *out, hipStream_t s) {
     const dim3 grid_(1), block_(kWave);
     const size_t base_nojc_ = walk_lds_bytes(rb, kWave, false), base_jc_ = walk_lds_bytes(rb, kWave, true);
     const size_t max_lds_ = device_max_lds();
-#define ARGS_ rb, ed, ed.rec, qa, qb, nst, e, res, out, jc
+#define ARGS_ rb, ed, ed.rec, src, e, res, out, jc
     VK_STAGED(k_validate_edge_one)
 #undef ARGS_
     return hipGetLastError();

@@ -12,13 +12,19 @@ hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int6
 hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const float *q,
                                   int64_t n, int64_t ldq, uint8_t *out, hipStream_t s);
 hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s);
-hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const float *qa,
-                                 const float *qb, const int32_t *nst, int64_t n_edges, float res,
-                                 uint8_t *out, unsigned long long *queue, int grid, int block,
-                                 hipStream_t s, unsigned long long *flops = nullptr);
-hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed,
-                                    const float *qa, const float *qb, const int32_t *nst,
+hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
+                                 int64_t n_edges, float res, uint8_t *out,
+                                 unsigned long long *queue, int grid, int block, hipStream_t s,
+                                 unsigned long long *flops = nullptr);
+hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                     int64_t e, float res, uint8_t *out, hipStream_t s);
+// kNN runs as partial lists over candidate parts plus a merge; the partial lists need a
+// workspace of knn_workspace_bytes(n, k) bytes.
+int knn_parts(int64_t n);
+size_t knn_workspace_bytes(int64_t n, int k);
+hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, float *d2,
+                      void *workspace, hipStream_t s);
+hipError_t launch_knn_pairs(const int32_t *idx, int64_t n, int k, int32_t *pairs, hipStream_t s);
 hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, float *cost, hipStream_t s);
 size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, bool jc);

@@ -127,6 +127,17 @@ struct EnvDev {
 };
 
 // One edge set of a mixed-robot batch.
+// Where the endpoints of edge e come from: rows e of qa and qb (pairs == nullptr), or rows
+// pairs[2e] and pairs[2e+1] of the node array qa ([n_nodes][dof]).  nst, when not null, gives
+// each edge's state count.
+struct EdgeSrc {
+    const float *qa;
+    const float *qb;
+    const int32_t *pairs;
+    int64_t n_nodes;
+    const int32_t *nst;
+};
+
 struct BatchSet {
     RobotDev rb;
     EnvDev env;

@@ -15,6 +15,9 @@ Workloads (sizes are the defaults; tests pass smaller ``n``):
 ``states14_cloud`` two 7-DoF arms on a torso (120 spheres, 1,500 pairs); 300 spheres + a
                    20,000-point cloud; 2^20 uniform states
 ``cost7``          the states7 robot and scene; 4,096 trajectories x 64 waypoints
+``prm7_shelf``     the 7-DoF robot in the shelf scene; 8,192 roadmap samples, k = 10
+``shortcut7_shelf`` the 7-DoF robot in the shelf scene; 4,096 jittered straight paths of 32
+                   waypoints, 8 random shortcut candidates per path (32,768 edges)
 ``mixed``          1,024 edge sets over the 7/8/14-DoF robots, lognormal(4, 1) edges per set,
                    a random scene of 50-300 primitives per set
 =================  ============================================================================
@@ -61,6 +64,15 @@ def trajectories(g: np.random.Generator, dof: int, n_traj: int, n_way: int = 64,
     q[:, 1:-1, :] += g.normal(0.0, sigma, (n_traj, n_way - 2, dof))
     q = np.clip(q, -limit, limit).reshape(n_traj * n_way, dof).astype(np.float32)
     return np.ascontiguousarray(q.T)
+
+
+def shortcut_pairs(g: np.random.Generator, n_paths: int, n_way: int, per_path: int) -> np.ndarray:
+    """Random shortcut candidates (i < j, j - i >= 2) between waypoints of each path, as node
+    index pairs; waypoint w of path p is node p * n_way + w."""
+    i = g.integers(0, n_way - 2, (n_paths, per_path))
+    j = i + 2 + np.floor(g.random((n_paths, per_path)) * (n_way - 2 - i)).astype(np.int64)
+    base = (np.arange(n_paths) * n_way)[:, None]
+    return np.stack([base + i, base + j], axis=-1).reshape(-1, 2).astype(np.int32)
 
 
 def robot7():
@@ -127,6 +139,21 @@ def workload(name: str, n: int | None = None, variant: int = 0) -> dict:
         env = point_cloud_scene(rng("states14_cloud", "env"), mounts=TORSO_MOUNTS)
         q = uniform_states(rng("states14_cloud", "q"), robot["dof"], n or (1 << 20))
         return {"name": name, "robot": robot, "env": env, "q": q}
+    if name == "prm7_shelf":
+        # PRM roadmap: samples uniform in the limits, each joined to its k nearest
+        robot = robot7()
+        env = shelf_scene(rng("shelf", "env"))
+        nodes = uniform_states(rng("prm7_shelf", "nodes"), robot["dof"], n or 8192, layout="aos")
+        return {"name": name, "robot": robot, "env": env, "nodes": nodes, "k": 10}
+    if name == "shortcut7_shelf":
+        # shortcut candidates on many jittered straight-line paths of 32 waypoints each
+        robot = robot7()
+        env = shelf_scene(rng("shelf", "env"))
+        n_paths, n_way = n or 4096, 32
+        way = trajectories(rng("shortcut7_shelf", "paths"), robot["dof"], n_paths, n_way)
+        nodes = np.ascontiguousarray(way.T)
+        pairs = shortcut_pairs(rng("shortcut7_shelf", "pairs"), n_paths, n_way, 8)
+        return {"name": name, "robot": robot, "env": env, "nodes": nodes, "pairs": pairs}
     if name == "cost7":
         robot = robot7()
         env = cube_scene(rng("states7", "env"))

@@ -53,7 +53,7 @@ def test_schedule_invariance(vk):
     r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
     qa, qb = dev(w["qa"]), dev(w["qb"])
     ref = host(vk.validate_edges(r, e, qa, qb, per_edge=True))
-    for block, bpc in ((64, 1), (128, 3), (256, 8), (192, 2), (256, 1)):
+    for block, bpc in ((64, 1), (128, 3), (256, 8), (192, 2), (256, 1), (512, 4), (1024, 2), (960, 1)):
         say("launch", block, bpc)
         vk.set_edge_launch(block, bpc)
         np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb)), ref)
