@@ -51,7 +51,10 @@ typedef struct {
     const double *sphere_xyzr;    /* [S][4] centre in its link frame, radius              */
     int n_pairs;
     const int32_t *pairs;         /* [P][2] self-collision sphere pairs                    */
+    const int32_t *joint_type;    /* [dof] 0 revolute, 1 prismatic; NULL = all revolute     */
 } orc_robot;
+
+static int prismatic(const orc_robot *rb, int j) { return rb->joint_type && rb->joint_type[j] == 1; }
 
 typedef struct {
     int n_spheres;   const double *spheres;    /* [n][4]  centre, radius                    */
@@ -98,7 +101,10 @@ static void dh_matrix(double a, double d, double ca, double sa, double theta, do
 
 /*
  * Forward kinematics (Sec. III-B): pose of every link for one configuration.
- *   T_0 = I;  P_j = T_parent(j) * M_j;  T_{j+1} = P_j * A(q_j + theta_offset_j).
+ *   T_0 = I;  P_j = T_parent(j) * M_j;
+ *   revolute:  T_{j+1} = P_j * Rz(q_j + theta_offset_j) Tz(d_j) Tx(a_j) Rx(alpha_j),
+ *   prismatic: T_{j+1} = P_j * Rz(theta_offset_j) Tz(d_j + q_j) Tx(a_j) Rx(alpha_j)
+ * (a prismatic joint slides along the z axis of P_j by q_j).
  * link_T: [(dof+1)][12] row-major 3x4 of every link (link 0 first).
  * joint_P: [dof][12] frame of each joint (its z column is the rotation axis, its last column
  * the point the axis passes through); may be NULL.
@@ -111,7 +117,10 @@ void orc_fk(const orc_robot *rb, const double *q, double *link_T, double *joint_
         const double *dh = rb->dh + 5 * j;
         mat_from_3x4(rb->mount + 12 * j, M);
         mat_mul(T[rb->parent_link[j]], M, P);
-        dh_matrix(dh[0], dh[1], dh[2], dh[3], q[j] + dh[4], A);
+        if (prismatic(rb, j))
+            dh_matrix(dh[0], dh[1] + q[j], dh[2], dh[3], dh[4], A);
+        else
+            dh_matrix(dh[0], dh[1], dh[2], dh[3], q[j] + dh[4], A);
         mat_mul(P, A, T[j + 1]);
         if (joint_P) memcpy(joint_P + 12 * j, P, 12 * sizeof(double));
     }
@@ -436,9 +445,16 @@ void orc_cost_grad(const orc_robot *rb, const orc_env *env, const double *q, dou
         double acc = 0.0;
         for (int s = 0; s < S; ++s) {
             if (!moved_by(rb, rb->sphere_link[s], j)) continue;
+            /* Jacobian column of the sphere centre: z x (c - o) for a revolute joint, z for a
+             * prismatic one */
             double v[3] = {c[3 * s] - o[0], c[3 * s + 1] - o[1], c[3 * s + 2] - o[2]};
             double jc[3] = {z[1] * v[2] - z[2] * v[1], z[2] * v[0] - z[0] * v[2],
                             z[0] * v[1] - z[1] * v[0]};
+            if (prismatic(rb, j)) {
+                jc[0] = z[0];
+                jc[1] = z[1];
+                jc[2] = z[2];
+            }
             acc += dot3(jc, f + 3 * s);
         }
         grad[j] = acc;

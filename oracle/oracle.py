@@ -39,7 +39,7 @@ class _Robot(C.Structure):
                 ("mount", C.POINTER(C.c_double)), ("dh", C.POINTER(C.c_double)),
                 ("n_spheres", C.c_int), ("sphere_link", C.POINTER(C.c_int32)),
                 ("sphere_xyzr", C.POINTER(C.c_double)), ("n_pairs", C.c_int),
-                ("pairs", C.POINTER(C.c_int32))]
+                ("pairs", C.POINTER(C.c_int32)), ("joint_type", C.POINTER(C.c_int32))]
 
 
 class _Env(C.Structure):
@@ -114,9 +114,12 @@ class Robot:
         self.sphere_xyzr = _f64(desc["sphere_xyzr"], (-1, 4))
         self.pairs = np.ascontiguousarray(np.asarray(desc["self_pairs"], dtype=np.int32).reshape(-1, 2))
         self.n_spheres = len(self.sphere_link)
+        jt = desc.get("joint_type")
+        self.joint_type = None if jt is None else np.ascontiguousarray(jt, dtype=np.int32)
         self.c = _Robot(dof, _ip(self.parent_link), _dp(self.mount), _dp(self.dh),
                         self.n_spheres, _ip(self.sphere_link), _dp(self.sphere_xyzr),
-                        len(self.pairs), _ip(self.pairs))
+                        len(self.pairs), _ip(self.pairs),
+                        None if self.joint_type is None else _ip(self.joint_type))
 
 
 class Env:

@@ -6,7 +6,7 @@ no collision test.  The robot and scene layouts follow the workloads described f
 method's evaluation (7-, 8- and 14-DoF arms; shelf, tabletop and cluttered scenes), drawn from
 one root seed so every consumer sees bit-identical inputs.
 """
-from .robots import (chain_robot, bimanual_robot, robot_summary, link_parents,
+from .robots import (chain_robot, bimanual_robot, lift_arm_robot, robot_summary, link_parents,
                      candidate_pairs)
 from .scenes import (cube_scene, shelf_scene, point_cloud_scene, random_scene,
                      empty_scene, scene_summary)
@@ -14,7 +14,7 @@ from .workloads import (ROOT_SEED, rng, uniform_states, uniform_edges, trajector
                         workload, pack_edge_sets)
 
 __all__ = [
-    "chain_robot", "bimanual_robot", "robot_summary", "link_parents", "candidate_pairs",
+    "chain_robot", "bimanual_robot", "lift_arm_robot", "robot_summary", "link_parents", "candidate_pairs",
     "cube_scene", "shelf_scene", "point_cloud_scene", "random_scene", "empty_scene",
     "scene_summary", "ROOT_SEED", "rng", "uniform_states", "uniform_edges", "trajectories",
     "workload", "pack_edge_sets",

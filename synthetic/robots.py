@@ -127,6 +127,35 @@ def chain_robot(g: np.random.Generator, dof: int, spheres_per_link: int,
                    n_pairs, g)
 
 
+LIFT_RANGE = (0.0, 0.4)
+
+
+def lift_arm_robot(g: np.random.Generator, arm_dof: int = 7, spheres_per_link: int = 6,
+                   torso_spheres: int = 4, n_pairs: int | None = None) -> dict:
+    """A mobile-manipulator-like tree: joint 0 is a prismatic lift along the base z axis
+    (stroke LIFT_RANGE, frame 0.3 m up at zero stroke) carrying a torso column (link 1,
+    spheres below the lift frame) and a revolute arm on top of it (joints 1..arm_dof)."""
+    dof = arm_dof + 1
+    dh = np.concatenate([np.array([[0.0, 0.3, 1.0, 0.0, 0.0]]), _draw_joints(g, arm_dof)], axis=0)
+    parent_link = np.arange(dof)
+    mount = np.tile(_identity_mount(), (dof, 1))
+    z = -0.1 * np.arange(0, torso_spheres)
+    r = g.uniform(0.05, 0.08, torso_spheres)
+    rows = [np.stack([np.zeros_like(z), np.zeros_like(z), z, r], axis=1)]
+    links = [1] * torso_spheres
+    counts = [0, torso_spheres]
+    for j in range(1, dof):
+        rows.append(_link_spheres(g, dh[j], spheres_per_link))
+        links += [j + 1] * spheres_per_link
+        counts.append(spheres_per_link)
+    xyzr = np.concatenate(rows, axis=0)
+    robot = _finish(dof, parent_link, mount, dh, np.array(links), xyzr, np.array(counts),
+                    n_pairs, g)
+    robot["joint_type"] = np.array([1] + [0] * arm_dof, dtype=np.int32)
+    robot["q_lo"][0], robot["q_hi"][0] = LIFT_RANGE
+    return robot
+
+
 def bimanual_robot(g: np.random.Generator, arm_dof: int = 7, spheres_per_link: int = 8,
                    torso_spheres: int = 8, n_pairs: int | None = None) -> dict:
     """Two serial arms mounted left and right on a fixed torso (link 0)."""

@@ -12,6 +12,8 @@ Workloads (sizes are the defaults; tests pass smaller ``n``):
 ``edges7_shelf``   the same 7-DoF robot in the shelf scene (100 boxes + 50 capsules);
                    65,536 edges with endpoints uniform in the limits
 ``edges8_shelf``   8-DoF chain, 4 base + 8x7 spheres (60), 400 pairs; shelf scene; 65,536 edges
+``edges8p_shelf``  prismatic lift (0-0.4 m) + 7-DoF arm, 4 torso + 7x6 spheres (46), 400 pairs;
+                   shelf scene; 65,536 edges uniform in each joint's range
 ``states14_cloud`` two 7-DoF arms on a torso (120 spheres, 1,500 pairs); 300 spheres + a
                    20,000-point cloud; 2^20 uniform states
 ``cost7``          the states7 robot and scene; 4,096 trajectories x 64 waypoints
@@ -28,7 +30,7 @@ import zlib
 
 import numpy as np
 
-from .robots import chain_robot, bimanual_robot, Q_LIMIT
+from .robots import chain_robot, bimanual_robot, lift_arm_robot, Q_LIMIT
 from .scenes import cube_scene, shelf_scene, point_cloud_scene, random_scene
 
 ROOT_SEED = 230914545
@@ -47,10 +49,14 @@ def uniform_states(g: np.random.Generator, dof: int, n: int, limit: float = Q_LI
     return np.ascontiguousarray(q.T) if layout == "soa" else q
 
 
-def uniform_edges(g: np.random.Generator, dof: int, n: int, limit: float = Q_LIMIT):
-    """n edges; endpoints uniform in the limits; AoS [n][dof] each."""
-    qa = g.uniform(-limit, limit, (n, dof)).astype(np.float32)
-    qb = g.uniform(-limit, limit, (n, dof)).astype(np.float32)
+def uniform_edges(g: np.random.Generator, dof: int, n: int, limit: float = Q_LIMIT,
+                  lo=None, hi=None):
+    """n edges; endpoints uniform in the limits (per joint when lo/hi are given); AoS [n][dof]
+    each."""
+    lo = -limit if lo is None else np.asarray(lo, np.float64)
+    hi = limit if hi is None else np.asarray(hi, np.float64)
+    qa = g.uniform(lo, hi, (n, dof)).astype(np.float32)
+    qb = g.uniform(lo, hi, (n, dof)).astype(np.float32)
     return qa, qb
 
 
@@ -77,6 +83,11 @@ def shortcut_pairs(g: np.random.Generator, n_paths: int, n_way: int, per_path: i
 
 def robot7():
     return chain_robot(rng("robot7", "robot"), dof=7, spheres_per_link=6)
+
+
+def robot8p():
+    return lift_arm_robot(rng("robot8p", "robot"), arm_dof=7, spheres_per_link=6, torso_spheres=4,
+                          n_pairs=400)
 
 
 def robot8():
@@ -133,6 +144,13 @@ def workload(name: str, n: int | None = None, variant: int = 0) -> dict:
         robot = robot8()
         env = shelf_scene(rng("shelf", "env"))
         qa, qb = uniform_edges(rng("edges8_shelf", "edges"), robot["dof"], n or 65536)
+        return {"name": name, "robot": robot, "env": env, "qa": qa, "qb": qb}
+    if name == "edges8p_shelf":
+        # prismatic lift + 7-DoF arm in the shelf scene; endpoints uniform in each joint's range
+        robot = robot8p()
+        env = shelf_scene(rng("shelf", "env"))
+        qa, qb = uniform_edges(rng("edges8p_shelf", "edges"), robot["dof"], n or 65536,
+                               lo=robot["q_lo"], hi=robot["q_hi"])
         return {"name": name, "robot": robot, "env": env, "qa": qa, "qb": qb}
     if name == "states14_cloud":
         robot = robot14()

@@ -7,7 +7,7 @@ one gradient component to zero.
 import numpy as np
 import pytest
 
-from synthetic import workload, chain_robot, rng, empty_scene
+from synthetic import workload, chain_robot, lift_arm_robot, rng, empty_scene
 
 
 def _one_link():
@@ -121,3 +121,32 @@ def test_jacobian_column_matches_centre_differences(orc):
 def test_non_finite_cost(orc):
     assert np.isnan(orc.cost(_one_link(), {}, [np.nan]))
     assert np.isnan(orc.cost_grad(_one_link(), {}, [np.inf])).all()
+
+
+def test_prismatic_gradient_and_jacobian(orc):
+    """A prismatic lift: its Jacobian column is the slide axis itself (every sphere above it
+    moves with unit speed along the axis), and the analytic gradient matches central
+    differences of the cost."""
+    g = rng("pins", "lift")
+    robot = lift_arm_robot(g, 4, 3, 3)
+    env = {"boxes": np.array([[0.2, 0.1, 0.45, 1, 0, 0, 0, 1, 0, 0, 0, 1, 0.25, 0.2, 0.1]]),
+           "spheres": np.array([[0.0, 0.2, 0.6, 0.2]])}
+    rb, ev = orc.Robot(robot), orc.Env(env)
+    lo, hi = robot["q_lo"].astype(np.float64), robot["q_hi"].astype(np.float64)
+    checked = 0
+    for _ in range(300):
+        q = g.uniform(lo, hi)
+        _, P = orc.fk(rb, q)
+        h = 1e-6
+        qp, qm = q.copy(), q.copy()
+        qp[0] += h
+        qm[0] -= h
+        dc = (orc.sphere_centres(rb, qp) - orc.sphere_centres(rb, qm)) / (2 * h)
+        np.testing.assert_allclose(dc, np.tile(P[0][:, 2], (len(dc), 1)), atol=1e-8)
+        if orc.cost(rb, ev, q) == 0.0:
+            continue
+        ga = orc.cost_grad(rb, ev, q)
+        gf = orc.cost_grad_fd(rb, ev, q)
+        assert np.linalg.norm(ga - gf) <= 1e-6 * max(np.linalg.norm(ga), 1e-3)
+        checked += 1
+    assert checked > 20

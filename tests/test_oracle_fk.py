@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from synthetic import chain_robot, bimanual_robot, rng
+from synthetic import chain_robot, bimanual_robot, lift_arm_robot, rng
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -28,6 +28,7 @@ def _robot_from_case(case):
         "sphere_link": spheres[:, 0].astype(np.int32),
         "sphere_xyzr": spheres[:, 1:5],
         "self_pairs": np.zeros((0, 2), np.int32),
+        "joint_type": np.asarray(case["joint_type"], np.int32) if "joint_type" in case else None,
     }
 
 
@@ -64,13 +65,18 @@ def _rodrigues(axis, angle):
     return np.eye(3) + np.sin(angle) * k + (1 - np.cos(angle)) * k @ k
 
 
-@pytest.mark.parametrize("kind", ["chain7", "chain8", "bimanual"])
+@pytest.mark.parametrize("kind", ["chain7", "chain8", "bimanual", "lift"])
 def test_product_of_exponentials(orc, kind):
     """A second formulation: T_link(q) = prod_{j in path} exp(xi_j q_j) * T_link(0), with the
-    twists xi_j taken from the joint axes and points at the zero pose."""
+    twists xi_j taken from the joint axes and points at the zero pose: a rotation about the
+    axis through the point for a revolute joint, a translation along the axis for a prismatic
+    one."""
     g = rng("pins", kind)
     robot = {"chain7": lambda: chain_robot(g, 7, 2), "chain8": lambda: chain_robot(g, 8, 2, 2),
-             "bimanual": lambda: bimanual_robot(g, 3, 2, 2)}[kind]()
+             "bimanual": lambda: bimanual_robot(g, 3, 2, 2),
+             "lift": lambda: lift_arm_robot(g, 4, 2, 2)}[kind]()
+    jt = robot.get("joint_type")
+    jt = np.zeros(robot["dof"], int) if jt is None else jt
     dof = robot["dof"]
     T0, P0 = orc.fk(robot, np.zeros(dof))
     parent = np.concatenate([[-1], robot["parent_link"]])
@@ -85,11 +91,14 @@ def test_product_of_exponentials(orc, kind):
                 k = parent[k]
             M = np.eye(4)
             for j in reversed(path):       # base-most joint first
-                R = _rodrigues(P0[j][:, 2], q[j])
-                o = P0[j][:, 3]
                 E = np.eye(4)
-                E[:3, :3] = R
-                E[:3, 3] = o - R @ o
+                if jt[j] == 1:
+                    E[:3, 3] = P0[j][:, 2] * q[j]
+                else:
+                    R = _rodrigues(P0[j][:, 2], q[j])
+                    o = P0[j][:, 3]
+                    E[:3, :3] = R
+                    E[:3, 3] = o - R @ o
                 M = M @ E
             Tz = np.eye(4)
             Tz[:3, :] = T0[link]
