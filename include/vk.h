@@ -51,11 +51,14 @@ typedef struct vk_env_s *vk_env;
 typedef struct vk_edge_batch_s *vk_edge_batch;
 
 /*
- * Robot: a revolute kinematic tree whose links carry collision spheres (Sec. III-C).
- * Links are numbered 0..dof; link 0 is the fixed base at the world origin; joint j moves link
- * j+1 and hangs off link parent_link[j] (0 <= parent_link[j] <= j).  Frames follow standard DH:
- *   P_j = T_parent(j) * M_j,  T_{j+1} = P_j * Rz(q_j + theta_offset_j) Tz(d_j) Tx(a_j) Rx(alpha_j)
- * and joint j turns about the z axis of P_j.
+ * Robot: a kinematic tree of revolute and prismatic joints whose links carry collision spheres
+ * (Sec. III-C).  Links are numbered 0..dof; link 0 is the fixed base at the world origin; joint
+ * j moves link j+1 and hangs off link parent_link[j] (0 <= parent_link[j] <= j).  Frames follow
+ * standard DH (Sec. III-B), with P_j = T_parent(j) * M_j and
+ *   revolute:  T_{j+1} = P_j * Rz(q_j + theta_offset_j) Tz(d_j) Tx(a_j) Rx(alpha_j)
+ *   prismatic: T_{j+1} = P_j * Rz(theta_offset_j) Tz(d_j + q_j) Tx(a_j) Rx(alpha_j),
+ * so joint j turns about, or slides along, the z axis of P_j.  Edge discretisation treats all
+ * joint values alike (the resolution is per unit of q: radians or metres).
  */
 typedef struct {
     int32_t dof;                  /* 1..64                                                    */
@@ -69,6 +72,7 @@ typedef struct {
     const float *sphere_xyzr;     /* [S][4] centre in the link frame, radius > 0               */
     int32_t n_self_pairs;         /* P >= 0                                                    */
     const int32_t *self_pairs;    /* [P][2] sphere indices on two different links              */
+    const int32_t *joint_type;    /* [dof] 0 revolute, 1 prismatic; NULL = all revolute        */
 } vk_robot_desc;
 
 /* Environment of primitives (Sec. III-C: spheres, cylinders, cuboids; capsules = swept
@@ -86,7 +90,7 @@ typedef struct {
  * sphere of the link's spheres (the mid-phase of Sec. III-D) and orders the self pairs by
  * their later link so each is tested right after that link is posed (interleaving,
  * Sec. III-D).  Errors: VK_ERR_INVALID_ARG for a bad parent, link index, sphere order, radius
- * <= 0 or a pair on one link; VK_ERR_UNSUPPORTED for dof > 64. */
+ * <= 0, a pair on one link or a joint type other than 0/1; VK_ERR_UNSUPPORTED for dof > 64. */
 vk_status vk_robot_create(const vk_robot_desc *desc, vk_robot *out);
 vk_status vk_robot_destroy(vk_robot robot);
 int32_t vk_robot_dof(vk_robot robot);

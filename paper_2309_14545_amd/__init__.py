@@ -41,7 +41,7 @@ class _RobotDesc(C.Structure):
                 ("q_lo", C.POINTER(C.c_float)), ("q_hi", C.POINTER(C.c_float)),
                 ("n_spheres", C.c_int32), ("sphere_link", C.POINTER(C.c_int32)),
                 ("sphere_xyzr", C.POINTER(C.c_float)), ("n_self_pairs", C.c_int32),
-                ("self_pairs", C.POINTER(C.c_int32))]
+                ("self_pairs", C.POINTER(C.c_int32)), ("joint_type", C.POINTER(C.c_int32))]
 
 
 class _EnvDesc(C.Structure):
@@ -133,10 +133,12 @@ class Robot:
             "sphere_link": _i32(desc["sphere_link"], (-1,)),
             "sphere_xyzr": _f32(desc["sphere_xyzr"], (-1, 4)),
             "self_pairs": _i32(desc.get("self_pairs", np.zeros((0, 2))), (-1, 2)),
+            "joint_type": _i32(desc["joint_type"], (-1,)) if desc.get("joint_type") is not None else None,
         }
         d = _RobotDesc(dof, _ip(keep["parent_link"]), _fp(keep["mount"]), _fp(keep["dh"]), None,
                        None, len(keep["sphere_link"]), _ip(keep["sphere_link"]),
-                       _fp(keep["sphere_xyzr"]), len(keep["self_pairs"]), _ip(keep["self_pairs"]))
+                       _fp(keep["sphere_xyzr"]), len(keep["self_pairs"]), _ip(keep["self_pairs"]),
+                       _ip(keep["joint_type"]))
         h = C.c_void_p()
         _check(lib().vk_robot_create(C.byref(d), C.byref(h)))
         self.handle = h

@@ -346,6 +346,11 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
         J.ca = h[2];
         J.sa = h[3];
         J.theta_off = h[4];
+        J.s_off = (float)std::sin((double)h[4]);
+        J.c_off = (float)std::cos((double)h[4]);
+        J.prismatic = d->joint_type ? d->joint_type[j] : 0;
+        if (J.prismatic != 0 && J.prismatic != 1)
+            raise(VK_ERR_INVALID_ARG, "joint_type must be 0 (revolute) or 1 (prismatic)");
         J.twist = (h[2] == 1.0f && h[3] == 0.0f)    ? kTwist0
                   : (h[2] == 0.0f && h[3] == 1.0f)  ? kTwistP90
                   : (h[2] == 0.0f && h[3] == -1.0f) ? kTwistM90

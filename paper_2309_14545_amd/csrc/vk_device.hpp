@@ -37,24 +37,45 @@ __device__ __forceinline__ void frame_mount(Frame &T, const float *m) {
     T.p[2] = p[2];
 }
 
+// Values of one joint at q: sine and cosine of the DH angle and the offset along z.  A revolute
+// joint turns (angle q + theta_off, offset d); a prismatic joint slides (angle theta_off, whose
+// sine and cosine come with the record, offset d + q).
+struct JointVal {
+    float s, c, d;
+};
+
+__device__ __forceinline__ JointVal joint_val(const JointRec &J, float q) {
+    JointVal v;
+    if (J.prismatic) {
+        v.s = J.s_off;
+        v.c = J.c_off;
+        v.d = J.d + q;
+    } else {
+        sincosf(q + J.theta_off, &v.s, &v.c);
+        v.d = J.d;
+    }
+    return v;
+}
+
 // T <- T * Rz(theta) Tz(d) Tx(a) Rx(alpha): the standard DH link transform (Sec. III-B).
 // Column form: c0' = c c0 + s c1, c1' = -s c0 + c c1, p' = p + d c2 + a c0', then the twist
-// mixes c1' and c2.  Twists of 0 and +-90 degrees are folded (no multiplies).
-// DH update with the joint angle given by its sine and cosine (theta + theta_off).
-__device__ __forceinline__ void frame_dh_sc(Frame &T, const JointRec &J, float s, float c) {
+// mixes c1' and c2.  Twists of 0 and +-90 degrees are folded (no multiplies); the twist is
+// wave-uniform, so the switch sits outside the row loop.
+template <int TW>
+__device__ __forceinline__ void frame_dh_rows(Frame &T, const JointRec &J, const JointVal &v) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const float c0 = T.r[3 * i], c1 = T.r[3 * i + 1], c2 = T.r[3 * i + 2];
-        const float n0 = fmaf(c, c0, s * c1);
-        const float n1 = fmaf(c, c1, -s * c0);
-        T.p[i] = fmaf(J.a, n0, fmaf(J.d, c2, T.p[i]));
+        const float n0 = fmaf(v.c, c0, v.s * c1);
+        const float n1 = fmaf(v.c, c1, -v.s * c0);
+        T.p[i] = fmaf(J.a, n0, fmaf(v.d, c2, T.p[i]));
         T.r[3 * i] = n0;
-        if (J.twist == kTwist0) {
+        if (TW == kTwist0) {
             T.r[3 * i + 1] = n1;
-        } else if (J.twist == kTwistP90) {
+        } else if (TW == kTwistP90) {
             T.r[3 * i + 1] = c2;
             T.r[3 * i + 2] = -n1;
-        } else if (J.twist == kTwistM90) {
+        } else if (TW == kTwistM90) {
             T.r[3 * i + 1] = -c2;
             T.r[3 * i + 2] = n1;
         } else {
@@ -64,21 +85,27 @@ __device__ __forceinline__ void frame_dh_sc(Frame &T, const JointRec &J, float s
     }
 }
 
-__device__ __forceinline__ void frame_dh(Frame &T, const JointRec &J, float theta) {
-    float s, c;
-    sincosf(theta + J.theta_off, &s, &c);
-    frame_dh_sc(T, J, s, c);
+__device__ __forceinline__ void frame_dh_val(Frame &T, const JointRec &J, const JointVal &v) {
+    switch (J.twist) {
+    case kTwist0: frame_dh_rows<kTwist0>(T, J, v); break;
+    case kTwistP90: frame_dh_rows<kTwistP90>(T, J, v); break;
+    case kTwistM90: frame_dh_rows<kTwistM90>(T, J, v); break;
+    default: frame_dh_rows<kTwistGeneral>(T, J, v); break;
+    }
+}
+
+__device__ __forceinline__ void frame_dh(Frame &T, const JointRec &J, float q) {
+    frame_dh_val(T, J, joint_val(J, q));
 }
 
 // Full joint update: optional mount, then the DH transform.
-__device__ __forceinline__ void frame_joint(Frame &T, const JointRec &J, float q) {
+__device__ __forceinline__ void frame_joint_val(Frame &T, const JointRec &J, const JointVal &v) {
     if (J.has_mount) frame_mount(T, J.m);
-    frame_dh(T, J, q);
+    frame_dh_val(T, J, v);
 }
 
-__device__ __forceinline__ void frame_joint_sc(Frame &T, const JointRec &J, float s, float c) {
-    if (J.has_mount) frame_mount(T, J.m);
-    frame_dh_sc(T, J, s, c);
+__device__ __forceinline__ void frame_joint(Frame &T, const JointRec &J, float q) {
+    frame_joint_val(T, J, joint_val(J, q));
 }
 
 // World position of a point given in the frame's coordinates.

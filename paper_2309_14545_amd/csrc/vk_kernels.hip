@@ -184,13 +184,25 @@ struct StepCache {
         y = base[(st * 3 + 1) * kWave + lane];
         z = base[(st * 3 + 2) * kWave + lane];
     }
-    __device__ __forceinline__ void put_sc(int j, float s, float c) const {
-        base[joint_off + (j * 2 + 0) * kWave + lane] = s;
-        base[joint_off + (j * 2 + 1) * kWave + lane] = c;
+    // joint values: (sin, cos) of a revolute joint's angle, (offset, unused) of a prismatic one
+    __device__ __forceinline__ void put_val(int j, const JointRec &J, const JointVal &v) const {
+        base[joint_off + (j * 2 + 0) * kWave + lane] = J.prismatic ? v.d : v.s;
+        base[joint_off + (j * 2 + 1) * kWave + lane] = v.c;
     }
-    __device__ __forceinline__ void get_sc(int j, float &s, float &c) const {
-        s = base[joint_off + (j * 2 + 0) * kWave + lane];
-        c = base[joint_off + (j * 2 + 1) * kWave + lane];
+    __device__ __forceinline__ JointVal get_val(int j, const JointRec &J) const {
+        const float u = base[joint_off + (j * 2 + 0) * kWave + lane];
+        const float w = base[joint_off + (j * 2 + 1) * kWave + lane];
+        JointVal v;
+        if (J.prismatic) {
+            v.s = J.s_off;
+            v.c = J.c_off;
+            v.d = u;
+        } else {
+            v.s = u;
+            v.c = w;
+            v.d = J.d;
+        }
+        return v;
     }
 };
 
@@ -222,21 +234,17 @@ __device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, 
         for (int k = 0; k < S.restart_len; ++k) {
             const int j = ld(rb.paths, S.restart_off + k);
             const JointRec J = ld(rb.joints, j);
-            if (sc && sc->joint_off >= 0) {
-                float sj, cj;
-                sc->get_sc(j, sj, cj);
-                frame_joint_sc(T, J, sj, cj);
-            } else {
+            if (sc && sc->joint_off >= 0)
+                frame_joint_val(T, J, sc->get_val(j, J));
+            else
                 frame_joint(T, J, q(j));
-            }
             w.add(flop::kFk, flop::kJoint + (J.has_mount ? flop::kMount : 0));
         }
     }
     const JointRec J = ld(rb.joints, S.joint);
-    float sj, cj;
-    sincosf(q(S.joint) + J.theta_off, &sj, &cj);
-    if (sc && sc->joint_off >= 0) sc->put_sc(S.joint, sj, cj);
-    frame_joint_sc(T, J, sj, cj);
+    const JointVal v = joint_val(J, q(S.joint));
+    if (sc && sc->joint_off >= 0) sc->put_val(S.joint, J, v);
+    frame_joint_val(T, J, v);
     w.add(flop::kFk, flop::kJoint + (J.has_mount ? flop::kMount : 0));
 }
 
@@ -259,13 +267,10 @@ __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B
     for (int k = k0; k < B.path_len; ++k) {
         const int j = ld(rb.paths, B.path_off + k);
         const JointRec J = ld(rb.joints, j);
-        if (sc.joint_off >= 0) {
-            float sj, cj;
-            sc.get_sc(j, sj, cj);
-            frame_joint_sc(Ta, J, sj, cj);
-        } else {
+        if (sc.joint_off >= 0)
+            frame_joint_val(Ta, J, sc.get_val(j, J));
+        else
             frame_joint(Ta, J, q(j));
-        }
         w.add(flop::kSelf, flop::kJoint + (J.has_mount ? flop::kMount : 0));
     }
     ta_link = B.link;
@@ -1037,7 +1042,9 @@ __global__ void __launch_bounds__(256)
         const float Mx = slots.at(l, 3) - (oy * Fz - oz * Fy);
         const float My = slots.at(l, 4) - (oz * Fx - ox * Fz);
         const float Mz = slots.at(l, 5) - (ox * Fy - oy * Fx);
-        const float g = fmaf(zx, Mx, fmaf(zy, My, zz * Mz));
+        // revolute: z . (M - o x F); prismatic: the force along the slide axis, z . F
+        const float g = J.prismatic ? fmaf(zx, Fx, fmaf(zy, Fy, zz * Fz))
+                                    : fmaf(zx, Mx, fmaf(zy, My, zz * Mz));
         if (active) grad[j * ldg + i] = finite ? gc * g : __builtin_nanf("");
         frame_dh(T, J, qs(j));
         cur = l;

@@ -26,13 +26,16 @@ constexpr int kMaxDof = 64;
 // specialised update).
 enum Twist : int32_t { kTwist0 = 0, kTwistP90 = 1, kTwistM90 = 2, kTwistGeneral = 3 };
 
-struct JointRec {                  // 80 bytes
+struct JointRec {                  // 96 bytes
     float a, d, ca, sa;            // DH length, offset, cos/sin of twist
     float theta_off;
+    float s_off, c_off;            // sin/cos of theta_off (the fixed angle of a prismatic joint)
     int32_t twist;                 // Twist
     int32_t has_mount;             // 0: mount is identity
     int32_t parent;                // link the joint hangs off
+    int32_t prismatic;             // 1: slides along z by q (offset d + q), 0: turns by q
     float m[12];                   // mount, row-major 3x4
+    float pad;
 };
 
 // One link step.  If `joint` >= 0 the step first poses link joint+1: when `restart_len` >= 0

@@ -38,6 +38,15 @@ def _cases():
         cyl.append(np.concatenate([g.uniform(-1, 1, 3), w_, [g.uniform(.05, .3), g.uniform(.03, .15)]]))
     env["cylinders"] = np.asarray(cyl, np.float32)
     yield "bimanual14_mixed", r14, env, uniform_states(rng("gpu-cost", "q14"), 14, 64 * 24), 64
+    # prismatic lift + arm, trajectories within each joint's range, shelf scene
+    wl = workload("edges8p_shelf", n=1)
+    rl = wl["robot"]
+    g = rng("gpu-cost", "lift")
+    a = g.uniform(rl["q_lo"], rl["q_hi"], (24, 1, 8))
+    b = g.uniform(rl["q_lo"], rl["q_hi"], (24, 1, 8))
+    t = np.linspace(0.0, 1.0, 64)[None, :, None]
+    ql = (a + t * (b - a)).reshape(-1, 8).astype(np.float32)
+    yield "lift8_shelf", rl, wl["env"], np.ascontiguousarray(ql.T), 64
 
 
 @pytest.mark.parametrize("case", list(_cases()), ids=lambda c: c[0])

@@ -20,7 +20,7 @@ def vk():
     vk.set_edge_launch(0, 0)
 
 
-@pytest.mark.parametrize("name", ["edges7_shelf", "edges8_shelf"])
+@pytest.mark.parametrize("name", ["edges7_shelf", "edges8_shelf", "edges8p_shelf"])
 @pytest.mark.parametrize("per_edge", [False, True], ids=["batched", "per_edge"])
 def test_edges_parity(vk, orc, name, per_edge):
     w = workload(name, n=1500)

@@ -27,6 +27,7 @@ def _robots():
         "chain7": workload("states7", n=1)["robot"],
         "chain8": workload("edges8_shelf", n=1)["robot"],
         "bimanual14": workload("states14_cloud", n=1)["robot"],
+        "lift8": workload("edges8p_shelf", n=1)["robot"],
     }
 
 
@@ -44,17 +45,21 @@ def test_fk_hand_values(vk, orc):
         sp = np.asarray(case["spheres"], np.float32).reshape(-1, 5)
         robot = {"dof": len(dh), "parent_link": np.asarray(case.get("parent_link", range(len(dh)))),
                  "mount": np.asarray(case["mount"], np.float32) if "mount" in case else None,
-                 "dh": dh, "sphere_link": sp[:, 0].astype(np.int32), "sphere_xyzr": sp[:, 1:]}
+                 "dh": dh, "sphere_link": sp[:, 0].astype(np.int32), "sphere_xyzr": sp[:, 1:],
+                 "joint_type": np.asarray(case["joint_type"], np.int32) if "joint_type" in case else None}
         r = vk.Robot(robot)
         c = host(vk.fk_spheres(r, dev(np.asarray(case["q"], np.float32).reshape(-1, 1))))
         np.testing.assert_allclose(c[:, :, 0], np.asarray(case["centres"]), atol=CENTRE_TOL)
 
 
-@pytest.mark.parametrize("name", ["chain7", "chain8", "bimanual14"])
+@pytest.mark.parametrize("name", ["chain7", "chain8", "bimanual14", "lift8"])
 def test_fk_spheres_parity(vk, orc, name):
     robot = _robots()[name]
     n = 1037                                  # several 256-lane blocks and a ragged tail
     q = uniform_states(rng("gpu-fk", name), robot["dof"], n)
+    if robot.get("joint_type") is not None:   # prismatic strokes within their range
+        g = rng("gpu-fk", name + "-range")
+        q = np.ascontiguousarray(g.uniform(robot["q_lo"], robot["q_hi"], (n, robot["dof"])).T.astype(np.float32))
     say("fk_spheres", name, "n", n)
     c = host(vk.fk_spheres(vk.Robot(robot), dev(q)))
     ref = _oracle_centres(orc, robot, q.astype(np.float64))
@@ -108,6 +113,12 @@ def _state_case(name):
         env = cube_scene(rng("gpu-st", "env14"), n_spheres=6, n_boxes=1,
                          mounts=((0, .25, .5), (0, -.25, .5)), sphere_r=(0.02, 0.06))
         return r, env, uniform_states(rng("gpu-st", name), 14, 1037)
+    if name == "lift8_shelf":
+        w = workload("edges8p_shelf", n=1)
+        r = w["robot"]
+        g = rng("gpu-st", name)
+        q = g.uniform(r["q_lo"], r["q_hi"], (1500, 8)).T.astype(np.float32)
+        return r, w["env"], np.ascontiguousarray(q)
     if name == "chain7_mixed_kinds":
         r = workload("states7", n=1)["robot"]
         env = random_scene(rng("gpu-st", "mixed-env"))
@@ -130,7 +141,7 @@ def _state_case(name):
 
 
 @pytest.mark.parametrize("name", ["states7", "chain8_shelf", "bimanual14_cube",
-                                  "chain7_mixed_kinds", "chain7_big_env"])
+                                  "chain7_mixed_kinds", "chain7_big_env", "lift8_shelf"])
 def test_validate_states_parity(vk, orc, name):
     robot, env, q = _state_case(name)
     say("validate_states", name, "n", q.shape[1])
