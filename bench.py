@@ -126,15 +126,19 @@ def extra_edges(vk, name, steps):
 def extra_states(vk, name, n, steps):
     import torch
     from synthetic import workload
+    from paper_2309_14545_amd import autotune
     w = workload(name, n=n)
     robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
     q = torch.from_numpy(w["q"]).cuda()
+    tuned = autotune.tune_states(robot, env, q)          # untimed schedule choice
     out = vk.validate_states(robot, env, q)
     torch.cuda.synchronize()
     ms = _events_ms(lambda: vk.validate_states(robot, env, q), steps)
     m = float(np.median(ms))
+    vk.set_states_split(0, 1)
     return {"workload": name, "states": q.shape[1], "states_per_s": q.shape[1] / (m * 1e-3),
-            "median_ms": m, "collision_rate": float(out.float().mean().item())}
+            "median_ms": m, "collision_rate": float(out.float().mean().item()),
+            "schedule_split": tuned["split"]}
 
 
 def extra_cost(vk, steps):

@@ -238,6 +238,19 @@ vk_status vk_edge_batch_destroy(vk_edge_batch batch);
 vk_status vk_set_edge_launch(int32_t block_threads, int32_t blocks_per_cu);
 vk_status vk_get_edge_launch(int32_t *block_threads, int32_t *blocks_per_cu);
 
+/*
+ * Schedule of validate_states: with num > 0 it runs in two passes.  Pass 1 tests the first
+ * floor(S * num / den) of the robot's S link steps for every state; pass 2 walks only the states still
+ * free, packed densely into waves, testing the remaining steps.  Flags are identical to one
+ * pass; the split pays off when most states collide early (a wave of independent states walks
+ * as long as its last live lane), and costs time when they do not.  (0, 1) = one pass, the
+ * default.  The project's autotuner picks it per workload.  Needs 0 <= num < den, else
+ * VK_ERR_INVALID_ARG.  The two-pass form keeps a survivor list (4 bytes per state) in a scratch
+ * buffer the library holds per stream.
+ */
+vk_status vk_set_states_split(int32_t num, int32_t den);
+vk_status vk_get_states_split(int32_t *num, int32_t *den);
+
 /* Text of the calling thread's last non-OK status ("" if none). */
 const char *vk_last_error(void);
 

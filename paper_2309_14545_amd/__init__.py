@@ -26,7 +26,8 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
            "vk_knn", "vk_knn_pairs", "penetration_cost_fwd", "penetration_cost_bwd",
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_destroy",
-           "vk_set_edge_launch", "vk_get_edge_launch", "vk_last_error")
+           "vk_set_edge_launch", "vk_get_edge_launch", "vk_set_states_split",
+           "vk_get_states_split", "vk_last_error")
 
 
 class VkError(RuntimeError):
@@ -91,6 +92,8 @@ def lib():
         L.vk_edge_batch_run.argtypes = [vp, vp]
         L.vk_edge_batch_destroy.argtypes = [vp]
         L.vk_set_edge_launch.argtypes = [i32, i32]
+        L.vk_set_states_split.argtypes = [i32, i32]
+        L.vk_get_states_split.argtypes = [C.POINTER(i32), C.POINTER(i32)]
         L.vk_get_edge_launch.argtypes = [C.POINTER(i32), C.POINTER(i32)]
         L.vk_last_error.restype = C.c_char_p
         for name in EXPORTS:
@@ -400,6 +403,17 @@ class EdgeBatch:
 
 def set_edge_launch(block_threads: int = 0, blocks_per_cu: int = 0):
     _check(lib().vk_set_edge_launch(int(block_threads), int(blocks_per_cu)))
+
+
+def set_states_split(num: int, den: int = 1):
+    """Two-pass schedule of validate_states (see vk_set_states_split); (0, 1) = one pass."""
+    _check(lib().vk_set_states_split(int(num), int(den)))
+
+
+def get_states_split():
+    n, d = C.c_int32(), C.c_int32()
+    _check(lib().vk_get_states_split(C.byref(n), C.byref(d)))
+    return n.value, d.value
 
 
 def get_edge_launch():

@@ -13,7 +13,7 @@ import json
 import os
 import time
 
-from . import get_edge_launch, set_edge_launch, validate_edges
+from . import get_edge_launch, set_edge_launch, validate_edges, set_states_split, validate_states
 
 BLOCKS = (64, 128, 256, 512, 1024)
 PER_CU = (1, 2, 4, 8)
@@ -127,4 +127,31 @@ def tune_batch(make_batch, reps: int = 3, log=None):
     return b, {"block": block, "per_cu": per_cu, "ms": ms}
 
 
-__all__ = ["tune_edges", "tune_batch", "workload_key", "get_edge_launch"]
+SPLITS = ((0, 1), (1, 3), (1, 2), (2, 3))
+
+
+def tune_states(robot, env, q, reps: int = 3, log=None):
+    """Pick and apply the fastest validate_states schedule (one pass, or two passes split after
+    1/3, 1/2 or 2/3 of the link steps) for this batch; flags are the same for all of them."""
+    import torch
+    results = []
+    for num, den in SPLITS:
+        set_states_split(num, den)
+        validate_states(robot, env, q)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(reps):
+            validate_states(robot, env, q)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        results.append((ms, num, den))
+        if log:
+            log(f"autotune states: split {num}/{den}: {ms:.3f} ms")
+    ms, num, den = min(results)
+    set_states_split(num, den)
+    return {"split": [num, den], "ms": ms}
+
+
+__all__ = ["tune_edges", "tune_batch", "tune_states", "workload_key", "get_edge_launch"]

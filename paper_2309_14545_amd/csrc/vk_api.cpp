@@ -62,6 +62,7 @@ std::map<int, DeviceInfo> g_dev;
 std::map<std::pair<int, hipStream_t>, unsigned long long *> g_queues;
 int g_edge_block = 256;
 int g_edge_bpc = 4;
+int g_states_split_num = 0, g_states_split_den = 1;   // one pass by default
 
 const DeviceInfo &device_info(int dev) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -95,23 +96,24 @@ unsigned long long *queue_for(int dev, hipStream_t s) {
     return g_queues[key] = static_cast<unsigned long long *>(p);
 }
 
-// Scratch of the kNN partial lists, per (device, stream), grown on demand and kept until the
-// process ends (calls on one stream are ordered, so they may share it).
-std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_knn_ws;
+// Scratch of the multi-kernel calls (kNN partial lists, the survivor list of two-pass state
+// validation), per (device, stream), grown on demand and kept until the process ends (calls on
+// one stream are ordered, so they may share it).
+std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_scratch;
 
-void *knn_workspace(int dev, hipStream_t s, size_t bytes) {
+void *scratch_for(int dev, hipStream_t s, size_t bytes) {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto &w = g_knn_ws[std::make_pair(dev, s)];
+    auto &w = g_scratch[std::make_pair(dev, s)];
     if (w.second < bytes) {
         if (w.first) {
             // the previous buffer may still be in use by work queued on this stream
-            hip_check(hipStreamSynchronize(s), "kNN workspace sync");
+            hip_check(hipStreamSynchronize(s), "scratch sync");
             (void)hipFree(w.first);
             w.first = nullptr;
             w.second = 0;
         }
         void *p = nullptr;
-        hip_check(hipMalloc(&p, bytes), "kNN workspace");
+        hip_check(hipMalloc(&p, bytes), "scratch");
         w.first = p;
         w.second = bytes;
     }
@@ -881,10 +883,18 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
         check_pair(robot, env);
         check_batch(n, ldq, q, collide, "validate_states");
         if (n == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        int num, den;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            num = g_states_split_num;
+            den = g_states_split_den;
+        }
+        const int split = states_split(robot->dev, n, num, den);
+        void *scratch = split > 0 ? scratch_for(robot->device, s, states_scratch_bytes(n)) : nullptr;
         hip_check(launch_validate_states(robot->dev,
                                          env_for_launch(env, walk_lds_bytes(robot->dev, 256)), q, n,
-                                         ldq, collide,
-                                         (hipStream_t)stream),
+                                         ldq, collide, split, scratch, s),
                   "validate_states launch");
     });
 }
@@ -984,7 +994,7 @@ vk_status vk_knn(const float *x, int64_t n, int32_t dim, int32_t k, int32_t *idx
         if (!x || !idx || !dist2) raise(VK_ERR_INVALID_ARG, "vk_knn: NULL array");
         if (n >= (int64_t(1) << 31) / 32) raise(VK_ERR_SHAPE, "vk_knn: too many samples");
         hipStream_t s = (hipStream_t)stream;
-        void *ws = knn_workspace(current_device(), s, knn_workspace_bytes(n, k));
+        void *ws = scratch_for(current_device(), s, knn_workspace_bytes(n, k));
         hip_check(launch_knn(x, n, dim, k, idx, dist2, ws, s), "vk_knn launch");
     });
 }
@@ -1151,6 +1161,24 @@ vk_status vk_edge_batch_destroy(vk_edge_batch batch) {
         hipError_t err = hipFree(batch->blob);
         delete batch;
         hip_check(err, "hipFree");
+    });
+}
+
+vk_status vk_set_states_split(int32_t num, int32_t den) {
+    return guarded([&] {
+        if (num < 0 || den < 1 || num >= den) raise(VK_ERR_INVALID_ARG, "need 0 <= num < den");
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_states_split_num = num;
+        g_states_split_den = den;
+    });
+}
+
+vk_status vk_get_states_split(int32_t *num, int32_t *den) {
+    return guarded([&] {
+        if (!num || !den) raise(VK_ERR_INVALID_ARG, "NULL output");
+        std::lock_guard<std::mutex> lk(g_mu);
+        *num = g_states_split_num;
+        *den = g_states_split_den;
     });
 }
 

@@ -40,6 +40,13 @@ __device__ __forceinline__ T ld(const T *p, int64_t i) {
     return out;
 }
 
+// Value of the first active lane, as a wave-uniform 64-bit integer.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
+    const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)v);
+    const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 // Joint value sources ------------------------------------------------------------------------
 struct QEdge {                 // state on a straight edge: qa + t (qb - qa), qa/qb uniform
     const float *a;            // (t = 1 gives qb exactly, so both endpoints are the inputs)
@@ -348,21 +355,23 @@ __device__ __forceinline__ bool grid_hit(const EnvView &ev, const EnvDev &g, flo
         }                                                                           \
     }
 
-// The interleaved FK + collision walk of one configuration per lane.
+// The interleaved FK + collision walk of one configuration per lane.  Steps [test_from, test_to)
+// are tested; earlier steps are posed and cached only, and the walk stops at test_to.
 //   EDGE = true : returns as soon as any lane of the wave collides (the edge is invalid);
 //                 the return value is then wave-uniform.
 //   EDGE = false: per-lane result; lanes that collided stop contributing, and the walk ends
 //                 when every lane has collided.  `col` on entry marks lanes already decided.
 template <bool EDGE, class Q, class W = NoWork>
 __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev &ed, const Q &q,
-                             const StepCache &sc, bool col, W &&work = W()) {
+                             const StepCache &sc, bool col, int test_from, int test_to,
+                             W &&work = W()) {
     Frame Tm, Ta;
     frame_identity(Tm);
     frame_identity(Ta);
     int ta_link = 0, ta_depth = 0;
     bool live = !col;
     if (!EDGE && !wave_ballot(live)) return col;
-    for (int st = 0; st < rb.n_steps; ++st) {
+    for (int st = 0; st < rb.n_steps && st < test_to; ++st) {
         const StepRec S = ld(rb.steps, st);
         pose_step(rb, S, Tm, q, work, &sc);
         const int cnt = S.sph_count;
@@ -372,6 +381,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
         sc.put(st, Cx, Cy, Cz);
+        if (st < test_from) continue;         // tested by an earlier pass: pose and cache only
         // the step's fine spheres, placed on first use (uniform decision)
         float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl];
         bool placed = false;
@@ -579,7 +589,66 @@ __global__ void __launch_bounds__(256)
     bool col = !active;                       // inactive lanes count as decided
     if (active)
         for (int j = 0; j < rb.dof; ++j) col |= !isfinite(qs(j));
-    col = walk_collide<false>(rb, ev, ed, qs, sc, col);
+    col = walk_collide<false>(rb, ev, ed, qs, sc, col, 0, rb.n_steps);
+    if (active) out[i] = col ? 1 : 0;
+}
+
+// Two-pass state validation.  In a wave of independent states the walk lasts until its last
+// live lane ends, so when most states collide early a few free lanes keep whole waves walking
+// at low occupancy of their lanes.  Pass 1 tests the first `split` link steps of every state
+// and appends the states still free to a survivor list (one atomic per wave); pass 2 walks the
+// survivors packed densely into waves, posing the first `split` steps again and testing the
+// rest.  Flags are those of the single pass.
+template <int STAGE>
+__global__ void __launch_bounds__(256)
+    k_validate_states_screen(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+                             const float *__restrict__ q, int64_t n, int64_t ldq,
+                             uint8_t *__restrict__ out, int jc, int split,
+                             int32_t *__restrict__ surv, unsigned long long *__restrict__ n_surv) {
+    extern __shared__ float4 lds_dyn[];
+    float *lf = reinterpret_cast<float *>(lds_dyn);
+    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
+    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
+    const EnvView ev = make_view<STAGE>(ed, lds_env);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    QState qs{q, ldq, active ? i : 0};
+    bool col = !active;
+    if (active)
+        for (int j = 0; j < rb.dof; ++j) col |= !isfinite(qs(j));
+    col = walk_collide<false>(rb, ev, ed, qs, sc, col, 0, split);
+    const bool keep = active && !col;
+    if (active && col) out[i] = 1;
+    const unsigned long long m = wave_ballot(keep);
+    const unsigned long long base =
+        uniform_u64(atomicAdd(n_surv, lane == 0 ? (unsigned long long)__popcll(m) : 0ull));
+    const int below = __builtin_amdgcn_mbcnt_hi((unsigned int)(m >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((unsigned int)m, 0u));
+    if (keep) surv[base + below] = (int32_t)i;
+}
+
+template <int STAGE>
+__global__ void __launch_bounds__(256)
+    k_validate_states_rest(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+                           const float *__restrict__ q, int64_t ldq, uint8_t *__restrict__ out,
+                           int jc, int split, const int32_t *__restrict__ surv,
+                           const unsigned long long *__restrict__ n_surv) {
+    const int64_t count = (int64_t)*n_surv;
+    if ((int64_t)blockIdx.x * blockDim.x >= count) return;     // whole workgroup past the list
+    extern __shared__ float4 lds_dyn[];
+    float *lf = reinterpret_cast<float *>(lds_dyn);
+    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
+    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
+    const EnvView ev = make_view<STAGE>(ed, lds_env);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = g < count;
+    const int64_t i = active ? surv[g] : 0;
+    QState qs{q, ldq, i};
+    bool col = !active;
+    col = walk_collide<false>(rb, ev, ed, qs, sc, col, split, rb.n_steps);
     if (active) out[i] = col ? 1 : 0;
 }
 
@@ -628,7 +697,7 @@ __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, co
         idx = idx < n ? idx : n - 1;          // surplus lanes repeat the last state
         const float t = idx == n - 1 ? 1.0f : (float)idx * inv;
         QEdge qs{a, b, t};
-        if (walk_collide<true>(rb, ev, ed, qs, sc, false, work)) return 1;
+        if (walk_collide<true>(rb, ev, ed, qs, sc, false, 0, rb.n_steps, work)) return 1;
     }
     return 0;
 }
@@ -639,11 +708,6 @@ __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, co
 // flow out of the persistent loop matters: a lane-0-only `if` around the atomic can be threaded
 // by the compiler across iterations, after which the broadcast reads a lane that never took a
 // ticket.
-__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v) {
-    const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)v);
-    const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(unsigned int)(v >> 32));
-    return ((unsigned long long)hi << 32) | lo;
-}
 
 __device__ __forceinline__ unsigned long long take_ticket(unsigned long long *ctr, int lane) {
     return uniform_u64(atomicAdd(ctr, lane == 0 ? 1ull : 0ull));
@@ -1288,14 +1352,39 @@ static bool pick_joint_cache(const void *kernel, int block, size_t without, size
         }                                                                                       \
     }
 
+// Link steps pass 1 of the two-pass state validation tests, for a fraction num/den of the
+// robot's steps (0: one pass).
+int states_split(const RobotDev &rb, int64_t n, int num, int den) {
+    if (num <= 0 || den <= 0) return 0;
+    const int split = (int)((int64_t)rb.n_steps * num / den);
+    if (split <= 0 || split >= rb.n_steps || n >= (int64_t(1) << 31)) return 0;
+    return split;
+}
+
+size_t states_scratch_bytes(int64_t n) { return 256 + (size_t)n * sizeof(int32_t); }
+
 hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
-                                  int64_t ldq, uint8_t *out, hipStream_t s) {
+                                  int64_t ldq, uint8_t *out, int split, void *scratch,
+                                  hipStream_t s) {
     const int bs = 256;
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
     const size_t base_nojc_ = walk_lds_bytes(rb, bs, false), base_jc_ = walk_lds_bytes(rb, bs, true);
     const size_t max_lds_ = device_max_lds();
+    if (!scratch) split = 0;
+    if (split == 0) {
 #define ARGS_ rb, ed, ed.rec, q, n, ldq, out, jc
-    VK_STAGED(k_validate_states)
+        VK_STAGED(k_validate_states)
+#undef ARGS_
+        return hipGetLastError();
+    }
+    unsigned long long *n_surv = static_cast<unsigned long long *>(scratch);
+    int32_t *surv = reinterpret_cast<int32_t *>(static_cast<char *>(scratch) + 256);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, n_surv, 0ull, 1, 1);
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, out, jc, split, surv, n_surv
+    VK_STAGED(k_validate_states_screen)
+#undef ARGS_
+#define ARGS_ rb, ed, ed.rec, q, ldq, out, jc, split, surv, n_surv
+    VK_STAGED(k_validate_states_rest)
 #undef ARGS_
     return hipGetLastError();
 }

@@ -9,8 +9,13 @@ namespace vk {
 
 hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int64_t ldq,
                              float *out, int64_t ldc, hipStream_t s);
-hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const float *q,
-                                  int64_t n, int64_t ldq, uint8_t *out, hipStream_t s);
+// State validation; with split > 0 and scratch (states_scratch_bytes(n) bytes) it runs in two
+// passes, the second over the states still free after the first `split` link steps.
+int states_split(const RobotDev &rb, int64_t n, int num, int den);
+size_t states_scratch_bytes(int64_t n);
+hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const float *q, int64_t n,
+                                  int64_t ldq, uint8_t *out, int split, void *scratch,
+                                  hipStream_t s);
 hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s);
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,

@@ -110,3 +110,8 @@ def test_launch_configuration_checks(vk):
     assert vk.get_edge_launch() == (128, 3)
     assert lib.vk_set_edge_launch(0, 0) == 0
     assert vk.get_edge_launch() == (256, 4)
+    assert lib.vk_set_states_split(1, 1) == -1
+    assert lib.vk_set_states_split(-1, 2) == -1
+    assert lib.vk_set_states_split(2, 3) == 0
+    assert vk.get_states_split() == (2, 3)
+    assert lib.vk_set_states_split(0, 1) == 0

@@ -175,3 +175,21 @@ def test_validate_states_empty_and_free(vk):
     bare["self_pairs"] = np.zeros((0, 2), np.int32)
     flags = host(vk.validate_states(vk.Robot(bare), vk.Env({}), dev(w["q"])))
     assert not flags.any()
+
+
+@pytest.mark.parametrize("name", ["states7", "bimanual14_cube", "chain7_big_env", "lift8_shelf"])
+def test_two_pass_schedule_matches_one_pass(vk, name):
+    """The two-pass schedule (screen the first link steps, then walk the survivors densely)
+    gives bitwise the same flags as one pass, for every split; ragged sizes included."""
+    robot, env, q = _state_case(name)
+    r, e = vk.Robot(robot), vk.Env(env)
+    qd = dev(q)
+    vk.set_states_split(0, 1)
+    ref = host(vk.validate_states(r, e, qd))
+    try:
+        for num, den in ((1, 3), (1, 2), (2, 3), (9, 10)):
+            vk.set_states_split(num, den)
+            np.testing.assert_array_equal(host(vk.validate_states(r, e, qd)), ref)
+            np.testing.assert_array_equal(host(vk.validate_states(r, e, qd[:, :77])), ref[:77])
+    finally:
+        vk.set_states_split(0, 1)
