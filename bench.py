@@ -204,6 +204,36 @@ def extra_shortcut(vk, steps):
             "states_per_s": n_states / (m * 1e-3)}
 
 
+def extra_rrt(vk, n_queries=1024):
+    """Many-query RRT-Connect: 1,024 start/goal pairs (collision-free states, screened with
+    validate_states) in the shelf scene, planned in lockstep; wall time of the whole solve."""
+    import torch
+    from synthetic import workload, rng, uniform_states
+    from paper_2309_14545_amd import planning
+    w = workload("edges7_shelf", n=1)
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    g = rng("bench-rrt", "queries")
+    free = []
+    while sum(len(f) for f in free) < 2 * n_queries:
+        q = uniform_states(g, 7, 8192)
+        flag = vk.validate_states(robot, env, torch.from_numpy(q).cuda()).cpu().numpy()
+        free.append(q[:, flag == 0].T)
+    pts = np.concatenate(free)[:2 * n_queries]
+    starts = torch.from_numpy(np.ascontiguousarray(pts[0::2])).cuda()
+    goals = torch.from_numpy(np.ascontiguousarray(pts[1::2])).cuda()
+    lo, hi = w["robot"]["q_lo"], w["robot"]["q_hi"]
+    planning.rrt_connect(robot, env, starts[:32], goals[:32], lo, hi, max_iters=5, cap=256)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = planning.rrt_connect(robot, env, starts, goals, lo, hi, max_iters=300, cap=2048, seed=1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    solved = int(res["solved"].sum())
+    return {"workload": "rrt7_shelf", "queries": n_queries, "solved": solved,
+            "wall_s": dt, "iterations": res["iterations"], "rounds": res["rounds"],
+            "edges_checked": res["edges"], "plans_per_s": solved / dt}
+
+
 def extra_mixed(vk, n_batches, reps):
     import torch
     from synthetic import workload, pack_edge_sets
@@ -394,6 +424,7 @@ def main():
                         ("cost7", lambda: extra_cost(vk, 10)),
                         ("prm7_shelf", lambda: extra_prm(vk, 10)),
                         ("shortcut7_shelf", lambda: extra_shortcut(vk, 10)),
+                        ("rrt7_shelf", lambda: extra_rrt(vk)),
                         ("mixed", lambda: extra_mixed(vk, 3, 20))):
             t0 = time.perf_counter()
             extra[key] = fn()

@@ -173,6 +173,32 @@ vk_status vk_knn(const float *x, int64_t n, int32_t dim, int32_t k, int32_t *idx
  * [0, n) or equal to i become holes. */
 vk_status vk_knn_pairs(const int32_t *idx, int64_t n, int32_t k, int32_t *pairs, void *stream);
 
+/*
+ * Tree primitives of a many-query RRT-Connect (the planner of Sec. III-E, run for nq queries
+ * in lockstep; the host loop lives in the Python package).  Query q owns a tree of up to `cap`
+ * nodes: nodes[q][cap][dof] (device FP32), parents[q][cap] (int32), sizes[q] (int32, nodes in
+ * use).  All arrays are device memory; per-query vectors are [nq] or [nq][dof].
+ *
+ * vk_tree_nearest: near[q] = index of the tree node nearest to targets[q] (Euclidean; squared
+ *   distance accumulated in joint order with separately rounded FP32 products and sums, ties to
+ *   the lower index), or -1 for an empty tree or when active (optional, uint8 [nq]) is 0.
+ * vk_tree_steer: qnew[q] = targets[q] if it lies within `step` of node near[q] (reached[q] = 1),
+ *   else near + (targets - near) * step / |targets - near| (reached[q] = 0); near < 0 copies the
+ *   target with reached = 0.  step must be finite and > 0.
+ * vk_tree_append: where ok[q] != 0, near[q] is a node of the tree and the tree has room,
+ *   appends qnew[q] with parent near[q] and writes its index to added[q]; else added[q] = -1.
+ * Errors: VK_ERR_INVALID_ARG for NULL arrays, cap < 1, dof outside [1, 64] or nq < 0.
+ */
+vk_status vk_tree_nearest(const float *nodes, const int32_t *sizes, int32_t cap, int32_t dof,
+                          int64_t nq, const float *targets, const uint8_t *active, int32_t *near,
+                          void *stream);
+vk_status vk_tree_steer(const float *nodes, int32_t cap, int32_t dof, int64_t nq,
+                        const int32_t *near, const float *targets, float step, float *qnew,
+                        uint8_t *reached, void *stream);
+vk_status vk_tree_append(float *nodes, int32_t *parents, int32_t *sizes, int32_t cap, int32_t dof,
+                         int64_t nq, const float *qnew, const int32_t *near, const uint8_t *ok,
+                         int32_t *added, void *stream);
+
 /* Measurement variant of validate_edges: the same flags from the same kernel code, which in
  * addition adds to flops[0..4] (five device uint64, not cleared by the call) the FP32
  * operations the launch executed, by the model's count per operation (fused multiply-add = 2;

@@ -24,7 +24,8 @@ _STATUS = {-1: "VK_ERR_INVALID_ARG", -2: "VK_ERR_SHAPE", -3: "VK_ERR_UNSUPPORTED
 EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_spheres",
            "vk_env_create", "vk_env_destroy", "fk_spheres", "validate_states", "validate_edges",
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
-           "vk_knn", "vk_knn_pairs", "penetration_cost_fwd", "penetration_cost_bwd",
+           "vk_knn", "vk_knn_pairs", "vk_tree_nearest", "vk_tree_steer", "vk_tree_append",
+           "penetration_cost_fwd", "penetration_cost_bwd",
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_destroy",
            "vk_set_edge_launch", "vk_get_edge_launch", "vk_set_states_split",
            "vk_get_states_split", "vk_last_error")
@@ -84,6 +85,9 @@ def lib():
         L.validate_edges_indexed.argtypes = [vp, vp, vp, i64, vp, vp, i64, fp, vp, vp]
         L.vk_knn.argtypes = [vp, i64, i32, i32, vp, vp, vp]
         L.vk_knn_pairs.argtypes = [vp, i64, i32, vp, vp]
+        L.vk_tree_nearest.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp]
+        L.vk_tree_steer.argtypes = [vp, i32, i32, i64, vp, vp, fp, vp, vp, vp]
+        L.vk_tree_append.argtypes = [vp, vp, vp, i32, i32, i64, vp, vp, vp, vp, vp]
         L.penetration_cost_fwd.argtypes = [vp, vp, vp, i64, i64, vp, vp]
         L.penetration_cost_bwd.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
         L.vk_edge_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), i32,
@@ -319,6 +323,46 @@ def knn_pairs(idx):
     pairs = torch.empty((n * k, 2), dtype=torch.int32, device=idx.device)
     _check(lib().vk_knn_pairs(idx.data_ptr(), n, k, pairs.data_ptr(), _stream()))
     return pairs
+
+
+def tree_nearest(nodes, sizes, targets, active=None, out=None):
+    """Index [Q] of the node of each query's tree (nodes [Q, cap, dof], sizes [Q]) nearest to
+    targets [Q, dof]; -1 for empty trees or inactive queries."""
+    torch = _torch()
+    Q, cap, dof = nodes.shape
+    if out is None:
+        out = torch.empty(Q, dtype=torch.int32, device=nodes.device)
+    _check(lib().vk_tree_nearest(nodes.data_ptr(), sizes.data_ptr(), cap, dof, Q,
+                                 targets.data_ptr(), active.data_ptr() if active is not None else None,
+                                 out.data_ptr(), _stream()))
+    return out
+
+
+def tree_steer(nodes, near, targets, step: float, qnew=None, reached=None):
+    """(qnew [Q, dof], reached uint8 [Q]): a step of at most `step` from node near[q] toward
+    targets[q]."""
+    torch = _torch()
+    Q, cap, dof = nodes.shape
+    if qnew is None:
+        qnew = torch.empty((Q, dof), dtype=torch.float32, device=nodes.device)
+    if reached is None:
+        reached = torch.empty(Q, dtype=torch.uint8, device=nodes.device)
+    _check(lib().vk_tree_steer(nodes.data_ptr(), cap, dof, Q, near.data_ptr(), targets.data_ptr(),
+                               float(step), qnew.data_ptr(), reached.data_ptr(), _stream()))
+    return qnew, reached
+
+
+def tree_append(nodes, parents, sizes, qnew, near, ok, added=None):
+    """Append qnew[q] (parent near[q]) to the trees where ok[q]; returns the new indices (-1 where
+    nothing was added)."""
+    torch = _torch()
+    Q, cap, dof = nodes.shape
+    if added is None:
+        added = torch.empty(Q, dtype=torch.int32, device=nodes.device)
+    _check(lib().vk_tree_append(nodes.data_ptr(), parents.data_ptr(), sizes.data_ptr(), cap, dof, Q,
+                                qnew.data_ptr(), near.data_ptr(), ok.data_ptr(), added.data_ptr(),
+                                _stream()))
+    return added
 
 
 def penetration_cost_fwd(robot: Robot, env: Env, q):

@@ -1009,6 +1009,55 @@ vk_status vk_knn_pairs(const int32_t *idx, int64_t n, int32_t k, int32_t *pairs,
     });
 }
 
+static void check_trees(int32_t cap, int32_t dof, int64_t nq) {
+    if (cap < 1 || dof < 1 || dof > kMaxDof || nq < 0)
+        raise(VK_ERR_INVALID_ARG, "tree call: bad capacity, dof or query count");
+    if (nq >= (int64_t(1) << 31) || (int64_t)cap * dof >= (int64_t(1) << 31))
+        raise(VK_ERR_SHAPE, "tree call: sizes too large");
+}
+
+vk_status vk_tree_nearest(const float *nodes, const int32_t *sizes, int32_t cap, int32_t dof,
+                          int64_t nq, const float *targets, const uint8_t *active, int32_t *near,
+                          void *stream) {
+    return guarded([&] {
+        check_trees(cap, dof, nq);
+        if (nq == 0) return;
+        if (!nodes || !sizes || !targets || !near) raise(VK_ERR_INVALID_ARG, "vk_tree_nearest: NULL array");
+        hip_check(launch_tree_nearest(nodes, sizes, cap, dof, nq, targets, active, near,
+                                      (hipStream_t)stream),
+                  "vk_tree_nearest launch");
+    });
+}
+
+vk_status vk_tree_steer(const float *nodes, int32_t cap, int32_t dof, int64_t nq,
+                        const int32_t *near, const float *targets, float step, float *qnew,
+                        uint8_t *reached, void *stream) {
+    return guarded([&] {
+        check_trees(cap, dof, nq);
+        if (!(step > 0.0f && std::isfinite(step))) raise(VK_ERR_INVALID_ARG, "vk_tree_steer: step must be > 0");
+        if (nq == 0) return;
+        if (!nodes || !near || !targets || !qnew || !reached)
+            raise(VK_ERR_INVALID_ARG, "vk_tree_steer: NULL array");
+        hip_check(launch_tree_steer(nodes, cap, dof, nq, near, targets, step, qnew, reached,
+                                    (hipStream_t)stream),
+                  "vk_tree_steer launch");
+    });
+}
+
+vk_status vk_tree_append(float *nodes, int32_t *parents, int32_t *sizes, int32_t cap, int32_t dof,
+                         int64_t nq, const float *qnew, const int32_t *near, const uint8_t *ok,
+                         int32_t *added, void *stream) {
+    return guarded([&] {
+        check_trees(cap, dof, nq);
+        if (nq == 0) return;
+        if (!nodes || !parents || !sizes || !qnew || !near || !ok || !added)
+            raise(VK_ERR_INVALID_ARG, "vk_tree_append: NULL array");
+        hip_check(launch_tree_append(nodes, parents, sizes, cap, dof, nq, qnew, near, ok, added,
+                                     (hipStream_t)stream),
+                  "vk_tree_append launch");
+    });
+}
+
 vk_status penetration_cost_fwd(vk_robot robot, vk_env env, const float *q, int64_t n,
                                int64_t ldq, float *cost, void *stream) {
     return guarded([&] {

@@ -1240,6 +1240,105 @@ __global__ void __launch_bounds__(256) k_knn_merge(const int32_t *__restrict__ p
         }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Tree primitives of a many-query RRT-Connect (Sec. III-E's planner, run for many queries in
+// lockstep): every query q owns a tree of up to `cap` nodes, nodes[q][cap][dof], of which the
+// first sizes[q] are in use.  The planner loop itself runs on the host; the edge checks are
+// validate_edges.
+// ---------------------------------------------------------------------------------------------
+
+// Nearest tree node to targets[q] (one wave per query; squared distance accumulated in joint
+// order with separately rounded products and sums, ties to the lower index); -1 for an empty
+// tree or an inactive query.
+__global__ void __launch_bounds__(256) k_tree_nearest(const float *__restrict__ nodes,
+                                                      const int32_t *__restrict__ sizes, int cap,
+                                                      int dof, int64_t nq,
+                                                      const float *__restrict__ targets,
+                                                      const uint8_t *__restrict__ active,
+                                                      int32_t *__restrict__ near) {
+#pragma clang fp contract(off)                 // products and sums rounded separately
+    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (qi >= nq) return;                      // whole wave past the queries
+    const bool on = !active || active[qi];
+    const int size = on ? min(sizes[qi], cap) : 0;
+    const float *tree = nodes + qi * (int64_t)cap * dof;
+    const float *tg = targets + qi * dof;
+    float best = INFINITY;
+    int bi = 0x7fffffff;
+    for (int v = lane; v < size; v += kWave) {
+        float s = 0.0f;
+        for (int j = 0; j < dof; ++j) {
+            const float d = tree[(int64_t)v * dof + j] - tg[j];
+            const float dd = d * d;
+            s = s + dd;
+        }
+        if (knn_less(s, v, best, bi)) {
+            best = s;
+            bi = v;
+        }
+    }
+    for (int m = 1; m < kWave; m <<= 1) {      // wave minimum of (distance, index)
+        const float ob = __shfl_xor(best, m);
+        const int oi = __shfl_xor(bi, m);
+        if (knn_less(ob, oi, best, bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    if (lane == 0) near[qi] = bi == 0x7fffffff ? -1 : bi;
+}
+
+// Steer from node near[q] toward targets[q] by at most `step` (Euclidean): q_new = target when
+// it is that close (reached[q] = 1), else near + d * (step / |d|).  Queries with near < 0 get
+// reached = 0 and q_new = target.
+__global__ void k_tree_steer(const float *__restrict__ nodes, int cap, int dof, int64_t nq,
+                             const int32_t *__restrict__ near, const float *__restrict__ targets,
+                             float step, float *__restrict__ qnew, uint8_t *__restrict__ reached) {
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= nq) return;
+    const float *tg = targets + qi * dof;
+    float *o = qnew + qi * dof;
+    const int ni = near[qi];
+    if (ni < 0 || ni >= cap) {
+        for (int j = 0; j < dof; ++j) o[j] = tg[j];
+        reached[qi] = 0;
+        return;
+    }
+    const float *a = nodes + (qi * (int64_t)cap + ni) * dof;
+    float s = 0.0f;
+    for (int j = 0; j < dof; ++j) {
+        const float d = tg[j] - a[j];
+        s = fmaf(d, d, s);
+    }
+    const float len = sqrtf(s);
+    const bool close = len <= step;
+    const float f = close ? 1.0f : step / len;
+    for (int j = 0; j < dof; ++j) o[j] = close ? tg[j] : fmaf(f, tg[j] - a[j], a[j]);
+    reached[qi] = close ? 1 : 0;
+}
+
+// Append qnew[q] to tree q with parent near[q] where ok[q] (and the tree has room); the new
+// node's index goes to added[q] (-1 when nothing was added).
+__global__ void k_tree_append(float *__restrict__ nodes, int32_t *__restrict__ parents,
+                              int32_t *__restrict__ sizes, int cap, int dof, int64_t nq,
+                              const float *__restrict__ qnew, const int32_t *__restrict__ near,
+                              const uint8_t *__restrict__ ok, int32_t *__restrict__ added) {
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= nq) return;
+    const int size = sizes[qi];
+    const int ni = near[qi];
+    if (!ok[qi] || ni < 0 || ni >= size || size >= cap) {
+        added[qi] = -1;
+        return;
+    }
+    float *dst = nodes + (qi * (int64_t)cap + size) * dof;
+    for (int j = 0; j < dof; ++j) dst[j] = qnew[qi * dof + j];
+    parents[qi * (int64_t)cap + size] = ni;
+    sizes[qi] = size + 1;
+    added[qi] = size;
+}
+
 // Undirected roadmap edges from kNN lists, one slot per (i, m): (i, j) for j = idx[i][m] when
 // i < j or when i is not in j's list, else the hole (-1, -1); each edge appears exactly once.
 __global__ void k_knn_pairs(const int32_t *__restrict__ idx, int64_t n, int k,
@@ -1426,6 +1525,31 @@ hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, f
         else VK_KNN(32, 64);
     }
 #undef VK_KNN
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_nearest(const float *nodes, const int32_t *sizes, int cap, int dof,
+                               int64_t nq, const float *targets, const uint8_t *active,
+                               int32_t *near, hipStream_t s) {
+    const int wpb = 4;
+    hipLaunchKernelGGL(k_tree_nearest, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(wpb * kWave), 0,
+                       s, nodes, sizes, cap, dof, nq, targets, active, near);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_steer(const float *nodes, int cap, int dof, int64_t nq, const int32_t *near,
+                             const float *targets, float step, float *qnew, uint8_t *reached,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_tree_steer, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nodes,
+                       cap, dof, nq, near, targets, step, qnew, reached);
+    return hipGetLastError();
+}
+
+hipError_t launch_tree_append(float *nodes, int32_t *parents, int32_t *sizes, int cap, int dof,
+                              int64_t nq, const float *qnew, const int32_t *near,
+                              const uint8_t *ok, int32_t *added, hipStream_t s) {
+    hipLaunchKernelGGL(k_tree_append, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nodes,
+                       parents, sizes, cap, dof, nq, qnew, near, ok, added);
     return hipGetLastError();
 }
 

@@ -30,6 +30,15 @@ size_t knn_workspace_bytes(int64_t n, int k);
 hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, float *d2,
                       void *workspace, hipStream_t s);
 hipError_t launch_knn_pairs(const int32_t *idx, int64_t n, int k, int32_t *pairs, hipStream_t s);
+hipError_t launch_tree_nearest(const float *nodes, const int32_t *sizes, int cap, int dof,
+                               int64_t nq, const float *targets, const uint8_t *active,
+                               int32_t *near, hipStream_t s);
+hipError_t launch_tree_steer(const float *nodes, int cap, int dof, int64_t nq, const int32_t *near,
+                             const float *targets, float step, float *qnew, uint8_t *reached,
+                             hipStream_t s);
+hipError_t launch_tree_append(float *nodes, int32_t *parents, int32_t *sizes, int cap, int dof,
+                              int64_t nq, const float *qnew, const int32_t *near,
+                              const uint8_t *ok, int32_t *added, hipStream_t s);
 hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, float *cost, hipStream_t s);
 size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, bool jc);
