@@ -44,6 +44,21 @@ struct JointVal {
     float s, c, d;
 };
 
+// Sine and cosine of x (radians) from the hardware sine and cosine of a fraction of a turn.
+// x / 2pi = n + f with n an integer and |f| <= 1/2 (Cody and Waite's argument reduction, with
+// the period measured in turns): an FMA forms x * hi - n from the exact product, rounded once,
+// and a second FMA adds x * lo, the part of 1/2pi that hi (1/2pi rounded to FP32) leaves out.
+// f then holds x / 2pi - n to within about an ulp of f plus |x| * 1e-16, and the hardware
+// evaluates sin(2 pi f) and cos(2 pi f).
+__device__ __forceinline__ void sincos_turns(float x, float &s, float &c) {
+    constexpr float kInv2PiHi = 0x1.45f306p-3f;    // 1/2pi rounded to FP32
+    constexpr float kInv2PiLo = 0x1.b93910p-28f;   // 1/2pi - kInv2PiHi, rounded
+    const float n = rintf(x * kInv2PiHi);
+    const float f = fmaf(x, kInv2PiLo, fmaf(x, kInv2PiHi, -n));
+    s = __builtin_amdgcn_sinf(f);
+    c = __builtin_amdgcn_cosf(f);
+}
+
 __device__ __forceinline__ JointVal joint_val(const JointRec &J, float q) {
     JointVal v;
     if (J.prismatic) {
@@ -51,7 +66,7 @@ __device__ __forceinline__ JointVal joint_val(const JointRec &J, float q) {
         v.c = J.c_off;
         v.d = J.d + q;
     } else {
-        sincosf(q + J.theta_off, &v.s, &v.c);
+        sincos_turns(q + J.theta_off, v.s, v.c);
         v.d = J.d;
     }
     return v;

@@ -101,6 +101,31 @@ def test_fk_spheres_leading_dimensions(vk, orc):
     assert vk.lib().fk_spheres(r.handle, qd.data_ptr(), n, n - 1, out.data_ptr(), ldc, st) == -2
 
 
+@pytest.mark.parametrize("theta_off", [0.0, 0.3])
+def test_joint_angle_accuracy(vk, theta_off):
+    """One revolute joint driving a 1 m link: the sphere at the link's end sits at
+    (cos t, sin t, 0) with t = q + theta_off, so its position error is the error of the joint's
+    sine and cosine in radians.  Swept densely over several turns and checked against the closed
+    form of the FP32 angle the kernel forms, and (within +-7 rad) of the exact angle."""
+    desc = dict(dof=1, parent_link=np.array([0], np.int32), mount=None,
+                dh=np.array([[1, 0, 1, 0, theta_off]], np.float32),
+                sphere_link=np.array([1], np.int32),
+                sphere_xyzr=np.array([[0, 0, 0, 0.1]], np.float32),
+                self_pairs=np.zeros((0, 2), np.int32))
+    r = vk.Robot(desc)
+    for hi in (3.2, 7.0, 100.0):
+        q = np.linspace(-hi, hi, 1 << 20, dtype=np.float32)
+        q[:4] = [0.0, np.float32(np.pi / 2), -np.float32(np.pi), np.float32(1e-30)]
+        c = host(vk.fk_spheres(r, dev(q[None, :])))[0]
+        t32 = (q + np.float32(theta_off)).astype(np.float64)
+        err = np.hypot(c[0] - np.cos(t32), c[1] - np.sin(t32)).max()
+        say(f"joint angle error over +-{hi}: {err:.3g} rad")
+        assert err <= 1e-6 and np.all(c[2] == 0)
+        if hi <= 7.0:
+            t = q.astype(np.float64) + np.float64(np.float32(theta_off))
+            assert np.hypot(c[0] - np.cos(t), c[1] - np.sin(t)).max() <= 1e-6
+
+
 def _state_case(name):
     if name == "states7":
         w = workload("states7")
