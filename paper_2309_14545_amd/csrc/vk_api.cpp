@@ -182,41 +182,40 @@ double point_segment(const double x[3], const double p[3], const double u[3]) {
     return std::sqrt(d2);
 }
 
-// Bounding capsule of a set of spheres: the axis is the principal direction of the centres
-// (power iteration on their covariance) or, if tighter, the line through the two farthest
-// centres; the segment spans the centres' projections.  Written to a StepRec.
+// Bounding capsule of a set of spheres about their bounding sphere's centre c (st.coarse): the
+// segment c - h .. c + h, whose axis is the principal direction of the centres (power iteration
+// on their covariance) or, if that gives a smaller radius, the direction of the two farthest
+// centres; |h| reaches the farthest projection of a centre.  Written to a StepRec.
 void bounding_capsule(const std::vector<const float *> &sph, StepRec &st) {
     const size_t n = sph.size();
-    auto fit = [&](const double axis[3], double p[3], double u[3]) {
-        double c[3] = {0, 0, 0};
+    const double c[3] = {st.coarse[0], st.coarse[1], st.coarse[2]};
+    auto fit = [&](const double axis[3], double h[3]) {
+        double len = 0.0;
         for (const float *s : sph)
-            for (int a = 0; a < 3; ++a) c[a] += s[a] / (double)n;
-        double lo = 1e300, hi = -1e300;
-        for (const float *s : sph) {
-            const double t = (s[0] - c[0]) * axis[0] + (s[1] - c[1]) * axis[1] + (s[2] - c[2]) * axis[2];
-            lo = std::min(lo, t);
-            hi = std::max(hi, t);
+            len = std::max(len, std::fabs((s[0] - c[0]) * axis[0] + (s[1] - c[1]) * axis[1] +
+                                          (s[2] - c[2]) * axis[2]));
+        double p[3], u[3];
+        for (int a = 0; a < 3; ++a) {
+            h[a] = len * axis[a];
+            p[a] = c[a] - h[a];
+            u[a] = 2.0 * h[a];
         }
         double r = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            p[a] = c[a] + lo * axis[a];
-            u[a] = (hi - lo) * axis[a];
-        }
         for (const float *s : sph) {
             const double x[3] = {s[0], s[1], s[2]};
             r = std::max(r, point_segment(x, p, u) + s[3]);
         }
         return r;
     };
-    double best_p[3] = {0, 0, 0}, best_u[3] = {0, 0, 0}, best_r = 1e300;
+    double best_h[3] = {0, 0, 0}, best_r = 1e300;
     std::vector<std::array<double, 3>> axes;
     {   // principal direction
-        double c[3] = {0, 0, 0}, C[3][3] = {{0}};
+        double m[3] = {0, 0, 0}, C[3][3] = {{0}};
         for (const float *s : sph)
-            for (int a = 0; a < 3; ++a) c[a] += s[a] / (double)n;
+            for (int a = 0; a < 3; ++a) m[a] += s[a] / (double)n;
         for (const float *s : sph)
             for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) C[a][b] += (s[a] - c[a]) * (s[b] - c[b]);
+                for (int b = 0; b < 3; ++b) C[a][b] += (s[a] - m[a]) * (s[b] - m[b]);
         double v[3] = {1.0, 0.7, 0.3};
         for (int it = 0; it < 200; ++it) {
             double w[3] = {0, 0, 0};
@@ -246,26 +245,27 @@ void bounding_capsule(const std::vector<const float *> &sph, StepRec &st) {
         axes.push_back({ax[0], ax[1], ax[2]});
     }
     for (const auto &ax : axes) {
-        double p[3], u[3];
-        const double r = fit(ax.data(), p, u);
+        double h[3];
+        const double r = fit(ax.data(), h);
         if (r < best_r) {
             best_r = r;
-            for (int a = 0; a < 3; ++a) {
-                best_p[a] = p[a];
-                best_u[a] = u[a];
-            }
+            for (int a = 0; a < 3; ++a) best_h[a] = h[a];
         }
     }
-    double uu = 0.0;
+    double hh = 0.0;
     for (int a = 0; a < 3; ++a) {
-        st.cap_p[a] = (float)best_p[a];
-        st.cap_u[a] = (float)best_u[a];
-        uu += (double)st.cap_u[a] * st.cap_u[a];
+        st.cap_h[a] = (float)best_h[a];
+        hh += (double)st.cap_h[a] * st.cap_h[a];
     }
     // the float-rounded segment moves by at most a few 1e-8 m; the 1 mm padding covers it
     st.cap_r = std::nextafter((float)(best_r + 1e-3), INFINITY);
-    st.cap_uu = (float)uu;
-    st.cap_inv = uu > 0.0 ? (float)(1.0 / uu) : 0.0f;
+    // h rotated to the world frame and stored as three halves rounded toward zero: each
+    // component is off by less than 2^-10 of |h| (plus 2^-24 for a subnormal half), so the
+    // stored segment lies within sqrt(3) (2^-10 |h| + 2^-24) of the exact one
+    const double herr = std::sqrt(3.0) * (std::ldexp(std::sqrt(hh), -10) + std::ldexp(1.0, -24));
+    st.cap_rq = std::nextafter((float)((double)st.cap_r + herr + 1e-6), INFINITY);
+    st.cap_uu = (float)(4.0 * hh);
+    st.cap_inv = hh > 0.0 ? (float)(1.0 / (4.0 * hh)) : 0.0f;
 }
 
 }  // namespace
@@ -429,6 +429,7 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
             std::memset(&B, 0, sizeof B);
             B.step_a = sa;
             B.link = A;
+            steps[sa].slot = 1;           // read by a later block: numbered below
             const std::vector<int> path = anc(A);
             B.path_off = (int)paths.size();
             B.path_len = (int)path.size();
@@ -466,6 +467,9 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
         }
         steps[si].blk_count = (int)blocks.size() - steps[si].blk_first;
     }
+    // walk-cache slots: only the steps a later block reads keep their bounds per lane
+    int n_slots = 0;
+    for (StepRec &st : steps) st.slot = st.slot ? n_slots++ : -1;
 
     std::vector<float4> spheres(S + kSpl, make_float4(0, 0, 0, 0));   // kSpl padding records
     for (int s = 0; s < S; ++s)
@@ -493,6 +497,7 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
     r->dev.sphere_step = reinterpret_cast<const int32_t *>(base + o_ss);
     r->dev.dof = dof;
     r->dev.n_steps = (int)steps.size();
+    r->dev.n_slots = n_slots;
     r->dev.n_spheres = S;
     r->dev.n_links = dof + 1;
     r->dof = dof;
@@ -1082,8 +1087,8 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
         if (n == 0) return;
         const DeviceInfo &di = device_info(robot->device);
         int block = 256;
-        while (block > 64 && cost_bwd_slot_bytes(robot->dev, block, false) > di.max_lds) block /= 2;
-        const size_t slots = cost_bwd_slot_bytes(robot->dev, block, false);
+        while (block > 64 && cost_bwd_slot_bytes(robot->dev, block, 0) > di.max_lds) block /= 2;
+        const size_t slots = cost_bwd_slot_bytes(robot->dev, block, 0);
         if (slots > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the backward kernel");
         hip_check(launch_cost_bwd(robot->dev, env_for_launch(env, slots), q, n, ldq, grad_cost,
                                   grad_q, ldg, block, (hipStream_t)stream),
@@ -1154,15 +1159,16 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
                 block = g_edge_block;
                 bpc = g_edge_bpc;
             }
-            // per wave: link bound centres, and optionally the joint sines/cosines
-            int cache_floats = 0, cache_floats_jc = 0;
+            // per wave: link bound centres, and optionally capsule halves and joint values
+            int max_slots = 0, max_dof = 0;
             for (const BatchSet &b : recs) {
-                cache_floats = std::max(cache_floats, b.rb.n_steps * 3 * kWave);
-                cache_floats_jc = std::max(cache_floats_jc, (b.rb.n_steps * 3 + b.rb.dof * 2) * kWave);
+                max_slots = std::max(max_slots, b.rb.n_slots);
+                max_dof = std::max(max_dof, b.rb.dof);
             }
-            while (block > kWave && (size_t)(block / kWave) * cache_floats * sizeof(float) > di.max_lds)
+            const int min_floats = step_cache_floats(max_slots, max_dof, 0);
+            while (block > kWave && (size_t)(block / kWave) * min_floats * sizeof(float) > di.max_lds)
                 block -= kWave;
-            if ((size_t)(block / kWave) * cache_floats * sizeof(float) > di.max_lds)
+            if ((size_t)(block / kWave) * min_floats * sizeof(float) > di.max_lds)
                 raise(VK_ERR_UNSUPPORTED, "robots too large for the LDS step cache");
             const int64_t want = (total + block / kWave - 1) / (block / kWave);
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
@@ -1174,7 +1180,7 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             if (err == hipSuccess && total > 0)
                 err = launch_validate_edge_batch(d_sets, d_pre, (int)recs.size(), total, resolution,
                                                  qa, qb, collide, bt->queue, grid, block,
-                                                 cache_floats, cache_floats_jc, cs);
+                                                 max_slots, max_dof, cs);
             hipGraph_t g = nullptr;
             hipError_t err2 = hipStreamEndCapture(cs, &g);
             (void)hipStreamDestroy(cs);

@@ -138,6 +138,35 @@ __device__ __forceinline__ void frame_rotate(const Frame &T, float x, float y, f
     oz = fmaf(T.r[6], x, fmaf(T.r[7], y, T.r[8] * z));
 }
 
+// Squared distance between the segments p1 + s d1 and p2 + t d2 (s, t in [0, 1]), given
+// a = d1.d1 and e = d2.d2 with their reciprocals ia, ie (0 for a segment of zero length).  This
+// is the closest-point construction for two segments (Ericson, Real-Time Collision Detection,
+// sec. 5.1.9), without branches: s minimises the distance between the lines (0 when they are
+// parallel), t is the closest parameter on the second segment for it, and when t leaves [0, 1]
+// (or the second segment is a point) t is clamped and s recomputed for the clamped t.  The two
+// points are always on the segments, so the result can only exceed the exact minimum through
+// rounding in s and t.
+__device__ __forceinline__ float seg_seg2(float p1x, float p1y, float p1z, float d1x, float d1y,
+                                          float d1z, float a, float ia, float p2x, float p2y,
+                                          float p2z, float d2x, float d2y, float d2z, float e,
+                                          float ie) {
+    const float rx = p1x - p2x, ry = p1y - p2y, rz = p1z - p2z;
+    const float b = fmaf(d1x, d2x, fmaf(d1y, d2y, d1z * d2z));
+    const float c = fmaf(d1x, rx, fmaf(d1y, ry, d1z * rz));
+    const float f = fmaf(d2x, rx, fmaf(d2y, ry, d2z * rz));
+    const float den = fmaf(a, e, -b * b);
+    float s = den > 1e-6f * a * e
+                  ? fminf(fmaxf(fmaf(b, f, -c * e) * __builtin_amdgcn_rcpf(den), 0.0f), 1.0f)
+                  : 0.0f;
+    const float t = fmaf(b, s, f) * ie;
+    const float tc = fminf(fmaxf(t, 0.0f), 1.0f);
+    if (t != tc || e == 0.0f) s = fminf(fmaxf(fmaf(tc, b, -c) * ia, 0.0f), 1.0f);
+    const float x = fmaf(-tc, d2x, fmaf(s, d1x, rx));
+    const float y = fmaf(-tc, d2y, fmaf(s, d1y, ry));
+    const float z = fmaf(-tc, d2z, fmaf(s, d1z, rz));
+    return fmaf(x, x, fmaf(y, y, z * z));
+}
+
 // ---------------------------------------------------------------------------------------
 // Overlap tests of a robot sphere (centre c, radius r > 0) with one primitive.  Collision
 // means clearance sd(c) - r < 0; each test is that inequality rewritten without a square

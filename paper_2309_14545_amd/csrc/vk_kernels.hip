@@ -160,8 +160,9 @@ __device__ __forceinline__ void stage_env(float4 *lds, const float4 *__restrict_
 namespace flop {
 constexpr uint32_t kJoint = 30, kMount = 63, kPlace = 18, kSphere = 11, kCapsule = 25,
                    kCylinder = 35, kBox = 34, kPair = 11;
-// sphere against a segment-swept sphere (capsule) bound, and placing a capsule bound's segment
-constexpr uint32_t kSphereCapsule = 25, kPlaceSegment = 33;
+// capsule bound against capsule bound (unpacking the earlier one and the segment distance),
+// sphere bound against capsule bound, and rotating a step's capsule half-vector to the world frame
+constexpr uint32_t kCapsuleCapsule = 67, kSphereCapsule = 28, kPlaceHalf = 15;
 enum Cat { kFk = 0, kCull = 1, kFine = 2, kSelf = 3 };
 }
 struct NoWork {
@@ -173,14 +174,18 @@ struct Work {
 };
 
 // Per-wave LDS cache, per lane: the world centre of every step's link bounding sphere
-// ([step][axis][lane]) and the sine and cosine of every joint angle ([joint][2][lane]), both
-// written by the walk as it poses each link.  The centres gate self blocks without posing the
-// earlier link; the joint sines and cosines make re-posing an earlier link (and rebuilding a
-// tree branch) cost the DH products only.
+// ([step][axis][lane]), the world half-vector of every step's bounding capsule as three halves
+// ([step][2][lane], after the centres) and the sine and cosine of every joint angle
+// ([joint][2][lane], after those), all written by the walk as it poses each link.  The centres
+// and capsules gate self blocks without posing the earlier link; the joint sines and cosines
+// make re-posing an earlier link (and rebuilding a tree branch) cost the DH products only.
+typedef __fp16 half2_t __attribute__((ext_vector_type(2)));
+
 struct StepCache {
     float *base;
     int lane;
-    int joint_off;                 // n_steps * 3 * kWave, or -1 without the joint slots
+    int half_off;                  // n_slots * 3 * kWave, or -1 without the capsule halves
+    int joint_off;                 // after the centres and halves, or -1 without the joint slots
     __device__ __forceinline__ void put(int st, float x, float y, float z) const {
         base[(st * 3 + 0) * kWave + lane] = x;
         base[(st * 3 + 1) * kWave + lane] = y;
@@ -190,6 +195,20 @@ struct StepCache {
         x = base[(st * 3 + 0) * kWave + lane];
         y = base[(st * 3 + 1) * kWave + lane];
         z = base[(st * 3 + 2) * kWave + lane];
+    }
+    // capsule half-vector, each component rounded toward zero to half precision
+    __device__ __forceinline__ void put_h(int st, float x, float y, float z) const {
+        base[half_off + (st * 2 + 0) * kWave + lane] =
+            __builtin_bit_cast(float, __builtin_amdgcn_cvt_pkrtz(x, y));
+        base[half_off + (st * 2 + 1) * kWave + lane] =
+            __builtin_bit_cast(float, __builtin_amdgcn_cvt_pkrtz(z, 0.0f));
+    }
+    __device__ __forceinline__ void get_h(int st, float &x, float &y, float &z) const {
+        const half2_t u = __builtin_bit_cast(half2_t, base[half_off + (st * 2 + 0) * kWave + lane]);
+        const half2_t w = __builtin_bit_cast(half2_t, base[half_off + (st * 2 + 1) * kWave + lane]);
+        x = (float)u.x;
+        y = (float)u.y;
+        z = (float)w.x;
     }
     // joint values: (sin, cos) of a revolute joint's angle, (offset, unused) of a prismatic one
     __device__ __forceinline__ void put_val(int j, const JointRec &J, const JointVal &v) const {
@@ -213,19 +232,20 @@ struct StepCache {
     }
 };
 
-// Floats of LDS per wave for the cache (jc: with the joint slots; a launch leaves them out when
-// their LDS would cost resident waves).
-__host__ __device__ constexpr int step_cache_floats(int n_steps, int dof, bool jc) {
-    return (n_steps * 3 + (jc ? dof * 2 : 0)) * kWave;
+__device__ __forceinline__ StepCache make_step_cache(float *base, int n_slots, int cf) {
+    const int words = (cf & kCacheCaps) ? 5 : 3;
+    return StepCache{base, (int)(threadIdx.x & (kWave - 1)),
+                     (cf & kCacheCaps) ? n_slots * 3 * kWave : -1,
+                     (cf & kCacheJoints) ? n_slots * words * kWave : -1};
 }
 
 // Dynamic LDS of the walks: [cache of every wave of the block][environment records].
-__device__ __forceinline__ StepCache step_cache(float *lds, int n_steps, int dof, bool jc) {
-    return StepCache{lds + (threadIdx.x / kWave) * step_cache_floats(n_steps, dof, jc),
-                     (int)(threadIdx.x & (kWave - 1)), jc ? n_steps * 3 * kWave : -1};
+__device__ __forceinline__ StepCache step_cache(float *lds, int n_slots, int dof, int cf) {
+    return make_step_cache(lds + (threadIdx.x / kWave) * step_cache_floats(n_slots, dof, cf),
+                           n_slots, cf);
 }
-__device__ __forceinline__ float4 *after_caches(float *lds, int n_steps, int dof, bool jc) {
-    return reinterpret_cast<float4 *>(lds + (blockDim.x / kWave) * step_cache_floats(n_steps, dof, jc));
+__device__ __forceinline__ float4 *after_caches(float *lds, int n_slots, int dof, int cf) {
+    return reinterpret_cast<float4 *>(lds + (blockDim.x / kWave) * step_cache_floats(n_slots, dof, cf));
 }
 
 // Pose the link of step S into T (rebuilding a tree branch from the base when needed).  With a
@@ -380,7 +400,16 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         float Cx, Cy, Cz;
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
-        sc.put(st, Cx, Cy, Cz);
+        const bool kept = S.slot >= 0, halves = kept && sc.half_off >= 0;
+        if (kept) sc.put(S.slot, Cx, Cy, Cz);
+        // the step's capsule half-vector (world), for its own self blocks and, kept per lane, for
+        // the blocks of later steps
+        float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+        if (halves || S.blk_count > 0) {
+            frame_rotate(Tm, S.cap_h[0], S.cap_h[1], S.cap_h[2], hx, hy, hz);
+            work.add(flop::kSelf, flop::kPlaceHalf);
+            if (halves) sc.put_h(S.slot, hx, hy, hz);
+        }
         if (st < test_from) continue;         // tested by an earlier pass: pose and cache only
         // the step's fine spheres, placed on first use (uniform decision)
         float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl];
@@ -460,7 +489,8 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         }
 
         // self pairs completed by this step: gate each block with the earlier step's link
-        // bounding sphere (cached centre), then pose its link into Ta, gate each of its spheres
+        // bounding sphere (cached centre) and then with the two links' bounding capsules (the
+        // earlier one cached), then pose its link into Ta, gate each of its spheres
         // with this step's bounding sphere, and test the pairs of those that pass.  The pair
         // test runs relative to this step's bound centre C: with u_k = c_k - C and t' = t - C,
         //   |t' - u_k| < r_t + r_k  <=>  t'.u_k + al_k + r_t r_k > (|t'|^2 - r_t^2) / 2,
@@ -468,33 +498,42 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         // so a pair costs three FMAs, an add and a max; r_t r_k comes with the entry (-inf for
         // pairs not in its mask).  |t'| and |u_k| are at most a few link lengths, so the
         // rounding of the expanded form stays near 1e-7 m^2.
-        bool rel = false, seg = false;
+        bool rel = false;
         float al[kSpl];
-        float px = 0.0f, py = 0.0f, pz = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f;
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec B = ld(rb.blocks, S.blk_first + b);
+            const StepRec SA = ld(rb.steps, B.step_a);
             float ax, ay, az;
-            sc.get(B.step_a, ax, ay, az);
-            const float RA = ld(rb.steps, B.step_a).coarse[3];
+            sc.get(SA.slot, ax, ay, az);
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
-            const float rr = RA + CR;
+            const float rr = SA.coarse[3] + CR;
             work.add(flop::kSelf, flop::kPair);
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
-            // second gate, still without posing A: A's bounding sphere against this step's
-            // bounding capsule (segment placed once per step)
-            if (!seg) {
-                frame_point(Tm, S.cap_p[0], S.cap_p[1], S.cap_p[2], px, py, pz);
-                frame_rotate(Tm, S.cap_u[0], S.cap_u[1], S.cap_u[2], ux, uy, uz);
-                work.add(flop::kSelf, flop::kPlaceSegment);
-                seg = true;
-            }
-            {
+            // second gate, still without posing A: the segments c -+ h of the two links'
+            // bounding capsules (A's half-vector from the cache, in half precision, whose error
+            // A's cap_rq covers); without the halves in the cache, A's bounding sphere against
+            // this step's capsule
+            if (sc.half_off < 0) {
+                const float px = Cx - hx, py = Cy - hy, pz = Cz - hz;
                 const float rx = ax - px, ry = ay - py, rz = az - pz;
-                const float t = fminf(fmaxf(fmaf(rx, ux, fmaf(ry, uy, rz * uz)) * S.cap_inv, 0.0f), 1.0f);
-                const float ex = fmaf(-t, ux, rx), ey = fmaf(-t, uy, ry), ez = fmaf(-t, uz, rz);
-                const float rc = RA + S.cap_r;
+                const float t = fminf(fmaxf(2.0f * fmaf(rx, hx, fmaf(ry, hy, rz * hz)) * S.cap_inv,
+                                            0.0f), 1.0f);
+                const float ex = fmaf(-2.0f * t, hx, rx), ey = fmaf(-2.0f * t, hy, ry),
+                            ez = fmaf(-2.0f * t, hz, rz);
+                const float rc = SA.coarse[3] + S.cap_r;
                 work.add(flop::kSelf, flop::kSphereCapsule);
                 if (!wave_ballot(live && fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rc * rc)) continue;
+            } else {
+                float hax, hay, haz;
+                sc.get_h(SA.slot, hax, hay, haz);
+                const float a = 4.0f * fmaf(hax, hax, fmaf(hay, hay, haz * haz));
+                const float ia = a > 0.0f ? __builtin_amdgcn_rcpf(a) : 0.0f;
+                const float d2 = seg_seg2(ax - hax, ay - hay, az - haz, 2.0f * hax, 2.0f * hay,
+                                          2.0f * haz, a, ia, Cx - hx, Cy - hy, Cz - hz, 2.0f * hx,
+                                          2.0f * hy, 2.0f * hz, S.cap_uu, S.cap_inv);
+                const float rc = SA.cap_rq + S.cap_r;
+                work.add(flop::kSelf, flop::kCapsuleCapsule);
+                if (!wave_ballot(live && d2 < rc * rc)) continue;
             }
             pose_block(rb, B, Ta, ta_link, ta_depth, sc, q, work);
             const float ox = Ta.p[0] - Cx, oy = Ta.p[1] - Cy, oz = Ta.p[2] - Cz;
@@ -576,11 +615,11 @@ template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_validate_states(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                       const float *__restrict__ q, int64_t n, int64_t ldq,
-                      uint8_t *__restrict__ out, int jc) {
+                      uint8_t *__restrict__ out, int cf) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
-    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
+    float4 *lds_env = after_caches(lf, rb.n_slots, rb.dof, cf);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -603,12 +642,12 @@ template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_validate_states_screen(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                              const float *__restrict__ q, int64_t n, int64_t ldq,
-                             uint8_t *__restrict__ out, int jc, int split,
+                             uint8_t *__restrict__ out, int cf, int split,
                              int32_t *__restrict__ surv, unsigned long long *__restrict__ n_surv) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
-    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
+    float4 *lds_env = after_caches(lf, rb.n_slots, rb.dof, cf);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int lane = threadIdx.x & (kWave - 1);
@@ -633,14 +672,14 @@ template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_validate_states_rest(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                            const float *__restrict__ q, int64_t ldq, uint8_t *__restrict__ out,
-                           int jc, int split, const int32_t *__restrict__ surv,
+                           int cf, int split, const int32_t *__restrict__ surv,
                            const unsigned long long *__restrict__ n_surv) {
     const int64_t count = (int64_t)*n_surv;
     if ((int64_t)blockIdx.x * blockDim.x >= count) return;     // whole workgroup past the list
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
-    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
+    float4 *lds_env = after_caches(lf, rb.n_slots, rb.dof, cf);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -764,11 +803,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
     k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                      EdgeSrc src, int64_t n_edges, float res,
                      uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
-                     int chunk, unsigned long long *__restrict__ flops, int jc) {
+                     int chunk, unsigned long long *__restrict__ flops, int cf) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
-    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
+    float4 *lds_env = after_caches(lf, rb.n_slots, rb.dof, cf);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int lane = threadIdx.x & (kWave - 1);
@@ -801,11 +840,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
 template <int STAGE>
 __global__ void __launch_bounds__(64)
     k_validate_edge_one(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
-                        EdgeSrc src, int64_t e, float res, uint8_t *__restrict__ out, int jc) {
+                        EdgeSrc src, int64_t e, float res, uint8_t *__restrict__ out, int cf) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
-    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
+    float4 *lds_env = after_caches(lf, rb.n_slots, rb.dof, cf);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const float *a = nullptr, *b = nullptr;
@@ -825,7 +864,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
     k_validate_edge_batch(const BatchSet *__restrict__ sets, const int64_t *__restrict__ prefix,
                           int n_sets, int64_t total, float res, const float *__restrict__ qa,
                           const float *__restrict__ qb, uint8_t *__restrict__ out,
-                          unsigned long long *__restrict__ queue, int chunk, int cache_floats, int jc) {
+                          unsigned long long *__restrict__ queue, int chunk, int cache_floats, int cf) {
     extern __shared__ float4 lds_dyn[];
     float *cache_base = reinterpret_cast<float *>(lds_dyn) + (threadIdx.x / kWave) * cache_floats;
     const int lane = threadIdx.x & (kWave - 1);
@@ -844,7 +883,7 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
         const float *b = qb + S.qa_offset + local * S.rb.dof;
         const int n = edge_count(a, b, S.rb.dof, res);
         const EnvView ev = make_view<0>(S.env, nullptr);
-        const StepCache sc{cache_base, lane, jc ? S.rb.n_steps * 3 * kWave : -1};
+        const StepCache sc = make_step_cache(cache_base, S.rb.n_slots, cf);
         const uint8_t hit = edge_body(S.rb, ev, S.env, sc, a, b, n);
         out[S.out_offset + local] = hit;      // wave-uniform value
     }
@@ -930,7 +969,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
         float Cx, Cy, Cz;
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
-        sc.put(st, Cx, Cy, Cz);
+        if (S.slot >= 0) sc.put(S.slot, Cx, Cy, Cz);
         if (CR <= ed.vcap) {
             int b, e;
             voxel_range(ev, ed, Cx, Cy, Cz, CR, b, e);
@@ -978,10 +1017,11 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
         }
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec B = ld(rb.blocks, S.blk_first + b);
+            const StepRec SA = ld(rb.steps, B.step_a);
             float ax, ay, az;
-            sc.get(B.step_a, ax, ay, az);
+            sc.get(SA.slot, ax, ay, az);
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
-            const float rr = ld(rb.steps, B.step_a).coarse[3] + CR;
+            const float rr = SA.coarse[3] + CR;
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
             pose_block(rb, B, Ta, ta_link, ta_depth, sc, q);
             for (int e = 0; e < B.ent_count; ++e) {
@@ -1024,11 +1064,11 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
 template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_cost_fwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
-               const float *__restrict__ q, int64_t n, int64_t ldq, float *__restrict__ cost, int jc) {
+               const float *__restrict__ q, int64_t n, int64_t ldq, float *__restrict__ cost, int cf) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
-    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
-    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
+    float4 *lds_env = after_caches(lf, rb.n_slots, rb.dof, cf);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1048,15 +1088,15 @@ template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_cost_bwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                const float *__restrict__ q, int64_t n, int64_t ldq,
-               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg, int jc) {
+               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg, int cf) {
     extern __shared__ float4 lds_dyn[];
     // layout: [slots for every wave of the block][env records]
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const int slot_floats = rb.n_links * 6 * kWave;
     float *slot_base = reinterpret_cast<float *>(lds_dyn);
     float *lf = slot_base + slot_floats * (blockDim.x / kWave);
-    const StepCache sc = step_cache(lf, rb.n_steps, rb.dof, jc);
-    float4 *lds_env = after_caches(lf, rb.n_steps, rb.dof, jc);
+    const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
+    float4 *lds_env = after_caches(lf, rb.n_slots, rb.dof, cf);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     LinkSlots slots{slot_base + wave * slot_floats, lane};
@@ -1366,8 +1406,8 @@ hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int6
     return hipGetLastError();
 }
 
-size_t walk_lds_bytes(const RobotDev &rb, int block, bool jc) {
-    return (size_t)(block / kWave) * step_cache_floats(rb.n_steps, rb.dof, jc) * sizeof(float);
+size_t walk_lds_bytes(const RobotDev &rb, int block, int cf) {
+    return (size_t)(block / kWave) * step_cache_floats(rb.n_slots, rb.dof, cf) * sizeof(float);
 }
 
 // Resident workgroups per CU of a kernel at a block size and dynamic LDS (memoised: the
@@ -1421,29 +1461,40 @@ static size_t device_max_lds() {
     return memo[dev] = (size_t)v;
 }
 
-// Joint slots of the walk cache (see StepCache): kept when they cost no resident workgroups.
-#ifndef VK_JOINT_CACHE
-#define VK_JOINT_CACHE 1           // 0: never, 1: when it costs no resident workgroups, 2: always
+// Optional parts of the walk cache (see StepCache), in the order of preference: the capsule
+// halves (a second self-block gate before posing) ahead of the joint values (cheaper
+// re-posing).  A launch takes the option, with its best staging mode, that keeps the most
+// resident workgroups, then one that stages records, then the earlier option.
+#ifndef VK_CACHE_PARTS
+#define VK_CACHE_PARTS (kCacheCaps | kCacheJoints)   // the parts a launch may use
 #endif
-static bool pick_joint_cache(const void *kernel, int block, size_t without, size_t with,
-                             size_t max_lds) {
-    if (VK_JOINT_CACHE == 0 || with > max_lds) return false;
-    if (VK_JOINT_CACHE == 2) return true;
-    return resident_blocks(kernel, block, with) >= resident_blocks(kernel, block, without);
-}
+static const int kCacheOrder[4] = {kCacheCaps | kCacheJoints, kCacheCaps, kCacheJoints, 0};
 
-// Launch KERNEL<stage, ...> with the joint-cache choice and the staging mode; the launcher
-// defines grid_, block_, base_nojc_, base_jc_ (dynamic LDS before staging) and ARGS_.
+// Launch KERNEL<stage, ...> with the cache parts and the staging mode chosen as above; the
+// launcher defines grid_, block_, lds_(cf) (dynamic LDS before staging with cache parts cf),
+// parts_ (the parts its kernel reads), max_lds_ and ARGS_ (which passes cf).
 #define VK_STAGED(KERNEL, ...)                                                                  \
     {                                                                                           \
+        const void *k_[3] = {reinterpret_cast<const void *>(&KERNEL<0 __VA_ARGS__>),           \
+                             reinterpret_cast<const void *>(&KERNEL<1 __VA_ARGS__>),           \
+                             reinterpret_cast<const void *>(&KERNEL<2 __VA_ARGS__>)};          \
         EnvDev ed = ed_in;                                                                      \
-        const void *k0_ = reinterpret_cast<const void *>(&KERNEL<0 __VA_ARGS__>);              \
-        const int jc = pick_joint_cache(k0_, (int)block_.x, base_nojc_, base_jc_, max_lds_);   \
-        const size_t base_ = jc ? base_jc_ : base_nojc_;                                        \
-        const int mode = pick_stage(ed, k0_, reinterpret_cast<const void *>(&KERNEL<1 __VA_ARGS__>), \
-                                    reinterpret_cast<const void *>(&KERNEL<2 __VA_ARGS__>),     \
-                                    (int)block_.x, base_);                                      \
-        const size_t sh_ = base_ + (size_t)ed.n_stage * 16;                                     \
+        int cf = 0, mode = 0, best_ = -1;                                                       \
+        for (int o_ = 0; o_ < 4; ++o_) {                                                        \
+            const int c_ = kCacheOrder[o_];                                                     \
+            if ((c_ & ~(parts_ & (VK_CACHE_PARTS))) != 0 || lds_(c_) > max_lds_) continue;      \
+            EnvDev e_ = ed_in;                                                                  \
+            const int m_ = pick_stage(e_, k_[0], k_[1], k_[2], (int)block_.x, lds_(c_));       \
+            const int r_ = resident_blocks(k_[m_], (int)block_.x, lds_(c_) + (size_t)e_.n_stage * 16); \
+            if (r_ > best_ || (r_ == best_ && m_ > 0 && mode == 0)) {                           \
+                best_ = r_;                                                                     \
+                cf = c_;                                                                        \
+                mode = m_;                                                                      \
+                ed = e_;                                                                        \
+            }                                                                                   \
+        }                                                                                       \
+        if (best_ < 0) ed.n_stage = 0;                                                          \
+        const size_t sh_ = lds_(cf) + (size_t)ed.n_stage * 16;                                  \
         switch (mode) {                                                                         \
         case 0: hipLaunchKernelGGL((KERNEL<0 __VA_ARGS__>), grid_, block_, sh_, s, ARGS_); break; \
         case 1: hipLaunchKernelGGL((KERNEL<1 __VA_ARGS__>), grid_, block_, sh_, s, ARGS_); break; \
@@ -1467,11 +1518,12 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const
                                   hipStream_t s) {
     const int bs = 256;
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
-    const size_t base_nojc_ = walk_lds_bytes(rb, bs, false), base_jc_ = walk_lds_bytes(rb, bs, true);
+    const auto lds_ = [&](int c) { return walk_lds_bytes(rb, bs, c); };
+    const int parts_ = kCacheCaps | kCacheJoints;
     const size_t max_lds_ = device_max_lds();
     if (!scratch) split = 0;
     if (split == 0) {
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, out, jc
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, out, cf
         VK_STAGED(k_validate_states)
 #undef ARGS_
         return hipGetLastError();
@@ -1479,10 +1531,10 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const
     unsigned long long *n_surv = static_cast<unsigned long long *>(scratch);
     int32_t *surv = reinterpret_cast<int32_t *>(static_cast<char *>(scratch) + 256);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, n_surv, 0ull, 1, 1);
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, out, jc, split, surv, n_surv
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, out, cf, split, surv, n_surv
     VK_STAGED(k_validate_states_screen)
 #undef ARGS_
-#define ARGS_ rb, ed, ed.rec, q, ldq, out, jc, split, surv, n_surv
+#define ARGS_ rb, ed, ed.rec, q, ldq, out, cf, split, surv, n_surv
     VK_STAGED(k_validate_states_rest)
 #undef ARGS_
     return hipGetLastError();
@@ -1581,10 +1633,11 @@ hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const 
                                  unsigned long long *queue, int grid, int block, hipStream_t s,
                                  unsigned long long *flops) {
     const dim3 grid_(grid), block_(block);
-    const size_t base_nojc_ = walk_lds_bytes(rb, block, false), base_jc_ = walk_lds_bytes(rb, block, true);
+    const auto lds_ = [&](int c) { return walk_lds_bytes(rb, block, c); };
+    const int parts_ = kCacheCaps | kCacheJoints;
     const size_t max_lds_ = device_max_lds();
     const int chunk = work_chunk(n_edges, grid, block);
-#define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, jc
+#define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, cf
     if (flops) {
         VK_STAGED(k_validate_edges, , true)
     } else {
@@ -1597,9 +1650,10 @@ hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const 
 hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed_in, const EdgeSrc &src,
                                     int64_t e, float res, uint8_t *out, hipStream_t s) {
     const dim3 grid_(1), block_(kWave);
-    const size_t base_nojc_ = walk_lds_bytes(rb, kWave, false), base_jc_ = walk_lds_bytes(rb, kWave, true);
+    const auto lds_ = [&](int c) { return walk_lds_bytes(rb, kWave, c); };
+    const int parts_ = kCacheCaps | kCacheJoints;
     const size_t max_lds_ = device_max_lds();
-#define ARGS_ rb, ed, ed.rec, src, e, res, out, jc
+#define ARGS_ rb, ed, ed.rec, src, e, res, out, cf
     VK_STAGED(k_validate_edge_one)
 #undef ARGS_
     return hipGetLastError();
@@ -1609,27 +1663,28 @@ hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed_in, const float 
                            int64_t ldq, float *cost, hipStream_t s) {
     const int bs = 256;
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
-    const size_t base_nojc_ = walk_lds_bytes(rb, bs, false), base_jc_ = walk_lds_bytes(rb, bs, true);
+    const auto lds_ = [&](int c) { return walk_lds_bytes(rb, bs, c); };
+    const int parts_ = kCacheCaps | kCacheJoints;
     const size_t max_lds_ = device_max_lds();
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, cost, jc
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, cost, cf
     VK_STAGED(k_cost_fwd)
 #undef ARGS_
     return hipGetLastError();
 }
 
-size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, bool jc) {
+size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, int cf) {
     return (size_t)rb.n_links * 6 * kWave * sizeof(float) * (block / kWave) +
-           walk_lds_bytes(rb, block, jc);
+           walk_lds_bytes(rb, block, cf);
 }
 
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
                            int64_t ldq, const float *gcost, float *grad, int64_t ldg, int block,
                            hipStream_t s) {
     const dim3 grid_((unsigned)((n + block - 1) / block)), block_(block);
-    const size_t base_nojc_ = cost_bwd_slot_bytes(rb, block, false),
-                 base_jc_ = cost_bwd_slot_bytes(rb, block, true);
+    const auto lds_ = [&](int c) { return cost_bwd_slot_bytes(rb, block, c); };
+    const int parts_ = kCacheJoints;          // the cost walks gate self blocks by spheres only
     const size_t max_lds_ = device_max_lds();
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg, jc
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg, cf
     VK_STAGED(k_cost_bwd)
 #undef ARGS_
     return hipGetLastError();
@@ -1639,15 +1694,25 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float 
 hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
                                       int64_t total, float res, const float *qa, const float *qb,
                                       uint8_t *out, unsigned long long *queue, int grid, int block,
-                                      int cache_floats_nojc, int cache_floats_jc, hipStream_t s) {
-    const size_t waves = (size_t)(block / kWave);
-    const size_t without = waves * cache_floats_nojc * sizeof(float);
-    const size_t with = waves * cache_floats_jc * sizeof(float);
-    const int jc = pick_joint_cache(reinterpret_cast<const void *>(&k_validate_edge_batch), block,
-                                    without, with, device_max_lds());
-    hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block), jc ? with : without, s,
-                       sets, prefix, n_sets, total, res, qa, qb, out, queue,
-                       work_chunk(total, grid, block), jc ? cache_floats_jc : cache_floats_nojc, jc);
+                                      int max_slots, int max_dof, hipStream_t s) {
+    // cache parts as for the other walks (no staging here: the records change per set)
+    const void *k = reinterpret_cast<const void *>(&k_validate_edge_batch);
+    const size_t waves = (size_t)(block / kWave), max_lds = device_max_lds();
+    int cf = 0, best = -1;
+    for (int o = 0; o < 4; ++o) {
+        const int c = kCacheOrder[o];
+        const size_t bytes = waves * step_cache_floats(max_slots, max_dof, c) * sizeof(float);
+        if ((c & ~(VK_CACHE_PARTS)) != 0 || bytes > max_lds) continue;
+        const int r = resident_blocks(k, block, bytes);
+        if (r > best) {
+            best = r;
+            cf = c;
+        }
+    }
+    const int floats = step_cache_floats(max_slots, max_dof, cf);
+    hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block), waves * floats * sizeof(float),
+                       s, sets, prefix, n_sets, total, res, qa, qb, out, queue,
+                       work_chunk(total, grid, block), floats, cf);
     return hipGetLastError();
 }
 

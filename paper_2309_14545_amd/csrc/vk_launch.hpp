@@ -41,11 +41,11 @@ hipError_t launch_tree_append(float *nodes, int32_t *parents, int32_t *sizes, in
                               const uint8_t *ok, int32_t *added, hipStream_t s);
 hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, float *cost, hipStream_t s);
-size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, bool jc);
+size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, int cf);
 // Per-workgroup LDS of the walk caches (link bound centres and joint sines/cosines, per wave).
 // With jc the joint sine/cosine slots are included; launchers add them only when they cost no
 // resident workgroups, so callers size their checks without them.
-size_t walk_lds_bytes(const RobotDev &rb, int block, bool jc = false);
+size_t walk_lds_bytes(const RobotDev &rb, int block, int cf = 0);
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
                            int block, hipStream_t s);
@@ -53,6 +53,6 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
 hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
                                       int64_t total, float res, const float *qa, const float *qb,
                                       uint8_t *out, unsigned long long *queue, int grid, int block,
-                                      int cache_floats_nojc, int cache_floats_jc, hipStream_t s);
+                                      int max_slots, int max_dof, hipStream_t s);
 
 }  // namespace vk

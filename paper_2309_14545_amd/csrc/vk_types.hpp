@@ -43,20 +43,37 @@ struct JointRec {                  // 96 bytes
 // paths[restart_off...] (a tree branch), otherwise the step continues from the previous
 // step's pose (serial chain).  A link with more than kSpl spheres is split into several steps;
 // the later ones have joint = -1 and reuse the pose.
-struct StepRec {                   // 80 bytes
+struct StepRec {                   // 96 bytes
     int32_t joint;
     int32_t restart_off, restart_len;
     int32_t sph_first, sph_count;  // fine spheres of this step (<= kSpl)
     int32_t blk_first, blk_count;  // self-collision blocks completed by this step
     int32_t link;
     float coarse[4];               // bounding sphere of the step's spheres, link frame
-    // Bounding capsule of the step's spheres (link frame): segment p + s u, s in [0, 1], and
-    // radius cap_r (padded by 1 mm: it only gates self blocks, and the padding covers the FP32
-    // rounding of the segment distance).  cap_uu = u.u and cap_inv = 1 / u.u (0 if u = 0).
-    float cap_p[3], cap_u[3];
-    float cap_r, cap_uu, cap_inv;
-    float pad[3];
+    // Bounding capsule of the step's spheres (link frame): the segment c - h .. c + h about the
+    // bounding sphere's centre c, radius cap_r (padded by 1 mm: it only gates self blocks, and
+    // the padding covers the FP32 rounding of the segment distance).  cap_rq adds the bound of
+    // the error of h stored in half precision (how an earlier step's capsule is kept per lane).
+    // cap_uu = |2h|^2 and cap_inv = 1 / cap_uu (0 if h = 0).
+    float cap_h[3];
+    float cap_r, cap_rq, cap_uu, cap_inv;
+    int32_t slot;                  // walk-cache slot of this step's bounds, -1 if no later
+                                   // step's self block reads them
+    float pad[4];
 };
+static_assert(sizeof(StepRec) == 96, "StepRec layout");
+
+// Parts of the walk cache a launch includes besides the bounding-sphere centres.
+constexpr int kCacheJoints = 1;     // two floats per joint and lane
+constexpr int kCacheCaps = 2;       // the capsule half-vector, two floats per slot and lane
+
+// Floats of LDS per wave for the walk cache: per slot and lane the link bounding sphere's
+// centre (3) and, with kCacheCaps, the capsule half-vector as halves (2); with kCacheJoints
+// also two per joint and lane.  A launch leaves parts out when their LDS would cost resident
+// waves.
+__host__ __device__ constexpr int step_cache_floats(int n_slots, int dof, int cf) {
+    return (n_slots * ((cf & kCacheCaps) ? 5 : 3) + ((cf & kCacheJoints) ? dof * 2 : 0)) * kWave;
+}
 
 // Self pairs between this step's spheres and the spheres of one earlier step (on link A).  The
 // earlier step's link bounding sphere (its world centre is kept per lane in LDS) gates the
@@ -91,6 +108,7 @@ struct RobotDev {
     const float4 *spheres;         // [S] centre (link frame), radius
     const int32_t *sphere_step;    // [S] step index of each sphere (cost backward)
     int32_t dof, n_steps, n_spheres, n_links;
+    int32_t n_slots;               // steps with a walk-cache slot
 };
 
 // Environment.  Primitive records, packed as float4 in one buffer:

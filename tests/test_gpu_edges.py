@@ -33,6 +33,20 @@ def test_edges_parity(vk, orc, name, per_edge):
     assert bad == 0
 
 
+@pytest.mark.parametrize("name", ["edges7_shelf", "edges8_shelf", "edges8p_shelf"])
+def test_self_only_edges_parity(vk, orc, name):
+    """No obstacles: every colliding edge collides with the robot itself, so the self-block
+    gates (bounding spheres, then bounding capsules, one of them kept per lane in half
+    precision) decide alone whether a pair is tested."""
+    w = workload(name, n=1500)
+    flags = host(vk.validate_edges(vk.Robot(w["robot"]), vk.Env({}), dev(w["qa"]), dev(w["qb"]),
+                                   resolution=RES))
+    _, cls, _ = orc.edges(w["robot"], {}, w["qa"], w["qb"], res=RES)
+    bad, near = edge_mismatches(flags, cls)
+    say(f"self-only edges {name}: mismatches {bad}, near-contact {near}, rate {flags.mean():.3f}")
+    assert bad == 0 and flags.any()
+
+
 def test_edges_full_size_sampled(vk, orc):
     """The full 65,536-edge 7-DoF shelf batch in the default launch; the oracle checks a seeded
     sample of 600 edges."""

@@ -177,6 +177,26 @@ def test_validate_states_parity(vk, orc, name):
     assert bad == 0
 
 
+@pytest.mark.parametrize("name", ["chain7", "chain8", "bimanual14", "lift8"])
+def test_self_only_states_parity(vk, orc, name):
+    """No obstacles: every collision is a self-collision, decided through the self-block gates
+    alone (both the one-pass and the two-pass schedule)."""
+    robot = _robots()[name]
+    q = uniform_states(rng("gpu-self", name), robot["dof"], 3001)
+    cmin, _ = orc.states(robot, {}, q)
+    r, e = vk.Robot(robot), vk.Env({})
+    for split in ((0, 1), (1, 2)):
+        vk.set_states_split(*split)
+        try:
+            flags = host(vk.validate_states(r, e, dev(q)))
+        finally:
+            vk.set_states_split(0, 1)
+        bad, near = state_mismatches(flags, cmin)
+        say(f"self-only states {name} split {split}: mismatches {bad}, near {near}, "
+            f"rate {flags.mean():.3f}")
+        assert bad == 0 and flags.any()
+
+
 def test_validate_states_non_finite(vk, orc):
     w = workload("states7", n=512)
     q = w["q"].copy()
