@@ -512,6 +512,9 @@ float int_bits(int v) {
 
 constexpr int kGridMinSpheres = 1024;
 constexpr double kGridRobotR = 0.08;   // robot radius the point-grid cell size is tuned for
+constexpr double kFieldCell = 0.02;    // clearance-field cell edge (m)
+constexpr double kFieldStep = 0.0005;  // clearance-field unit (m): it reaches 255 x 0.5 mm
+constexpr int64_t kFieldMaxCells = int64_t(1) << 23;
 constexpr double kVoxCap = 0.5;        // voxel lists cover link bounding spheres up to 0.5 m
 constexpr double kVoxMinCell = 0.05;
 constexpr double kVoxMaxCells = 49152; // byte field of at most 48 KiB (fits LDS with records)
@@ -714,6 +717,7 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
 
     // point grid: cell size sized so robot spheres up to kGridRobotR scan a 3x3x3 neighbourhood
     std::vector<float4> pts;
+    std::vector<uint8_t> pfield;
     if (!grid_idx.empty()) {
         const double h = kGridRobotR + gmax_r;
         double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300};
@@ -757,6 +761,57 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
         }
         e->dev.ginv = (float)(1.0 / h);
         e->dev.gmax_r = gmax_r;
+
+        // clearance field: 2 cm cells (coarser for a very large cloud) over the points' box
+        // widened by their largest radius plus the field's reach, so that a location outside it
+        // is farther than the reach from every point
+        const double reach = 255.0 * kFieldStep;
+        double plo[3], phi[3], cell = kFieldCell;
+        for (int a = 0; a < 3; ++a) {
+            plo[a] = glo[a] + 1e-3 - gmax_r - reach;
+            phi[a] = ghi[a] + gmax_r + reach;
+        }
+        int pd[3];
+        for (;;) {
+            for (int a = 0; a < 3; ++a) pd[a] = (int)std::ceil((phi[a] - plo[a]) / cell);
+            if ((int64_t)pd[0] * pd[1] * pd[2] <= kFieldMaxCells) break;
+            cell *= 1.25;
+        }
+        std::vector<float> clear((size_t)pd[0] * pd[1] * pd[2], (float)reach);
+        for (int i : grid_idx) {
+            const double p[3] = {d->spheres[4 * i], d->spheres[4 * i + 1], d->spheres[4 * i + 2]};
+            const double rp = d->spheres[4 * i + 3];
+            int c0[3], c1[3];
+            for (int a = 0; a < 3; ++a) {
+                c0[a] = std::max(0, (int)std::floor((p[a] - rp - reach - plo[a]) / cell));
+                c1[a] = std::min(pd[a] - 1, (int)std::floor((p[a] + rp + reach - plo[a]) / cell));
+            }
+            for (int z = c0[2]; z <= c1[2]; ++z)
+                for (int y = c0[1]; y <= c1[1]; ++y)
+                    for (int x = c0[0]; x <= c1[0]; ++x) {
+                        const int c[3] = {x, y, z};
+                        double d2 = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            const double lo = plo[a] + c[a] * cell, hi = lo + cell;
+                            const double g = std::max(0.0, std::max(lo - p[a], p[a] - hi));
+                            d2 += g * g;
+                        }
+                        float &v = clear[((size_t)z * pd[1] + y) * pd[0] + x];
+                        v = std::min(v, (float)(std::sqrt(d2) - rp));
+                    }
+        }
+        // rounded down, less 10 um for the device's float cell lookup near a cell face
+        pfield.resize(clear.size());
+        for (size_t c = 0; c < clear.size(); ++c) {
+            const double u = std::floor(((double)clear[c] - 1e-5) / kFieldStep);
+            pfield[c] = (uint8_t)std::min(255.0, std::max(0.0, u));
+        }
+        for (int a = 0; a < 3; ++a) {
+            e->dev.pdim[a] = pd[a];
+            e->dev.porg[a] = (float)plo[a];
+        }
+        e->dev.pinv = (float)(1.0 / cell);
+        e->dev.pq = std::nextafter((float)kFieldStep, 0.0f);
     } else {
         e->dev.off_cell = (int)rec.size();
     }
@@ -778,6 +833,7 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     const size_t o_p = bl.add(pts.data(), pts.size() * sizeof(float4));
     const size_t o_s = bl.add(vstart.data(), vstart.size() * sizeof(int));
     const size_t o_l = bl.add(vlist.data(), vlist.size() * sizeof(int2));
+    const size_t o_f = bl.add(pfield.data(), pfield.size());
     e->device = current_device();
     e->blob = bl.upload();
     char *base = static_cast<char *>(e->blob);
@@ -785,6 +841,7 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     e->dev.grid_pts = reinterpret_cast<const float4 *>(base + o_p);
     e->dev.vstart = reinterpret_cast<const int32_t *>(base + o_s);
     e->dev.vlist = reinterpret_cast<const int2 *>(base + o_l);
+    e->dev.pfield = pfield.empty() ? nullptr : reinterpret_cast<const uint8_t *>(base + o_f);
 }
 
 // Environment for one launch, with the number of leading records staged in LDS: the

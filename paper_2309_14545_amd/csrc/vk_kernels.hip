@@ -163,6 +163,8 @@ constexpr uint32_t kJoint = 30, kMount = 63, kPlace = 18, kSphere = 11, kCapsule
 // capsule bound against capsule bound (unpacking the earlier one and the segment distance),
 // sphere bound against capsule bound, and rotating a step's capsule half-vector to the world frame
 constexpr uint32_t kCapsuleCapsule = 67, kSphereCapsule = 28, kPlaceHalf = 15;
+// looking up a location in the point-cloud clearance field
+constexpr uint32_t kClearance = 7;
 enum Cat { kFk = 0, kCull = 1, kFine = 2, kSelf = 3 };
 }
 struct NoWork {
@@ -332,14 +334,18 @@ template <class F>
 __device__ __forceinline__ void grid_scan(const EnvView &ev, const EnvDev &g, float cx, float cy,
                                           float cz, float r, F &&visit) {
     const float *cell = ev.cell;
-    const int R = (int)ceilf((r + g.gmax_r) * g.ginv * 1.00001f + 1e-5f);
-    const float lim = 1.0e6f;
-    const int ix = (int)fminf(fmaxf(floorf((cx - g.gorg[0]) * g.ginv), -lim), lim);
-    const int iy = (int)fminf(fmaxf(floorf((cy - g.gorg[1]) * g.ginv), -lim), lim);
-    const int iz = (int)fminf(fmaxf(floorf((cz - g.gorg[2]) * g.ginv), -lim), lim);
-    const int x0 = max(ix - R, 0), x1 = min(ix + R, g.gdim[0] - 1);
-    const int y0 = max(iy - R, 0), y1 = min(iy + R, g.gdim[1] - 1);
-    const int z0 = max(iz - R, 0), z1 = min(iz + R, g.gdim[2] - 1);
+    // the cells that the box c -+ (r + largest point radius) touches (widened a little for the
+    // float rounding of the cell coordinates)
+    const float reach = (r + g.gmax_r) * 1.00001f + 1e-5f, lim = 1.0e6f;
+    const auto lo = [&](float c, float o) {
+        return max((int)fminf(fmaxf(floorf((c - reach - o) * g.ginv), -lim), lim), 0);
+    };
+    const auto hi = [&](float c, float o, int n) {
+        return min((int)fminf(fmaxf(floorf((c + reach - o) * g.ginv), -lim), lim), n - 1);
+    };
+    const int x0 = lo(cx, g.gorg[0]), x1 = hi(cx, g.gorg[0], g.gdim[0]);
+    const int y0 = lo(cy, g.gorg[1]), y1 = hi(cy, g.gorg[1], g.gdim[1]);
+    const int z0 = lo(cz, g.gorg[2]), z1 = hi(cz, g.gorg[2], g.gdim[2]);
     if (x0 > x1) return;
     for (int z = z0; z <= z1; ++z)
         for (int y = y0; y <= y1; ++y) {
@@ -348,6 +354,19 @@ __device__ __forceinline__ void grid_scan(const EnvView &ev, const EnvDev &g, fl
             for (int p = b; p < e; ++p)
                 if (visit(g.grid_pts[p])) return;
         }
+}
+
+// Lower bound of the clearance of location (x, y, z) to every point of the grid, from the
+// clearance field (a location outside the field is at least 255 units away).
+__device__ __forceinline__ float point_clearance(const EnvDev &g, float x, float y, float z) {
+    const float lim = 1.0e6f;
+    const int ix = (int)fminf(fmaxf(floorf((x - g.porg[0]) * g.pinv), -lim), lim);
+    const int iy = (int)fminf(fmaxf(floorf((y - g.porg[1]) * g.pinv), -lim), lim);
+    const int iz = (int)fminf(fmaxf(floorf((z - g.porg[2]) * g.pinv), -lim), lim);
+    const bool in = ix >= 0 && iy >= 0 && iz >= 0 && ix < g.pdim[0] && iy < g.pdim[1] &&
+                    iz < g.pdim[2];
+    const int c = in ? (iz * g.pdim[1] + iy) * g.pdim[0] + ix : 0;
+    return (in ? (float)g.pfield[c] : 255.0f) * g.pq;
 }
 
 __device__ __forceinline__ bool grid_hit(const EnvView &ev, const EnvDev &g, float cx, float cy,
@@ -475,16 +494,24 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
                         hit_box(cx[k], cy[k], cz[k], cr[k], X, Y, Z, O))
             }
         }
+        // points: the clearance field rules out a link (its bounding sphere) or a sphere whose
+        // neighbourhood holds no point within its radius before the grid is scanned
         if (ed.n_cells > 0) {
-            VK_PLACE()
+            const bool near = live && !col && point_clearance(ed, Cx, Cy, Cz) < CR;
+            work.add(flop::kCull, flop::kClearance);
+            if (wave_ballot(near)) {
+                VK_PLACE()
 #pragma unroll
-            for (int k = 0; k < kSpl; ++k)
-                if (k < cnt && live && !col) col |= grid_hit(ev, ed, cx[k], cy[k], cz[k], cr[k]);
-            if (EDGE) {
-                if (wave_ballot(col)) return true;
-            } else {
-                live = !col;
-                if (!wave_ballot(live)) return col;
+                for (int k = 0; k < kSpl; ++k)
+                    if (k < cnt && near && !col &&
+                        point_clearance(ed, cx[k], cy[k], cz[k]) < cr[k])
+                        col |= grid_hit(ev, ed, cx[k], cy[k], cz[k], cr[k]);
+                if (EDGE) {
+                    if (wave_ballot(col)) return true;
+                } else {
+                    live = !col;
+                    if (!wave_ballot(live)) return col;
+                }
             }
         }
 
@@ -1005,10 +1032,10 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
                              sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
             }
         }
-        if (ed.n_cells > 0 && live) {
+        if (ed.n_cells > 0 && live && point_clearance(ed, Cx, Cy, Cz) < CR) {
 #pragma unroll
             for (int k = 0; k < kSpl; ++k) {
-                if (k >= cnt) continue;
+                if (k >= cnt || point_clearance(ed, cx[k], cy[k], cz[k]) >= cr[k]) continue;
                 grid_scan(ev, ed, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
                     VK_PEN(sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
                     return false;

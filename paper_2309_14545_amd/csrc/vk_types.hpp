@@ -145,6 +145,13 @@ struct EnvDev {
     float gorg[3];
     float ginv;                    // 1 / cell size
     float gmax_r;                  // largest point radius
+    // Clearance field of those points on a finer uniform grid: per cell a lower bound, over
+    // every location in the cell, of (distance to a point's centre) - (that point's radius), in
+    // units of pq, rounded down and saturated at 255.  Locations outside the field are at
+    // least 255 pq from every point.
+    const uint8_t *pfield;
+    int32_t pdim[3];
+    float porg[3], pinv, pq;
 };
 
 // One edge set of a mixed-robot batch.
