@@ -718,6 +718,8 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     // point grid: cell size sized so robot spheres up to kGridRobotR scan a 3x3x3 neighbourhood
     std::vector<float4> pts;
     std::vector<uint8_t> pfield;
+    GridDev gd;
+    std::memset(&gd, 0, sizeof gd);
     if (!grid_idx.empty()) {
         const double h = kGridRobotR + gmax_r;
         double glo[3] = {1e300, 1e300, 1e300}, ghi[3] = {-1e300, -1e300, -1e300};
@@ -754,13 +756,13 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
         std::memcpy(cells.data(), start.data(), start.size() * sizeof(int));
         e->dev.off_cell = put(cells);
         e->dev.n_cells = (int)ncell;
-        e->dev.n_pts = (int)pts.size();
+        gd.n_pts = (int)pts.size();
         for (int a = 0; a < 3; ++a) {
-            e->dev.gdim[a] = dim[a];
-            e->dev.gorg[a] = (float)glo[a];
+            gd.gdim[a] = dim[a];
+            gd.gorg[a] = (float)glo[a];
         }
-        e->dev.ginv = (float)(1.0 / h);
-        e->dev.gmax_r = gmax_r;
+        gd.ginv = (float)(1.0 / h);
+        gd.gmax_r = gmax_r;
 
         // clearance field: 2 cm cells (coarser for a very large cloud) over the points' box
         // widened by their largest radius plus the field's reach, so that a location outside it
@@ -807,11 +809,11 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
             pfield[c] = (uint8_t)std::min(255.0, std::max(0.0, u));
         }
         for (int a = 0; a < 3; ++a) {
-            e->dev.pdim[a] = pd[a];
-            e->dev.porg[a] = (float)plo[a];
+            gd.pdim[a] = pd[a];
+            gd.porg[a] = (float)plo[a];
         }
-        e->dev.pinv = (float)(1.0 / cell);
-        e->dev.pq = std::nextafter((float)kFieldStep, 0.0f);
+        gd.pinv = (float)(1.0 / cell);
+        gd.pq = std::nextafter((float)kFieldStep, 0.0f);
     } else {
         e->dev.off_cell = (int)rec.size();
     }
@@ -834,14 +836,19 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     const size_t o_s = bl.add(vstart.data(), vstart.size() * sizeof(int));
     const size_t o_l = bl.add(vlist.data(), vlist.size() * sizeof(int2));
     const size_t o_f = bl.add(pfield.data(), pfield.size());
+    const size_t o_g = bl.add(&gd, sizeof gd);     // its pointers are set after the upload
     e->device = current_device();
     e->blob = bl.upload();
     char *base = static_cast<char *>(e->blob);
     e->dev.rec = reinterpret_cast<const float4 *>(base + o_r);
-    e->dev.grid_pts = reinterpret_cast<const float4 *>(base + o_p);
+    if (e->dev.n_cells > 0) {
+        gd.pts = reinterpret_cast<const float4 *>(base + o_p);
+        gd.pfield = reinterpret_cast<const uint8_t *>(base + o_f);
+        hip_check(hipMemcpy(base + o_g, &gd, sizeof gd, hipMemcpyHostToDevice), "hipMemcpy");
+        e->dev.grid = reinterpret_cast<const GridDev *>(base + o_g);
+    }
     e->dev.vstart = reinterpret_cast<const int32_t *>(base + o_s);
     e->dev.vlist = reinterpret_cast<const int2 *>(base + o_l);
-    e->dev.pfield = pfield.empty() ? nullptr : reinterpret_cast<const uint8_t *>(base + o_f);
 }
 
 // Environment for one launch, with the number of leading records staged in LDS: the
@@ -850,7 +857,7 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
 // caches, adjoint slots) and must fit on its own.
 EnvDev env_for_launch(const vk_env_s *e, size_t extra) {
     const DeviceInfo &di = device_info(e->device);
-    if (extra > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the LDS step cache");
+    if (extra > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the LDS walk cache");
     EnvDev d = e->dev;
     auto fits = [&](int n) {
         const size_t b = (size_t)n * 16;
@@ -1226,7 +1233,7 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             while (block > kWave && (size_t)(block / kWave) * min_floats * sizeof(float) > di.max_lds)
                 block -= kWave;
             if ((size_t)(block / kWave) * min_floats * sizeof(float) > di.max_lds)
-                raise(VK_ERR_UNSUPPORTED, "robots too large for the LDS step cache");
+                raise(VK_ERR_UNSUPPORTED, "robots too large for the LDS walk cache");
             const int64_t want = (total + block / kWave - 1) / (block / kWave);
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
             // capture {queue reset, persistent launch} once; vk_edge_batch_run replays it

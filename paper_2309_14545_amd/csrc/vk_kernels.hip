@@ -175,10 +175,11 @@ struct Work {
     __device__ __forceinline__ void add(int c, uint32_t x) { f[c] += x; }
 };
 
-// Per-wave LDS cache, per lane: the world centre of every step's link bounding sphere
-// ([step][axis][lane]), the world half-vector of every step's bounding capsule as three halves
-// ([step][2][lane], after the centres) and the sine and cosine of every joint angle
-// ([joint][2][lane], after those), all written by the walk as it poses each link.  The centres
+// Per-wave LDS cache, per lane, with a slot for each step whose bounds a later self block
+// reads: the world centre of the step's link bounding sphere ([slot][axis][lane]), optionally
+// the world half-vector of its bounding capsule as three halves ([slot][2][lane], after the
+// centres), and optionally the sine and cosine of every joint angle ([joint][2][lane], after
+// those), all written by the walk as it poses each link.  The centres
 // and capsules gate self blocks without posing the earlier link; the joint sines and cosines
 // make re-posing an earlier link (and rebuilding a tree branch) cost the DH products only.
 typedef __fp16 half2_t __attribute__((ext_vector_type(2)));
@@ -331,7 +332,7 @@ __device__ __forceinline__ void place_step(const RobotDev &rb, const StepRec &S,
 // in the sorted point array, so each (z, y) row is one contiguous range.  Per lane (the cells
 // differ between configurations); `visit(p)` returns true to stop.
 template <class F>
-__device__ __forceinline__ void grid_scan(const EnvView &ev, const EnvDev &g, float cx, float cy,
+__device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, float cx, float cy,
                                           float cz, float r, F &&visit) {
     const float *cell = ev.cell;
     // the cells that the box c -+ (r + largest point radius) touches (widened a little for the
@@ -352,13 +353,13 @@ __device__ __forceinline__ void grid_scan(const EnvView &ev, const EnvDev &g, fl
             const int row = (z * g.gdim[1] + y) * g.gdim[0];
             const int b = __float_as_int(cell[row + x0]), e = __float_as_int(cell[row + x1 + 1]);
             for (int p = b; p < e; ++p)
-                if (visit(g.grid_pts[p])) return;
+                if (visit(g.pts[p])) return;
         }
 }
 
 // Lower bound of the clearance of location (x, y, z) to every point of the grid, from the
 // clearance field (a location outside the field is at least 255 units away).
-__device__ __forceinline__ float point_clearance(const EnvDev &g, float x, float y, float z) {
+__device__ __forceinline__ float point_clearance(const GridDev &g, float x, float y, float z) {
     const float lim = 1.0e6f;
     const int ix = (int)fminf(fmaxf(floorf((x - g.porg[0]) * g.pinv), -lim), lim);
     const int iy = (int)fminf(fmaxf(floorf((y - g.porg[1]) * g.pinv), -lim), lim);
@@ -369,7 +370,7 @@ __device__ __forceinline__ float point_clearance(const EnvDev &g, float x, float
     return (in ? (float)g.pfield[c] : 255.0f) * g.pq;
 }
 
-__device__ __forceinline__ bool grid_hit(const EnvView &ev, const EnvDev &g, float cx, float cy,
+__device__ __forceinline__ bool grid_hit(const EnvView &ev, const GridDev &g, float cx, float cy,
                                          float cz, float r) {
     bool hit = false;
     grid_scan(ev, g, cx, cy, cz, r, [&](const float4 &p) {
@@ -497,15 +498,16 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         // points: the clearance field rules out a link (its bounding sphere) or a sphere whose
         // neighbourhood holds no point within its radius before the grid is scanned
         if (ed.n_cells > 0) {
-            const bool near = live && !col && point_clearance(ed, Cx, Cy, Cz) < CR;
+            const GridDev G = ld(ed.grid, 0);
+            const bool near = live && !col && point_clearance(G, Cx, Cy, Cz) < CR;
             work.add(flop::kCull, flop::kClearance);
             if (wave_ballot(near)) {
                 VK_PLACE()
 #pragma unroll
                 for (int k = 0; k < kSpl; ++k)
                     if (k < cnt && near && !col &&
-                        point_clearance(ed, cx[k], cy[k], cz[k]) < cr[k])
-                        col |= grid_hit(ev, ed, cx[k], cy[k], cz[k], cr[k]);
+                        point_clearance(G, cx[k], cy[k], cz[k]) < cr[k])
+                        col |= grid_hit(ev, G, cx[k], cy[k], cz[k], cr[k]);
                 if (EDGE) {
                     if (wave_ballot(col)) return true;
                 } else {
@@ -996,7 +998,13 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
         float Cx, Cy, Cz;
         frame_point(Tm, S.coarse[0], S.coarse[1], S.coarse[2], Cx, Cy, Cz);
         const float CR = S.coarse[3];
+        const bool halves = S.slot >= 0 && sc.half_off >= 0;
         if (S.slot >= 0) sc.put(S.slot, Cx, Cy, Cz);
+        float hx = 0.0f, hy = 0.0f, hz = 0.0f;      // capsule half-vector (world), as in the walk
+        if (halves || S.blk_count > 0) {
+            frame_rotate(Tm, S.cap_h[0], S.cap_h[1], S.cap_h[2], hx, hy, hz);
+            if (halves) sc.put_h(S.slot, hx, hy, hz);
+        }
         if (CR <= ed.vcap) {
             int b, e;
             voxel_range(ev, ed, Cx, Cy, Cz, CR, b, e);
@@ -1032,14 +1040,17 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
                              sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
             }
         }
-        if (ed.n_cells > 0 && live && point_clearance(ed, Cx, Cy, Cz) < CR) {
+        if (ed.n_cells > 0 && live) {
+            const GridDev G = ld(ed.grid, 0);
+            if (point_clearance(G, Cx, Cy, Cz) < CR) {
 #pragma unroll
-            for (int k = 0; k < kSpl; ++k) {
-                if (k >= cnt || point_clearance(ed, cx[k], cy[k], cz[k]) >= cr[k]) continue;
-                grid_scan(ev, ed, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
-                    VK_PEN(sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
-                    return false;
-                });
+                for (int k = 0; k < kSpl; ++k) {
+                    if (k >= cnt || point_clearance(G, cx[k], cy[k], cz[k]) >= cr[k]) continue;
+                    grid_scan(ev, G, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
+                        VK_PEN(sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
+                        return false;
+                    });
+                }
             }
         }
         for (int b = 0; b < S.blk_count; ++b) {
@@ -1050,11 +1061,28 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
             const float rr = SA.coarse[3] + CR;
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
+            // the gates of the collision walk: no pair they rule out can penetrate, so the
+            // cost and its gradient do not change
+            if (sc.half_off >= 0) {
+                float hax, hay, haz;
+                sc.get_h(SA.slot, hax, hay, haz);
+                const float a = 4.0f * fmaf(hax, hax, fmaf(hay, hay, haz * haz));
+                const float ia = a > 0.0f ? __builtin_amdgcn_rcpf(a) : 0.0f;
+                const float d2 = seg_seg2(ax - hax, ay - hay, az - haz, 2.0f * hax, 2.0f * hay,
+                                          2.0f * haz, a, ia, Cx - hx, Cy - hy, Cz - hz, 2.0f * hx,
+                                          2.0f * hy, 2.0f * hz, S.cap_uu, S.cap_inv);
+                const float rc = SA.cap_rq + S.cap_r;
+                if (!wave_ballot(live && d2 < rc * rc)) continue;
+            }
             pose_block(rb, B, Ta, ta_link, ta_depth, sc, q);
             for (int e = 0; e < B.ent_count; ++e) {
                 const EntryRec E = ld(rb.entries, B.ent_first + e);
                 float tx, ty, tz;
                 frame_point(Ta, E.x, E.y, E.z, tx, ty, tz);
+                {
+                    const float ex = tx - Cx, ey = ty - Cy, ez = tz - Cz;
+                    if (!wave_ballot(live && fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < E.gate2)) continue;
+                }
                 float gtx = 0.0f, gty = 0.0f, gtz = 0.0f;
 #pragma unroll
                 for (int k = 0; k < kSpl; ++k) {
@@ -1457,7 +1485,7 @@ static int resident_blocks(const void *kernel, int block, size_t lds) {
 
 // Staging mode of a launch (see make_view).  ed.n_stage arrives as the largest prefix that fits
 // the LDS; a prefix is staged only if it costs no resident workgroups against reading every
-// record from global memory: when the per-wave step caches already fill the LDS, staging the
+// record from global memory: when the per-wave walk caches already fill the LDS, staging the
 // records would trade occupancy for latency, and occupancy matters more here.  On return
 // ed.n_stage is the prefix the chosen mode stages.
 static int pick_stage(EnvDev &ed, const void *k0, const void *k1, const void *k2, int block,
@@ -1499,7 +1527,7 @@ static const int kCacheOrder[4] = {kCacheCaps | kCacheJoints, kCacheCaps, kCache
 
 // Launch KERNEL<stage, ...> with the cache parts and the staging mode chosen as above; the
 // launcher defines grid_, block_, lds_(cf) (dynamic LDS before staging with cache parts cf),
-// parts_ (the parts its kernel reads), max_lds_ and ARGS_ (which passes cf).
+// max_lds_ and ARGS_ (which passes cf).
 #define VK_STAGED(KERNEL, ...)                                                                  \
     {                                                                                           \
         const void *k_[3] = {reinterpret_cast<const void *>(&KERNEL<0 __VA_ARGS__>),           \
@@ -1509,7 +1537,7 @@ static const int kCacheOrder[4] = {kCacheCaps | kCacheJoints, kCacheCaps, kCache
         int cf = 0, mode = 0, best_ = -1;                                                       \
         for (int o_ = 0; o_ < 4; ++o_) {                                                        \
             const int c_ = kCacheOrder[o_];                                                     \
-            if ((c_ & ~(parts_ & (VK_CACHE_PARTS))) != 0 || lds_(c_) > max_lds_) continue;      \
+            if ((c_ & ~(VK_CACHE_PARTS)) != 0 || lds_(c_) > max_lds_) continue;                 \
             EnvDev e_ = ed_in;                                                                  \
             const int m_ = pick_stage(e_, k_[0], k_[1], k_[2], (int)block_.x, lds_(c_));       \
             const int r_ = resident_blocks(k_[m_], (int)block_.x, lds_(c_) + (size_t)e_.n_stage * 16); \
@@ -1546,7 +1574,6 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const
     const int bs = 256;
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, bs, c); };
-    const int parts_ = kCacheCaps | kCacheJoints;
     const size_t max_lds_ = device_max_lds();
     if (!scratch) split = 0;
     if (split == 0) {
@@ -1661,7 +1688,6 @@ hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const 
                                  unsigned long long *flops) {
     const dim3 grid_(grid), block_(block);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, block, c); };
-    const int parts_ = kCacheCaps | kCacheJoints;
     const size_t max_lds_ = device_max_lds();
     const int chunk = work_chunk(n_edges, grid, block);
 #define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, cf
@@ -1678,7 +1704,6 @@ hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed_in, con
                                     int64_t e, float res, uint8_t *out, hipStream_t s) {
     const dim3 grid_(1), block_(kWave);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, kWave, c); };
-    const int parts_ = kCacheCaps | kCacheJoints;
     const size_t max_lds_ = device_max_lds();
 #define ARGS_ rb, ed, ed.rec, src, e, res, out, cf
     VK_STAGED(k_validate_edge_one)
@@ -1691,7 +1716,6 @@ hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed_in, const float 
     const int bs = 256;
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, bs, c); };
-    const int parts_ = kCacheCaps | kCacheJoints;
     const size_t max_lds_ = device_max_lds();
 #define ARGS_ rb, ed, ed.rec, q, n, ldq, cost, cf
     VK_STAGED(k_cost_fwd)
@@ -1709,7 +1733,6 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float 
                            hipStream_t s) {
     const dim3 grid_((unsigned)((n + block - 1) / block)), block_(block);
     const auto lds_ = [&](int c) { return cost_bwd_slot_bytes(rb, block, c); };
-    const int parts_ = kCacheJoints;          // the cost walks gate self blocks by spheres only
     const size_t max_lds_ = device_max_lds();
 #define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg, cf
     VK_STAGED(k_cost_bwd)

@@ -76,10 +76,10 @@ __host__ __device__ constexpr int step_cache_floats(int n_slots, int dof, int cf
 }
 
 // Self pairs between this step's spheres and the spheres of one earlier step (on link A).  The
-// earlier step's link bounding sphere (its world centre is kept per lane in LDS) gates the
-// block; only then is A posed into a second register frame, continuing from the frame's
-// current link when that link is an ancestor of A (anc bits), else from the base along the
-// full path of joints.
+// earlier step's link bounding sphere and bounding capsule (their world centre and half-vector
+// are kept per lane in LDS) gate the block; only then is A posed into a second register frame,
+// continuing from the frame's current link when that link is an ancestor of A (anc bits), else
+// from the base along the full path of joints.
 struct BlockRec {                  // 48 bytes
     int32_t step_a;                // earlier step
     int32_t path_off, path_len;    // joints from the base to link A, base-most first
@@ -136,20 +136,28 @@ struct EnvDev {
     const int2 *vlist;
     int32_t vdim[3], n_vox;
     float vorg[3], vinv, vq, vcap;
-    // Uniform grid over a large set of small spheres (point clouds); n_cells == 0 when absent.
-    // The cell index is part of the record buffer at off_cell; the points themselves, sorted by
-    // cell, stay in global memory (L2).
-    const float4 *grid_pts;        // [n_pts] centre, radius
-    int32_t n_cells, n_pts;
+    // Uniform grid over a large set of small spheres (point clouds); n_cells == 0 and
+    // grid == nullptr when absent.  The cell index is part of the record buffer at off_cell;
+    // the rest of the grid is described by *grid.
+    const struct GridDev *grid;
+    int32_t n_cells;
+};
+
+// The point grid and its clearance field, kept in the environment's device buffer (so that a
+// walk reads it only where it meets a point cloud).  The points, sorted by cell, stay in global
+// memory (L2).
+struct GridDev {
+    const float4 *pts;             // [n_pts] centre, radius
+    // Clearance field of the points on a finer uniform grid: per cell a lower bound, over every
+    // location in the cell, of (distance to a point's centre) - (that point's radius), in units
+    // of pq, rounded down and saturated at 255.  Locations outside the field are at least
+    // 255 pq from every point.
+    const uint8_t *pfield;
+    int32_t n_pts;
     int32_t gdim[3];
     float gorg[3];
     float ginv;                    // 1 / cell size
     float gmax_r;                  // largest point radius
-    // Clearance field of those points on a finer uniform grid: per cell a lower bound, over
-    // every location in the cell, of (distance to a point's centre) - (that point's radius), in
-    // units of pq, rounded down and saturated at 255.  Locations outside the field are at
-    // least 255 pq from every point.
-    const uint8_t *pfield;
     int32_t pdim[3];
     float porg[3], pinv, pq;
 };
