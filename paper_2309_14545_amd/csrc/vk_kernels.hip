@@ -1219,7 +1219,10 @@ __global__ void __launch_bounds__(256)
 // distances go to the lower index.  Candidates with a non-finite distance are skipped; list
 // slots left without a neighbour hold index -1 and distance +inf.
 // ---------------------------------------------------------------------------------------------
-constexpr int kKnnTile = 128;
+#ifndef VK_KNN_TILE
+#define VK_KNN_TILE 128
+#endif
+constexpr int kKnnTile = VK_KNN_TILE;
 
 __device__ __forceinline__ bool knn_less(float d, int i, float e, int j) {
     return d < e || (d == e && i < j);
@@ -1253,19 +1256,38 @@ __device__ __forceinline__ void knn_insert(float (&bd)[K], int (&bi)[K], float s
 // part p, [p n / parts, (p+1) n / parts), through LDS; each lane keeps the best K of that part
 // in registers and writes them to part lists [parts][n][K] (index 0x7fffffff = none).  Splitting
 // the candidates over parts gives the launch parts x n / 64 waves instead of n / 64.
-template <int K, int MAXD>
+// A candidate that beats its lane's current K-th goes to the lane's buffer in LDS first; the
+// lanes merge their buffers into their lists when one lane's buffer is full (and at the end).
+// Inserting one candidate at a time, a wave would run the sorted insertion for every
+// candidate some lane accepts; with the buffers it runs as many insertions as its busiest lane
+// accepted.  Every buffered candidate is still inserted in (distance, index) order, so the
+// lists are the same.
+#ifndef VK_KNN_BUF
+#define VK_KNN_BUF 16
+#endif
+constexpr int kKnnBuf = VK_KNN_BUF;            // buffered candidates per lane
+
+// DP: the dimension padded to a multiple of 4.  The query and the tile hold zeros past dim, and
+// adding a zero term leaves a sum unchanged, so the padded sum equals the sum over dim terms
+// in the same order; each candidate is read as DP / 4 16-byte LDS loads, with no branch per
+// dimension.
+template <int K, int DP>
 __global__ void __launch_bounds__(64) k_knn_part(const float *__restrict__ x, int64_t n, int dim,
                                                  int parts, int32_t *__restrict__ pidx,
                                                  float *__restrict__ pd2) {
 #pragma clang fp contract(off)                 // products and sums rounded separately
-    extern __shared__ float tile[];            // [dim][kKnnTile]
+    extern __shared__ float4 lds4[];
+    float4 *tile = lds4;                       // [kKnnTile][DP / 4]
+    float *bufd = reinterpret_cast<float *>(lds4 + kKnnTile * (DP / 4));   // [kKnnBuf][64]
+    int *bufi = reinterpret_cast<int *>(bufd + kKnnBuf * kWave);
+    const int lane = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = i < n;
     const int p = blockIdx.y;
     const int64_t c0 = n * p / parts, c1 = n * (p + 1) / parts;
-    float xi[MAXD];
+    float xi[DP];
 #pragma unroll
-    for (int j = 0; j < MAXD; ++j) xi[j] = (active && j < dim) ? x[i * dim + j] : 0.0f;
+    for (int j = 0; j < DP; ++j) xi[j] = (active && j < dim) ? x[i * dim + j] : 0.0f;
     float bd[K];
     int bi[K];
 #pragma unroll
@@ -1273,27 +1295,44 @@ __global__ void __launch_bounds__(64) k_knn_part(const float *__restrict__ x, in
         bd[m] = INFINITY;
         bi[m] = 0x7fffffff;
     }
+    int nb = 0;                                // this lane's buffered candidates
+    const auto flush = [&]() {
+        for (int b = 0; b < nb; ++b) knn_insert<K>(bd, bi, bufd[b * kWave + lane], bufi[b * kWave + lane]);
+        nb = 0;
+    };
+    float *tile_f = reinterpret_cast<float *>(tile);
     for (int64_t t0 = c0; t0 < c1; t0 += kKnnTile) {
         const int tn = (int)(c1 - t0 < kKnnTile ? c1 - t0 : kKnnTile);
         __syncthreads();
-        for (int v = threadIdx.x; v < tn * dim; v += blockDim.x) {
-            const int t = v / dim, j = v - t * dim;
-            tile[j * kKnnTile + t] = x[(t0 + t) * dim + j];
+        for (int v = threadIdx.x; v < tn * DP; v += blockDim.x) {
+            const int t = v / DP, j = v - t * DP;
+            tile_f[v] = j < dim ? x[(t0 + t) * dim + j] : 0.0f;
         }
         __syncthreads();
         for (int t = 0; t < tn; ++t) {
+            float4 y[DP / 4];
+#pragma unroll
+            for (int q = 0; q < DP / 4; ++q) y[q] = tile[t * (DP / 4) + q];
             float s = 0.0f;
 #pragma unroll
-            for (int j = 0; j < MAXD; ++j)
-                if (j < dim) {                 // plain operators: the pragma above keeps them apart
-                    const float d = xi[j] - tile[j * kKnnTile + t];
-                    const float dd = d * d;
-                    s = s + dd;
-                }
+            for (int q = 0; q < DP / 4; ++q) {   // plain operators: the pragma above keeps them apart
+                const float d0 = xi[4 * q] - y[q].x, d1 = xi[4 * q + 1] - y[q].y;
+                const float d2 = xi[4 * q + 2] - y[q].z, d3 = xi[4 * q + 3] - y[q].w;
+                s = s + d0 * d0;
+                s = s + d1 * d1;
+                s = s + d2 * d2;
+                s = s + d3 * d3;
+            }
             const int c = (int)(t0 + t);
-            if (active && c != i && isfinite(s)) knn_insert<K>(bd, bi, s, c);
+            if (active && c != i && isfinite(s) && knn_less(s, c, bd[K - 1], bi[K - 1])) {
+                bufd[nb * kWave + lane] = s;
+                bufi[nb * kWave + lane] = c;
+                ++nb;
+            }
+            if (wave_ballot(nb == kKnnBuf)) flush();
         }
     }
+    flush();
     if (!active) return;
     const int64_t o = ((int64_t)p * n + i) * K;
 #pragma unroll
@@ -1304,8 +1343,10 @@ __global__ void __launch_bounds__(64) k_knn_part(const float *__restrict__ x, in
 }
 
 // Merge the parts' lists of each query into its k nearest (same order: distance, then index).
+// A part's list is sorted, so once one of its entries does not beat the current K-th, none of
+// the rest does either.
 template <int K>
-__global__ void __launch_bounds__(256) k_knn_merge(const int32_t *__restrict__ pidx,
+__global__ void __launch_bounds__(64) k_knn_merge(const int32_t *__restrict__ pidx,
                                                    const float *__restrict__ pd2, int64_t n,
                                                    int parts, int k, int32_t *__restrict__ idx,
                                                    float *__restrict__ d2out) {
@@ -1322,8 +1363,9 @@ __global__ void __launch_bounds__(256) k_knn_merge(const int32_t *__restrict__ p
         const int64_t o = ((int64_t)p * n + i) * K;
         for (int m = 0; m < K; ++m) {
             const int c = pidx[o + m];
-            if (c == 0x7fffffff) break;        // the part's list is sorted: the rest is empty
-            knn_insert<K>(bd, bi, pd2[o + m], c);
+            const float dm = pd2[o + m];
+            if (c == 0x7fffffff || !knn_less(dm, c, bd[K - 1], bi[K - 1])) break;
+            knn_insert<K>(bd, bi, dm, c);
         }
     }
 #pragma unroll
@@ -1613,23 +1655,29 @@ hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, f
     int32_t *pidx = static_cast<int32_t *>(workspace);
     float *pd2 = reinterpret_cast<float *>(pidx + (size_t)parts * n * K);
     const dim3 grid_((unsigned)((n + kWave - 1) / kWave), (unsigned)parts), block_(kWave);
-    const size_t sh = (size_t)dim * kKnnTile * sizeof(float);
-    const dim3 mgrid((unsigned)((n + 255) / 256)), mblock(256);
+    const int dp = dim <= 4 ? 4 : dim <= 8 ? 8 : dim <= 16 ? 16 : dim <= 32 ? 32 : 64;
+    const size_t sh = (size_t)dp * kKnnTile * sizeof(float) + (size_t)kKnnBuf * kWave * 8;
+    const dim3 mgrid((unsigned)((n + kWave - 1) / kWave)), mblock(kWave);
 #define VK_KNN(KK, D)                                                                              \
     do {                                                                                           \
         hipLaunchKernelGGL((k_knn_part<KK, D>), grid_, block_, sh, s, x, n, dim, parts, pidx, pd2); \
         hipLaunchKernelGGL((k_knn_merge<KK>), mgrid, mblock, 0, s, pidx, pd2, n, parts, k, idx, d2); \
     } while (0)
-    if (dim <= 16) {
-        if (K == 4) VK_KNN(4, 16);
-        else if (K == 8) VK_KNN(8, 16);
-        else if (K == 16) VK_KNN(16, 16);
-        else VK_KNN(32, 16);
-    } else {
-        if (K <= 8) VK_KNN(8, 64);
-        else if (K == 16) VK_KNN(16, 64);
-        else VK_KNN(32, 64);
+#define VK_KNN_K(D)                                                                               \
+    do {                                                                                           \
+        if (K == 4) VK_KNN(4, D);                                                                  \
+        else if (K == 8) VK_KNN(8, D);                                                             \
+        else if (K == 16) VK_KNN(16, D);                                                           \
+        else VK_KNN(32, D);                                                                        \
+    } while (0)
+    switch (dp) {
+    case 4: VK_KNN_K(4); break;
+    case 8: VK_KNN_K(8); break;
+    case 16: VK_KNN_K(16); break;
+    case 32: VK_KNN_K(32); break;
+    default: VK_KNN_K(64); break;
     }
+#undef VK_KNN_K
 #undef VK_KNN
     return hipGetLastError();
 }
