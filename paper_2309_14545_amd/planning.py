@@ -37,22 +37,24 @@ def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
     gen.manual_seed(int(seed))
     lo = torch.as_tensor(np.asarray(q_lo, np.float32), device=dev)
     span = torch.as_tensor(np.asarray(q_hi, np.float32), device=dev) - lo
-    rounds = edges = 0
+    rounds = 0
     it = 0
 
+    rows = torch.arange(Q, device=dev)
+    edge_count = torch.zeros((), dtype=torch.int64, device=dev)
+
     def extend(t, target, active):
-        """One extension of tree t toward target[q] for the active queries."""
-        nonlocal rounds, edges
+        """One extension of tree t toward target[q] for the active queries.  Every row's edge is
+        checked in one batch (an inactive row's edge has length zero, two states) so that no
+        host synchronisation is needed to pick the active rows."""
+        nonlocal rounds
         near = tree_nearest(nodes[t], sizes[t], target, active.to(torch.uint8))
         qnew, reached = tree_steer(nodes[t], near, target, step)
-        idx = active.nonzero().squeeze(1)                # check only the active queries' edges
-        qnear = nodes[t][idx, near[idx].clamp(min=0).long()]
-        flags = torch.ones(Q, dtype=torch.uint8, device=dev)
-        if idx.numel():
-            flags[idx] = validate_edges(robot, env, qnear, qnew[idx].contiguous(),
-                                        resolution=resolution)
+        qnear = nodes[t][rows, near.clamp(min=0).long()]
+        qnew = torch.where(active[:, None], qnew, qnear).contiguous()
+        flags = validate_edges(robot, env, qnear, qnew, resolution=resolution)
         rounds += 1
-        edges += int(idx.numel())
+        edge_count.add_(active.sum())
         ok = active & (flags == 0) & (near >= 0)
         added = tree_append(nodes[t], parents[t], sizes[t], qnew, near, ok.to(torch.uint8))
         return qnew, reached.bool(), added
@@ -79,6 +81,7 @@ def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
             going = going & (addb >= 0) & ~reached
         a = b
 
+    edges = int(edge_count.item())
     # paths, on the host: root of tree 0 .. meeting node, then tree 1's meeting node .. root
     sol = solved.cpu().numpy()
     nd = nodes.cpu().numpy()
