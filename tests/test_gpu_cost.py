@@ -91,6 +91,38 @@ def test_cost_gradient(vk, orc, case):
     assert np.all(g[:, free] == 0.0)
 
 
+def test_cost_full_size_sampled(vk, orc):
+    """The full trajectory batch the benchmark times (4,096 trajectories x 64 waypoints, 262,144
+    states) in one launch each way; the oracle checks a seeded sample of 24 trajectories with
+    the tolerances above."""
+    w = workload("cost7")
+    robot, env, q = w["robot"], w["env"], w["q"]
+    n, per = q.shape[1], 64
+    gc = np.random.default_rng(6).uniform(0.5, 2.0, n).astype(np.float32)
+    r, e = vk.Robot(robot), vk.Env(env)
+    qd = dev(q)
+    c = host(vk.penetration_cost_fwd(r, e, qd)).astype(np.float64)
+    g = host(vk.penetration_cost_bwd(r, e, qd, dev(gc))).astype(np.float64)
+    say("cost full size", n)
+    trajs = np.sort(np.random.default_rng(12).choice(n // per, 24, replace=False))
+    cols = (trajs[:, None] * per + np.arange(per)[None, :]).ravel()
+    qs = np.ascontiguousarray(q[:, cols])
+    ref = orc.costs(robot, env, qs)
+    assert np.all(np.abs(c[cols] - ref) <= 1e-6 + 2e-4 * ref)
+    gref = orc.cost_grads(robot, env, qs) * gc[cols][None, :].astype(np.float64)
+    cmin, _ = orc.states(robot, env, qs)
+    checked = 0
+    for t in range(len(trajs)):
+        sl = slice(t * per, (t + 1) * per)
+        if -np.nanmin(cmin[sl]) < 1e-3:
+            continue
+        gs = g[:, cols[sl]]
+        assert np.linalg.norm(gs - gref[:, sl]) <= 1e-4 * np.linalg.norm(gref[:, sl])
+        checked += 1
+    assert checked > 0
+    assert np.all(g[:, cols[cmin > 1e-4]] == 0.0)
+
+
 def test_autograd_function(vk):
     import torch
     w = workload("cost7", n=8)
