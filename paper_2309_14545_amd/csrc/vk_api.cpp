@@ -462,7 +462,6 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
                 sp.push_back(x);
             }
             B.ent_count = (int)kv.second.size();
-            bounding_sphere(sp, B.coarse);
             blocks.push_back(B);
         }
         steps[si].blk_count = (int)blocks.size() - steps[si].blk_first;
@@ -470,6 +469,14 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
     // walk-cache slots: only the steps a later block reads keep their bounds per lane
     int n_slots = 0;
     for (StepRec &st : steps) st.slot = st.slot ? n_slots++ : -1;
+    for (StepRec &st : steps)
+        if (st.joint >= 0) st.jr = joints[st.joint];
+    for (BlockRec &B : blocks) {
+        const StepRec &A = steps[B.step_a];
+        B.slot_a = A.slot;
+        B.ra = A.coarse[3];
+        B.rqa = A.cap_rq;
+    }
 
     std::vector<float4> spheres(S + kSpl, make_float4(0, 0, 0, 0));   // kSpl padding records
     for (int s = 0; s < S; ++s)

@@ -271,7 +271,7 @@ __device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, 
             w.add(flop::kFk, flop::kJoint + (J.has_mount ? flop::kMount : 0));
         }
     }
-    const JointRec J = ld(rb.joints, S.joint);
+    const JointRec &J = S.jr;
     const JointVal v = joint_val(J, q(S.joint));
     if (sc && sc->joint_off >= 0) sc->put_val(S.joint, J, v);
     frame_joint_val(T, J, v);
@@ -531,11 +531,10 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
         float al[kSpl];
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec B = ld(rb.blocks, S.blk_first + b);
-            const StepRec SA = ld(rb.steps, B.step_a);
             float ax, ay, az;
-            sc.get(SA.slot, ax, ay, az);
+            sc.get(B.slot_a, ax, ay, az);
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
-            const float rr = SA.coarse[3] + CR;
+            const float rr = B.ra + CR;
             work.add(flop::kSelf, flop::kPair);
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
             // second gate, still without posing A: the segments c -+ h of the two links'
@@ -549,18 +548,18 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
                                             0.0f), 1.0f);
                 const float ex = fmaf(-2.0f * t, hx, rx), ey = fmaf(-2.0f * t, hy, ry),
                             ez = fmaf(-2.0f * t, hz, rz);
-                const float rc = SA.coarse[3] + S.cap_r;
+                const float rc = B.ra + S.cap_r;
                 work.add(flop::kSelf, flop::kSphereCapsule);
                 if (!wave_ballot(live && fmaf(ex, ex, fmaf(ey, ey, ez * ez)) < rc * rc)) continue;
             } else {
                 float hax, hay, haz;
-                sc.get_h(SA.slot, hax, hay, haz);
+                sc.get_h(B.slot_a, hax, hay, haz);
                 const float a = 4.0f * fmaf(hax, hax, fmaf(hay, hay, haz * haz));
                 const float ia = a > 0.0f ? __builtin_amdgcn_rcpf(a) : 0.0f;
                 const float d2 = seg_seg2(ax - hax, ay - hay, az - haz, 2.0f * hax, 2.0f * hay,
                                           2.0f * haz, a, ia, Cx - hx, Cy - hy, Cz - hz, 2.0f * hx,
                                           2.0f * hy, 2.0f * hz, S.cap_uu, S.cap_inv);
-                const float rc = SA.cap_rq + S.cap_r;
+                const float rc = B.rqa + S.cap_r;
                 work.add(flop::kSelf, flop::kCapsuleCapsule);
                 if (!wave_ballot(live && d2 < rc * rc)) continue;
             }
@@ -1055,23 +1054,22 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
         }
         for (int b = 0; b < S.blk_count; ++b) {
             const BlockRec B = ld(rb.blocks, S.blk_first + b);
-            const StepRec SA = ld(rb.steps, B.step_a);
             float ax, ay, az;
-            sc.get(SA.slot, ax, ay, az);
+            sc.get(B.slot_a, ax, ay, az);
             const float dx = ax - Cx, dy = ay - Cy, dz = az - Cz;
-            const float rr = SA.coarse[3] + CR;
+            const float rr = B.ra + CR;
             if (!wave_ballot(live && fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rr * rr)) continue;
             // the gates of the collision walk: no pair they rule out can penetrate, so the
             // cost and its gradient do not change
             if (sc.half_off >= 0) {
                 float hax, hay, haz;
-                sc.get_h(SA.slot, hax, hay, haz);
+                sc.get_h(B.slot_a, hax, hay, haz);
                 const float a = 4.0f * fmaf(hax, hax, fmaf(hay, hay, haz * haz));
                 const float ia = a > 0.0f ? __builtin_amdgcn_rcpf(a) : 0.0f;
                 const float d2 = seg_seg2(ax - hax, ay - hay, az - haz, 2.0f * hax, 2.0f * hay,
                                           2.0f * haz, a, ia, Cx - hx, Cy - hy, Cz - hz, 2.0f * hx,
                                           2.0f * hy, 2.0f * hz, S.cap_uu, S.cap_inv);
-                const float rc = SA.cap_rq + S.cap_r;
+                const float rc = B.rqa + S.cap_r;
                 if (!wave_ballot(live && d2 < rc * rc)) continue;
             }
             pose_block(rb, B, Ta, ta_link, ta_depth, sc, q);

@@ -43,7 +43,7 @@ struct JointRec {                  // 96 bytes
 // paths[restart_off...] (a tree branch), otherwise the step continues from the previous
 // step's pose (serial chain).  A link with more than kSpl spheres is split into several steps;
 // the later ones have joint = -1 and reuse the pose.
-struct StepRec {                   // 96 bytes
+struct StepRec {                   // 192 bytes
     int32_t joint;
     int32_t restart_off, restart_len;
     int32_t sph_first, sph_count;  // fine spheres of this step (<= kSpl)
@@ -60,8 +60,11 @@ struct StepRec {                   // 96 bytes
     int32_t slot;                  // walk-cache slot of this step's bounds, -1 if no later
                                    // step's self block reads them
     float pad[4];
+    // a copy of joints[joint] (when joint >= 0): the walk reads it with the step's own record
+    // instead of waiting for the step's joint index before loading it
+    JointRec jr;
 };
-static_assert(sizeof(StepRec) == 96, "StepRec layout");
+static_assert(sizeof(StepRec) == 192, "StepRec layout");
 
 // Parts of the walk cache a launch includes besides the bounding-sphere centres.
 constexpr int kCacheJoints = 1;     // two floats per joint and lane
@@ -86,8 +89,13 @@ struct BlockRec {                  // 48 bytes
     int32_t ent_first, ent_count;
     int32_t link;                  // A
     uint32_t anc_lo, anc_hi;       // bit l-1: link l (>= 1) is a proper ancestor of A
-    float coarse[4];               // bounding sphere of the block's earlier spheres, A's frame
+    // copies from the earlier step's record, so that the gates need no second dependent load:
+    // its walk-cache slot, its bounding-sphere radius and its capsule gate radius (cap_rq)
+    int32_t slot_a;
+    float ra, rqa;
+    float pad;
 };
+static_assert(sizeof(BlockRec) == 48, "BlockRec layout");
 
 // One earlier sphere t of a block and the mask of this step's spheres it is paired with.
 struct EntryRec {                  // 64 bytes (one scalar load)
