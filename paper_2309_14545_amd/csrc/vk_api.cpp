@@ -342,6 +342,7 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
     for (int j = 0; j < dof; ++j) {
         JointRec &J = joints[j];
         std::memset(&J, 0, sizeof J);
+        J.index = j;
         const float *h = d->dh + 5 * j;
         J.a = h[0];
         J.d = h[1];
@@ -490,6 +491,9 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
     const size_t o_b = b.add(blocks.data(), blocks.size() * sizeof(BlockRec));
     const size_t o_e = b.add(entries.data(), entries.size() * sizeof(EntryRec));
     const size_t o_p = b.add(paths.data(), paths.size() * sizeof(int));
+    std::vector<JointRec> path_recs(paths.size());
+    for (size_t i = 0; i < paths.size(); ++i) path_recs[i] = joints[std::min<int>(paths[i], dof - 1)];
+    const size_t o_pr = b.add(path_recs.data(), path_recs.size() * sizeof(JointRec));
     const size_t o_sp = b.add(spheres.data(), spheres.size() * sizeof(float4));
     const size_t o_ss = b.add(sphere_step.data(), sphere_step.size() * sizeof(int));
     r->device = current_device();
@@ -500,6 +504,7 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
     r->dev.blocks = reinterpret_cast<const BlockRec *>(base + o_b);
     r->dev.entries = reinterpret_cast<const EntryRec *>(base + o_e);
     r->dev.paths = reinterpret_cast<const int32_t *>(base + o_p);
+    r->dev.path_recs = reinterpret_cast<const JointRec *>(base + o_pr);
     r->dev.spheres = reinterpret_cast<const float4 *>(base + o_sp);
     r->dev.sphere_step = reinterpret_cast<const int32_t *>(base + o_ss);
     r->dev.dof = dof;

@@ -262,8 +262,8 @@ __device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, 
     if (S.restart_len >= 0) {
         frame_identity(T);
         for (int k = 0; k < S.restart_len; ++k) {
-            const int j = ld(rb.paths, S.restart_off + k);
-            const JointRec J = ld(rb.joints, j);
+            const JointRec J = ld(rb.path_recs, S.restart_off + k);
+            const int j = J.index;
             if (sc && sc->joint_off >= 0)
                 frame_joint_val(T, J, sc->get_val(j, J));
             else
@@ -295,8 +295,8 @@ __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B
         k0 = 0;
     }
     for (int k = k0; k < B.path_len; ++k) {
-        const int j = ld(rb.paths, B.path_off + k);
-        const JointRec J = ld(rb.joints, j);
+        const JointRec J = ld(rb.path_recs, B.path_off + k);
+        const int j = J.index;
         if (sc.joint_off >= 0)
             frame_joint_val(Ta, J, sc.get_val(j, J));
         else

@@ -35,7 +35,7 @@ struct JointRec {                  // 96 bytes
     int32_t parent;                // link the joint hangs off
     int32_t prismatic;             // 1: slides along z by q (offset d + q), 0: turns by q
     float m[12];                   // mount, row-major 3x4
-    float pad;
+    int32_t index;                 // the joint's own index (copies of the record carry it)
 };
 
 // One link step.  If `joint` >= 0 the step first poses link joint+1: when `restart_len` >= 0
@@ -113,6 +113,7 @@ struct RobotDev {
     const BlockRec *blocks;
     const EntryRec *entries;
     const int32_t *paths;
+    const JointRec *path_recs;     // path_recs[i] = joints[paths[i]]: one load per path joint
     const float4 *spheres;         // [S] centre (link frame), radius
     const int32_t *sphere_step;    // [S] step index of each sphere (cost backward)
     int32_t dof, n_steps, n_spheres, n_links;
