@@ -87,17 +87,21 @@ typedef struct {
 } vk_env_desc;
 
 /* Create / destroy a device-resident robot.  The library precomputes, per link, a bounding
- * sphere of the link's spheres (the mid-phase of Sec. III-D) and orders the self pairs by
- * their later link so each is tested right after that link is posed (interleaving,
- * Sec. III-D).  Errors: VK_ERR_INVALID_ARG for a bad parent, link index, sphere order, radius
+ * sphere of the link's spheres (the mid-phase of Sec. III-D) and a bounding capsule (which
+ * gates self pairs before the earlier link is posed), and orders the self pairs by their later
+ * link so each is tested right after that link is posed (interleaving, Sec. III-D).  Errors: VK_ERR_INVALID_ARG for a bad parent, link index, sphere order, radius
  * <= 0, a pair on one link or a joint type other than 0/1; VK_ERR_UNSUPPORTED for dof > 64. */
 vk_status vk_robot_create(const vk_robot_desc *desc, vk_robot *out);
 vk_status vk_robot_destroy(vk_robot robot);
 int32_t vk_robot_dof(vk_robot robot);
 int32_t vk_robot_n_spheres(vk_robot robot);
 
-/* Create / destroy a device-resident environment.  Large point-cloud-like sets of spheres get
- * a uniform grid index (broadphase) built here; queries are unchanged. */
+/* Create / destroy a device-resident environment.  The primitives get a voxel broadphase
+ * (per cell, the primitives that may come within 0.5 m, sorted by a distance bound).  A large
+ * set of small spheres (more than 1,024, those up to twice the median radius: a point cloud) goes
+ * to a uniform grid instead, with a clearance field of 2 cm cells that bounds the distance to
+ * the nearest point from below (2.2 MB of device memory for the 20,000 points of a 2.7 m x
+ * 2.2 m x 2 m scene).  Queries are unchanged: these structures only skip tests that cannot hit. */
 vk_status vk_env_create(const vk_env_desc *desc, vk_env *out);
 vk_status vk_env_destroy(vk_env env);
 
@@ -203,7 +207,9 @@ vk_status vk_tree_append(float *nodes, int32_t *parents, int32_t *sizes, int32_t
  * addition adds to flops[0..4] (five device uint64, not cleared by the call) the FP32
  * operations the launch executed, by the model's count per operation (fused multiply-add = 2;
  * revolute joint 30, mount 63, sphere placement 18, sphere-sphere and self pair 11, capsule 25,
- * box 34, cylinder 35), summed over the lanes that execute it.  flops[0] is the total;
+ * box 34, cylinder 35; self-block gates: capsule bound against capsule bound 67, sphere bound
+ * against capsule bound 28, placing a capsule half-vector 15; a point-cloud clearance lookup
+ * 7), summed over the lanes that execute it.  flops[0] is the total;
  * flops[1..4] split it into FK and sphere placement, culling (voxel lookups and link
  * bounding-sphere tests), fine environment tests and self pairs (with re-posing).  Early exits,
  * skipped tests and lanes masked off by divergent control flow add nothing. */
@@ -256,9 +262,10 @@ vk_status vk_edge_batch_destroy(vk_edge_batch batch);
 /*
  * Launch configuration of the persistent edge launches (validate_edges and batches created
  * afterwards): workgroup size (a multiple of 64 up to 1024) and workgroups per compute unit
- * (1..64).  Both 0 restores the built-in default (256, 4).  A launch whose per-wave LDS caches
- * (3 floats per link step and 2 per joint, per lane) would not fit the workgroup's LDS uses the
- * largest smaller workgroup that fits.  The project's autotuner (a Python helper next to the
+ * (1..64).  Both 0 restores the built-in default (256, 4).  A launch whose per-wave LDS cache
+ * (3 floats per lane for each link step a later self pair reads, 2 more with the capsule
+ * halves, and optionally 2 per joint) would not fit the workgroup's LDS uses the largest
+ * smaller workgroup that fits.  The project's autotuner (a Python helper next to the
  * binding) times candidates and calls this.  Invalid values: VK_ERR_INVALID_ARG.
  */
 vk_status vk_set_edge_launch(int32_t block_threads, int32_t blocks_per_cu);
