@@ -132,7 +132,9 @@ struct Blob {
     void *upload() {
         void *d = nullptr;
         hip_check(hipMalloc(&d, host.size()), "hipMalloc");
-        hip_check(hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice), "hipMemcpy");
+        const hipError_t err = hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice);
+        if (err != hipSuccess) (void)hipFree(d);
+        hip_check(err, "hipMemcpy");
         return d;
     }
 };
@@ -903,6 +905,7 @@ vk_status vk_robot_create(const vk_robot_desc *desc, vk_robot *out) {
         try {
             build_robot(desc, r);
         } catch (...) {
+            if (r->blob) (void)hipFree(r->blob);   // a failure after the upload
             delete r;
             throw;
         }
@@ -930,6 +933,7 @@ vk_status vk_env_create(const vk_env_desc *desc, vk_env *out) {
         try {
             build_env(desc, e);
         } catch (...) {
+            if (e->blob) (void)hipFree(e->blob);   // a failure after the upload (grid record)
             delete e;
             throw;
         }
