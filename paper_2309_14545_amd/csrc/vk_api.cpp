@@ -290,7 +290,7 @@ struct vk_env_s {
 
 struct vk_edge_batch_s {
     int device = 0;
-    void *blob = nullptr;              // BatchSet records and set prefix sums
+    void *blob = nullptr;              // BatchSet records and the set of every edge
     unsigned long long *queue = nullptr;  // the batch's own work-queue counter
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1193,7 +1193,6 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
         for (int i = 0; i < n_envs; ++i)
             if (!envs[i]) raise(VK_ERR_INVALID_ARG, "env handle is NULL");
         std::vector<BatchSet> recs;
-        std::vector<int64_t> prefix;
         int64_t total = 0;
         for (int k = 0; k < n_sets; ++k) {
             const vk_edge_set &s = sets[k];
@@ -1209,8 +1208,8 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             b.qa_offset = s.qa_offset;
             b.n_edges = s.n_edges;
             b.out_offset = s.out_offset;
+            b.first = total;
             recs.push_back(b);
-            prefix.push_back(total);
             total += s.n_edges;
         }
         if (total > 0 && (!qa || !qb || !collide)) raise(VK_ERR_INVALID_ARG, "NULL edge array");
@@ -1219,19 +1218,21 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
         try {
             bt->device = current_device();
             bt->total = total;
-            if (recs.empty()) {
-                recs.push_back(BatchSet{});
-                prefix.push_back(0);
-            }
+            // the set of every edge (sets in order, each covering its n_edges consecutive edges)
+            std::vector<int32_t> edge_set((size_t)std::max<int64_t>(total, 1), 0);
+            for (size_t k = 0; k < recs.size(); ++k)
+                std::fill(edge_set.begin() + recs[k].first,
+                          edge_set.begin() + recs[k].first + recs[k].n_edges, (int32_t)k);
+            if (recs.empty()) recs.push_back(BatchSet{});
             Blob bl;
             const size_t o_s = bl.add(recs.data(), recs.size() * sizeof(BatchSet));
-            const size_t o_p = bl.add(prefix.data(), prefix.size() * sizeof(int64_t));
+            const size_t o_p = bl.add(edge_set.data(), edge_set.size() * sizeof(int32_t));
             bt->blob = bl.upload();
             void *q = nullptr;
             hip_check(hipMalloc(&q, kQueueBytes), "batch queue");
             bt->queue = static_cast<unsigned long long *>(q);
             const BatchSet *d_sets = reinterpret_cast<const BatchSet *>(static_cast<char *>(bt->blob) + o_s);
-            const int64_t *d_pre = reinterpret_cast<const int64_t *>(static_cast<char *>(bt->blob) + o_p);
+            const int32_t *d_eset = reinterpret_cast<const int32_t *>(static_cast<char *>(bt->blob) + o_p);
             const DeviceInfo &di = device_info(bt->device);
             int block, bpc;
             {
@@ -1258,7 +1259,7 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (err == hipSuccess) err = launch_reset_queue(bt->queue, cs);
             if (err == hipSuccess && total > 0)
-                err = launch_validate_edge_batch(d_sets, d_pre, (int)recs.size(), total, resolution,
+                err = launch_validate_edge_batch(d_sets, d_eset, (int)recs.size(), total, resolution,
                                                  qa, qb, collide, bt->queue, grid, block,
                                                  max_slots, max_dof, cs);
             hipGraph_t g = nullptr;

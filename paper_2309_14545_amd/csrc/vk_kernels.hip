@@ -888,8 +888,9 @@ __global__ void __launch_bounds__(64)
 // Mixed-robot batch: every edge set has its own robot and environment; one persistent launch
 // pulls edges from a single queue across all sets.  The environment is read from global
 // memory with wave-uniform loads (it changes from item to item, so it is not staged in LDS).
+// edge_set[e] names edge e's set, so finding it costs one load.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_EDGE_WAVES, 8)))
-    k_validate_edge_batch(const BatchSet *__restrict__ sets, const int64_t *__restrict__ prefix,
+    k_validate_edge_batch(const BatchSet *__restrict__ sets, const int32_t *__restrict__ edge_set,
                           int n_sets, int64_t total, float res, const float *__restrict__ qa,
                           const float *__restrict__ qb, uint8_t *__restrict__ out,
                           unsigned long long *__restrict__ queue, int chunk, int cache_floats, int cf) {
@@ -900,13 +901,8 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
     int64_t first, count;
     while (pull(pl, lane, first, count))
     for (int64_t e = first; e < first + count; ++e) {
-        int lo = 0, hi = n_sets - 1;          // last set whose first edge is <= e
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (ld(prefix, mid) <= e) lo = mid; else hi = mid - 1;
-        }
-        const BatchSet S = ld(sets, lo);
-        const int64_t local = e - ld(prefix, lo);
+        const BatchSet S = ld(sets, ld(edge_set, e));
+        const int64_t local = e - S.first;
         const float *a = qa + S.qa_offset + local * S.rb.dof;
         const float *b = qb + S.qa_offset + local * S.rb.dof;
         const int n = edge_count(a, b, S.rb.dof, res);
@@ -1787,7 +1783,7 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float 
 }
 #undef VK_STAGED
 
-hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
+hipError_t launch_validate_edge_batch(const BatchSet *sets, const int32_t *edge_set, int n_sets,
                                       int64_t total, float res, const float *qa, const float *qb,
                                       uint8_t *out, unsigned long long *queue, int grid, int block,
                                       int max_slots, int max_dof, hipStream_t s) {
@@ -1807,7 +1803,7 @@ hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefi
     }
     const int floats = step_cache_floats(max_slots, max_dof, cf);
     hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block), waves * floats * sizeof(float),
-                       s, sets, prefix, n_sets, total, res, qa, qb, out, queue,
+                       s, sets, edge_set, n_sets, total, res, qa, qb, out, queue,
                        work_chunk(total, grid, block), floats, cf);
     return hipGetLastError();
 }

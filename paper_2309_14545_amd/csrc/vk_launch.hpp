@@ -50,7 +50,7 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
                            int block, hipStream_t s);
 
-hipError_t launch_validate_edge_batch(const BatchSet *sets, const int64_t *prefix, int n_sets,
+hipError_t launch_validate_edge_batch(const BatchSet *sets, const int32_t *edge_set, int n_sets,
                                       int64_t total, float res, const float *qa, const float *qb,
                                       uint8_t *out, unsigned long long *queue, int grid, int block,
                                       int max_slots, int max_dof, hipStream_t s);

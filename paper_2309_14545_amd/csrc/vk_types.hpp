@@ -189,6 +189,7 @@ struct BatchSet {
     int64_t qa_offset;             // float offset of the set's first edge in qa / qb
     int64_t n_edges;
     int64_t out_offset;
+    int64_t first;                 // index of the set's first edge in the batch
 };
 
 }  // namespace vk
