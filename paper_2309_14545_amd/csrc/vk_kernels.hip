@@ -1637,7 +1637,7 @@ int knn_parts(int64_t n) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(p, 64));
 }
 
-static int knn_list_len(int k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 16 ? 16 : 32; }
+static int knn_list_len(int k) { return k <= 4 ? 4 : k <= 8 ? 8 : k <= 12 ? 12 : k <= 16 ? 16 : 32; }
 
 size_t knn_workspace_bytes(int64_t n, int k) {
     return (size_t)knn_parts(n) * n * knn_list_len(k) * (sizeof(int32_t) + sizeof(float));
@@ -1661,6 +1661,7 @@ hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, f
     do {                                                                                           \
         if (K == 4) VK_KNN(4, D);                                                                  \
         else if (K == 8) VK_KNN(8, D);                                                             \
+        else if (K == 12) VK_KNN(12, D);                                                           \
         else if (K == 16) VK_KNN(16, D);                                                           \
         else VK_KNN(32, D);                                                                        \
     } while (0)
