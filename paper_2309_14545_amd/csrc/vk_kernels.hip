@@ -327,9 +327,9 @@ __device__ __forceinline__ void place_step(const RobotDev &rb, const StepRec &S,
 
 
 // Grid broadphase over a large set of small spheres.  A point of radius <= gmax_r can touch a
-// robot sphere (c, r) only if it lies within r + gmax_r of c, i.e. in a cell at most
-// R = ceil((r + gmax_r) / h) cells away along each axis; the cells of one row are contiguous
-// in the sorted point array, so each (z, y) row is one contiguous range.  Per lane (the cells
+// robot sphere (c, r) only if its centre lies within r + gmax_r of c, i.e. in one of the cells
+// that the box c -+ (r + gmax_r) touches; the cells of one row are contiguous in the sorted
+// point array, so each (z, y) row of that box is one contiguous range.  Per lane (the cells
 // differ between configurations); `visit(p)` returns true to stop.
 template <class F>
 __device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, float cx, float cy,
@@ -347,14 +347,22 @@ __device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, f
     const int x0 = lo(cx, g.gorg[0]), x1 = hi(cx, g.gorg[0], g.gdim[0]);
     const int y0 = lo(cy, g.gorg[1]), y1 = hi(cy, g.gorg[1], g.gdim[1]);
     const int z0 = lo(cz, g.gorg[2]), z1 = hi(cz, g.gorg[2], g.gdim[2]);
-    if (x0 > x1) return;
-    for (int z = z0; z <= z1; ++z)
-        for (int y = y0; y <= y1; ++y) {
-            const int row = (z * g.gdim[1] + y) * g.gdim[0];
-            const int b = __float_as_int(cell[row + x0]), e = __float_as_int(cell[row + x1 + 1]);
-            for (int p = b; p < e; ++p)
-                if (visit(g.pts[p])) return;
-        }
+    if (x0 > x1 || y0 > y1 || z0 > z1) return;
+    // every (z, y) row once, the row holding the centre first: a sphere that touches a point
+    // usually touches one there, and its lane then stops early
+    const int ny = y1 - y0 + 1, nrow = ny * (z1 - z0 + 1);
+    const auto at = [&](float c, float o, int a, int b) {
+        return min(max((int)fminf(fmaxf(floorf((c - o) * g.ginv), -lim), lim), a), b);
+    };
+    const int first = (at(cz, g.gorg[2], z0, z1) - z0) * ny + (at(cy, g.gorg[1], y0, y1) - y0);
+    for (int k = 0; k < nrow; ++k) {
+        const int i = k == 0 ? first : (k <= first ? k - 1 : k);
+        const int zi = i / ny, z = z0 + zi, y = y0 + i - zi * ny;
+        const int row = (z * g.gdim[1] + y) * g.gdim[0];
+        const int b = __float_as_int(cell[row + x0]), e = __float_as_int(cell[row + x1 + 1]);
+        for (int p = b; p < e; ++p)
+            if (visit(g.pts[p])) return;
+    }
 }
 
 // Lower bound of the clearance of location (x, y, z) to every point of the grid, from the
