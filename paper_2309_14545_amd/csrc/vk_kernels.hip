@@ -330,8 +330,10 @@ __device__ __forceinline__ void place_step(const RobotDev &rb, const StepRec &S,
 // robot sphere (c, r) only if its centre lies within r + gmax_r of c, i.e. in one of the cells
 // that the box c -+ (r + gmax_r) touches; the cells of one row are contiguous in the sorted
 // point array, so each (z, y) row of that box is one contiguous range.  Per lane (the cells
-// differ between configurations); `visit(p)` returns true to stop.
-template <class F>
+// differ between configurations); `visit(p)` returns true to stop.  With CENTRE_FIRST the row
+// holding the centre is scanned first (the state walks); the edge walk keeps the plain order,
+// whose fewer live registers spare it two register spills on scenes without points.
+template <bool CENTRE_FIRST, class F>
 __device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, float cx, float cy,
                                           float cz, float r, F &&visit) {
     const float *cell = ev.cell;
@@ -347,9 +349,20 @@ __device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, f
     const int x0 = lo(cx, g.gorg[0]), x1 = hi(cx, g.gorg[0], g.gdim[0]);
     const int y0 = lo(cy, g.gorg[1]), y1 = hi(cy, g.gorg[1], g.gdim[1]);
     const int z0 = lo(cz, g.gorg[2]), z1 = hi(cz, g.gorg[2], g.gdim[2]);
-    if (x0 > x1 || y0 > y1 || z0 > z1) return;
+    if (x0 > x1) return;
+    if (!CENTRE_FIRST) {
+        for (int z = z0; z <= z1; ++z)
+            for (int y = y0; y <= y1; ++y) {
+                const int row = (z * g.gdim[1] + y) * g.gdim[0];
+                const int b = __float_as_int(cell[row + x0]), e = __float_as_int(cell[row + x1 + 1]);
+                for (int p = b; p < e; ++p)
+                    if (visit(g.pts[p])) return;
+            }
+        return;
+    }
     // every (z, y) row once, the row holding the centre first: a sphere that touches a point
     // usually touches one there, and its lane then stops early
+    if (y0 > y1 || z0 > z1) return;
     const int ny = y1 - y0 + 1, nrow = ny * (z1 - z0 + 1);
     const auto at = [&](float c, float o, int a, int b) {
         return min(max((int)fminf(fmaxf(floorf((c - o) * g.ginv), -lim), lim), a), b);
@@ -378,10 +391,11 @@ __device__ __forceinline__ float point_clearance(const GridDev &g, float x, floa
     return (in ? (float)g.pfield[c] : 255.0f) * g.pq;
 }
 
+template <bool CENTRE_FIRST>
 __device__ __forceinline__ bool grid_hit(const EnvView &ev, const GridDev &g, float cx, float cy,
                                          float cz, float r) {
     bool hit = false;
-    grid_scan(ev, g, cx, cy, cz, r, [&](const float4 &p) {
+    grid_scan<CENTRE_FIRST>(ev, g, cx, cy, cz, r, [&](const float4 &p) {
         hit = hit_sphere(cx, cy, cz, r, p);
         return hit;
     });
@@ -515,7 +529,7 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
                 for (int k = 0; k < kSpl; ++k)
                     if (k < cnt && near && !col &&
                         point_clearance(G, cx[k], cy[k], cz[k]) < cr[k])
-                        col |= grid_hit(ev, G, cx[k], cy[k], cz[k], cr[k]);
+                        col |= grid_hit<!EDGE>(ev, G, cx[k], cy[k], cz[k], cr[k]);
                 if (EDGE) {
                     if (wave_ballot(col)) return true;
                 } else {
@@ -1049,7 +1063,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
 #pragma unroll
                 for (int k = 0; k < kSpl; ++k) {
                     if (k >= cnt || point_clearance(G, cx[k], cy[k], cz[k]) >= cr[k]) continue;
-                    grid_scan(ev, G, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
+                    grid_scan<false>(ev, G, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
                         VK_PEN(sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
                         return false;
                     });
