@@ -203,6 +203,39 @@ vk_status vk_tree_append(float *nodes, int32_t *parents, int32_t *sizes, int32_t
                          int64_t nq, const float *qnew, const int32_t *near, const uint8_t *ok,
                          int32_t *added, void *stream);
 
+/* Fused steps of the many-query RRT-Connect (the planner of Sec. III-E run for nq queries in
+ * lockstep), so that one extension of every query's tree is three launches: vk_rrt_extend,
+ * validate_edges on its edges, vk_rrt_commit.  Arrays as for the tree primitives above (device,
+ * caller-owned, row-major): nodes [nq][cap][dof], sizes and parents per tree, targets, qnear and
+ * qnew [nq][dof].
+ *
+ * vk_rrt_extend: for each query with active[q] != 0 (uint8 [nq], required), near[q] = the tree
+ *   node nearest to targets[q] as vk_tree_nearest finds it, and qnew[q], reached[q] as
+ *   vk_tree_steer computes them from it (bit-identical); qnear[q] = that node, so that
+ *   qnear -> qnew is the edge to check.  An inactive query, or one whose tree is empty, gets
+ *   near = -1, reached = 0 and qnear = qnew = the tree's first node (the target for an empty
+ *   tree): a zero-length edge.  step must be finite and > 0.
+ * vk_rrt_commit: after validate_edges(qnear, qnew) -> flags (uint8 [nq], 1 = collides), for each
+ *   query with going[q] != 0: adds 1 to *edges (one device uint64, not cleared) and appends
+ *   qnew[q] with parent near[q] when flags[q] == 0, near[q] is a node and the tree has room;
+ *   added[q] = the new node's index, else -1 (also for queries not going).  going (uint8 [nq])
+ *   is updated in place.  With from_added == NULL (an extension toward a sample):
+ *   going[q] = (added[q] >= 0).  Otherwise (an extension toward the node from_added[q] that the
+ *   other tree just added): a node added with reached[q] != 0 joins the trees, so solved[q] = 1,
+ *   meet_this[q] = added[q] and meet_from[q] = from_added[q] (int64 [nq] each, this tree's and
+ *   the other tree's meeting nodes); going[q] = (added[q] >= 0 && reached[q] == 0).  Entries of
+ *   queries that do not meet are left as they are.
+ * Errors: VK_ERR_INVALID_ARG for NULL arrays (meet_this, meet_from and solved may be NULL only
+ *   without from_added), cap < 1, dof outside [1, 64] or nq < 0. */
+vk_status vk_rrt_extend(const float *nodes, const int32_t *sizes, int32_t cap, int32_t dof,
+                        int64_t nq, const float *targets, const uint8_t *active, float step,
+                        float *qnear, float *qnew, int32_t *near, uint8_t *reached, void *stream);
+vk_status vk_rrt_commit(float *nodes, int32_t *parents, int32_t *sizes, int32_t cap, int32_t dof,
+                        int64_t nq, const float *qnew, const int32_t *near, const uint8_t *reached,
+                        const uint8_t *flags, uint8_t *going, int32_t *added,
+                        const int32_t *from_added, int64_t *meet_this, int64_t *meet_from,
+                        uint8_t *solved, uint64_t *edges, void *stream);
+
 /* Measurement variant of validate_edges: the same flags from the same kernel code, which in
  * addition adds to flops[0..4] (five device uint64, not cleared by the call) the FP32
  * operations the launch executed, by the model's count per operation (fused multiply-add = 2;

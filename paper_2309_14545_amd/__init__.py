@@ -25,6 +25,7 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "vk_env_create", "vk_env_destroy", "fk_spheres", "validate_states", "validate_edges",
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
            "vk_knn", "vk_knn_pairs", "vk_tree_nearest", "vk_tree_steer", "vk_tree_append",
+           "vk_rrt_extend", "vk_rrt_commit",
            "penetration_cost_fwd", "penetration_cost_bwd",
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_destroy",
            "vk_set_edge_launch", "vk_get_edge_launch", "vk_set_states_split",
@@ -88,6 +89,9 @@ def lib():
         L.vk_tree_nearest.argtypes = [vp, vp, i32, i32, i64, vp, vp, vp, vp]
         L.vk_tree_steer.argtypes = [vp, i32, i32, i64, vp, vp, fp, vp, vp, vp]
         L.vk_tree_append.argtypes = [vp, vp, vp, i32, i32, i64, vp, vp, vp, vp, vp]
+        L.vk_rrt_extend.argtypes = [vp, vp, i32, i32, i64, vp, vp, fp, vp, vp, vp, vp, vp]
+        L.vk_rrt_commit.argtypes = [vp, vp, vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                    vp, vp, vp]
         L.penetration_cost_fwd.argtypes = [vp, vp, vp, i64, i64, vp, vp]
         L.penetration_cost_bwd.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
         L.vk_edge_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), i32,
@@ -363,6 +367,32 @@ def tree_append(nodes, parents, sizes, qnew, near, ok, added=None):
                                 qnew.data_ptr(), near.data_ptr(), ok.data_ptr(), added.data_ptr(),
                                 _stream()))
     return added
+
+
+def rrt_extend(nodes, sizes, targets, active, step: float, qnear, qnew, near, reached):
+    """One fused extension of every active query's tree (nodes [Q, cap, dof], sizes [Q]) toward
+    targets [Q, dof]: fills near [Q], reached [Q] and the edge qnear -> qnew ([Q, dof] each) that
+    validate_edges checks next.  Inactive queries get a zero-length edge and near = -1."""
+    Q, cap, dof = nodes.shape
+    _check(lib().vk_rrt_extend(nodes.data_ptr(), sizes.data_ptr(), cap, dof, Q, targets.data_ptr(),
+                               active.data_ptr(), float(step), qnear.data_ptr(), qnew.data_ptr(),
+                               near.data_ptr(), reached.data_ptr(), _stream()))
+
+
+def rrt_commit(nodes, parents, sizes, qnew, near, reached, flags, going, added, edges,
+               from_added=None, meet_this=None, meet_from=None, solved=None):
+    """Bookkeeping after an extension's edges were checked (flags [Q]): appends the free ones'
+    new nodes (added [Q], -1 where none), counts the going queries' edges into edges (int64 [1])
+    and updates going [Q] in place.  With from_added (the other tree's nodes added this
+    iteration) a node added at its target joins the trees: solved, meet_this and meet_from are
+    set for those queries."""
+    Q, cap, dof = nodes.shape
+    ptr = lambda t: t.data_ptr() if t is not None else None   # noqa: E731
+    _check(lib().vk_rrt_commit(nodes.data_ptr(), parents.data_ptr(), sizes.data_ptr(), cap, dof, Q,
+                               qnew.data_ptr(), near.data_ptr(), reached.data_ptr(),
+                               flags.data_ptr(), going.data_ptr(), added.data_ptr(),
+                               ptr(from_added), ptr(meet_this), ptr(meet_from), ptr(solved),
+                               edges.data_ptr(), _stream()))
 
 
 def penetration_cost_fwd(robot: Robot, env: Env, q):

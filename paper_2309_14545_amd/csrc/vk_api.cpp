@@ -1011,6 +1011,13 @@ static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_
     }
     // a workgroup's per-wave caches must fit the LDS: smaller workgroups for large robots
     while (block > kWave && walk_lds_bytes(robot->dev, block) > di.max_lds) block -= kWave;
+    // a batch too small to give every CU a workgroup of this size (planner rounds of a few
+    // thousand edges) is spread over more CUs in smaller workgroups of at least four waves:
+    // such launches are bound by the latency of one walk, not by throughput
+    if (n_edges < (int64_t)di.n_cu * (block / kWave)) {
+        const int64_t waves = std::max<int64_t>(4, (n_edges + di.n_cu - 1) / di.n_cu);
+        block = (int)std::min<int64_t>(block, waves * kWave);
+    }
     const int64_t want = (n_edges + block / kWave - 1) / (block / kWave);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
     hip_check(launch_reset_queue(queue, s), "queue reset");
@@ -1140,6 +1147,42 @@ vk_status vk_tree_append(float *nodes, int32_t *parents, int32_t *sizes, int32_t
         hip_check(launch_tree_append(nodes, parents, sizes, cap, dof, nq, qnew, near, ok, added,
                                      (hipStream_t)stream),
                   "vk_tree_append launch");
+    });
+}
+
+vk_status vk_rrt_extend(const float *nodes, const int32_t *sizes, int32_t cap, int32_t dof,
+                        int64_t nq, const float *targets, const uint8_t *active, float step,
+                        float *qnear, float *qnew, int32_t *near, uint8_t *reached,
+                        void *stream) {
+    return guarded([&] {
+        check_trees(cap, dof, nq);
+        if (!(step > 0.0f && std::isfinite(step))) raise(VK_ERR_INVALID_ARG, "vk_rrt_extend: step must be > 0");
+        if (nq == 0) return;
+        if (!nodes || !sizes || !targets || !active || !qnear || !qnew || !near || !reached)
+            raise(VK_ERR_INVALID_ARG, "vk_rrt_extend: NULL array");
+        hip_check(launch_rrt_extend(nodes, sizes, cap, dof, nq, targets, active, step, qnear, qnew,
+                                    near, reached, (hipStream_t)stream),
+                  "vk_rrt_extend launch");
+    });
+}
+
+vk_status vk_rrt_commit(float *nodes, int32_t *parents, int32_t *sizes, int32_t cap, int32_t dof,
+                        int64_t nq, const float *qnew, const int32_t *near, const uint8_t *reached,
+                        const uint8_t *flags, uint8_t *going, int32_t *added,
+                        const int32_t *from_added, int64_t *meet_this, int64_t *meet_from,
+                        uint8_t *solved, uint64_t *edges, void *stream) {
+    return guarded([&] {
+        check_trees(cap, dof, nq);
+        if (nq == 0) return;
+        if (!nodes || !parents || !sizes || !qnew || !near || !reached || !flags || !going ||
+            !added || !edges)
+            raise(VK_ERR_INVALID_ARG, "vk_rrt_commit: NULL array");
+        if (from_added && (!meet_this || !meet_from || !solved))
+            raise(VK_ERR_INVALID_ARG, "vk_rrt_commit: from_added needs meet_this, meet_from and solved");
+        hip_check(launch_rrt_commit(nodes, parents, sizes, cap, dof, nq, qnew, near, reached, flags,
+                                    going, added, from_added, meet_this, meet_from, solved, edges,
+                                    (hipStream_t)stream),
+                  "vk_rrt_commit launch");
     });
 }
 

@@ -1400,23 +1400,12 @@ __global__ void __launch_bounds__(64) k_knn_merge(const int32_t *__restrict__ pi
 // validate_edges.
 // ---------------------------------------------------------------------------------------------
 
-// Nearest tree node to targets[q] (one wave per query; squared distance accumulated in joint
-// order with separately rounded products and sums, ties to the lower index); -1 for an empty
-// tree or an inactive query.
-__global__ void __launch_bounds__(256) k_tree_nearest(const float *__restrict__ nodes,
-                                                      const int32_t *__restrict__ sizes, int cap,
-                                                      int dof, int64_t nq,
-                                                      const float *__restrict__ targets,
-                                                      const uint8_t *__restrict__ active,
-                                                      int32_t *__restrict__ near) {
+// Index of the node of tree[0 .. size) nearest to tg, by one wave (squared distance accumulated
+// in joint order with separately rounded products and sums, ties to the lower index); -1 when
+// size is 0.  Every lane returns the result.
+__device__ int wave_nearest(const float *__restrict__ tree, int size, int dof,
+                            const float *__restrict__ tg, int lane) {
 #pragma clang fp contract(off)                 // products and sums rounded separately
-    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (qi >= nq) return;                      // whole wave past the queries
-    const bool on = !active || active[qi];
-    const int size = on ? min(sizes[qi], cap) : 0;
-    const float *tree = nodes + qi * (int64_t)cap * dof;
-    const float *tg = targets + qi * dof;
     float best = INFINITY;
     int bi = 0x7fffffff;
     for (int v = lane; v < size; v += kWave) {
@@ -1439,12 +1428,48 @@ __global__ void __launch_bounds__(256) k_tree_nearest(const float *__restrict__ 
             bi = oi;
         }
     }
-    if (lane == 0) near[qi] = bi == 0x7fffffff ? -1 : bi;
+    return bi == 0x7fffffff ? -1 : bi;
 }
 
-// Steer from node near[q] toward targets[q] by at most `step` (Euclidean): q_new = target when
-// it is that close (reached[q] = 1), else near + d * (step / |d|).  Queries with near < 0 get
-// reached = 0 and q_new = target.
+// Nearest tree node to targets[q] (one wave per query); -1 for an empty tree or an inactive
+// query.
+__global__ void __launch_bounds__(256) k_tree_nearest(const float *__restrict__ nodes,
+                                                      const int32_t *__restrict__ sizes, int cap,
+                                                      int dof, int64_t nq,
+                                                      const float *__restrict__ targets,
+                                                      const uint8_t *__restrict__ active,
+                                                      int32_t *__restrict__ near) {
+    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (qi >= nq) return;                      // whole wave past the queries
+    const bool on = !active || active[qi];
+    const int size = on ? min(sizes[qi], cap) : 0;
+    const int bi = wave_nearest(nodes + qi * (int64_t)cap * dof, size, dof, targets + qi * dof, lane);
+    if (lane == 0) near[qi] = bi;
+}
+
+// Step from node a toward target tg by at most `step` (Euclidean): the factor f with
+// q_new = a + f (tg - a), and whether tg lies within the step (then q_new = tg).  The squared
+// length is accumulated in joint order with fused multiply-adds.
+__device__ inline float steer_factor(const float *__restrict__ a, const float *__restrict__ tg,
+                                     int dof, float step, bool &close) {
+    float s = 0.0f;
+    for (int j = 0; j < dof; ++j) {
+        const float d = tg[j] - a[j];
+        s = fmaf(d, d, s);
+    }
+    const float len = sqrtf(s);
+    close = len <= step;
+    return close ? 1.0f : step / len;
+}
+
+__device__ inline float steer_joint(float a, float tg, float f, bool close) {
+    return close ? tg : fmaf(f, tg - a, a);
+}
+
+// Steer from node near[q] toward targets[q] by at most `step`: q_new = target when it is that
+// close (reached[q] = 1), else near + d * (step / |d|).  Queries with near < 0 get reached = 0
+// and q_new = target.
 __global__ void k_tree_steer(const float *__restrict__ nodes, int cap, int dof, int64_t nq,
                              const int32_t *__restrict__ near, const float *__restrict__ targets,
                              float step, float *__restrict__ qnew, uint8_t *__restrict__ reached) {
@@ -1459,15 +1484,9 @@ __global__ void k_tree_steer(const float *__restrict__ nodes, int cap, int dof, 
         return;
     }
     const float *a = nodes + (qi * (int64_t)cap + ni) * dof;
-    float s = 0.0f;
-    for (int j = 0; j < dof; ++j) {
-        const float d = tg[j] - a[j];
-        s = fmaf(d, d, s);
-    }
-    const float len = sqrtf(s);
-    const bool close = len <= step;
-    const float f = close ? 1.0f : step / len;
-    for (int j = 0; j < dof; ++j) o[j] = close ? tg[j] : fmaf(f, tg[j] - a[j], a[j]);
+    bool close;
+    const float f = steer_factor(a, tg, dof, step, close);
+    for (int j = 0; j < dof; ++j) o[j] = steer_joint(a[j], tg[j], f, close);
     reached[qi] = close ? 1 : 0;
 }
 
@@ -1490,6 +1509,97 @@ __global__ void k_tree_append(float *__restrict__ nodes, int32_t *__restrict__ p
     parents[qi * (int64_t)cap + size] = ni;
     sizes[qi] = size + 1;
     added[qi] = size;
+}
+
+// One extension of every query's tree toward its target, fused into one launch: the nearest
+// node (as k_tree_nearest), the step toward the target (as k_tree_steer) and the edge to check,
+// qnear[q] -> qnew[q].  A query that is inactive, or whose tree is empty, gets near = -1,
+// reached = 0 and a zero-length edge at its tree's root (at the target for an empty tree).
+// One wave per query; lanes write the joints.
+__global__ void __launch_bounds__(256) k_rrt_extend(const float *__restrict__ nodes,
+                                                    const int32_t *__restrict__ sizes, int cap,
+                                                    int dof, int64_t nq,
+                                                    const float *__restrict__ targets,
+                                                    const uint8_t *__restrict__ active, float step,
+                                                    float *__restrict__ qnear,
+                                                    float *__restrict__ qnew,
+                                                    int32_t *__restrict__ near,
+                                                    uint8_t *__restrict__ reached) {
+    const int64_t qi = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (qi >= nq) return;                      // whole wave past the queries
+    const float *tree = nodes + qi * (int64_t)cap * dof;
+    const float *tg = targets + qi * dof;
+    const int size = min(sizes[qi], cap);
+    const int bi = active[qi] ? wave_nearest(tree, size, dof, tg, lane) : -1;
+    float *on = qnear + qi * dof, *ow = qnew + qi * dof;
+    if (bi < 0) {
+        const float *p = size > 0 ? tree : tg;
+        for (int j = lane; j < dof; j += kWave) on[j] = ow[j] = p[j];
+        if (lane == 0) {
+            near[qi] = -1;
+            reached[qi] = 0;
+        }
+        return;
+    }
+    const float *a = tree + (int64_t)bi * dof;
+    bool close;
+    const float f = steer_factor(a, tg, dof, step, close);   // the same value in every lane
+    for (int j = lane; j < dof; j += kWave) {
+        on[j] = a[j];
+        ow[j] = steer_joint(a[j], tg[j], f, close);
+    }
+    if (lane == 0) {
+        near[qi] = bi;
+        reached[qi] = close ? 1 : 0;
+    }
+}
+
+// Bookkeeping after the edges of an extension of tree t were checked (flags[q] != 0: the edge
+// collides), fused into one launch.  For each query with going[q] != 0: count its edge, and append
+// qnew[q] (parent near[q]) when its edge is free, near[q] is a node and the tree has room;
+// added[q] = the new node's index, else -1.  Then going[q] becomes:
+//  - without from_added (the extension toward a sample): whether a node was added;
+//  - with from_added (an extension toward the other tree's new node from_added[q]): whether a
+//    node was added short of the target.  A node added at the target joins the trees: solved[q]
+//    = 1, meet_this[q] = added[q], meet_from[q] = from_added[q].
+// One thread per query.
+__global__ void k_rrt_commit(float *__restrict__ nodes, int32_t *__restrict__ parents,
+                             int32_t *__restrict__ sizes, int cap, int dof, int64_t nq,
+                             const float *__restrict__ qnew, const int32_t *__restrict__ near,
+                             const uint8_t *__restrict__ reached,
+                             const uint8_t *__restrict__ flags, uint8_t *__restrict__ going,
+                             int32_t *__restrict__ added, const int32_t *__restrict__ from_added,
+                             int64_t *__restrict__ meet_this, int64_t *__restrict__ meet_from,
+                             uint8_t *__restrict__ solved, unsigned long long *__restrict__ edges) {
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= nq) return;
+    const bool act = going[qi] != 0;
+    int ai = -1;
+    if (act) {
+        atomicAdd(edges, 1ull);
+        const int size = sizes[qi];
+        const int ni = near[qi];
+        if (!flags[qi] && ni >= 0 && ni < size && size < cap) {
+            float *dst = nodes + (qi * (int64_t)cap + size) * dof;
+            for (int j = 0; j < dof; ++j) dst[j] = qnew[qi * dof + j];
+            parents[qi * (int64_t)cap + size] = ni;
+            sizes[qi] = size + 1;
+            ai = size;
+        }
+    }
+    added[qi] = ai;
+    if (!from_added) {
+        going[qi] = ai >= 0 ? 1 : 0;
+        return;
+    }
+    const bool at = ai >= 0 && reached[qi];
+    if (at) {
+        meet_this[qi] = ai;
+        meet_from[qi] = from_added[qi];
+        solved[qi] = 1;
+    }
+    going[qi] = ai >= 0 && !reached[qi] ? 1 : 0;
 }
 
 // Undirected roadmap edges from kNN lists, one slot per (i, m): (i, j) for j = idx[i][m] when
@@ -1721,6 +1831,29 @@ hipError_t launch_tree_append(float *nodes, int32_t *parents, int32_t *sizes, in
                               const uint8_t *ok, int32_t *added, hipStream_t s) {
     hipLaunchKernelGGL(k_tree_append, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nodes,
                        parents, sizes, cap, dof, nq, qnew, near, ok, added);
+    return hipGetLastError();
+}
+
+hipError_t launch_rrt_extend(const float *nodes, const int32_t *sizes, int cap, int dof,
+                             int64_t nq, const float *targets, const uint8_t *active, float step,
+                             float *qnear, float *qnew, int32_t *near, uint8_t *reached,
+                             hipStream_t s) {
+    const int wpb = 4;
+    hipLaunchKernelGGL(k_rrt_extend, dim3((unsigned)((nq + wpb - 1) / wpb)), dim3(wpb * kWave), 0,
+                       s, nodes, sizes, cap, dof, nq, targets, active, step, qnear, qnew, near,
+                       reached);
+    return hipGetLastError();
+}
+
+hipError_t launch_rrt_commit(float *nodes, int32_t *parents, int32_t *sizes, int cap, int dof,
+                             int64_t nq, const float *qnew, const int32_t *near,
+                             const uint8_t *reached, const uint8_t *flags, uint8_t *going,
+                             int32_t *added, const int32_t *from_added, int64_t *meet_this,
+                             int64_t *meet_from, uint8_t *solved, uint64_t *edges,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_rrt_commit, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, nodes,
+                       parents, sizes, cap, dof, nq, qnew, near, reached, flags, going, added,
+                       from_added, meet_this, meet_from, solved, (unsigned long long *)edges);
     return hipGetLastError();
 }
 

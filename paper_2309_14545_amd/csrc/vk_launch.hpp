@@ -39,6 +39,16 @@ hipError_t launch_tree_steer(const float *nodes, int cap, int dof, int64_t nq, c
 hipError_t launch_tree_append(float *nodes, int32_t *parents, int32_t *sizes, int cap, int dof,
                               int64_t nq, const float *qnew, const int32_t *near,
                               const uint8_t *ok, int32_t *added, hipStream_t s);
+hipError_t launch_rrt_extend(const float *nodes, const int32_t *sizes, int cap, int dof,
+                             int64_t nq, const float *targets, const uint8_t *active, float step,
+                             float *qnear, float *qnew, int32_t *near, uint8_t *reached,
+                             hipStream_t s);
+hipError_t launch_rrt_commit(float *nodes, int32_t *parents, int32_t *sizes, int cap, int dof,
+                             int64_t nq, const float *qnew, const int32_t *near,
+                             const uint8_t *reached, const uint8_t *flags, uint8_t *going,
+                             int32_t *added, const int32_t *from_added, int64_t *meet_this,
+                             int64_t *meet_from, uint8_t *solved, uint64_t *edges,
+                             hipStream_t s);
 hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, float *cost, hipStream_t s);
 size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, int cf);

@@ -3,17 +3,17 @@
 RRT-Connect grows one tree from the start and one from the goal.  Each iteration samples a
 configuration, extends one tree toward it by at most `step`, then repeatedly extends the other
 tree toward the new node until it reaches it or an edge collides; the trees swap roles every
-iteration.  Here one iteration does this for every unsolved query at once: nearest nodes,
-steering and appends are kernels over the queries (vk_tree_*), and each extension round checks
-all of its edges with one validate_edges launch, at the same resolution as every other edge.
-The loop itself, a handful of launches per round, runs on the host; samples come from a seeded
-torch generator on the device.
+iteration.  Here one iteration does this for every unsolved query at once.  An extension round
+is three launches over all queries: rrt_extend (nearest node, step, the edge to check),
+validate_edges (every query's edge in one launch, at the same resolution as every other edge)
+and rrt_commit (appends, the meeting nodes, which queries go on), followed by one host check of
+whether any query goes on.  Samples come from a seeded torch generator on the device.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import tree_append, tree_nearest, tree_steer, validate_edges
+from . import rrt_commit, rrt_extend, validate_edges
 
 
 def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
@@ -31,59 +31,53 @@ def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
     sizes = torch.ones((2, Q), dtype=torch.int32, device=dev)
     nodes[0, :, 0] = starts
     nodes[1, :, 0] = goals
-    solved = torch.zeros(Q, dtype=torch.bool, device=dev)
+    solved = torch.zeros(Q, dtype=torch.uint8, device=dev)
     meet = torch.full((2, Q), -1, dtype=torch.int64, device=dev)    # meeting node per tree
     gen = torch.Generator(device=dev)
     gen.manual_seed(int(seed))
     lo = torch.as_tensor(np.asarray(q_lo, np.float32), device=dev)
     span = torch.as_tensor(np.asarray(q_hi, np.float32), device=dev) - lo
+    edge_count = torch.zeros(1, dtype=torch.int64, device=dev)
+    # per-round buffers, one set per role: [0] the extension toward the sample, [1] the connects
+    f32 = dict(dtype=torch.float32, device=dev)
+    qnear = torch.empty((2, Q, dof), **f32)
+    qnew = torch.empty((2, Q, dof), **f32)
+    near = torch.empty((2, Q), dtype=torch.int32, device=dev)
+    reached = torch.empty((2, Q), dtype=torch.uint8, device=dev)
+    added = torch.empty((2, Q), dtype=torch.int32, device=dev)
+    flags = torch.empty(Q, dtype=torch.uint8, device=dev)
+    going = torch.empty(Q, dtype=torch.uint8, device=dev)
     rounds = 0
     it = 0
 
-    rows = torch.arange(Q, device=dev)
-    edge_count = torch.zeros((), dtype=torch.int64, device=dev)
-
-    def extend(t, target, active):
-        """One extension of tree t toward target[q] for the active queries.  Every row's edge is
-        checked in one batch (an inactive row's edge has length zero, two states) so that no
-        host synchronisation is needed to pick the active rows."""
+    def extend(t, r, target, from_added=None, a=None):
         nonlocal rounds
-        near = tree_nearest(nodes[t], sizes[t], target, active.to(torch.uint8))
-        qnew, reached = tree_steer(nodes[t], near, target, step)
-        qnear = nodes[t][rows, near.clamp(min=0).long()]
-        qnew = torch.where(active[:, None], qnew, qnear).contiguous()
-        flags = validate_edges(robot, env, qnear, qnew, resolution=resolution)
+        rrt_extend(nodes[t], sizes[t], target, going, step, qnear[r], qnew[r], near[r], reached[r])
+        validate_edges(robot, env, qnear[r], qnew[r], resolution=resolution, out=flags)
+        rrt_commit(nodes[t], parents[t], sizes[t], qnew[r], near[r], reached[r], flags, going,
+                   added[r], edge_count, from_added=from_added,
+                   meet_this=None if from_added is None else meet[t],
+                   meet_from=None if from_added is None else meet[a], solved=solved)
         rounds += 1
-        edge_count.add_(active.sum())
-        ok = active & (flags == 0) & (near >= 0)
-        added = tree_append(nodes[t], parents[t], sizes[t], qnew, near, ok.to(torch.uint8))
-        return qnew, reached.bool(), added
 
     a = 0
     for it in range(1, max_iters + 1):
-        active = ~solved
-        if not bool(active.any()):
+        torch.eq(solved, 0, out=going)
+        if not bool(going.any()):
             it -= 1
             break
         q_rand = lo + span * torch.rand((Q, dof), generator=gen, device=dev)
-        q_new, _, added = extend(a, q_rand, active)
+        extend(a, 0, q_rand)
         b = 1 - a
-        target = q_new
-        going = added >= 0
         for _ in range(max_connect):
             if not bool(going.any()):
                 break
-            _, reached, addb = extend(b, target, going)
-            hit = going & (addb >= 0) & reached
-            meet[a] = torch.where(hit, added.long(), meet[a])
-            meet[b] = torch.where(hit, addb.long(), meet[b])
-            solved |= hit
-            going = going & (addb >= 0) & ~reached
+            extend(b, 1, qnew[0], from_added=added[0], a=a)
         a = b
 
     edges = int(edge_count.item())
     # paths, on the host: root of tree 0 .. meeting node, then tree 1's meeting node .. root
-    sol = solved.cpu().numpy()
+    sol = solved.cpu().numpy().astype(bool)
     nd = nodes.cpu().numpy()
     par = parents.cpu().numpy()
     mt = meet.cpu().numpy()
