@@ -275,7 +275,10 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
  * vk_edge_batch_run.  Set k covers edges [edge_offset, edge_offset + n_edges) of the qa/qb
  * arrays given to vk_edge_batch_create (AoS with that set's robot dof, offsets in floats) and
  * writes collide[out_offset + i].  The arrays passed at create are device pointers that must
- * stay valid for the batch's life; run replays on them.
+ * stay valid for the batch's life; run replays on them.  A batch owns one work-queue counter
+ * set, so replays of one batch must not overlap in time: replays on one stream are ordered by
+ * it, replays on different streams must be ordered by the caller (events).  Different batches
+ * are independent.
  */
 typedef struct {
     int32_t robot;          /* index into robots[] */
