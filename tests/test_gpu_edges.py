@@ -74,6 +74,24 @@ def test_schedule_invariance(vk):
     vk.set_edge_launch(0, 0)
 
 
+def test_small_batch_launch_shapes(vk):
+    """Batches too small to give every CU a workgroup of the tuned size run in smaller
+    workgroups over more CUs: the flags of every prefix batch, at sizes around those thresholds,
+    equal the full batch's."""
+    w = workload("edges7_shelf", n=8192)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = w["qa"], w["qb"]
+    for block, bpc in ((1024, 2), (256, 8)):
+        vk.set_edge_launch(block, bpc)
+        full = host(vk.validate_edges(r, e, dev(qa), dev(qb)))
+        assert 0 < full.mean() < 1
+        for E in (1, 2, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 4095, 4096, 4097):
+            say("launch", block, bpc, "edges", E)
+            got = host(vk.validate_edges(r, e, dev(qa[:E]), dev(qb[:E])))
+            np.testing.assert_array_equal(got, full[:E])
+    vk.set_edge_launch(0, 0)
+
+
 def test_explicit_state_counts(vk, orc):
     import torch
     w = workload("edges7_shelf", n=800)
