@@ -17,21 +17,25 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_BUILD_PATH = os.path.join(_HERE, "liboracle.so")
+# The planted-mistake tests point this at a mutated build of oracle.c; nothing else sets it.
+_LIB_PATH = os.environ.get("VK_ORACLE_LIB") or _BUILD_PATH
 _lib = None
 
 SPHERE, CAPSULE, CYLINDER, BOX = 0, 1, 2, 3
 BAND = 1e-4
 
 
+CFLAGS = ["-O2", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-fPIC", "-shared", "-pthread"]
+
+
 def build(force: bool = True) -> str:
     """Compile oracle.c with gcc (plain -O2: no fast-math, no vector intrinsics)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=200809L", "-fPIC",
-                               "-shared", "-pthread", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    if force or not os.path.exists(_BUILD_PATH):
+        tmp = _BUILD_PATH + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _BUILD_PATH)
+    return _BUILD_PATH
 
 
 class _Robot(C.Structure):
@@ -60,7 +64,8 @@ def _ip(a):
 def _lib_handle():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or (os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+        if _LIB_PATH == _BUILD_PATH and (not os.path.exists(_LIB_PATH) or
+                                         os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
             build()
         lib = C.CDLL(_LIB_PATH)
         R, E = C.POINTER(_Robot), C.POINTER(_Env)

@@ -60,6 +60,25 @@ def test_planar_closed_form(orc):
             np.testing.assert_allclose(T[-1, :, 3], exp, atol=1e-12)
 
 
+def test_mount_under_a_moving_parent(orc):
+    """A fixed mount sits between the parent link and the joint (T_parent M A): a planar 2R
+    chain with unit links whose second joint is mounted 0.5 along link 1's x axis and turned a
+    quarter turn about z.  Closed form: link 2's origin is 1.5 (cos q1, sin q1) plus the unit
+    vector at angle q1 + pi/2 + q2, which is also the direction of link 2's x axis."""
+    phi, m = np.pi / 2, 0.5
+    mount = [[1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0],
+             [np.cos(phi), -np.sin(phi), 0, m, np.sin(phi), np.cos(phi), 0, 0, 0, 0, 1, 0]]
+    robot = _robot_from_case({"dh": [[1, 0, 1, 0, 0], [1, 0, 1, 0, 0]], "mount": mount})
+    g = np.random.default_rng(4)
+    for _ in range(20):
+        q1, q2 = g.uniform(-3.0, 3.0, 2)
+        T, _ = orc.fk(robot, [q1, q2])
+        th = q1 + phi + q2
+        want = [1.5 * np.cos(q1) + np.cos(th), 1.5 * np.sin(q1) + np.sin(th), 0.0]
+        np.testing.assert_allclose(T[2, :, 3], want, atol=1e-12)
+        np.testing.assert_allclose(T[2, :, 0], [np.cos(th), np.sin(th), 0.0], atol=1e-12)
+
+
 def _rodrigues(axis, angle):
     k = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
     return np.eye(3) + np.sin(angle) * k + (1 - np.cos(angle)) * k @ k

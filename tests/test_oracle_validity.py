@@ -46,6 +46,25 @@ def test_one_link_hand_values(orc):
     assert abs(orc.state_min_clearance(r, _env(boxes=[box]), [np.pi / 2]) - 0.15) < 1e-12
 
 
+def test_touching_is_free(orc):
+    """A state collides only when some clearance is strictly negative.  The link origin sits at
+    exactly (1, 0, 0) for q = 0, so a 0.25 sphere there touches a 0.75 sphere about the world
+    origin with clearance exactly 0.0: free, as a state, in a batch and as a zero-length edge.
+    Moved 1e-9 closer, it collides."""
+    r = _one_link(spheres=((0.0, 0.0, 0.0, 0.25),))
+    env = _env(spheres=[[0.0, 0.0, 0.0, 0.75]])
+    assert orc.state_min_clearance(r, env, [0.0]) == 0.0
+    assert orc.state_collides(r, env, [0.0]) == 0
+    cmin, flag = orc.states(r, env, np.zeros((1, 3)))
+    assert np.all(cmin == 0.0) and not flag.any()
+    flag, _, emin = orc.edges(r, env, np.zeros((1, 1)), np.zeros((1, 1)), res=1.0 / 32.0)
+    assert flag[0] == 0 and emin[0] == 0.0
+    closer = _env(spheres=[[1e-9, 0.0, 0.0, 0.75]])
+    assert orc.state_collides(r, closer, [0.0]) == 1
+    assert orc.states(r, closer, np.zeros((1, 3)))[1].all()
+    assert orc.edges(r, closer, np.zeros((1, 1)), np.zeros((1, 1)), res=1.0 / 32.0)[0][0] == 1
+
+
 def test_self_pair_hand_value(orc):
     """Planar 3R with unit links at (0, 120, 120) deg closes an equilateral triangle: the
     origins of links 1 and 3 are 1 apart, so two 0.6 spheres there overlap by 0.2."""
