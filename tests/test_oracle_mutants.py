@@ -1,6 +1,6 @@
 """Planted mistakes in the oracle (CPU only).
 
-Each mutant below is oracle.c with one plausible slip: a sign, a dropped term, a transposed
+Each mutant below is oracle.c (or oracle/roadmap.py) with one plausible slip: a sign, a dropped term, a transposed
 operand, a wrong index, an off-by-one or a non-strict comparison.  Every mutant must make at
 least one of the oracle's pin tests fail (hand values, closed forms, brute force, invariants,
 finite differences).  A mutant that passes all of them would mean the pins do not bind that
@@ -104,6 +104,50 @@ MUTANTS = [
 ]
 
 
+# Planted mistakes in the Python half of the oracle (oracle/roadmap.py), checked against the
+# roadmap pins.
+ROADMAP = os.path.join(ROOT, "oracle", "roadmap.py")
+ROADMAP_PINS = [os.path.join(ROOT, "tests", "test_oracle_roadmap.py")]
+ROADMAP_MUTANTS = [
+    ("knn_self_is_a_neighbour", "            s[np.arange(len(qb)), qb] = np.inf",
+     "            pass"),
+    ("knn_ties_to_higher_index", "np.lexsort((np.broadcast_to(np.arange(n), s.shape), s), axis=1)",
+     "np.lexsort((np.broadcast_to(-np.arange(n), s.shape), s), axis=1)"),
+    ("knn_non_finite_kept", "            order = np.where(np.isfinite(dd), order, -1)\n",
+     ""),
+    ("dist_abs_not_squared", "s = (s + (d * d).astype(np.float32)).astype(np.float32)",
+     "s = (s + np.abs(d)).astype(np.float32)"),
+    ("pairs_both_directions", "if i < j or i not in idx[j]:", "if True:"),
+    ("pairs_mutual_dropped", "if i < j or i not in idx[j]:", "if i < j:"),
+]
+
+# Loads a mutated roadmap.py in place of oracle.roadmap, then runs the given pin tests.
+_ROADMAP_RUNNER = """
+import importlib.util, sys
+import pytest
+sys.path.insert(0, {root!r})
+import oracle
+spec = importlib.util.spec_from_file_location("oracle.roadmap", {path!r})
+mod = importlib.util.module_from_spec(spec)
+spec.loader.exec_module(mod)
+sys.modules["oracle.roadmap"] = mod
+oracle.roadmap = mod
+sys.exit(pytest.main(["-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu", *{pins!r}]))
+"""
+
+
+def _run_roadmap_mutant(tmp, name, old, new):
+    src = open(ROADMAP).read()
+    assert src.count(old) == 1, f"{name}: the text to mutate must occur once in roadmap.py"
+    path = os.path.join(tmp, f"roadmap_{name}.py")
+    with open(path, "w") as f:
+        f.write(src.replace(old, new))
+    code = _ROADMAP_RUNNER.format(root=ROOT, path=path, pins=ROADMAP_PINS)
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=600)
+    return r.returncode, (r.stdout + r.stderr)[-1500:]
+
+
 def _run_mutant(tmp, name, old, new):
     src = open(SRC).read()
     assert src.count(old) == 1, f"{name}: the text to mutate must occur once in oracle.c"
@@ -126,19 +170,23 @@ def outcomes(tmp_path_factory):
     tmp = str(tmp_path_factory.mktemp("mutants"))
     with ThreadPoolExecutor(max_workers=4) as ex:
         futs = {m[0]: ex.submit(_run_mutant, tmp, *m) for m in MUTANTS}
+        futs.update({m[0]: ex.submit(_run_roadmap_mutant, tmp, *m) for m in ROADMAP_MUTANTS})
         return {k: f.result() for k, f in futs.items()}
 
 
-def test_unmutated_oracle_passes_its_pins():
+def test_unmutated_oracle_passes_its_pins(tmp_path):
     from oracle import oracle as O
     O.build(force=False)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         "-m", "not gpu", *PINS], cwd=ROOT, capture_output=True, text=True,
                        timeout=600)
     assert r.returncode == 0, r.stdout[-1500:]
+    # the runner that swaps in a roadmap module passes with the module unchanged
+    rc, tail = _run_roadmap_mutant(str(tmp_path), "none", "import numpy as np", "import numpy as np")
+    assert rc == 0, tail
 
 
-@pytest.mark.parametrize("name", [m[0] for m in MUTANTS])
+@pytest.mark.parametrize("name", [m[0] for m in MUTANTS + ROADMAP_MUTANTS])
 def test_pins_catch_planted_mistake(outcomes, name):
     rc, tail = outcomes[name]
     assert rc == 1, f"mutant {name} was not caught (pytest exit {rc}):\n{tail}"
