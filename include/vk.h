@@ -99,8 +99,9 @@ int32_t vk_robot_n_spheres(vk_robot robot);
 /* Create / destroy a device-resident environment.  The primitives get a voxel broadphase
  * (per cell, the primitives that may come within 0.5 m, sorted by a distance bound).  A large
  * set of small spheres (more than 1,024, those up to twice the median radius: a point cloud) goes
- * to a uniform grid instead, with a clearance field of 2 cm cells that bounds the distance to
- * the nearest point from below (2.2 MB of device memory for the 20,000 points of a 2.7 m x
+ * to a uniform grid instead, with a clearance field of 2 cm cells (the clearance at each cell's
+ * centre, which less the distance to that centre bounds the clearance to the nearest point
+ * from below anywhere in the cell; 2.2 MB of device memory for the 20,000 points of a 2.7 m x
  * 2.2 m x 2 m scene).  Queries are unchanged: these structures only skip tests that cannot hit. */
 vk_status vk_env_create(const vk_env_desc *desc, vk_env *out);
 vk_status vk_env_destroy(vk_env env);
@@ -242,7 +243,7 @@ vk_status vk_rrt_commit(float *nodes, int32_t *parents, int32_t *sizes, int32_t 
  * revolute joint 30, mount 63, sphere placement 18, sphere-sphere and self pair 11, capsule 25,
  * box 34, cylinder 35; self-block gates: capsule bound against capsule bound 67, sphere bound
  * against capsule bound 28, placing a capsule half-vector 15; a point-cloud clearance lookup
- * 7), summed over the lanes that execute it.  flops[0] is the total;
+ * 23), summed over the lanes that execute it.  flops[0] is the total;
  * flops[1..4] split it into FK and sphere placement, culling (voxel lookups and link
  * bounding-sphere tests), fine environment tests and self pairs (with re-posing).  Early exits,
  * skipped tests and lanes masked off by divergent control flow add nothing. */

@@ -808,15 +808,14 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
                         const int c[3] = {x, y, z};
                         double d2 = 0.0;
                         for (int a = 0; a < 3; ++a) {
-                            const double lo = plo[a] + c[a] * cell, hi = lo + cell;
-                            const double g = std::max(0.0, std::max(lo - p[a], p[a] - hi));
+                            const double g = plo[a] + (c[a] + 0.5) * cell - p[a];
                             d2 += g * g;
                         }
                         float &v = clear[((size_t)z * pd[1] + y) * pd[0] + x];
                         v = std::min(v, (float)(std::sqrt(d2) - rp));
                     }
         }
-        // rounded down, less 10 um for the device's float cell lookup near a cell face
+        // rounded down, less 10 um for the device's FP32 distance to the cell centre
         pfield.resize(clear.size());
         for (size_t c = 0; c < clear.size(); ++c) {
             const double u = std::floor(((double)clear[c] - 1e-5) / kFieldStep);
@@ -827,6 +826,7 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
             gd.porg[a] = (float)plo[a];
         }
         gd.pinv = (float)(1.0 / cell);
+        gd.pcell = (float)cell;
         gd.pq = std::nextafter((float)kFieldStep, 0.0f);
     } else {
         e->dev.off_cell = (int)rec.size();

@@ -163,8 +163,9 @@ constexpr uint32_t kJoint = 30, kMount = 63, kPlace = 18, kSphere = 11, kCapsule
 // capsule bound against capsule bound (unpacking the earlier one and the segment distance),
 // sphere bound against capsule bound, and rotating a step's capsule half-vector to the world frame
 constexpr uint32_t kCapsuleCapsule = 67, kSphereCapsule = 28, kPlaceHalf = 15;
-// looking up a location in the point-cloud clearance field
-constexpr uint32_t kClearance = 7;
+// looking up a location in the point-cloud clearance field (cell index, the distance to the
+// cell's centre, the bound)
+constexpr uint32_t kClearance = 23;
 enum Cat { kFk = 0, kCull = 1, kFine = 2, kSelf = 3 };
 }
 struct NoWork {
@@ -378,8 +379,10 @@ __device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, f
     }
 }
 
-// Lower bound of the clearance of location (x, y, z) to every point of the grid, from the
-// clearance field (a location outside the field is at least 255 units away).
+// Lower bound of the clearance of location (x, y, z) to every point of the grid: the field's
+// value at the centre of the cell holding the location, less the distance to that centre
+// (clearance changes by at most the distance moved, so the bound holds whichever cell FP32
+// rounding picks); a location outside the field is at least 255 units away.
 __device__ __forceinline__ float point_clearance(const GridDev &g, float x, float y, float z) {
     const float lim = 1.0e6f;
     const int ix = (int)fminf(fmaxf(floorf((x - g.porg[0]) * g.pinv), -lim), lim);
@@ -387,8 +390,12 @@ __device__ __forceinline__ float point_clearance(const GridDev &g, float x, floa
     const int iz = (int)fminf(fmaxf(floorf((z - g.porg[2]) * g.pinv), -lim), lim);
     const bool in = ix >= 0 && iy >= 0 && iz >= 0 && ix < g.pdim[0] && iy < g.pdim[1] &&
                     iz < g.pdim[2];
-    const int c = in ? (iz * g.pdim[1] + iy) * g.pdim[0] + ix : 0;
-    return (in ? (float)g.pfield[c] : 255.0f) * g.pq;
+    if (!in) return 255.0f * g.pq;
+    const float dx = x - fmaf((float)ix + 0.5f, g.pcell, g.porg[0]);
+    const float dy = y - fmaf((float)iy + 0.5f, g.pcell, g.porg[1]);
+    const float dz = z - fmaf((float)iz + 0.5f, g.pcell, g.porg[2]);
+    const float v = (float)g.pfield[(iz * g.pdim[1] + iy) * g.pdim[0] + ix] * g.pq;
+    return v - sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
 }
 
 template <bool CENTRE_FIRST>

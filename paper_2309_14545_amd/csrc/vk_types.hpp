@@ -157,10 +157,11 @@ struct EnvDev {
 // memory (L2).
 struct GridDev {
     const float4 *pts;             // [n_pts] centre, radius
-    // Clearance field of the points on a finer uniform grid: per cell a lower bound, over every
-    // location in the cell, of (distance to a point's centre) - (that point's radius), in units
-    // of pq, rounded down and saturated at 255.  Locations outside the field are at least
-    // 255 pq from every point.
+    // Clearance field of the points on a finer uniform grid: per cell the clearance at the
+    // cell's centre, min over points of (distance to the point's centre) - (its radius), in
+    // units of pq, rounded down and saturated at 255.  Clearance changes by at most the
+    // distance moved, so (value - distance to the centre) bounds it from below anywhere.
+    // Locations outside the field are at least 255 pq from every point.
     const uint8_t *pfield;
     int32_t n_pts;
     int32_t gdim[3];
@@ -168,7 +169,7 @@ struct GridDev {
     float ginv;                    // 1 / cell size
     float gmax_r;                  // largest point radius
     int32_t pdim[3];
-    float porg[3], pinv, pq;
+    float porg[3], pinv, pcell, pq;
 };
 
 // One edge set of a mixed-robot batch.
