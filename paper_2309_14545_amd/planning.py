@@ -7,7 +7,9 @@ iteration.  Here one iteration does this for every unsolved query at once.  An e
 is three launches over all queries: rrt_extend (nearest node, step, the edge to check),
 validate_edges (every query's edge in one launch, at the same resolution as every other edge)
 and rrt_commit (appends, the meeting nodes, which queries go on), followed by one host check of
-whether any query goes on.  Samples come from a seeded torch generator on the device.
+whether any query goes on.  The four kinds of round (either tree, toward the sample or toward
+the other tree's new node) are captured once as HIP graphs over fixed buffers and replayed.
+Samples come from a seeded torch generator on the device.
 """
 from __future__ import annotations
 
@@ -18,11 +20,13 @@ from . import rrt_commit, rrt_extend, validate_edges
 
 def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
                 max_iters: int = 500, max_connect: int = 16, cap: int = 4096, seed: int = 0,
-                resolution: float = 1.0 / 32.0):
+                resolution: float = 1.0 / 32.0, graphs: bool = True):
     """Plan for Q queries at once.  starts, goals: [Q, dof] collision-free configurations (CUDA
     float32); q_lo, q_hi: [dof] sampling bounds.  Returns a dict with `solved` (bool [Q]),
     `paths` (a list of [n_i, dof] numpy arrays, None for unsolved queries), `iterations`,
-    `rounds` (extension rounds, one edge batch each) and `edges` (edges checked)."""
+    `rounds` (extension rounds, one edge batch each) and `edges` (edges checked).  With
+    graphs=False every round is launched directly instead of replayed from a HIP graph (the
+    same kernels on the same buffers)."""
     import torch
     dev = starts.device
     Q, dof = starts.shape
@@ -47,18 +51,40 @@ def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
     added = torch.empty((2, Q), dtype=torch.int32, device=dev)
     flags = torch.empty(Q, dtype=torch.uint8, device=dev)
     going = torch.empty(Q, dtype=torch.uint8, device=dev)
+    q_rand = torch.empty((Q, dof), **f32)
     rounds = 0
     it = 0
 
-    def extend(t, r, target, from_added=None, a=None):
-        nonlocal rounds
-        rrt_extend(nodes[t], sizes[t], target, going, step, qnear[r], qnew[r], near[r], reached[r])
+    def launch(t, r):
+        """One extension round of tree t: toward the sample (r = 0) or toward the node the other
+        tree added this iteration (r = 1)."""
+        connect = r == 1
+        rrt_extend(nodes[t], sizes[t], qnew[0] if connect else q_rand, going, step, qnear[r],
+                   qnew[r], near[r], reached[r])
         validate_edges(robot, env, qnear[r], qnew[r], resolution=resolution, out=flags)
         rrt_commit(nodes[t], parents[t], sizes[t], qnew[r], near[r], reached[r], flags, going,
-                   added[r], edge_count, from_added=from_added,
-                   meet_this=None if from_added is None else meet[t],
-                   meet_from=None if from_added is None else meet[a], solved=solved)
-        rounds += 1
+                   added[r], edge_count, from_added=added[0] if connect else None,
+                   meet_this=meet[t] if connect else None,
+                   meet_from=meet[1 - t] if connect else None, solved=solved)
+
+    run = launch
+    if graphs:
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            # the library allocates a stream's work-queue counters at its first edge launch on
+            # that stream: do it before capturing on the stream
+            root = nodes[0, :1, 0]
+            validate_edges(robot, env, root, root, resolution=resolution, out=flags[:1])
+        torch.cuda.current_stream(dev).wait_stream(side)
+        captured = {}
+        for t in (0, 1):
+            for r in (0, 1):
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=side, capture_error_mode="thread_local"):
+                    launch(t, r)
+                captured[(t, r)] = g
+        run = lambda t, r: captured[(t, r)].replay()   # noqa: E731
 
     a = 0
     for it in range(1, max_iters + 1):
@@ -66,13 +92,16 @@ def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
         if not bool(going.any()):
             it -= 1
             break
-        q_rand = lo + span * torch.rand((Q, dof), generator=gen, device=dev)
-        extend(a, 0, q_rand)
+        torch.rand((Q, dof), generator=gen, device=dev, out=q_rand)
+        q_rand.mul_(span).add_(lo)
+        run(a, 0)
+        rounds += 1
         b = 1 - a
         for _ in range(max_connect):
             if not bool(going.any()):
                 break
-            extend(b, 1, qnew[0], from_added=added[0], a=a)
+            run(b, 1)
+            rounds += 1
         a = b
 
     edges = int(edge_count.item())

@@ -259,16 +259,19 @@ def _rrt_by_primitives(vk, r, e, starts, goals, q_lo, q_hi, step=0.6, max_iters=
                 iterations=it, **count)
 
 
-def test_rrt_connect_matches_the_primitive_loop(vk, orc):
+@pytest.mark.parametrize("graphs", [True, False], ids=["graphs", "direct"])
+def test_rrt_connect_matches_the_primitive_loop(vk, orc, graphs):
     """The fused planner takes exactly the steps of the loop composed from the primitives: the
-    same solved queries, iterations, rounds, edges and paths."""
+    same solved queries, iterations, rounds, edges and paths, whether its rounds are replayed
+    from HIP graphs (with the host's checks and sampling between replays) or launched
+    directly."""
     from paper_2309_14545_amd import planning
     w = workload("edges7_shelf", n=1)
     r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
     starts, goals = _queries(orc, w, 40, "q7-same")
     lo, hi = w["robot"]["q_lo"], w["robot"]["q_hi"]
     kw = dict(max_iters=60, cap=512, seed=11)
-    res = planning.rrt_connect(r, e, dev(starts), dev(goals), lo, hi, **kw)
+    res = planning.rrt_connect(r, e, dev(starts), dev(goals), lo, hi, graphs=graphs, **kw)
     ref = _rrt_by_primitives(vk, r, e, dev(starts), dev(goals), lo, hi, **kw)
     say(f"fused rrt-connect: solved {res['solved'].sum()} of {len(starts)}, {res['iterations']} "
         f"iterations, {res['rounds']} rounds, {res['edges']} edges")
