@@ -978,7 +978,7 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
         const int split = states_split(robot->dev, n, num, den);
         void *scratch = split > 0 ? scratch_for(robot->device, s, states_scratch_bytes(n)) : nullptr;
         hip_check(launch_validate_states(robot->dev,
-                                         env_for_launch(env, walk_lds_bytes(robot->dev, 256)), q, n,
+                                         env_for_launch(env, walk_lds_bytes(robot->dev, walk_block(robot->dev, 256))), q, n,
                                          ldq, collide, split, scratch, s),
                   "validate_states launch");
     });
@@ -1192,7 +1192,8 @@ vk_status penetration_cost_fwd(vk_robot robot, vk_env env, const float *q, int64
         check_pair(robot, env);
         check_batch(n, ldq, q, cost, "penetration_cost_fwd");
         if (n == 0) return;
-        hip_check(launch_cost_fwd(robot->dev, env_for_launch(env, walk_lds_bytes(robot->dev, 256)),
+        hip_check(launch_cost_fwd(robot->dev,
+                                  env_for_launch(env, walk_lds_bytes(robot->dev, walk_block(robot->dev, 256))),
                                   q, n, ldq, cost,
                                   (hipStream_t)stream),
                   "penetration_cost_fwd launch");

@@ -1640,6 +1640,15 @@ size_t walk_lds_bytes(const RobotDev &rb, int block, int cf) {
     return (size_t)(block / kWave) * step_cache_floats(rb.n_slots, rb.dof, cf) * sizeof(float);
 }
 
+static size_t device_max_lds();
+
+int walk_block(const RobotDev &rb, int want) {
+    const size_t max_lds = device_max_lds();
+    int bs = want;
+    while (bs > kWave && walk_lds_bytes(rb, bs, 0) > max_lds) bs -= kWave;
+    return bs;
+}
+
 // Resident workgroups per CU of a kernel at a block size and dynamic LDS (memoised: the
 // runtime query is not free and launches repeat with the same shapes).
 static int resident_blocks(const void *kernel, int block, size_t lds) {
@@ -1746,7 +1755,7 @@ size_t states_scratch_bytes(int64_t n) { return 256 + (size_t)n * sizeof(int32_t
 hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
                                   int64_t ldq, uint8_t *out, int split, void *scratch,
                                   hipStream_t s) {
-    const int bs = 256;
+    const int bs = walk_block(rb, 256);
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, bs, c); };
     const size_t max_lds_ = device_max_lds();
@@ -1918,7 +1927,7 @@ hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed_in, con
 
 hipError_t launch_cost_fwd(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
                            int64_t ldq, float *cost, hipStream_t s) {
-    const int bs = 256;
+    const int bs = walk_block(rb, 256);
     const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, bs, c); };
     const size_t max_lds_ = device_max_lds();

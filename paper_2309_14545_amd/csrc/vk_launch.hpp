@@ -56,6 +56,9 @@ size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, int cf);
 // With jc the joint sine/cosine slots are included; launchers add them only when they cost no
 // resident workgroups, so callers size their checks without them.
 size_t walk_lds_bytes(const RobotDev &rb, int block, int cf = 0);
+// Workgroup size of the state and cost-forward launches: `want` threads, fewer (whole waves,
+// at least one) when the per-wave walk caches of a long robot would not fit the LDS.
+int walk_block(const RobotDev &rb, int want);
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
                            int block, hipStream_t s);

@@ -1,0 +1,125 @@
+"""GPU parity at the limits of the robot description: links with more spheres than one register
+step holds (later steps of the link reuse its pose), links with no spheres, every twist code
+with fixed mounts, and long chains up to the 64-joint maximum.  Sphere centres, state flags and
+edge flags against the FP64 oracle, to the same bars as the other parity tests: centres within
+1e-5 m, flags exact outside the 1e-4 m near-contact band.  (A 64-joint chain could carry up to
+64 times a joint's FP32 error; measured, it stays below 1e-6 m.)
+"""
+import numpy as np
+import pytest
+
+from helpers import BAND, CENTRE_TOL, dev, host, say
+from synthetic import rng, workload
+
+pytestmark = pytest.mark.gpu
+RES = 1.0 / 32.0
+
+
+@pytest.fixture(scope="module")
+def vk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_14545_amd as vk
+    vk.lib()
+    return vk
+
+
+def _robot(name, counts, a, d, r_lo, r_hi, gap, mount_every=0):
+    """Serial chain with counts[l] spheres on link l (link 0 is the base); twists cycle through
+    0, +90, -90 degrees and a general angle; every mount_every-th joint gets a fixed mount (a
+    small turn and offset).  Self pairs: every pair of spheres on links at least `gap` apart."""
+    g = rng("gpu-limits", name)
+    dof = len(counts) - 1
+    tw = [0.0, np.pi / 2, -np.pi / 2, 0.4]
+    dh = np.array([[a, d, np.cos(tw[j % 4]), np.sin(tw[j % 4]), g.uniform(-0.5, 0.5)]
+                   for j in range(dof)])
+    mount = np.tile([1.0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], (dof, 1))
+    if mount_every:
+        for j in range(0, dof, mount_every):
+            c, s = np.cos(0.3), np.sin(0.3)
+            mount[j] = [c, -s, 0, 0.01, s, c, 0, 0.0, 0, 0, 1, 0.005]
+    link, xyzr = [], []
+    for l, n in enumerate(counts):
+        for _ in range(n):
+            u = g.uniform(0.0, 1.0)
+            xyzr.append([-a * u, g.uniform(-0.01, 0.01), g.uniform(-0.01, 0.01),
+                         g.uniform(r_lo, r_hi)])
+            link.append(l)
+    link = np.asarray(link, np.int32)
+    pairs = [(i, j) for i in range(len(link)) for j in range(i + 1, len(link))
+             if abs(int(link[i]) - int(link[j])) >= gap]
+    robot = {"dof": dof, "parent_link": np.arange(dof, dtype=np.int32),
+             "mount": mount.astype(np.float32), "dh": dh.astype(np.float32),
+             "q_lo": np.full(dof, -np.pi, np.float32), "q_hi": np.full(dof, np.pi, np.float32),
+             "sphere_link": link, "sphere_xyzr": np.asarray(xyzr, np.float32),
+             "self_pairs": np.asarray(pairs, np.int32).reshape(-1, 2)}
+    return robot
+
+
+CASES = {
+    # 19 spheres on link 2 (three steps), 9 and 12 on links 4 and 5 (two steps each), none on
+    # link 3
+    "split6": dict(counts=[2, 3, 19, 0, 9, 12, 1], a=0.3, d=0.05, r_lo=0.03, r_hi=0.06, gap=2),
+    "chain32": dict(counts=[0] + [2] * 32, a=0.06, d=0.01, r_lo=0.015, r_hi=0.03, gap=3,
+                    mount_every=5),
+    "chain64": dict(counts=[0] + [1] * 64, a=0.015, d=0.004, r_lo=0.006, r_hi=0.012, gap=4,
+                    mount_every=7),
+}
+# joint ranges that leave a mix of free and colliding states (wider, and the long chains fold
+# onto themselves in every state)
+AMPLITUDE = {"split6": np.pi, "chain32": 1.6, "chain64": 1.2}
+
+
+def _states(g, name, dof, n):
+    return g.uniform(-AMPLITUDE[name], AMPLITUDE[name], (dof, n)).astype(np.float32)
+
+
+def _env():
+    return workload("edges7_shelf", n=1)["env"]
+
+
+def _mismatches(flags, cmin):
+    nan = np.isnan(cmin)
+    truth = nan | (cmin < 0.0)
+    definite = nan | (np.abs(cmin) > BAND)
+    return int((definite & (flags.astype(bool) != truth)).sum()), int((~definite).sum())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_limit_robot_centres(vk, orc, name):
+    robot = _robot(name, **CASES[name])
+    q = _states(rng("gpu-limits", name + "-q"), name, robot["dof"], 300)
+    got = host(vk.fk_spheres(vk.Robot(robot), dev(q)))           # [S, 3, N]
+    want = np.stack([orc.sphere_centres(robot, q[:, i]) for i in range(q.shape[1])], axis=2)
+    err = np.sqrt(((got.astype(np.float64) - want) ** 2).sum(axis=1)).max()
+    say(f"{name}: dof {robot['dof']}, {len(robot['sphere_link'])} spheres, "
+        f"{len(robot['self_pairs'])} pairs; centre error {err:.2e} m")
+    assert err <= CENTRE_TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("scene", ["self_only", "shelf"])
+def test_limit_robot_states(vk, orc, name, scene):
+    robot = _robot(name, **CASES[name])
+    env = {} if scene == "self_only" else _env()
+    q = _states(rng("gpu-limits", name + "-states"), name, robot["dof"], 512)
+    flags = host(vk.validate_states(vk.Robot(robot), vk.Env(env), dev(q)))
+    cmin, _ = orc.states(robot, env, q)
+    bad, near = _mismatches(flags, cmin)
+    say(f"{name} {scene}: collision rate {flags.mean():.3f}, mismatches {bad}, near {near}")
+    assert bad == 0 and 0.0 < flags.mean() < 1.0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_limit_robot_edges(vk, orc, name):
+    robot = _robot(name, **CASES[name])
+    g = rng("gpu-limits", name + "-edges")
+    amp = AMPLITUDE[name]
+    qa = g.uniform(-amp, amp, (96, robot["dof"])).astype(np.float32)
+    qb = (qa + g.uniform(-0.8, 0.8, qa.shape)).astype(np.float32)   # up to ~27 states per edge
+    env = _env()
+    flags = host(vk.validate_edges(vk.Robot(robot), vk.Env(env), dev(qa), dev(qb), resolution=RES))
+    _, _, emin = orc.edges(robot, env, qa, qb, res=RES, early=False)
+    bad, near = _mismatches(flags, emin)
+    say(f"{name} edges: collision rate {flags.mean():.3f}, mismatches {bad}, near {near}")
+    assert bad == 0 and 0.0 < flags.mean() < 1.0
