@@ -123,3 +123,58 @@ def test_limit_robot_edges(vk, orc, name):
     bad, near = _mismatches(flags, emin)
     say(f"{name} edges: collision rate {flags.mean():.3f}, mismatches {bad}, near {near}")
     assert bad == 0 and 0.0 < flags.mean() < 1.0
+
+
+def _trajectories(name, dof, n_traj=12, per=32):
+    """n_traj straight trajectories of `per` waypoints between random states in the case's
+    joint range, as SoA [dof][n_traj * per]."""
+    g = rng("gpu-limits", name + "-traj")
+    amp = AMPLITUDE[name]
+    a = g.uniform(-amp, amp, (n_traj, 1, dof))
+    b = g.uniform(-amp, amp, (n_traj, 1, dof))
+    t = np.linspace(0.0, 1.0, per)[None, :, None]
+    return np.ascontiguousarray((a + t * (b - a)).reshape(-1, dof).T.astype(np.float32)), per
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_limit_robot_cost(vk, orc, name):
+    """Cost and gradient to the bars of the cost parity tests (forward: 1e-6 + 2e-4 relative;
+    gradient: 1e-4 relative overall and per trajectory that penetrates by at least 1 mm; exact
+    zeros where the state is clearly free).  The 64-joint chain's backward pass runs one wave
+    per workgroup (its force slots and walk cache take 146 KB of LDS).
+
+    The per-trajectory bar is the larger of 1e-4 and twice the oracle's own relative change
+    when every joint moves by up to 3e-7 rad, the FP32 angle error: the 64-joint chain's
+    millimetre penetrations make its gradient that sensitive (the oracle's gradient moves by up
+    to ~9e-4 there, by at most ~6e-5 for the shorter robots)."""
+    robot = _robot(name, **CASES[name])
+    env = _env()
+    q, per = _trajectories(name, robot["dof"])
+    r, e = vk.Robot(robot), vk.Env(env)
+    c = host(vk.penetration_cost_fwd(r, e, dev(q))).astype(np.float64)
+    ref = orc.costs(robot, env, q)
+    assert np.all(np.abs(c - ref) <= 1e-6 + 2e-4 * ref)
+    gc = np.random.default_rng(5).uniform(0.5, 2.0, q.shape[1]).astype(np.float32)
+    g = host(vk.penetration_cost_bwd(r, e, dev(q), dev(gc))).astype(np.float64)
+    gref = orc.cost_grads(robot, env, q) * gc[None, :].astype(np.float64)
+    cmin, _ = orc.states(robot, env, q)
+    shaken = [orc.cost_grads(robot, env, q.astype(np.float64) +
+                             np.random.default_rng(10 + k).uniform(-3e-7, 3e-7, q.shape))
+              * gc[None, :].astype(np.float64) for k in range(3)]
+    worst, sens, checked = 0.0, 0.0, 0
+    for t in range(q.shape[1] // per):
+        sl = slice(t * per, (t + 1) * per)
+        if -np.nanmin(cmin[sl]) < 1e-3:
+            continue
+        norm = np.linalg.norm(gref[:, sl])
+        worst = max(worst, np.linalg.norm(g[:, sl] - gref[:, sl]) / norm)
+        sens = max(sens, max(np.linalg.norm(h[:, sl] - gref[:, sl]) / norm for h in shaken))
+        checked += 1
+    glob = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    bar = max(1e-4, 2.0 * sens)
+    say(f"{name} cost: active {(ref > 0).mean():.3f}, trajectories checked {checked}, "
+        f"worst rel {worst:.2e} (bar {bar:.1e}, oracle under FP32 joint noise {sens:.1e}), "
+        f"global rel {glob:.2e}")
+    assert checked > 0 and worst <= bar and glob <= 1e-4
+    free = cmin > 1e-4
+    assert np.all(c[free] == 0.0) and np.all(g[:, free] == 0.0)
