@@ -70,3 +70,45 @@ def test_empty_batch(vk):
     b = vk.EdgeBatch(robots, envs, [], z, z, out)
     b.run()
     torch.cuda.synchronize()
+
+
+def test_batch_with_limit_robots(vk, orc):
+    """A mixed batch whose robots span the description's limits (the 7-DoF arm, a robot with a
+    19-sphere link and an empty link, 32- and 64-joint chains), each against the shelf and
+    against nothing: the batch sizes its workgroups for the largest walk cache.  Flags against
+    the oracle and equal to each robot's own validate_edges call."""
+    import torch
+    from test_gpu_limits import AMPLITUDE, CASES, _env, _robot
+    from synthetic import rng
+    descs = [workload("edges7_shelf", n=1)["robot"]] + [_robot(n, **CASES[n]) for n in CASES]
+    amps = [2.9] + [AMPLITUDE[n] for n in CASES]
+    env_descs = [_env(), {}]
+    g = rng("gpu-batch", "limits")
+    w = {"sets": [], "qa": [], "qb": []}
+    for ri, (d, amp) in enumerate(zip(descs, amps)):
+        for ei in range(len(env_descs)):
+            a = g.uniform(-amp, amp, (40, d["dof"])).astype(np.float32)
+            b = (a + g.uniform(-0.8, 0.8, a.shape)).astype(np.float32)
+            w["sets"].append((ri, ei, None))
+            w["qa"].append(a)
+            w["qb"].append(b)
+    robots = [vk.Robot(d) for d in descs]
+    envs = [vk.Env(e) for e in env_descs]
+    qa, qb, sets, total = pack_edge_sets(w)
+    qa_d, qb_d = dev(qa), dev(qb)
+    out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    batch = vk.EdgeBatch(robots, envs, sets, qa_d, qb_d, out)
+    batch.run()
+    flags = host(out).copy()
+    batch.run()                                  # a second replay gives the same flags
+    np.testing.assert_array_equal(host(out), flags)
+    bad_total = 0
+    for k, (ri, ei, off, ne, oo) in enumerate(sets):
+        a, b = w["qa"][k], w["qb"][k]
+        _, cls, _ = orc.edges(descs[ri], env_descs[ei], a, b)
+        bad_total += edge_mismatches(flags[oo:oo + ne], cls)[0]
+        single = host(vk.validate_edges(robots[ri], envs[ei], dev(a), dev(b)))
+        np.testing.assert_array_equal(single, flags[oo:oo + ne])
+    say(f"limit-robot batch: {len(sets)} sets, {total} edges, collision rate {flags.mean():.3f}, "
+        f"mismatches {bad_total}")
+    assert bad_total == 0 and 0.0 < flags.mean() < 1.0
