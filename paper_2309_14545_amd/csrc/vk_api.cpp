@@ -526,7 +526,7 @@ float int_bits(int v) {
 
 constexpr int kGridMinSpheres = 1024;
 constexpr double kGridRobotR = 0.08;   // robot radius the point-grid cell size is tuned for
-constexpr double kFieldCell = 0.02;    // clearance-field cell edge (m)
+constexpr double kFieldCell = 0.015;   // clearance-field cell edge (m)
 constexpr double kFieldStep = 0.0005;  // clearance-field unit (m): it reaches 255 x 0.5 mm
 constexpr int64_t kFieldMaxCells = int64_t(1) << 23;
 constexpr double kVoxCap = 0.5;        // voxel lists cover link bounding spheres up to 0.5 m
@@ -778,7 +778,7 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
         gd.ginv = (float)(1.0 / h);
         gd.gmax_r = gmax_r;
 
-        // clearance field: 2 cm cells (coarser for a very large cloud) over the points' box
+        // clearance field: 1.5 cm cells (coarser for a very large cloud) over the points' box
         // widened by their largest radius plus the field's reach, so that a location outside it
         // is farther than the reach from every point
         const double reach = 255.0 * kFieldStep;
