@@ -1346,8 +1346,12 @@ __global__ void __launch_bounds__(64) k_knn_part(const float *__restrict__ x, in
                 s = s + d2 * d2;
                 s = s + d3 * d3;
             }
+            // the part is scanned in increasing index order and its list holds only earlier
+            // candidates, so a tie with the K-th entry never wins and `s < K-th distance` is
+            // the whole acceptance test (false too for a NaN or infinite distance); buffered
+            // candidates are inserted later with the full (distance, index) order
             const int c = (int)(t0 + t);
-            if (active && c != i && isfinite(s) && knn_less(s, c, bd[K - 1], bi[K - 1])) {
+            if (active && c != i && s < bd[K - 1]) {
                 bufd[nb * kWave + lane] = s;
                 bufi[nb * kWave + lane] = c;
                 ++nb;
