@@ -1293,8 +1293,9 @@ constexpr int kKnnBuf = VK_KNN_BUF;            // buffered candidates per lane
 // DP: the dimension padded to a multiple of 4.  The query and the tile hold zeros past dim, and
 // adding a zero term leaves a sum unchanged, so the padded sum equals the sum over dim terms
 // in the same order; each candidate is read as DP / 4 16-byte LDS loads, with no branch per
-// dimension.
-template <int K, int DP>
+// dimension.  DX (<= DP): the terms actually summed, the exact dimension where a launch knows
+// it at compile time (7), else DP.
+template <int K, int DP, int DX = DP>
 __global__ void __launch_bounds__(64) k_knn_part(const float *__restrict__ x, int64_t n, int dim,
                                                  int parts, int32_t *__restrict__ pidx,
                                                  float *__restrict__ pd2) {
@@ -1336,15 +1337,12 @@ __global__ void __launch_bounds__(64) k_knn_part(const float *__restrict__ x, in
             float4 y[DP / 4];
 #pragma unroll
             for (int q = 0; q < DP / 4; ++q) y[q] = tile[t * (DP / 4) + q];
+            const float *yf = reinterpret_cast<const float *>(y);
             float s = 0.0f;
 #pragma unroll
-            for (int q = 0; q < DP / 4; ++q) {   // plain operators: the pragma above keeps them apart
-                const float d0 = xi[4 * q] - y[q].x, d1 = xi[4 * q + 1] - y[q].y;
-                const float d2 = xi[4 * q + 2] - y[q].z, d3 = xi[4 * q + 3] - y[q].w;
-                s = s + d0 * d0;
-                s = s + d1 * d1;
-                s = s + d2 * d2;
-                s = s + d3 * d3;
+            for (int j = 0; j < DX; ++j) {       // plain operators: the pragma above keeps them apart
+                const float d = xi[j] - yf[j];
+                s = s + d * d;
             }
             // the part is scanned in increasing index order and its list holds only earlier
             // candidates, so a tie with the K-th entry never wins and `s < K-th distance` is
@@ -1806,7 +1804,12 @@ hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, f
     const dim3 mgrid((unsigned)((n + kWave - 1) / kWave)), mblock(kWave);
 #define VK_KNN(KK, D)                                                                              \
     do {                                                                                           \
-        hipLaunchKernelGGL((k_knn_part<KK, D>), grid_, block_, sh, s, x, n, dim, parts, pidx, pd2); \
+        if (D == 8 && dim == 7)                                                                    \
+            hipLaunchKernelGGL((k_knn_part<KK, D, (D == 8 ? 7 : D)>), grid_, block_, sh, s, x, n,    \
+                               dim, parts, pidx, pd2);                                             \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_knn_part<KK, D>), grid_, block_, sh, s, x, n, dim, parts, pidx,   \
+                               pd2);                                                               \
         hipLaunchKernelGGL((k_knn_merge<KK>), mgrid, mblock, 0, s, pidx, pd2, n, parts, k, idx, d2); \
     } while (0)
 #define VK_KNN_K(D)                                                                               \
