@@ -1384,13 +1384,35 @@ __global__ void __launch_bounds__(64) k_knn_merge(const int32_t *__restrict__ pi
         bd[m] = INFINITY;
         bi[m] = 0x7fffffff;
     }
-    for (int p = 0; p < parts; ++p) {
+    // each part's list is read whole (K / 4 16-byte loads of indices and of distances; K is a
+    // multiple of 4 and every list starts on a 16-byte boundary), the next part's while this
+    // one merges, instead of one dependent load per entry
+    static_assert(K % 4 == 0, "list lengths are multiples of 4");
+    int4 ci[K / 4], cn[K / 4];
+    float4 di[K / 4], dn[K / 4];
+    const auto load = [&](int p, int4 (&c)[K / 4], float4 (&d)[K / 4]) {
         const int64_t o = ((int64_t)p * n + i) * K;
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) {
+            c[q] = reinterpret_cast<const int4 *>(pidx + o)[q];
+            d[q] = reinterpret_cast<const float4 *>(pd2 + o)[q];
+        }
+    };
+    load(0, ci, di);
+    for (int p = 0; p < parts; ++p) {
+        if (p + 1 < parts) load(p + 1, cn, dn);
+        const int *cc = reinterpret_cast<const int *>(ci);
+        const float *dd = reinterpret_cast<const float *>(di);
+        bool go = true;
+#pragma unroll
         for (int m = 0; m < K; ++m) {
-            const int c = pidx[o + m];
-            const float dm = pd2[o + m];
-            if (c == 0x7fffffff || !knn_less(dm, c, bd[K - 1], bi[K - 1])) break;
-            knn_insert<K>(bd, bi, dm, c);
+            go = go && cc[m] != 0x7fffffff && knn_less(dd[m], cc[m], bd[K - 1], bi[K - 1]);
+            if (go) knn_insert<K>(bd, bi, dd[m], cc[m]);
+        }
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) {
+            ci[q] = cn[q];
+            di[q] = dn[q];
         }
     }
 #pragma unroll
