@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--workload", default="edges7_shelf", choices=["edges7_shelf", "edges8_shelf"])
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the other workloads (8-DoF edges, states, point cloud, cost, mixed)")
+    ap.add_argument("--extras", default="", metavar="NAME,...",
+                    help="run only these of the other workloads (for profiling one of them)")
     ap.add_argument("--launch", default="", metavar="BLOCK,PER_CU",
                     help="fixed persistent launch shape instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -426,6 +428,8 @@ def main():
                         ("shortcut7_shelf", lambda: extra_shortcut(vk, 10)),
                         ("rrt7_shelf", lambda: extra_rrt(vk)),
                         ("mixed", lambda: extra_mixed(vk, 3, 20))):
+            if args.extras and key not in args.extras.split(","):
+                continue
             t0 = time.perf_counter()
             extra[key] = fn()
             log(f"extra {key}: {extra[key]} ({time.perf_counter() - t0:.1f}s)")
