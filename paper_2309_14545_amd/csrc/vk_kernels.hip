@@ -695,8 +695,10 @@ __global__ void __launch_bounds__(256)
 // and appends the states still free to a survivor list (one atomic per wave); pass 2 walks the
 // survivors packed densely into waves, posing the first `split` steps again and testing the
 // rest.  Flags are those of the single pass.
+// four waves per SIMD: without the bound the compiler takes 131 VGPRs, three waves; at 128 it
+// spills one or two and the point-cloud batch runs 2.5 % faster
 template <int STAGE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
     k_validate_states_screen(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                              const float *__restrict__ q, int64_t n, int64_t ldq,
                              uint8_t *__restrict__ out, int cf, int split,
