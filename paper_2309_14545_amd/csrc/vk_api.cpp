@@ -1210,8 +1210,10 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
         if (ldg < n) raise(VK_ERR_SHAPE, "penetration_cost_bwd: ldg < n");
         if (n == 0) return;
         const DeviceInfo &di = device_info(robot->device);
-        int block = 256;
-        while (block > 64 && cost_bwd_slot_bytes(robot->dev, block, 0) > di.max_lds) block /= 2;
+        // three waves per workgroup: the per-link force slots make the LDS the limit, and
+        // three 3-wave workgroups of the 7-DoF robot fit a CU where only two 4-wave ones do
+        int block = 192;
+        while (block > 64 && cost_bwd_slot_bytes(robot->dev, block, 0) > di.max_lds) block -= 64;
         const size_t slots = cost_bwd_slot_bytes(robot->dev, block, 0);
         if (slots > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the backward kernel");
         hip_check(launch_cost_bwd(robot->dev, env_for_launch(env, slots), q, n, ldq, grad_cost,
