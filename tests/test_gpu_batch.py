@@ -112,3 +112,41 @@ def test_batch_with_limit_robots(vk, orc):
     say(f"limit-robot batch: {len(sets)} sets, {total} edges, collision rate {flags.mean():.3f}, "
         f"mismatches {bad_total}")
     assert bad_total == 0 and 0.0 < flags.mean() < 1.0
+
+
+def test_batch_full_size_sampled(vk, orc):
+    """The full mixed batch the benchmark times (1,024 sets over the 7-, 8- and 14-DoF robots,
+    about 93 k edges), in the launch shape the autotuner picks for it, replayed twice; the oracle
+    checks a seeded sample of 400 edges across the sets."""
+    import torch
+    from paper_2309_14545_amd import autotune
+    w = workload("mixed")
+    robots = [vk.Robot(r) for r in w["robots"]]
+    envs = [vk.Env(e) for e in w["envs"]]
+    qa_h, qb_h, sets, total = pack_edge_sets(w)
+    qa, qb = dev(qa_h), dev(qb_h)
+    out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
+    batch, tuned = autotune.tune_batch(lambda: vk.EdgeBatch(robots, envs, sets, qa, qb, out))
+    say(f"mixed batch full size: {len(sets)} sets, {total} edges, launch {tuned}")
+    out.fill_(7)
+    batch.run()
+    flags = host(out).copy()
+    batch.run()
+    np.testing.assert_array_equal(host(out), flags)
+    vk.set_edge_launch(0, 0)
+    assert set(np.unique(flags)) <= {0, 1}
+    g = np.random.default_rng(17)
+    owner = np.concatenate([np.full(ne, k) for k, (_, _, _, ne, _) in enumerate(sets)])
+    pick = np.sort(g.choice(total, 400, replace=False))
+    bad_total = 0
+    for k in np.unique(owner[pick]):
+        ri, ei, off, ne, oo = sets[k]
+        dof = w["robots"][ri]["dof"]
+        rows = pick[owner[pick] == k] - oo
+        a = qa_h[off:off + ne * dof].reshape(ne, dof)[rows]
+        b = qb_h[off:off + ne * dof].reshape(ne, dof)[rows]
+        _, cls, _ = orc.edges(w["robots"][ri], w["envs"][ei], a, b)
+        bad_total += edge_mismatches(flags[oo + rows], cls)[0]
+    say(f"  sampled 400 edges from {len(np.unique(owner[pick]))} sets: mismatches {bad_total}, "
+        f"collision rate {flags.mean():.3f}")
+    assert bad_total == 0

@@ -47,10 +47,11 @@ def test_self_only_edges_parity(vk, orc, name):
     assert bad == 0 and flags.any()
 
 
-def test_edges_full_size_sampled(vk, orc):
-    """The full 65,536-edge 7-DoF shelf batch in the default launch; the oracle checks a seeded
-    sample of 600 edges."""
-    w = workload("edges7_shelf")
+@pytest.mark.parametrize("name", ["edges7_shelf", "edges8_shelf"])
+def test_edges_full_size_sampled(vk, orc, name):
+    """The full 65,536-edge shelf batches (7-DoF, the benchmark's; 8-DoF, 60 spheres and 400
+    pairs) in the default launch; the oracle checks a seeded sample of 600 edges."""
+    w = workload(name)
     E = len(w["qa"])
     say("validate_edges full size", E)
     flags = host(vk.validate_edges(vk.Robot(w["robot"]), vk.Env(w["env"]), dev(w["qa"]),
