@@ -8,15 +8,78 @@ validates those connections as motions (the PRM of Sec. III-E, measured in Sec. 
 the planner itself is outside this repository).  Nearest neighbours use the Euclidean norm of
 the configuration difference (Sec. III-E).
 
-Precision reading: a neighbour list is an integer decision taken on floating-point distances,
-so the reference takes it in the same FP32 arithmetic the GPU kernel uses, written out
-step by step: d_j = x_j - y_j rounded to FP32, then s = s + d_j * d_j accumulated in joint
-order with the product and the sum each rounded to FP32 (no fused multiply-add).  Ties in
-distance go to the lower sample index.  Independent FP64 checks live in the tests.
+Two references live here.
+
+* `knn_exact` is the definition: squared Euclidean distances of the FP32 samples evaluated in
+  FP64 (exact up to FP64 rounding, about 1e-15 relative), neighbours in ascending distance with
+  equal distances going to the lower sample index.  A sample with a non-finite coordinate is
+  nobody's neighbour.  This is the parity reference of the GPU lists.
+* `knn` takes the same decision in FP32 arithmetic written out step by step: d_j = x_j - y_j
+  rounded to FP32, then s = s + d_j * d_j accumulated in joint order with the product and the
+  sum each rounded to FP32 (no fused multiply-add).  It is a second, determinism reference: it
+  says which of two candidates whose exact distances lie within FP32 rounding of each other a
+  fixed-order FP32 evaluation picks.
+
+`fp32_rel_bound(dim)` bounds how far any FP32 evaluation of the squared distance in that order
+can be from the exact value, relative to it: each difference and each square is one rounding,
+and the dim - 1 additions of positive terms add at most one rounding each, so the relative
+error is at most (1 + u)^(dim + 2) - 1 with u = 2^-24.  Two candidates whose exact squared
+distances a < b satisfy b - a > bound * (a + b) are ordered the same way by every such
+evaluation; closer pairs are "near ties".
 """
 from __future__ import annotations
 
 import numpy as np
+
+U32 = 2.0 ** -24
+
+
+def fp32_rel_bound(dim: int) -> float:
+    """Relative error bound of an FP32 squared distance over `dim` coordinates (see above)."""
+    return (1.0 + U32) ** (dim + 2) - 1.0
+
+
+def dist2_exact(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Squared Euclidean distances between rows of x [n][d] and rows of y [m][d], in FP64."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    s = np.zeros((x.shape[0], y.shape[0]), np.float64)
+    for j in range(x.shape[1]):
+        d = x[:, j][:, None] - y[:, j][None, :]
+        s += d * d
+    return s
+
+
+def knn_exact(x: np.ndarray, k: int, rows=None):
+    """The k nearest other samples of each row of x [n][d] (FP32 values, distances in FP64).
+
+    Returns idx [r][k] (int32, -1 where a row has fewer than k neighbours), d2 [r][k] (FP64
+    squared distances, +inf for missing entries) and d2_next [r] (the (k+1)-th smallest squared
+    distance, +inf if there is none), for r = n rows or the rows listed in `rows`.  Order:
+    ascending distance, equal distances to the lower index."""
+    x = np.asarray(x, np.float32)
+    n = x.shape[0]
+    if k < 1:
+        raise ValueError("need k >= 1")
+    q = np.arange(n) if rows is None else np.asarray(rows)
+    finite = np.all(np.isfinite(x), axis=1)
+    idx = np.full((len(q), k), -1, np.int32)
+    d2 = np.full((len(q), k), np.inf, np.float64)
+    d2_next = np.full(len(q), np.inf, np.float64)
+    for r, i in enumerate(q):
+        if not finite[i]:
+            continue
+        s = dist2_exact(x[i:i + 1], x)[0]
+        s[~finite] = np.inf
+        s[i] = np.inf                               # a sample is not its own neighbour
+        order = np.lexsort((np.arange(n), s))       # by distance, then by index
+        take = [int(j) for j in order[:k + 1] if np.isfinite(s[j])]
+        for m, j in enumerate(take[:k]):
+            idx[r, m] = j
+            d2[r, m] = s[j]
+        if len(take) > k:
+            d2_next[r] = s[take[k]]
+    return idx, d2, d2_next
 
 
 def dist2_f32(x: np.ndarray, y: np.ndarray) -> np.ndarray:

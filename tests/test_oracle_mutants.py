@@ -119,6 +119,16 @@ ROADMAP_MUTANTS = [
      "s = (s + np.abs(d)).astype(np.float32)"),
     ("pairs_both_directions", "if i < j or i not in idx[j]:", "if True:"),
     ("pairs_mutual_dropped", "if i < j or i not in idx[j]:", "if i < j:"),
+    # the FP64 definition
+    ("exact_self_is_a_neighbour", "        s[i] = np.inf                               # a sample",
+     "        pass                                        # a sample"),
+    ("exact_ties_to_higher_index", "order = np.lexsort((np.arange(n), s))",
+     "order = np.lexsort((-np.arange(n), s))"),
+    ("exact_last_coordinate_dropped", "    for j in range(x.shape[1]):\n        d = x[:, j][:, None] - y[:, j][None, :]\n        s += d * d",
+     "    for j in range(x.shape[1] - 1):\n        d = x[:, j][:, None] - y[:, j][None, :]\n        s += d * d"),
+    ("exact_abs_not_squared", "        s += d * d\n", "        s += np.abs(d)\n"),
+    ("exact_next_off_by_one", "            d2_next[r] = s[take[k]]", "            d2_next[r] = s[take[k - 1]]"),
+    ("bound_too_tight", "return (1.0 + U32) ** (dim + 2) - 1.0", "return (1.0 + U32) ** dim - 1.0"),
 ]
 
 # Loads a mutated roadmap.py in place of oracle.roadmap, then runs the given pin tests.
