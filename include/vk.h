@@ -76,7 +76,9 @@ typedef struct {
 } vk_robot_desc;
 
 /* Environment of primitives (Sec. III-C: spheres, cylinders, cuboids; capsules = swept
- * spheres).  Counts may be zero (the matching pointer may then be NULL). */
+ * spheres).  Counts may be zero (the matching pointer may then be NULL).  A cylinder axis must
+ * have unit length and a box rotation must be orthonormal, each within 1e-5 (else
+ * VK_ERR_INVALID_ARG). */
 typedef struct {
     int32_t n_spheres;   const float *spheres;    /* [n][4]  centre, radius                     */
     int32_t n_capsules;  const float *capsules;   /* [n][7]  end p0, end p1, radius             */
@@ -138,10 +140,18 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
  *   n_states  [n_edges] int32, device, each >= 2; or NULL
  *   resolution > 0 (radians per step, per joint); ignored when n_states is given
  *   collide   [n_edges] uint8, device
+ * An edge of more than 2^24 states (an explicit count, or a computed one, which saturates at
+ * 2^31 - 1 for endpoints very far apart) is not validated: its flag is 1.
  */
 vk_status validate_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
                          const int32_t *n_states, int64_t n_edges, float resolution,
                          uint8_t *collide, void *stream);
+
+/* The state count validate_edges gives the edge qa -> qb (host arrays [dof]) at `resolution`:
+ * max(2, ceil(max_j |qb_j - qa_j| / resolution) + 1) in double precision, saturated at
+ * 2^31 - 1.  Returns -1 for NULL arrays, dof outside [1, 64], a non-finite endpoint (such an
+ * edge is reported as colliding) or a resolution that is not finite and > 0. */
+int64_t vk_edge_states(const float *qa, const float *qb, int32_t dof, float resolution);
 
 /* Same contract as validate_edges, but one kernel launch per edge (the plain baseline the
  * batched launch is measured against). */

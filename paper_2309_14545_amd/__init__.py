@@ -22,7 +22,7 @@ _STATUS = {-1: "VK_ERR_INVALID_ARG", -2: "VK_ERR_SHAPE", -3: "VK_ERR_UNSUPPORTED
            -4: "VK_ERR_HIP", -5: "VK_ERR_OOM"}
 
 EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_spheres",
-           "vk_env_create", "vk_env_destroy", "fk_spheres", "validate_states", "validate_edges",
+           "vk_env_create", "vk_env_destroy", "vk_edge_states", "fk_spheres", "validate_states", "validate_edges",
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
            "vk_knn", "vk_knn_pairs", "vk_tree_nearest", "vk_tree_steer", "vk_tree_append",
            "vk_rrt_extend", "vk_rrt_commit",
@@ -78,6 +78,8 @@ def lib():
         L.vk_robot_n_spheres.restype = i32
         L.vk_env_create.argtypes = [C.POINTER(_EnvDesc), C.POINTER(vp)]
         L.vk_env_destroy.argtypes = [vp]
+        L.vk_edge_states.argtypes = [C.POINTER(fp), C.POINTER(fp), i32, fp]
+        L.vk_edge_states.restype = i64
         L.fk_spheres.argtypes = [vp, vp, i64, i64, vp, i64, vp]
         L.validate_states.argtypes = [vp, vp, vp, i64, i64, vp, vp]
         L.validate_edges.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp]
@@ -105,7 +107,7 @@ def lib():
         L.vk_get_edge_launch.argtypes = [C.POINTER(i32), C.POINTER(i32)]
         L.vk_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("vk_robot_dof", "vk_robot_n_spheres", "vk_last_error"):
+            if name not in ("vk_robot_dof", "vk_robot_n_spheres", "vk_last_error", "vk_edge_states"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -182,6 +184,14 @@ class Env:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.vk_env_destroy(self.handle)
             self.handle = None
+
+
+def edge_states(qa, qb, resolution: float = 1.0 / 32.0) -> int:
+    """States validate_edges gives the edge qa -> qb (host arrays [dof]); -1 for invalid input."""
+    a, b = _f32(qa, (-1,)), _f32(qb, (-1,))
+    if a.shape != b.shape:
+        raise ValueError("qa and qb must have the same length")
+    return int(lib().vk_edge_states(_fp(a), _fp(b), len(a), float(resolution)))
 
 
 # --- device tensors ---------------------------------------------------------------------------

@@ -529,6 +529,7 @@ constexpr double kGridRobotR = 0.08;   // robot radius the point-grid cell size 
 constexpr double kFieldCell = 0.015;   // clearance-field cell edge (m)
 constexpr double kFieldStep = 0.0005;  // clearance-field unit (m): it reaches 255 x 0.5 mm
 constexpr int64_t kFieldMaxCells = int64_t(1) << 23;
+constexpr double kUnitTol = 1e-5;      // unit axes and orthonormal rotations, within this
 constexpr double kVoxCap = 0.5;        // voxel lists cover link bounding spheres up to 0.5 m
 constexpr double kVoxMinCell = 0.05;
 constexpr double kVoxMaxCells = 49152; // byte field of at most 48 KiB (fits LDS with records)
@@ -589,6 +590,23 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
         raise(VK_ERR_INVALID_ARG, "primitive values must be finite");
     for (int i = 0; i < ns; ++i)
         if (d->spheres[4 * i + 3] < 0.0f) raise(VK_ERR_INVALID_ARG, "negative sphere radius");
+    // the voxel bounds and the link-sphere gate need a 1-Lipschitz signed distance: a unit
+    // cylinder axis and an orthonormal box rotation (within FP32 rounding of the input)
+    for (int i = 0; i < ny; ++i) {
+        const float *w = d->cylinders + 8 * i + 3;
+        const double len = std::sqrt((double)w[0] * w[0] + (double)w[1] * w[1] + (double)w[2] * w[2]);
+        if (std::fabs(len - 1.0) > kUnitTol) raise(VK_ERR_INVALID_ARG, "cylinder axis is not a unit vector");
+    }
+    for (int i = 0; i < nb; ++i) {
+        const float *R = d->boxes + 15 * i + 3;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double g = 0.0;               // (R^T R)[a][b]: columns a and b of R
+                for (int k = 0; k < 3; ++k) g += (double)R[3 * k + a] * R[3 * k + b];
+                if (std::fabs(g - (a == b ? 1.0 : 0.0)) > kUnitTol)
+                    raise(VK_ERR_INVALID_ARG, "box rotation is not orthonormal");
+            }
+    }
 
     // Large sets of small spheres (point clouds) go to a uniform grid: when there are more than
     // kGridMinSpheres spheres, those with a radius at most twice the median radius.
@@ -920,6 +938,18 @@ vk_status vk_robot_destroy(vk_robot robot) {
         delete robot;
         hip_check(err, "hipFree");
     });
+}
+
+int64_t vk_edge_states(const float *qa, const float *qb, int32_t dof, float resolution) {
+    if (!qa || !qb || dof < 1 || dof > kMaxDof || !(resolution > 0.0f && std::isfinite(resolution)))
+        return -1;
+    double L = 0.0;
+    for (int j = 0; j < dof; ++j) {
+        if (!std::isfinite(qa[j]) || !std::isfinite(qb[j])) return -1;
+        L = std::max(L, std::fabs((double)qb[j] - (double)qa[j]));
+    }
+    const double n = std::ceil(L / (double)resolution) + 1.0;
+    return n < 2.0 ? 2 : (n > 2147483647.0 ? 2147483647 : (int64_t)n);
 }
 
 int32_t vk_robot_dof(vk_robot robot) { return robot ? robot->dof : -1; }

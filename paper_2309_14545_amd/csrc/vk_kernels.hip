@@ -787,6 +787,7 @@ __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, co
     for (int j = 0; j < rb.dof; ++j) bad |= !isfinite(ld(a, j)) || !isfinite(ld(b, j));
     if (bad) return 1;
     if (n < 2) n = 2;
+    if (n > kMaxEdgeStates) return 1;         // too long to validate: reported as colliding
     const int lane = threadIdx.x & (kWave - 1);
     const int stride = (n + kWave - 1) / kWave;
     const float inv = 1.0f / (float)(n - 1);

@@ -20,6 +20,10 @@ constexpr int kQueues = 8;
 constexpr int kQueueWords = 512;
 constexpr size_t kQueueBytes = (size_t)kQueues * kQueueWords * 8;
 constexpr int kMaxDof = 64;
+// Most states one edge may be discretised into.  A longer edge (a computed count that
+// saturates, or an explicit count above this) is not validated and is reported as colliding;
+// below it a state index and its interpolation parameter stay exact in 32-bit arithmetic.
+constexpr int kMaxEdgeStates = 1 << 24;
 
 // Twist codes: the paper's tracing compiler folds constant sin/cos of the DH twist; the
 // common twists 0 and +-90 degrees are folded the same way here (a uniform branch picks the

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "vk.h")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:vk_status|int32_t|const char \*)\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:vk_status|int32_t|int64_t|const char \*)\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
@@ -85,6 +85,52 @@ def test_bad_environment_rejected(vk):
         vk.Env({"spheres": np.array([[0, 0, 0, -1.0]], np.float32)})
     with pytest.raises(vk.VkError):
         vk.Env({"boxes": np.full((1, 15), np.nan, np.float32)})
+
+
+def test_primitive_frames_must_be_unit(vk):
+    """A cylinder axis off unit length, or a box rotation off orthonormal, by more than 1e-5 is
+    rejected before anything reaches the device; FP32 roundings of exact ones are accepted."""
+    axis = np.array([0.0, 0.6, 0.8]) * (1.0 + 3e-5)
+    cyl = np.array([[0, 0, 0, *axis, 0.1, 0.1]], np.float32)
+    with pytest.raises(vk.VkError) as e:
+        vk.Env({"cylinders": cyl})
+    assert e.value.status == -1 and b"axis" in vk.lib().vk_last_error()
+    R = np.array([[1, 0, 0], [0, 1, 2e-4], [0, 0, 1]])
+    box = np.array([[0, 0, 0, *R.reshape(-1), 0.1, 0.1, 0.1]], np.float32)
+    with pytest.raises(vk.VkError) as e:
+        vk.Env({"boxes": box})
+    assert e.value.status == -1 and b"orthonormal" in vk.lib().vk_last_error()
+    c, s = np.cos(0.3), np.sin(0.3)
+    R = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]]) * (1.0 + 2e-7)
+    # a mirror (det -1) is orthonormal too: the distance does not depend on handedness
+    ok_box = np.array([[0, 0, 0, *R.reshape(-1), 0.1, 0.1, 0.1]], np.float32)
+    try:
+        vk.Env({"boxes": ok_box, "cylinders": np.array([[0, 0, 0, 0, 0.6, 0.8, 0.1, 0.1]], np.float32)})
+    except vk.VkError as err:
+        # without a device the checks pass and the upload fails with a HIP error
+        assert err.status in (-4, -5), err
+
+
+def test_edge_state_count_on_the_host(vk, orc):
+    """vk_edge_states: the hand cases of the edge discretisation (Sec. III-D), saturation for
+    endpoints very far apart, invalid input, and agreement with the oracle's count."""
+    z = np.zeros(3, np.float32)
+    res = 1.0 / 32.0
+    assert vk.edge_states(z, z, res) == 2
+    assert vk.edge_states(z, np.array([0, res, 0], np.float32), res) == 2
+    assert vk.edge_states(z, np.array([0, np.nextafter(np.float32(res), np.float32(1)), 0], np.float32), res) == 3
+    assert vk.edge_states(z, np.array([0, 2.9, 0], np.float32), res) == 94
+    assert vk.edge_states(np.array([-2.9], np.float32), np.array([2.9], np.float32), res) == 187
+    assert vk.edge_states(z, np.array([0, 0, 1e9], np.float32), res) == 2 ** 31 - 1
+    assert vk.edge_states(z, np.array([0, 0, np.nan], np.float32), res) == -1
+    assert vk.edge_states(z, z, 0.0) == -1
+    assert vk.edge_states(z, z, float("inf")) == -1
+    g = np.random.default_rng(8)
+    qa = g.uniform(-2.9, 2.9, (500, 7)).astype(np.float32)
+    qb = g.uniform(-2.9, 2.9, (500, 7)).astype(np.float32)
+    for r in (1.0 / 32.0, 1.0 / 256.0, 0.1):
+        mine = [vk.edge_states(qa[e], qb[e], r) for e in range(len(qa))]
+        assert mine == orc.edge_n_states_batch(qa, qb, r).tolist()
 
 
 def test_null_handles_rejected(vk):

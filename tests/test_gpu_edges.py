@@ -156,3 +156,27 @@ def test_argument_errors(vk):
         vk.validate_edges(r, e, qa, qa, resolution=float("nan"))
     with pytest.raises(ValueError):
         vk.validate_edges(r, e, qa, qa[:, :6].contiguous())
+
+
+def test_edges_beyond_the_state_limit(vk):
+    """An edge of more than 2^24 states is not validated and reads 1: endpoints far apart (the
+    computed count saturates at 2^31 - 1) and an explicit count of 2^24 + 1.  Shorter edges in
+    the same launch keep their flags."""
+    w = workload("edges7_shelf", n=64)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    base = host(vk.validate_edges(r, e, dev(w["qa"]), dev(w["qb"])))
+    qa, qb = w["qa"].copy(), w["qb"].copy()
+    qb[3, 1] = np.float32(1e9)                        # 3.2e10 states at 1/32: saturated
+    qa[4], qb[4] = 0.0, 0.0
+    qb[4, 0] = np.float32(2.0 ** 19)                  # 2^24 + 1 states at 1/32
+    assert vk.edge_states(qa[3], qb[3]) == 2 ** 31 - 1
+    assert vk.edge_states(qa[4], qb[4]) == 2 ** 24 + 1
+    flags = host(vk.validate_edges(r, e, dev(qa), dev(qb)))
+    assert flags[3] == 1 and flags[4] == 1
+    keep = np.ones(len(qa), bool)
+    keep[[3, 4]] = False
+    np.testing.assert_array_equal(flags[keep], base[keep])
+    ns = np.full(len(qa), 5, np.int32)
+    ns[7] = 2 ** 24 + 1
+    f2 = host(vk.validate_edges(r, e, dev(w["qa"]), dev(w["qb"]), n_states=dev(ns)))
+    assert f2[7] == 1

@@ -143,10 +143,11 @@ def test_limit_robot_cost(vk, orc, name):
     zeros where the state is clearly free).  The 64-joint chain's backward pass runs one wave
     per workgroup (its force slots and walk cache take 146 KB of LDS).
 
-    The per-trajectory bar is the larger of 1e-4 and twice the oracle's own relative change
-    when every joint moves by up to 3e-7 rad, the FP32 angle error: the 64-joint chain's
-    millimetre penetrations make its gradient that sensitive (the oracle's gradient moves by up
-    to ~9e-4 there, by at most ~6e-5 for the shorter robots)."""
+    The per-trajectory bar is 1e-4, with one recorded exception: for the 64-joint chain it is
+    twice the oracle's own relative change when every joint moves by up to 3e-7 rad (the FP32
+    angle error), capped at 5e-4.  Its millimetre penetrations over 64 joints make the exact
+    gradient that sensitive (the oracle's gradient moves by up to ~9e-4 there, by at most ~6e-5
+    for the shorter robots, which therefore meet the plain 1e-4)."""
     robot = _robot(name, **CASES[name])
     env = _env()
     q, per = _trajectories(name, robot["dof"])
@@ -171,7 +172,7 @@ def test_limit_robot_cost(vk, orc, name):
         sens = max(sens, max(np.linalg.norm(h[:, sl] - gref[:, sl]) / norm for h in shaken))
         checked += 1
     glob = np.linalg.norm(g - gref) / np.linalg.norm(gref)
-    bar = max(1e-4, 2.0 * sens)
+    bar = min(5e-4, max(1e-4, 2.0 * sens)) if name == "chain64" else 1e-4
     say(f"{name} cost: active {(ref > 0).mean():.3f}, trajectories checked {checked}, "
         f"worst rel {worst:.2e} (bar {bar:.1e}, oracle under FP32 joint noise {sens:.1e}), "
         f"global rel {glob:.2e}")
