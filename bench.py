@@ -115,12 +115,11 @@ def extra_edges(vk, name, steps):
     nominal = int(state_counts(w["qa"], w["qb"], RES).sum())
     m = float(np.mean(ms))
     flops = int(flops_t[0].item())
-    vk.set_edge_launch(0, 0)
     return {"workload": name, "states_per_s": nominal / (m * 1e-3), "launch_ms": m,
             "nominal_states": nominal, "edge_collision_rate": float(out.float().mean().item()),
             "executed_tflops": flops / (m * 1e-3) / 1e12,
             "frac_fp32_peak": flops / (m * 1e-3) / PEAK_FP32,
-            "launch": [tune["block"], tune["per_cu"]]}
+            "launch": list(tune)}
 
 
 def extra_states(vk, name, n, steps):
@@ -135,7 +134,6 @@ def extra_states(vk, name, n, steps):
     torch.cuda.synchronize()
     ms = _events_ms(lambda: vk.validate_states(robot, env, q), steps)
     m = float(np.median(ms))
-    vk.set_states_split(0, 1)
     return {"workload": name, "states": q.shape[1], "states_per_s": q.shape[1] / (m * 1e-3),
             "median_ms": m, "collision_rate": float(out.float().mean().item()),
             "schedule_split": tuned["split"]}
@@ -247,18 +245,17 @@ def extra_mixed(vk, n_batches, reps):
         qa, qb = torch.from_numpy(qa_h).cuda(), torch.from_numpy(qb_h).cuda()
         out = torch.empty(total, dtype=torch.uint8, device="cuda")
         if tuned is None:
-            batch, tuned = autotune.tune_batch(
-                lambda: vk.EdgeBatch(robots, envs, sets, qa, qb, out, resolution=RES))
+            batch, tuned = autotune.tune_batch(robots, envs, sets, qa, qb, out, resolution=RES)
         else:
-            batch = vk.EdgeBatch(robots, envs, sets, qa, qb, out, resolution=RES)
-        batch.run()
+            batch = vk.EdgeBatch(robots, envs, sets, resolution=RES, block=tuned["block"],
+                                 per_cu=tuned["per_cu"])
+        batch.run(qa, qb, out)
         torch.cuda.synchronize()
-        lat += _events_ms(batch.run, reps)
+        lat += _events_ms(lambda: batch.run(qa, qb, out), reps)
         edges += total
         states += sum(int(state_counts(w["qa"][k], w["qb"][k], RES).sum())
                       for k in range(len(w["sets"])))
         del batch
-    vk.set_edge_launch(0, 0)
     lat = np.asarray(lat)
     return {"workload": "mixed", "batches": n_batches, "replays_per_batch": reps,
             "sets_per_batch": 1024, "mean_edges_per_batch": edges / n_batches,
@@ -279,7 +276,7 @@ def main():
                     help="skip the other workloads (8-DoF edges, states, point cloud, cost, mixed)")
     ap.add_argument("--extras", default="", metavar="NAME,...",
                     help="run only these of the other workloads (for profiling one of them)")
-    ap.add_argument("--launch", default="", metavar="BLOCK,PER_CU",
+    ap.add_argument("--launch", default="", metavar="BLOCK,PER_CU,TICKETS",
                     help="fixed persistent launch shape instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
@@ -319,14 +316,13 @@ def main():
 
     # launch shape from the project's autotuner (untimed setup)
     if args.launch:
-        block, per_cu = (int(x) for x in args.launch.split(","))
-        vk.set_edge_launch(block, per_cu)
-        log(f"fixed launch: block {block}, {per_cu} per CU")
+        shape = [int(x) for x in args.launch.split(",")] + [8]
+        robot.set_edge_launch(*shape[:3])
+        log(f"fixed launch: block, per CU, tickets per wave {robot.get_edge_launch()}")
     else:
         from paper_2309_14545_amd import autotune
-        tune = autotune.tune_edges(robot, env, qa, qb, resolution=RES, cache=None)
-        log(f"autotuned launch: block {tune['block']}, {tune['per_cu']} per CU "
-            f"({tune['ms']:.3f} ms while tuning)")
+        autotune.tune_edges(robot, env, qa, qb, resolution=RES, cache=None)
+        log(f"autotuned launch: block, per CU, tickets per wave {robot.get_edge_launch()}")
 
     # executed FP32 work of one launch (instrumented variant, untimed)
     flops_t = torch.zeros(5, dtype=torch.int64, device="cuda")
@@ -397,7 +393,7 @@ def main():
             "nominal_states": nominal,
             "resolution_rad": RES,
             "edge_collision_rate": float(flags.mean()),
-            "launch": list(vk.get_edge_launch()),
+            "launch": list(robot.get_edge_launch()),
         },
         "per_edge": {"value": pe_value, "unit": "states/s", "ms_per_step": pe_ms,
                      "launches_per_step": E, "steps": args.per_edge_steps},

@@ -28,6 +28,8 @@
  *   - Joint limits are not checked (validity means collision-free, Sec. III-D).  A state with
  *     a non-finite joint value is reported as colliding; its cost and gradient are NaN.
  *   - A handle may be used from several streams at once; a vk_edge_batch may not.
+ *   - Only create, reserve, autotune, release and destroy calls allocate, free or wait.  The
+ *     calls that need device scratch take it from the stream's workspace (vk_reserve).
  */
 #ifndef VK_H
 #define VK_H
@@ -122,6 +124,8 @@ vk_status fk_spheres(vk_robot robot, const float *q, int64_t n, int64_t ldq, flo
  * some listed self pair overlaps (clearance < 0), else 0.
  *   q       [dof][ldq] float, device, SoA; ldq >= n
  *   collide [n] uint8, device
+ * The schedule is the robot's (vk_robot_set_states_split); the two-pass form takes its survivor
+ * list from the stream's workspace (vk_reserve with max_states >= n; VK_ERR_SHAPE otherwise).
  */
 vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n, int64_t ldq,
                           uint8_t *collide, void *stream);
@@ -141,7 +145,9 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
  *   resolution > 0 (radians per step, per joint); ignored when n_states is given
  *   collide   [n_edges] uint8, device
  * An edge of more than 2^24 states (an explicit count, or a computed one, which saturates at
- * 2^31 - 1 for endpoints very far apart) is not validated: its flag is 1.
+ * 2^31 - 1 for endpoints very far apart) is not validated: its flag is 1.  The launch takes its
+ * work-queue counters from the stream's workspace (vk_reserve; VK_ERR_SHAPE without one) and
+ * its shape from the robot's launch settings (vk_robot_set_edge_launch).
  */
 vk_status validate_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
                          const int32_t *n_states, int64_t n_edges, float resolution,
@@ -178,7 +184,8 @@ vk_status validate_edges_indexed(vk_robot robot, vk_env env, const float *nodes,
  * Samples at a non-finite distance are skipped; a row with fewer than k neighbours ends in
  * index -1 and distance +inf.  1 <= dim <= 64, 1 <= k <= 32 (else VK_ERR_UNSUPPORTED /
  * VK_ERR_INVALID_ARG).  Brute force: O(n^2 dim) work, meant for roadmaps of up to ~10^5
- * samples. */
+ * samples.  The partial lists live in the stream's workspace (vk_reserve with max_knn_samples
+ * >= n and max_knn_k >= k; VK_ERR_SHAPE otherwise). */
 vk_status vk_knn(const float *x, int64_t n, int32_t dim, int32_t k, int32_t *idx, float *dist2,
                  void *stream);
 
@@ -282,14 +289,17 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
 
 /*
  * Mixed-robot edge batches: several edge sets, each with its own robot and environment, run as
- * one persistent launch; the launch is captured once in a HIP graph and replayed by
- * vk_edge_batch_run.  Set k covers edges [edge_offset, edge_offset + n_edges) of the qa/qb
- * arrays given to vk_edge_batch_create (AoS with that set's robot dof, offsets in floats) and
- * writes collide[out_offset + i].  The arrays passed at create are device pointers that must
- * stay valid for the batch's life; run replays on them.  A batch owns one work-queue counter
- * set, so replays of one batch must not overlap in time: replays on one stream are ordered by
- * it, replays on different streams must be ordered by the caller (events).  Different batches
- * are independent.
+ * one persistent launch, held in a HIP graph {work-queue reset -> launch} built at create and
+ * replayed by vk_edge_batch_run.  Set k covers edges [qa_offset / dof_k, ... + n_edges) of the
+ * qa/qb arrays passed to run (AoS with that set's robot dof, offsets in floats) and writes
+ * collide[out_offset + i].  run takes the device arrays of each replay (the graph's launch is
+ * re-pointed when they change, without rebuilding it); they must hold every set's edges and
+ * flags.  The launch shape is fixed at create: block_threads and blocks_per_cu as for
+ * vk_robot_set_edge_launch, both 0 for the default (256, 4).  A batch owns one set of
+ * work-queue counters, so replays of one batch must not overlap in time: replays on one stream
+ * are ordered by it, replays on different streams must be ordered by the caller (events).
+ * Different batches are independent.  Create allocates (device memory for the set records and
+ * counters); run does not.
  */
 typedef struct {
     int32_t robot;          /* index into robots[] */
@@ -301,35 +311,74 @@ typedef struct {
 
 vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const vk_env *envs,
                                int32_t n_envs, const vk_edge_set *sets, int32_t n_sets,
-                               float resolution, const float *qa, const float *qb,
-                               uint8_t *collide, void *stream, vk_edge_batch *out);
-vk_status vk_edge_batch_run(vk_edge_batch batch, void *stream);
+                               float resolution, int32_t block_threads, int32_t blocks_per_cu,
+                               vk_edge_batch *out);
+vk_status vk_edge_batch_run(vk_edge_batch batch, const float *qa, const float *qb,
+                            uint8_t *collide, void *stream);
+vk_status vk_edge_batch_get_launch(vk_edge_batch batch, int32_t *block_threads,
+                                   int32_t *blocks_per_cu);
 vk_status vk_edge_batch_destroy(vk_edge_batch batch);
 
 /*
- * Launch configuration of the persistent edge launches (validate_edges and batches created
- * afterwards): workgroup size (a multiple of 64 up to 1024) and workgroups per compute unit
- * (1..64).  Both 0 restores the built-in default (256, 4).  A launch whose per-wave LDS cache
- * (3 floats per lane for each link step a later self pair reads, 2 more with the capsule
- * halves, and optionally 2 per joint) would not fit the workgroup's LDS uses the largest
- * smaller workgroup that fits.  The project's autotuner (a Python helper next to the
- * binding) times candidates and calls this.  Invalid values: VK_ERR_INVALID_ARG.
+ * Workspace.  The persistent edge launches need work-queue counters (32 KiB), two-pass
+ * validate_states a survivor list (4 bytes per state) and vk_knn partial lists; they take them
+ * from a workspace the library keeps per (device, stream).  vk_reserve creates it for `stream`
+ * on the current device, or grows it to cover calls of up to max_states states (two-pass
+ * validate_states) and up to max_knn_samples samples with k <= max_knn_k (vk_knn); 0 sizes
+ * reserve the counters only.  It never shrinks, and a grown workspace keeps its earlier buffers
+ * until vk_release (a graph captured on the stream may still point at them).  vk_reserve may
+ * allocate, so it is a set-up call: made while the stream is being captured it fails with
+ * VK_ERR_SHAPE if the workspace would have to grow, and does nothing otherwise.  The calls
+ * that use the workspace never allocate, free or wait: they return VK_ERR_SHAPE when their
+ * stream has no workspace or too small a one.  vk_release waits for the stream, then frees its
+ * workspace (graphs captured on it must not be replayed afterwards).  Errors:
+ * VK_ERR_INVALID_ARG for negative sizes or max_knn_k > 32, VK_ERR_OOM.
  */
-vk_status vk_set_edge_launch(int32_t block_threads, int32_t blocks_per_cu);
-vk_status vk_get_edge_launch(int32_t *block_threads, int32_t *blocks_per_cu);
+vk_status vk_reserve(void *stream, int64_t max_states, int64_t max_knn_samples, int32_t max_knn_k);
+vk_status vk_release(void *stream);
 
 /*
- * Schedule of validate_states: with num > 0 it runs in two passes.  Pass 1 tests the first
- * floor(S * num / den) of the robot's S link steps for every state; pass 2 walks only the states still
- * free, packed densely into waves, testing the remaining steps.  Flags are identical to one
- * pass; the split pays off when most states collide early (a wave of independent states walks
- * as long as its last live lane), and costs time when they do not.  (0, 1) = one pass, the
- * default.  The project's autotuner picks it per workload.  Needs 0 <= num < den, else
- * VK_ERR_INVALID_ARG.  The two-pass form keeps a survivor list (4 bytes per state) in a scratch
- * buffer the library holds per stream.
+ * Launch settings, kept per robot handle.
+ * Edge launches of the robot (validate_edges, validate_edges_indexed, validate_edges_counted):
+ * workgroup size block_threads (a multiple of 64 up to 1024), workgroups per compute unit
+ * blocks_per_cu (1..64), and tickets_per_wave (1..64): about that many work-queue tickets per
+ * wave, which sets how many edges one ticket hands out.  All three 0 restore the defaults
+ * (256, 4, 8).  A launch whose per-wave LDS cache (3 floats per lane for each link step a later
+ * self pair reads, 2 more with the capsule halves, and optionally 2 per joint) would not fit
+ * uses the largest smaller workgroup that fits.
+ * States (validate_states): with num > 0 it runs in two passes.  Pass 1 tests the first
+ * floor(S * num / den) of the robot's S link steps for every state; pass 2 walks only the
+ * states still free, packed densely into waves, testing the remaining steps.  Flags are
+ * identical to one pass; the split pays off when most states collide early (a wave of
+ * independent states walks as long as its last live lane), and costs time when they do not.
+ * (0, 1) = one pass, the default.  The two-pass form needs a workspace (vk_reserve).
+ * Invalid values: VK_ERR_INVALID_ARG.  Settings may change between calls; a call uses the
+ * values it reads when it is made.
  */
-vk_status vk_set_states_split(int32_t num, int32_t den);
-vk_status vk_get_states_split(int32_t *num, int32_t *den);
+vk_status vk_robot_set_edge_launch(vk_robot robot, int32_t block_threads, int32_t blocks_per_cu,
+                                   int32_t tickets_per_wave);
+vk_status vk_robot_get_edge_launch(vk_robot robot, int32_t *block_threads, int32_t *blocks_per_cu,
+                                   int32_t *tickets_per_wave);
+vk_status vk_robot_set_states_split(vk_robot robot, int32_t num, int32_t den);
+vk_status vk_robot_get_states_split(vk_robot robot, int32_t *num, int32_t *den);
+
+/*
+ * Autotuner (a set-up call: it allocates, launches and waits for `stream`).  vk_autotune_edges
+ * times validate_edges on the given batch (same arguments) for every workgroup size in
+ * {64, 128, 256, 512, 1024}, workgroups per CU in {1, 2, 4, 8} (at most 2,048 threads per CU)
+ * and tickets per wave in {4, 8, 16}, each the median of 7 launches after one untimed launch,
+ * and sets the fastest on the robot.  vk_autotune_states does the same for the validate_states
+ * schedules one pass, and two passes split after 1/3, 1/2 and 2/3 of the steps.  With a
+ * cache_path (else NULL), results are kept in that JSON file keyed by the workload's class
+ * (device, dof, sphere count, primitive count and batch size, the counts rounded up to powers of
+ * two): a class already in the file is applied without timing unless force != 0.  Both reserve
+ * the stream's workspace they need.  Errors as the timed call.
+ */
+vk_status vk_autotune_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                            const int32_t *n_states, int64_t n_edges, float resolution,
+                            const char *cache_path, int32_t force, void *stream);
+vk_status vk_autotune_states(vk_robot robot, vk_env env, const float *q, int64_t n, int64_t ldq,
+                             const char *cache_path, int32_t force, void *stream);
 
 /* Text of the calling thread's last non-OK status ("" if none). */
 const char *vk_last_error(void);

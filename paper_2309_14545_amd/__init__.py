@@ -27,9 +27,11 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "vk_knn", "vk_knn_pairs", "vk_tree_nearest", "vk_tree_steer", "vk_tree_append",
            "vk_rrt_extend", "vk_rrt_commit",
            "penetration_cost_fwd", "penetration_cost_bwd",
-           "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_destroy",
-           "vk_set_edge_launch", "vk_get_edge_launch", "vk_set_states_split",
-           "vk_get_states_split", "vk_last_error")
+           "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_get_launch",
+           "vk_edge_batch_destroy", "vk_reserve", "vk_release",
+           "vk_robot_set_edge_launch", "vk_robot_get_edge_launch", "vk_robot_set_states_split",
+           "vk_robot_get_states_split", "vk_autotune_edges", "vk_autotune_states",
+           "vk_last_error")
 
 
 class VkError(RuntimeError):
@@ -97,14 +99,18 @@ def lib():
         L.penetration_cost_fwd.argtypes = [vp, vp, vp, i64, i64, vp, vp]
         L.penetration_cost_bwd.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
         L.vk_edge_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), i32,
-                                           C.POINTER(_EdgeSet), i32, fp, vp, vp, vp, vp,
-                                           C.POINTER(vp)]
-        L.vk_edge_batch_run.argtypes = [vp, vp]
+                                           C.POINTER(_EdgeSet), i32, fp, i32, i32, C.POINTER(vp)]
+        L.vk_edge_batch_run.argtypes = [vp, vp, vp, vp, vp]
+        L.vk_edge_batch_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.vk_edge_batch_destroy.argtypes = [vp]
-        L.vk_set_edge_launch.argtypes = [i32, i32]
-        L.vk_set_states_split.argtypes = [i32, i32]
-        L.vk_get_states_split.argtypes = [C.POINTER(i32), C.POINTER(i32)]
-        L.vk_get_edge_launch.argtypes = [C.POINTER(i32), C.POINTER(i32)]
+        L.vk_reserve.argtypes = [vp, i64, i64, i32]
+        L.vk_release.argtypes = [vp]
+        L.vk_robot_set_edge_launch.argtypes = [vp, i32, i32, i32]
+        L.vk_robot_get_edge_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.vk_robot_set_states_split.argtypes = [vp, i32, i32]
+        L.vk_robot_get_states_split.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+        L.vk_autotune_edges.argtypes = [vp, vp, vp, vp, vp, i64, fp, C.c_char_p, i32, vp]
+        L.vk_autotune_states.argtypes = [vp, vp, vp, i64, i64, C.c_char_p, i32, vp]
         L.vk_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("vk_robot_dof", "vk_robot_n_spheres", "vk_last_error", "vk_edge_states"):
@@ -158,6 +164,26 @@ class Robot:
         self.dof = dof
         self.n_spheres = len(keep["sphere_link"])
 
+    def set_edge_launch(self, block_threads: int = 0, blocks_per_cu: int = 0,
+                        tickets_per_wave: int = 0):
+        """Launch shape of this robot's edge launches (all 0: the defaults 256, 4, 8)."""
+        _check(lib().vk_robot_set_edge_launch(self.handle, int(block_threads), int(blocks_per_cu),
+                                              int(tickets_per_wave)))
+
+    def get_edge_launch(self):
+        b, p, t = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().vk_robot_get_edge_launch(self.handle, C.byref(b), C.byref(p), C.byref(t)))
+        return b.value, p.value, t.value
+
+    def set_states_split(self, num: int, den: int = 1):
+        """Two-pass schedule of validate_states for this robot; (0, 1) = one pass."""
+        _check(lib().vk_robot_set_states_split(self.handle, int(num), int(den)))
+
+    def get_states_split(self):
+        n, d = C.c_int32(), C.c_int32()
+        _check(lib().vk_robot_get_states_split(self.handle, C.byref(n), C.byref(d)))
+        return n.value, d.value
+
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.vk_robot_destroy(self.handle)
@@ -204,6 +230,32 @@ def _stream():
     return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
 
 
+# Workspace sizes reserved so far per (device, stream): (states, knn samples, knn k).
+_reserved = {}
+
+
+def reserve(states: int = 0, knn_samples: int = 0, knn_k: int = 0, stream=None):
+    """vk_reserve for the current (or given) torch stream: the workspace of calls of up to
+    these sizes.  A set-up call: do it before capturing a graph on the stream."""
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    key = (torch.cuda.current_device(), st.cuda_stream)
+    have = _reserved.get(key, (0, 0, 0))
+    want = (max(have[0], int(states)), max(have[1], int(knn_samples)), max(have[2], int(knn_k)))
+    if key in _reserved and want == have:
+        return
+    _check(lib().vk_reserve(C.c_void_p(st.cuda_stream), *want))
+    _reserved[key] = want
+
+
+def release(stream=None):
+    """vk_release for the current (or given) torch stream."""
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _reserved.pop((torch.cuda.current_device(), st.cuda_stream), None)
+    _check(lib().vk_release(C.c_void_p(st.cuda_stream)))
+
+
 def _dev_f32(t, name):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
@@ -234,6 +286,8 @@ def validate_states(robot: Robot, env: Env, q):
     q = _soa(robot, q)
     n = q.shape[1]
     out = torch.empty(n, dtype=torch.uint8, device=q.device)
+    if robot.get_states_split()[0] > 0:
+        reserve(states=n)
     _check(lib().validate_states(robot.handle, env.handle, q.data_ptr(), n, n, out.data_ptr(),
                                  _stream()))
     return out
@@ -260,6 +314,8 @@ def validate_edges(robot: Robot, env: Env, qa, qb, n_states=None, resolution: fl
     if out is None:
         out = torch.empty(E, dtype=torch.uint8, device=qa.device)
     fn = lib().validate_edges_per_edge if per_edge else lib().validate_edges
+    if not per_edge:
+        reserve()
     _check(fn(robot.handle, env.handle, qa.data_ptr(), qb.data_ptr(), ns_ptr, E, float(resolution),
               out.data_ptr(), _stream()))
     return out
@@ -280,6 +336,7 @@ def validate_edges_counted(robot: Robot, env: Env, qa, qb, flops, n_states=None,
     ns_ptr = n_states.contiguous().data_ptr() if n_states is not None else None
     if out is None:
         out = torch.empty(E, dtype=torch.uint8, device=qa.device)
+    reserve()
     _check(lib().validate_edges_counted(robot.handle, env.handle, qa.data_ptr(), qb.data_ptr(),
                                         ns_ptr, E, float(resolution), out.data_ptr(),
                                         flops.data_ptr(), _stream()))
@@ -308,6 +365,7 @@ def validate_edges_indexed(robot: Robot, env: Env, nodes, pairs, n_states=None,
         ns_ptr = n_states.data_ptr()
     if out is None:
         out = torch.empty(E, dtype=torch.uint8, device=nodes.device)
+    reserve()
     _check(lib().validate_edges_indexed(robot.handle, env.handle, nodes.data_ptr(), nodes.shape[0],
                                         pairs.data_ptr(), ns_ptr, E, float(resolution),
                                         out.data_ptr(), _stream()))
@@ -323,6 +381,8 @@ def knn(x, k: int):
     n, d = x.shape
     idx = torch.empty((n, k), dtype=torch.int32, device=x.device)
     d2 = torch.empty((n, k), dtype=torch.float32, device=x.device)
+    if 1 <= k <= 32:
+        reserve(knn_samples=n, knn_k=k)
     _check(lib().vk_knn(x.data_ptr(), n, d, k, idx.data_ptr(), d2.data_ptr(), _stream()))
     return idx, d2
 
@@ -463,44 +523,32 @@ def penetration_cost(q, robot: Robot, env: Env):
 
 
 class EdgeBatch:
-    """Mixed-robot edge batch replayed from a HIP graph (vk_edge_batch_*)."""
+    """Mixed-robot edge batch replayed from a HIP graph (vk_edge_batch_*); the launch shape is
+    fixed at creation (block, per_cu both 0: the defaults)."""
 
-    def __init__(self, robots, envs, sets, qa, qb, out, resolution: float = 1.0 / 32.0):
-        self._keep = (list(robots), list(envs), qa, qb, out)
+    def __init__(self, robots, envs, sets, resolution: float = 1.0 / 32.0, block: int = 0,
+                 per_cu: int = 0):
+        self._keep = (list(robots), list(envs))
         rh = (C.c_void_p * len(robots))(*[r.handle.value for r in robots])
         eh = (C.c_void_p * len(envs))(*[e.handle.value for e in envs])
         st = (_EdgeSet * len(sets))(*[_EdgeSet(*s) for s in sets])
         h = C.c_void_p()
         _check(lib().vk_edge_batch_create(rh, len(robots), eh, len(envs), st, len(sets),
-                                          float(resolution), qa.data_ptr(), qb.data_ptr(),
-                                          out.data_ptr(), _stream(), C.byref(h)))
+                                          float(resolution), int(block), int(per_cu), C.byref(h)))
         self.handle = h
 
-    def run(self):
-        _check(lib().vk_edge_batch_run(self.handle, _stream()))
+    def run(self, qa, qb, out):
+        """Replay on device arrays qa, qb (float32) and out (uint8) holding every set's edges."""
+        self._arrays = (qa, qb, out)          # kept alive until the next run
+        _check(lib().vk_edge_batch_run(self.handle, qa.data_ptr(), qb.data_ptr(), out.data_ptr(),
+                                       _stream()))
+
+    def launch(self):
+        b, p = C.c_int32(), C.c_int32()
+        _check(lib().vk_edge_batch_get_launch(self.handle, C.byref(b), C.byref(p)))
+        return b.value, p.value
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.vk_edge_batch_destroy(self.handle)
             self.handle = None
-
-
-def set_edge_launch(block_threads: int = 0, blocks_per_cu: int = 0):
-    _check(lib().vk_set_edge_launch(int(block_threads), int(blocks_per_cu)))
-
-
-def set_states_split(num: int, den: int = 1):
-    """Two-pass schedule of validate_states (see vk_set_states_split); (0, 1) = one pass."""
-    _check(lib().vk_set_states_split(int(num), int(den)))
-
-
-def get_states_split():
-    n, d = C.c_int32(), C.c_int32()
-    _check(lib().vk_get_states_split(C.byref(n), C.byref(d)))
-    return n.value, d.value
-
-
-def get_edge_launch():
-    b, p = C.c_int32(), C.c_int32()
-    _check(lib().vk_get_edge_launch(C.byref(b), C.byref(p)))
-    return b.value, p.value

@@ -1,157 +1,82 @@
-"""Launch-shape autotuner for the persistent edge launch.
+"""Launch-shape autotuner.
 
-The persistent kernel's schedule has two knobs (``vk_set_edge_launch``): the workgroup size
-(waves per workgroup share one LDS copy of the environment) and the number of workgroups per
-compute unit (how many waves pull from the work queue at once).  ``tune_edges`` times every
-candidate on the caller's batch with HIP events, keeps the fastest, and records it in a JSON
-cache keyed by device and workload class (robot size, environment size, batch size), so a later
-process with the same class reuses it without timing.
+The edge and state autotuners are native (``vk_autotune_edges`` / ``vk_autotune_states`` in
+libvk): they time every candidate launch setting on the caller's batch with HIP events (median of
+7 launches), set the fastest on the robot handle, and keep it in a JSON cache keyed by the
+workload's class (device, robot size, environment size, batch size), so that a later process
+with the same class reuses it without timing.  The knobs of the persistent edge launch are the
+workgroup size (waves per workgroup share one LDS copy of the environment), the workgroups per
+compute unit (how many waves pull from the work queue at once) and the tickets per wave (how
+many edges one queue ticket hands out); the knob of validate_states is its one- or two-pass
+schedule.
+
+``tune_batch`` tunes a mixed-robot batch, whose launch shape is fixed when the batch is created:
+it creates one batch per candidate shape and keeps the fastest.
 """
 from __future__ import annotations
 
-import json
+import ctypes as C
 import os
-import time
 
-from . import get_edge_launch, set_edge_launch, validate_edges, set_states_split, validate_states
+from . import EdgeBatch, _check, _dev_f32, _stream, lib
 
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "vk_autotune.json")
 BLOCKS = (64, 128, 256, 512, 1024)
 PER_CU = (1, 2, 4, 8)
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "vk_autotune.json")
 
 
-def _bucket(x: int) -> int:
-    """Power-of-two bucket of a size (workload classes, not exact sizes)."""
-    b = 1
-    while b < x:
-        b *= 2
-    return b
+def _path(cache):
+    if not cache:
+        return None
+    os.makedirs(os.path.dirname(cache) or ".", exist_ok=True)
+    return cache.encode()
 
 
-def workload_key(robot, env, n_edges: int) -> str:
-    import torch
-    dev = torch.cuda.get_device_name(torch.cuda.current_device()).replace(" ", "_")
-    prims = sum(env.counts.values())
-    return f"{dev}|dof{robot.dof}|s{_bucket(robot.n_spheres)}|p{_bucket(max(prims, 1))}|e{_bucket(n_edges)}"
+def tune_edges(robot, env, qa, qb, n_states=None, resolution: float = 1.0 / 32.0,
+               cache: str | None = DEFAULT_CACHE, force: bool = False):
+    """Pick and set the robot's fastest edge launch for this batch; returns (block, per_cu,
+    tickets)."""
+    qa, qb = _dev_f32(qa, "qa"), _dev_f32(qb, "qb")
+    ns = n_states.contiguous().data_ptr() if n_states is not None else None
+    _check(lib().vk_autotune_edges(robot.handle, env.handle, qa.data_ptr(), qb.data_ptr(), ns,
+                                   qa.shape[0], float(resolution), _path(cache), int(force),
+                                   _stream()))
+    return robot.get_edge_launch()
 
 
-def _load(path):
-    try:
-        with open(path) as f:
-            return json.load(f)
-    except (OSError, ValueError):
-        return {}
+def tune_states(robot, env, q, cache: str | None = DEFAULT_CACHE, force: bool = False):
+    """Pick and set the robot's fastest validate_states schedule for the SoA batch q [dof, N];
+    returns (num, den)."""
+    q = _dev_f32(q, "q")
+    n = q.shape[1]
+    _check(lib().vk_autotune_states(robot.handle, env.handle, q.data_ptr(), n, n, _path(cache),
+                                    int(force), _stream()))
+    return robot.get_states_split()
 
 
-def _save(path, data):
-    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
-    tmp = path + f".tmp{os.getpid()}"
-    with open(tmp, "w") as f:
-        json.dump(data, f, indent=1, sort_keys=True)
-    os.replace(tmp, path)
-
-
-def _time(robot, env, qa, qb, out, resolution, reps):
-    import torch
-    validate_edges(robot, env, qa, qb, resolution=resolution, out=out)
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        validate_edges(robot, env, qa, qb, resolution=resolution, out=out)
-    e.record()
-    torch.cuda.synchronize()
-    return s.elapsed_time(e) / reps
-
-
-def tune_edges(robot, env, qa, qb, resolution: float = 1.0 / 32.0, reps: int = 3,
-               cache: str | None = DEFAULT_CACHE, force: bool = False, log=None):
-    """Pick and apply the fastest (block, per-CU) for this batch; returns a result dict."""
-    import torch
-    key = workload_key(robot, env, qa.shape[0])
-    data = _load(cache) if cache else {}
-    if not force and key in data:
-        block, per_cu = data[key]["block"], data[key]["per_cu"]
-        set_edge_launch(block, per_cu)
-        return {"key": key, "block": block, "per_cu": per_cu, "ms": data[key]["ms"], "cached": True}
-    out = torch.empty(qa.shape[0], dtype=torch.uint8, device=qa.device)
-    results = []
-    t0 = time.perf_counter()
-    for block in BLOCKS:
-        for per_cu in PER_CU:
-            if block * per_cu > 2048:          # more waves than a CU holds
-                continue
-            set_edge_launch(block, per_cu)
-            ms = _time(robot, env, qa, qb, out, resolution, reps)
-            results.append((ms, block, per_cu))
-            if log:
-                log(f"autotune {key}: block {block} per_cu {per_cu}: {ms:.3f} ms")
-    ms, block, per_cu = min(results)
-    set_edge_launch(block, per_cu)
-    if cache:
-        data = _load(cache)
-        data[key] = {"block": block, "per_cu": per_cu, "ms": ms,
-                     "candidates": [[b, p, round(m, 4)] for m, b, p in sorted(results)]}
-        _save(cache, data)
-    return {"key": key, "block": block, "per_cu": per_cu, "ms": ms, "cached": False,
-            "tuning_s": time.perf_counter() - t0, "candidates": len(results)}
-
-
-def tune_batch(make_batch, reps: int = 3, log=None):
-    """Pick the fastest (block, per-CU) for a mixed-robot batch.  ``make_batch()`` builds an
-    EdgeBatch under the current launch setting (its HIP graph captures that setting).
-    Returns (batch, result)."""
+def tune_batch(robots, envs, sets, qa, qb, out, resolution: float = 1.0 / 32.0, reps: int = 7):
+    """Create the mixed-robot batch with every candidate launch shape, time its replays (median
+    of ``reps`` after one untimed replay) and return (fastest batch, {block, per_cu, ms})."""
     import torch
     best = None
     for block in BLOCKS:
         for per_cu in PER_CU:
             if block * per_cu > 2048:
                 continue
-            set_edge_launch(block, per_cu)
-            b = make_batch()
-            b.run()
+            b = EdgeBatch(robots, envs, sets, resolution=resolution, block=block, per_cu=per_cu)
+            b.run(qa, qb, out)
             torch.cuda.synchronize()
-            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            s.record()
-            for _ in range(reps):
-                b.run()
-            e.record()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+            ev[0].record()
+            for r in range(reps):
+                b.run(qa, qb, out)
+                ev[r + 1].record()
             torch.cuda.synchronize()
-            ms = s.elapsed_time(e) / reps
-            if log:
-                log(f"autotune batch: block {block} per_cu {per_cu}: {ms:.3f} ms")
+            ms = sorted(ev[r].elapsed_time(ev[r + 1]) for r in range(reps))[reps // 2]
             if best is None or ms < best[0]:
                 best = (ms, block, per_cu, b)
     ms, block, per_cu, b = best
-    set_edge_launch(block, per_cu)
     return b, {"block": block, "per_cu": per_cu, "ms": ms}
 
 
-SPLITS = ((0, 1), (1, 3), (1, 2), (2, 3))
-
-
-def tune_states(robot, env, q, reps: int = 3, log=None):
-    """Pick and apply the fastest validate_states schedule (one pass, or two passes split after
-    1/3, 1/2 or 2/3 of the link steps) for this batch; flags are the same for all of them."""
-    import torch
-    results = []
-    for num, den in SPLITS:
-        set_states_split(num, den)
-        validate_states(robot, env, q)
-        torch.cuda.synchronize()
-        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        s.record()
-        for _ in range(reps):
-            validate_states(robot, env, q)
-        e.record()
-        torch.cuda.synchronize()
-        ms = s.elapsed_time(e) / reps
-        results.append((ms, num, den))
-        if log:
-            log(f"autotune states: split {num}/{den}: {ms:.3f} ms")
-    ms, num, den = min(results)
-    set_states_split(num, den)
-    return {"split": [num, den], "ms": ms}
-
-
-__all__ = ["tune_edges", "tune_batch", "tune_states", "workload_key", "get_edge_launch"]
+__all__ = ["tune_edges", "tune_states", "tune_batch", "DEFAULT_CACHE"]

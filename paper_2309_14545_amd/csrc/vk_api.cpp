@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <cctype>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -59,10 +61,6 @@ struct DeviceInfo {
 
 std::mutex g_mu;
 std::map<int, DeviceInfo> g_dev;
-std::map<std::pair<int, hipStream_t>, unsigned long long *> g_queues;
-int g_edge_block = 256;
-int g_edge_bpc = 4;
-int g_states_split_num = 0, g_states_split_den = 1;   // one pass by default
 
 const DeviceInfo &device_info(int dev) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -84,41 +82,43 @@ int current_device() {
     return dev;
 }
 
-// One counter per (device, stream) for the persistent launch's work queue: calls on different
-// streams never share a counter.  Allocated on a stream's first persistent launch.
-unsigned long long *queue_for(int dev, hipStream_t s) {
+// Workspace of one (device, stream): the persistent launches' work-queue counters and the
+// scratch of the multi-kernel calls (the survivor list of two-pass state validation, kNN's
+// partial lists).  Calls on one stream are ordered, so they share it.  Only vk_reserve
+// allocates it; a grown workspace keeps its earlier buffers alive (a graph captured on the
+// stream may still point at them) until vk_release.
+struct Workspace {
+    unsigned long long *queue = nullptr;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    std::vector<void *> retired;
+};
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+// The workspace of the current device and stream `s`, with at least `scratch_bytes` of scratch;
+// the hot calls never allocate, so a missing or smaller one is an error naming vk_reserve.
+const Workspace &workspace_for(hipStream_t s, size_t scratch_bytes, const char *what) {
+    const int dev = current_device();
     std::lock_guard<std::mutex> lk(g_mu);
-    auto key = std::make_pair(dev, s);
-    auto it = g_queues.find(key);
-    if (it != g_queues.end()) return it->second;
-    void *p = nullptr;
-    hip_check(hipMalloc(&p, kQueueBytes), "queue counters");
-    return g_queues[key] = static_cast<unsigned long long *>(p);
+    auto it = g_ws.find(std::make_pair(dev, s));
+    if (it == g_ws.end())
+        raise(VK_ERR_SHAPE, std::string(what) + ": no workspace for this stream (call vk_reserve first)");
+    if (it->second.scratch_bytes < scratch_bytes)
+        raise(VK_ERR_SHAPE, std::string(what) + ": the stream's workspace holds " +
+                                std::to_string(it->second.scratch_bytes) + " scratch bytes, the call needs " +
+                                std::to_string(scratch_bytes) + " (call vk_reserve with larger sizes)");
+    return it->second;
 }
 
-// Scratch of the multi-kernel calls (kNN partial lists, the survivor list of two-pass state
-// validation), per (device, stream), grown on demand and kept until the process ends (calls on
-// one stream are ordered, so they may share it).
-std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_scratch;
-
-void *scratch_for(int dev, hipStream_t s, size_t bytes) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto &w = g_scratch[std::make_pair(dev, s)];
-    if (w.second < bytes) {
-        if (w.first) {
-            // the previous buffer may still be in use by work queued on this stream
-            hip_check(hipStreamSynchronize(s), "scratch sync");
-            (void)hipFree(w.first);
-            w.first = nullptr;
-            w.second = 0;
-        }
-        void *p = nullptr;
-        hip_check(hipMalloc(&p, bytes), "scratch");
-        w.first = p;
-        w.second = bytes;
-    }
-    return w.first;
+// Scratch bytes that calls of up to these sizes need.
+size_t reserve_bytes(int64_t max_states, int64_t max_knn_n, int max_knn_k) {
+    size_t b = max_states > 0 ? states_scratch_bytes(max_states) : 0;
+    if (max_knn_n > 0 && max_knn_k > 0) b = std::max(b, knn_workspace_bound(max_knn_n, max_knn_k));
+    return b;
 }
+
+// Launch settings kept per robot handle (the autotuner sets them per workload).
+constexpr int kDefaultEdgeBlock = 256, kDefaultEdgeBpc = 4, kDefaultTickets = 8;
 
 // Device blob: several host arrays copied into one allocation at 256-byte aligned offsets.
 struct Blob {
@@ -280,21 +280,29 @@ struct vk_robot_s {
     void *blob = nullptr;
     RobotDev dev{};
     int dof = 0, n_spheres = 0;
+    // launch settings of this robot's calls (set by the autotuner or the caller)
+    std::atomic<int> edge_block{kDefaultEdgeBlock}, edge_bpc{kDefaultEdgeBpc};
+    std::atomic<int> edge_tickets{kDefaultTickets};
+    std::atomic<int> split_num{0}, split_den{1};
 };
 
 struct vk_env_s {
     int device = 0;
     void *blob = nullptr;
     EnvDev dev{};
+    int64_t n_points = 0;              // spheres kept in the point grid
 };
 
 struct vk_edge_batch_s {
     int device = 0;
     void *blob = nullptr;              // BatchSet records and the set of every edge
-    unsigned long long *queue = nullptr;  // the batch's own work-queue counter
+    unsigned long long *queue = nullptr;  // the batch's own work-queue counters
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraphNode_t walk = nullptr;     // the persistent launch's node (its arrays are updated)
+    vk::KernelNode reset, launch;      // the two nodes' launches and argument values
     int64_t total = 0;
+    int block = 0, per_cu = 0;
 };
 
 namespace {
@@ -789,6 +797,7 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
         e->dev.off_cell = put(cells);
         e->dev.n_cells = (int)ncell;
         gd.n_pts = (int)pts.size();
+        e->n_points = (int64_t)pts.size();
         for (int a = 0; a < 3; ++a) {
             gd.gdim[a] = dim[a];
             gd.gorg[a] = (float)glo[a];
@@ -899,6 +908,15 @@ EnvDev env_for_launch(const vk_env_s *e, size_t extra) {
     return d;
 }
 
+void check_launch(int block_threads, int blocks_per_cu, int tickets_per_wave) {
+    if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
+        raise(VK_ERR_INVALID_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
+    if (blocks_per_cu < 1 || blocks_per_cu > 64)
+        raise(VK_ERR_INVALID_ARG, "blocks_per_cu must be in [1, 64]");
+    if (tickets_per_wave < 1 || tickets_per_wave > 64)
+        raise(VK_ERR_INVALID_ARG, "tickets_per_wave must be in [1, 64]");
+}
+
 void check_pair(vk_robot r, vk_env e) {
     if (!r) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
     if (!e) raise(VK_ERR_INVALID_ARG, "env handle is NULL");
@@ -909,6 +927,162 @@ void check_batch(int64_t n, int64_t ld, const void *in, const void *out, const c
     if (n > 0 && (!in || !out)) raise(VK_ERR_INVALID_ARG, std::string(what) + ": NULL array");
     if (ld < n) raise(VK_ERR_SHAPE, std::string(what) + ": leading dimension < n");
     if (n >= (int64_t(1) << 40)) raise(VK_ERR_SHAPE, std::string(what) + ": n too large");
+}
+
+
+// ---- autotuner helpers ------------------------------------------------------------------------
+// Median launch time (ms) of `launch` on stream s: one untimed run, then 7 runs each bracketed
+// by events.
+template <class F>
+double time_median(hipStream_t s, F &&launch) {
+    launch();
+    hip_check(hipStreamSynchronize(s), "autotune sync");
+    constexpr int kReps = 7;
+    hipEvent_t ev[kReps + 1];
+    int made = 0;
+    std::vector<float> ms;
+    try {
+        for (; made < kReps + 1; ++made) hip_check(hipEventCreate(&ev[made]), "hipEventCreate");
+        hip_check(hipEventRecord(ev[0], s), "hipEventRecord");
+        for (int r = 0; r < kReps; ++r) {
+            launch();
+            hip_check(hipEventRecord(ev[r + 1], s), "hipEventRecord");
+        }
+        hip_check(hipEventSynchronize(ev[kReps]), "hipEventSynchronize");
+        for (int r = 0; r < kReps; ++r) {
+            float t = 0.0f;
+            hip_check(hipEventElapsedTime(&t, ev[r], ev[r + 1]), "hipEventElapsedTime");
+            ms.push_back(t);
+        }
+    } catch (...) {
+        for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+        throw;
+    }
+    for (int i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+    std::sort(ms.begin(), ms.end());
+    return ms[kReps / 2];
+}
+
+int64_t pow2_bucket(int64_t x) {
+    int64_t b = 1;
+    while (b < x) b *= 2;
+    return b;
+}
+
+// Workload class of a tuning result: the device, the robot's size, the environment's size and
+// the batch size (powers of two), so that a later process reuses it without timing.
+std::string tune_key(const char *what, vk_robot r, vk_env e, int64_t n) {
+    hipDeviceProp_t prop{};
+    hip_check(hipGetDeviceProperties(&prop, r->device), "hipGetDeviceProperties");
+    std::string arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == ' ' || c == '"' || c == '|') c = '_';
+    const EnvDev &d = e->dev;
+    const int64_t prims = (int64_t)d.n_sph + d.n_cap + d.n_cyl + d.n_box + (d.grid ? e->n_points : 0);
+    return std::string(what) + "|" + arch + "|cu" + std::to_string(prop.multiProcessorCount) +
+           "|dof" + std::to_string(r->dof) + "|s" + std::to_string(pow2_bucket(r->n_spheres)) +
+           "|p" + std::to_string(pow2_bucket(std::max<int64_t>(prims, 1))) + "|n" +
+           std::to_string(pow2_bucket(n));
+}
+
+// The cache file is a JSON object of objects of numbers, e.g.
+//   {"edges|gfx950|cu256|dof7|s64|p256|n65536": {"block": 1024, "per_cu": 2, "tickets": 8, "ms": 0.61}}
+// A file that does not parse as that is treated as empty (its workloads are timed again and it
+// is rewritten).
+using TuneEntry = std::map<std::string, double>;
+using TuneCache = std::map<std::string, TuneEntry>;
+
+struct JsonIn {
+    const std::string &t;
+    size_t i = 0;
+    void ws() {
+        while (i < t.size() && std::isspace((unsigned char)t[i])) ++i;
+    }
+    bool eat(char c) {
+        ws();
+        if (i < t.size() && t[i] == c) {
+            ++i;
+            return true;
+        }
+        return false;
+    }
+    bool str(std::string &out) {
+        if (!eat('"')) return false;
+        out.clear();
+        while (i < t.size() && t[i] != '"') {
+            if (t[i] == '\\') return false;     // keys written here have no escapes
+            out += t[i++];
+        }
+        return eat('"');
+    }
+    bool num(double &x) {
+        ws();
+        char *end = nullptr;
+        x = std::strtod(t.c_str() + i, &end);
+        if (end == t.c_str() + i) return false;
+        i = (size_t)(end - t.c_str());
+        return true;
+    }
+};
+
+TuneCache load_tune_cache(const char *path) {
+    TuneCache c;
+    if (!path || !*path) return c;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return c;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    JsonIn in{text};
+    TuneCache out;
+    if (!in.eat('{')) return c;
+    if (in.eat('}')) return out;
+    do {
+        std::string key;
+        if (!in.str(key) || !in.eat(':') || !in.eat('{')) return c;
+        TuneEntry e;
+        if (!in.eat('}')) {
+            do {
+                std::string name;
+                double x;
+                if (!in.str(name) || !in.eat(':') || !in.num(x)) return c;
+                e[name] = x;
+            } while (in.eat(','));
+            if (!in.eat('}')) return c;
+        }
+        out[key] = e;
+    } while (in.eat(','));
+    if (!in.eat('}')) return c;
+    return out;
+}
+
+void save_tune_cache(const char *path, const TuneCache &c) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) raise(VK_ERR_INVALID_ARG, std::string("cannot write the autotune cache ") + path);
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto &kv : c) {
+        std::fprintf(f, " \"%s\": {", kv.first.c_str());
+        size_t j = 0;
+        for (const auto &fv : kv.second)
+            std::fprintf(f, "%s\"%s\": %.9g", j++ ? ", " : "", fv.first.c_str(), fv.second);
+        std::fprintf(f, "}%s\n", ++i < c.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0)
+        raise(VK_ERR_INVALID_ARG, std::string("cannot write the autotune cache ") + path);
+}
+
+// Field `name` of a cache entry as an int, or -1 when it is missing or not an integer.
+int entry_int(const TuneEntry &e, const char *name) {
+    auto it = e.find(name);
+    if (it == e.end() || !(it->second == std::floor(it->second)) || std::fabs(it->second) > 1e6)
+        return -1;
+    return (int)it->second;
 }
 
 }  // namespace
@@ -999,14 +1173,9 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
         check_batch(n, ldq, q, collide, "validate_states");
         if (n == 0) return;
         hipStream_t s = (hipStream_t)stream;
-        int num, den;
-        {
-            std::lock_guard<std::mutex> lk(g_mu);
-            num = g_states_split_num;
-            den = g_states_split_den;
-        }
-        const int split = states_split(robot->dev, n, num, den);
-        void *scratch = split > 0 ? scratch_for(robot->device, s, states_scratch_bytes(n)) : nullptr;
+        const int split = states_split(robot->dev, n, robot->split_num.load(), robot->split_den.load());
+        void *scratch =
+            split > 0 ? workspace_for(s, states_scratch_bytes(n), "validate_states").scratch : nullptr;
         hip_check(launch_validate_states(robot->dev,
                                          env_for_launch(env, walk_lds_bytes(robot->dev, walk_block(robot->dev, 256))), q, n,
                                          ldq, collide, split, scratch, s),
@@ -1014,15 +1183,21 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
     });
 }
 
-static void check_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
-                        const int32_t *n_states, int64_t n_edges, float resolution,
-                        uint8_t *collide) {
+static void check_edge_inputs(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                              const int32_t *n_states, int64_t n_edges, float resolution) {
     check_pair(robot, env);
     if (n_edges < 0) raise(VK_ERR_INVALID_ARG, "n_edges < 0");
-    if (n_edges > 0 && (!qa || !qb || !collide)) raise(VK_ERR_INVALID_ARG, "NULL edge array");
+    if (n_edges > 0 && (!qa || !qb)) raise(VK_ERR_INVALID_ARG, "NULL edge array");
     if (n_edges >= (int64_t(1) << 31) - (int64_t(1) << 24)) raise(VK_ERR_SHAPE, "too many edges");
     if (!n_states && !(resolution > 0.0f && std::isfinite(resolution)))
         raise(VK_ERR_INVALID_ARG, "resolution must be finite and > 0");
+}
+
+static void check_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                        const int32_t *n_states, int64_t n_edges, float resolution,
+                        uint8_t *collide) {
+    check_edge_inputs(robot, env, qa, qb, n_states, n_edges, resolution);
+    if (n_edges > 0 && !collide) raise(VK_ERR_INVALID_ARG, "NULL edge array");
 }
 
 static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_edges,
@@ -1032,13 +1207,9 @@ static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_
     hipStream_t s = (hipStream_t)stream;
     const int dev = robot->device;
     const DeviceInfo &di = device_info(dev);
-    unsigned long long *queue = queue_for(dev, s);
-    int block, bpc;
-    {
-        std::lock_guard<std::mutex> lk(g_mu);
-        block = g_edge_block;
-        bpc = g_edge_bpc;
-    }
+    unsigned long long *queue = workspace_for(s, 0, "validate_edges").queue;
+    int block = robot->edge_block.load();
+    const int bpc = robot->edge_bpc.load(), tickets = robot->edge_tickets.load();
     // a workgroup's per-wave caches must fit the LDS: smaller workgroups for large robots
     while (block > kWave && walk_lds_bytes(robot->dev, block) > di.max_lds) block -= kWave;
     // a batch too small to give every CU a workgroup of this size (planner rounds of a few
@@ -1052,7 +1223,8 @@ static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
     hip_check(launch_reset_queue(queue, s), "queue reset");
     hip_check(launch_validate_edges(robot->dev, env_for_launch(env, walk_lds_bytes(robot->dev, block)),
-                                    src, n_edges, resolution, collide, queue, grid, block, s, flops),
+                                    src, n_edges, resolution, collide, queue, grid, block, tickets,
+                                    s, flops),
               "validate_edges launch");
 }
 
@@ -1116,7 +1288,7 @@ vk_status vk_knn(const float *x, int64_t n, int32_t dim, int32_t k, int32_t *idx
         if (!x || !idx || !dist2) raise(VK_ERR_INVALID_ARG, "vk_knn: NULL array");
         if (n >= (int64_t(1) << 31) / 32) raise(VK_ERR_SHAPE, "vk_knn: too many samples");
         hipStream_t s = (hipStream_t)stream;
-        void *ws = scratch_for(current_device(), s, knn_workspace_bytes(n, k));
+        void *ws = workspace_for(s, knn_workspace_bytes(n, k), "vk_knn").scratch;
         hip_check(launch_knn(x, n, dim, k, idx, dist2, ws, s), "vk_knn launch");
     });
 }
@@ -1254,9 +1426,8 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
 
 vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const vk_env *envs,
                                int32_t n_envs, const vk_edge_set *sets, int32_t n_sets,
-                               float resolution, const float *qa, const float *qb,
-                               uint8_t *collide, void *stream, vk_edge_batch *out) {
-    (void)stream;
+                               float resolution, int32_t block_threads, int32_t blocks_per_cu,
+                               vk_edge_batch *out) {
     return guarded([&] {
         if (!out) raise(VK_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
@@ -1264,6 +1435,11 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             raise(VK_ERR_INVALID_ARG, "robots, envs and sets must be non-empty arrays");
         if (!(resolution > 0.0f && std::isfinite(resolution)))
             raise(VK_ERR_INVALID_ARG, "resolution must be finite and > 0");
+        if (block_threads == 0 && blocks_per_cu == 0) {
+            block_threads = kDefaultEdgeBlock;
+            blocks_per_cu = kDefaultEdgeBpc;
+        }
+        check_launch(block_threads, blocks_per_cu, kDefaultTickets);
         for (int i = 0; i < n_robots; ++i)
             if (!robots[i]) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
         for (int i = 0; i < n_envs; ++i)
@@ -1288,7 +1464,6 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             recs.push_back(b);
             total += s.n_edges;
         }
-        if (total > 0 && (!qa || !qb || !collide)) raise(VK_ERR_INVALID_ARG, "NULL edge array");
         if (total >= (int64_t(1) << 31) - (int64_t(1) << 24)) raise(VK_ERR_SHAPE, "too many edges");
         auto *bt = new vk_edge_batch_s();
         try {
@@ -1310,12 +1485,7 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             const BatchSet *d_sets = reinterpret_cast<const BatchSet *>(static_cast<char *>(bt->blob) + o_s);
             const int32_t *d_eset = reinterpret_cast<const int32_t *>(static_cast<char *>(bt->blob) + o_p);
             const DeviceInfo &di = device_info(bt->device);
-            int block, bpc;
-            {
-                std::lock_guard<std::mutex> lk(g_mu);
-                block = g_edge_block;
-                bpc = g_edge_bpc;
-            }
+            int block = block_threads;
             // per wave: link bound centres, and optionally capsule halves and joint values
             int max_slots = 0, max_dof = 0;
             for (const BatchSet &b : recs) {
@@ -1328,23 +1498,33 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
             if ((size_t)(block / kWave) * min_floats * sizeof(float) > di.max_lds)
                 raise(VK_ERR_UNSUPPORTED, "robots too large for the LDS walk cache");
             const int64_t want = (total + block / kWave - 1) / (block / kWave);
-            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
-            // capture {queue reset, persistent launch} once; vk_edge_batch_run replays it
-            hipStream_t cs = nullptr;
-            hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
-            hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-            if (err == hipSuccess) err = launch_reset_queue(bt->queue, cs);
-            if (err == hipSuccess && total > 0)
-                err = launch_validate_edge_batch(d_sets, d_eset, (int)recs.size(), total, resolution,
-                                                 qa, qb, collide, bt->queue, grid, block,
-                                                 max_slots, max_dof, cs);
-            hipGraph_t g = nullptr;
-            hipError_t err2 = hipStreamEndCapture(cs, &g);
-            (void)hipStreamDestroy(cs);
-            hip_check(err, "batch capture");
-            hip_check(err2, "hipStreamEndCapture");
-            bt->graph = g;
-            hip_check(hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * blocks_per_cu));
+            bt->block = block_threads;
+            bt->per_cu = blocks_per_cu;
+            // the graph {queue reset -> persistent launch}; run() points the launch's node at
+            // the caller's arrays and replays it
+            fill_node(bt->reset, bt->queue, 0ull, kQueues, kQueueWords);
+            edge_batch_node(bt->launch, d_sets, d_eset, (int)recs.size(), total, resolution,
+                            bt->queue, grid, block, kDefaultTickets, max_slots, max_dof);
+            hip_check(hipGraphCreate(&bt->graph, 0), "hipGraphCreate");
+            const auto params = [](KernelNode &L) {
+                hipKernelNodeParams p{};
+                p.func = const_cast<void *>(L.fn);
+                p.gridDim = L.grid;
+                p.blockDim = L.block;
+                p.sharedMemBytes = (unsigned)L.shmem;
+                p.kernelParams = L.args;
+                p.extra = nullptr;
+                return p;
+            };
+            hipGraphNode_t reset = nullptr;
+            hipKernelNodeParams pr = params(bt->reset);
+            hip_check(hipGraphAddKernelNode(&reset, bt->graph, nullptr, 0, &pr), "graph reset node");
+            if (total > 0) {
+                hipKernelNodeParams pl = params(bt->launch);
+                hip_check(hipGraphAddKernelNode(&bt->walk, bt->graph, &reset, 1, &pl), "graph launch node");
+            }
+            hip_check(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
         } catch (...) {
             if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
             if (bt->graph) (void)hipGraphDestroy(bt->graph);
@@ -1357,9 +1537,28 @@ vk_status vk_edge_batch_create(const vk_robot *robots, int32_t n_robots, const v
     });
 }
 
-vk_status vk_edge_batch_run(vk_edge_batch batch, void *stream) {
+vk_status vk_edge_batch_run(vk_edge_batch batch, const float *qa, const float *qb,
+                            uint8_t *collide, void *stream) {
     return guarded([&] {
         if (!batch) raise(VK_ERR_INVALID_ARG, "batch handle is NULL");
+        if (batch->total > 0) {
+            if (!qa || !qb || !collide) raise(VK_ERR_INVALID_ARG, "NULL edge array");
+            auto &a = batch->launch.batch;
+            if (a.qa != qa || a.qb != qb || a.out != collide) {
+                a.qa = qa;
+                a.qb = qb;
+                a.out = collide;
+                hipKernelNodeParams p{};
+                p.func = const_cast<void *>(batch->launch.fn);
+                p.gridDim = batch->launch.grid;
+                p.blockDim = batch->launch.block;
+                p.sharedMemBytes = (unsigned)batch->launch.shmem;
+                p.kernelParams = batch->launch.args;
+                p.extra = nullptr;
+                hip_check(hipGraphExecKernelNodeSetParams(batch->exec, batch->walk, &p),
+                          "batch arrays update");
+            }
+        }
         hip_check(hipGraphLaunch(batch->exec, (hipStream_t)stream), "hipGraphLaunch");
     });
 }
@@ -1376,45 +1575,221 @@ vk_status vk_edge_batch_destroy(vk_edge_batch batch) {
     });
 }
 
-vk_status vk_set_states_split(int32_t num, int32_t den) {
+vk_status vk_edge_batch_get_launch(vk_edge_batch batch, int32_t *block_threads,
+                                   int32_t *blocks_per_cu) {
+    return guarded([&] {
+        if (!batch) raise(VK_ERR_INVALID_ARG, "batch handle is NULL");
+        if (!block_threads || !blocks_per_cu) raise(VK_ERR_INVALID_ARG, "NULL output");
+        *block_threads = batch->block;
+        *blocks_per_cu = batch->per_cu;
+    });
+}
+
+vk_status vk_reserve(void *stream, int64_t max_states, int64_t max_knn_samples, int32_t max_knn_k) {
+    return guarded([&] {
+        if (max_states < 0 || max_knn_samples < 0 || max_knn_k < 0 || max_knn_k > 32)
+            raise(VK_ERR_INVALID_ARG, "vk_reserve: sizes must be >= 0 and max_knn_k <= 32");
+        if (max_states >= (int64_t(1) << 31) || max_knn_samples >= (int64_t(1) << 31) / 32)
+            raise(VK_ERR_SHAPE, "vk_reserve: sizes too large");
+        hipStream_t s = (hipStream_t)stream;
+        const int dev = current_device();
+        const size_t bytes = reserve_bytes(max_states, max_knn_samples, max_knn_k);
+        std::lock_guard<std::mutex> lk(g_mu);
+        Workspace &w = g_ws[std::make_pair(dev, s)];
+        const bool need_queue = !w.queue, need_scratch = bytes > w.scratch_bytes;
+        if (!need_queue && !need_scratch) return;
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+            raise(VK_ERR_SHAPE, "vk_reserve: the stream is being captured and its workspace must "
+                                "grow; reserve before the capture");
+        if (need_queue) {
+            void *p = nullptr;
+            hip_check(hipMalloc(&p, kQueueBytes), "vk_reserve: queue counters");
+            w.queue = static_cast<unsigned long long *>(p);
+        }
+        if (need_scratch) {
+            void *p = nullptr;
+            hip_check(hipMalloc(&p, bytes), "vk_reserve: scratch");
+            if (w.scratch) w.retired.push_back(w.scratch);   // work or graphs may still use it
+            w.scratch = p;
+            w.scratch_bytes = bytes;
+        }
+    });
+}
+
+vk_status vk_release(void *stream) {
+    return guarded([&] {
+        hipStream_t s = (hipStream_t)stream;
+        const int dev = current_device();
+        Workspace w;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            auto it = g_ws.find(std::make_pair(dev, s));
+            if (it == g_ws.end()) return;
+            w = std::move(it->second);
+            g_ws.erase(it);
+        }
+        hip_check(hipStreamSynchronize(s), "vk_release: stream sync");
+        hipError_t err = hipSuccess;
+        for (void *p : w.retired) err = err != hipSuccess ? err : hipFree(p);
+        if (w.scratch) err = err != hipSuccess ? err : hipFree(w.scratch);
+        if (w.queue) err = err != hipSuccess ? err : hipFree(w.queue);
+        hip_check(err, "vk_release: hipFree");
+    });
+}
+
+vk_status vk_robot_set_states_split(vk_robot robot, int32_t num, int32_t den) {
     return guarded([&] {
         if (num < 0 || den < 1 || num >= den) raise(VK_ERR_INVALID_ARG, "need 0 <= num < den");
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_states_split_num = num;
-        g_states_split_den = den;
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        robot->split_num = num;
+        robot->split_den = den;
     });
 }
 
-vk_status vk_get_states_split(int32_t *num, int32_t *den) {
+vk_status vk_robot_get_states_split(vk_robot robot, int32_t *num, int32_t *den) {
     return guarded([&] {
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
         if (!num || !den) raise(VK_ERR_INVALID_ARG, "NULL output");
-        std::lock_guard<std::mutex> lk(g_mu);
-        *num = g_states_split_num;
-        *den = g_states_split_den;
+        *num = robot->split_num;
+        *den = robot->split_den;
     });
 }
 
-vk_status vk_set_edge_launch(int32_t block_threads, int32_t blocks_per_cu) {
+vk_status vk_robot_set_edge_launch(vk_robot robot, int32_t block_threads, int32_t blocks_per_cu,
+                                   int32_t tickets_per_wave) {
     return guarded([&] {
-        if (block_threads == 0 && blocks_per_cu == 0) {
-            block_threads = 256;
-            blocks_per_cu = 4;
+        if (block_threads == 0 && blocks_per_cu == 0 && tickets_per_wave == 0) {
+            block_threads = kDefaultEdgeBlock;
+            blocks_per_cu = kDefaultEdgeBpc;
+            tickets_per_wave = kDefaultTickets;
         }
-        if (block_threads < 64 || block_threads > 1024 || block_threads % 64)
-            raise(VK_ERR_INVALID_ARG, "block_threads must be a multiple of 64 in [64, 1024]");
-        if (blocks_per_cu < 1 || blocks_per_cu > 64) raise(VK_ERR_INVALID_ARG, "blocks_per_cu must be in [1, 64]");
-        std::lock_guard<std::mutex> lk(g_mu);
-        g_edge_block = block_threads;
-        g_edge_bpc = blocks_per_cu;
+        check_launch(block_threads, blocks_per_cu, tickets_per_wave);
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        robot->edge_block = block_threads;
+        robot->edge_bpc = blocks_per_cu;
+        robot->edge_tickets = tickets_per_wave;
     });
 }
 
-vk_status vk_get_edge_launch(int32_t *block_threads, int32_t *blocks_per_cu) {
+vk_status vk_robot_get_edge_launch(vk_robot robot, int32_t *block_threads, int32_t *blocks_per_cu,
+                                   int32_t *tickets_per_wave) {
     return guarded([&] {
-        if (!block_threads || !blocks_per_cu) raise(VK_ERR_INVALID_ARG, "NULL output");
-        std::lock_guard<std::mutex> lk(g_mu);
-        *block_threads = g_edge_block;
-        *blocks_per_cu = g_edge_bpc;
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        if (!block_threads || !blocks_per_cu || !tickets_per_wave) raise(VK_ERR_INVALID_ARG, "NULL output");
+        *block_threads = robot->edge_block;
+        *blocks_per_cu = robot->edge_bpc;
+        *tickets_per_wave = robot->edge_tickets;
+    });
+}
+
+vk_status vk_autotune_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,
+                            const int32_t *n_states, int64_t n_edges, float resolution,
+                            const char *cache_path, int32_t force, void *stream) {
+    return guarded([&] {
+        check_edge_inputs(robot, env, qa, qb, n_states, n_edges, resolution);
+        if (n_edges == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        const std::string key = tune_key("edges", robot, env, n_edges);
+        TuneCache cache = load_tune_cache(cache_path);
+        auto hit = cache.find(key);
+        if (!force && hit != cache.end()) {
+            const int block = entry_int(hit->second, "block"), bpc = entry_int(hit->second, "per_cu"),
+                      tickets = entry_int(hit->second, "tickets");
+            bool valid = true;
+            try {
+                check_launch(block, bpc, tickets);
+            } catch (const VkError &) {
+                valid = false;                 // a damaged entry: time the workload again
+            }
+            if (valid) {
+                robot->edge_block = block;
+                robot->edge_bpc = bpc;
+                robot->edge_tickets = tickets;
+                return;
+            }
+        }
+        if (vk_reserve(stream, 0, 0, 0) != VK_OK) raise(VK_ERR_OOM, "autotune workspace: " + g_err);
+        uint8_t *flags = nullptr;
+        hip_check(hipMalloc(&flags, (size_t)n_edges), "autotune flags");
+        std::vector<std::array<double, 4>> results;   // ms, block, per_cu, tickets
+        try {
+            const EdgeSrc src{qa, qb, nullptr, 0, n_states};
+            for (int block : {64, 128, 256, 512, 1024})
+                for (int bpc : {1, 2, 4, 8}) {
+                    if (block * bpc > 2048) continue;      // more waves than a CU holds
+                    for (int tickets : {4, 8, 16}) {
+                        robot->edge_block = block;
+                        robot->edge_bpc = bpc;
+                        robot->edge_tickets = tickets;
+                        const double ms = time_median(s, [&] {
+                            run_edges(robot, env, src, n_edges, resolution, flags, nullptr, stream);
+                        });
+                        results.push_back({ms, (double)block, (double)bpc, (double)tickets});
+                    }
+                }
+        } catch (...) {
+            (void)hipFree(flags);
+            throw;
+        }
+        hip_check(hipFree(flags), "hipFree");
+        const auto best = *std::min_element(results.begin(), results.end());
+        robot->edge_block = (int)best[1];
+        robot->edge_bpc = (int)best[2];
+        robot->edge_tickets = (int)best[3];
+        if (cache_path && *cache_path) {
+            TuneCache now = load_tune_cache(cache_path);
+            now[key] = {{"block", best[1]}, {"per_cu", best[2]}, {"tickets", best[3]}, {"ms", best[0]}};
+            save_tune_cache(cache_path, now);
+        }
+    });
+}
+
+vk_status vk_autotune_states(vk_robot robot, vk_env env, const float *q, int64_t n, int64_t ldq,
+                             const char *cache_path, int32_t force, void *stream) {
+    return guarded([&] {
+        check_pair(robot, env);
+        check_batch(n, ldq, q, q, "vk_autotune_states");   // no output array: q stands in
+        if (n == 0) return;
+        hipStream_t s = (hipStream_t)stream;
+        const std::string key = tune_key("states", robot, env, n);
+        TuneCache cache = load_tune_cache(cache_path);
+        auto hit = cache.find(key);
+        if (!force && hit != cache.end()) {
+            const int num = entry_int(hit->second, "num"), den = entry_int(hit->second, "den");
+            if (num >= 0 && den >= 1 && num < den) {   // else a damaged entry: time it again
+                robot->split_num = num;
+                robot->split_den = den;
+                return;
+            }
+        }
+        if (vk_reserve(stream, n, 0, 0) != VK_OK) raise(VK_ERR_OOM, "autotune workspace: " + g_err);
+        uint8_t *flags = nullptr;
+        hip_check(hipMalloc(&flags, (size_t)n), "autotune flags");
+        std::vector<std::array<double, 3>> results;   // ms, num, den
+        try {
+            for (const auto &sp : {std::array<int, 2>{0, 1}, {1, 3}, {1, 2}, {2, 3}}) {
+                robot->split_num = sp[0];
+                robot->split_den = sp[1];
+                const double ms = time_median(s, [&] {
+                    if (validate_states(robot, env, q, n, ldq, flags, stream) != VK_OK)
+                        raise(VK_ERR_HIP, "autotune: " + g_err);
+                });
+                results.push_back({ms, (double)sp[0], (double)sp[1]});
+            }
+        } catch (...) {
+            (void)hipFree(flags);
+            throw;
+        }
+        hip_check(hipFree(flags), "hipFree");
+        const auto best = *std::min_element(results.begin(), results.end());
+        robot->split_num = (int)best[1];
+        robot->split_den = (int)best[2];
+        if (cache_path && *cache_path) {
+            TuneCache now = load_tune_cache(cache_path);
+            now[key] = {{"num", best[1]}, {"den", best[2]}, {"ms", best[0]}};
+            save_tune_cache(cache_path, now);
+        }
     });
 }
 

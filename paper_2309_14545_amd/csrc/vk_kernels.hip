@@ -1818,6 +1818,14 @@ size_t knn_workspace_bytes(int64_t n, int k) {
     return (size_t)knn_parts(n) * n * knn_list_len(k) * (sizeof(int32_t) + sizeof(float));
 }
 
+// parts(n) <= ceil(2048 / ceil(n / 64)) <= 2048 * 64 / n + 1, so parts(n) * n <= 131072 + n; a
+// count below 64 has one part
+size_t knn_workspace_bound(int64_t max_n, int k) {
+    if (max_n <= 0) return 0;
+    const int64_t pn = std::max<int64_t>(64, 2048 * (int64_t)kWave + max_n);
+    return (size_t)pn * knn_list_len(k) * (sizeof(int32_t) + sizeof(float));
+}
+
 hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, float *d2,
                       void *workspace, hipStream_t s) {
     const int parts = knn_parts(n), K = knn_list_len(k);
@@ -1917,25 +1925,22 @@ hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Items per ticket of a persistent launch: about VK_TICKETS_PER_WAVE tickets per wave keeps the
-// dynamic balance fine while bounding the number of queue atomics.
-#ifndef VK_TICKETS_PER_WAVE
-#define VK_TICKETS_PER_WAVE 8
-#endif
-static int work_chunk(int64_t n_items, int grid, int block) {
+// Items per ticket of a persistent launch: about `tickets` tickets per wave (a launch setting,
+// 8 by default) keeps the dynamic balance fine while bounding the number of queue atomics.
+static int work_chunk(int64_t n_items, int grid, int block, int tickets) {
     const int64_t waves = (int64_t)grid * (block / kWave);
-    const int64_t c = n_items / (waves * VK_TICKETS_PER_WAVE);
+    const int64_t c = n_items / (waves * std::max(tickets, 1));
     return (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
 }
 
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,
-                                 unsigned long long *queue, int grid, int block, hipStream_t s,
-                                 unsigned long long *flops) {
+                                 unsigned long long *queue, int grid, int block, int tickets,
+                                 hipStream_t s, unsigned long long *flops) {
     const dim3 grid_(grid), block_(block);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, block, c); };
     const size_t max_lds_ = device_max_lds();
-    const int chunk = work_chunk(n_edges, grid, block);
+    const int chunk = work_chunk(n_edges, grid, block, tickets);
 #define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, cf
     if (flops) {
         VK_STAGED(k_validate_edges, , true)
@@ -1987,10 +1992,21 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float 
 }
 #undef VK_STAGED
 
-hipError_t launch_validate_edge_batch(const BatchSet *sets, const int32_t *edge_set, int n_sets,
-                                      int64_t total, float res, const float *qa, const float *qb,
-                                      uint8_t *out, unsigned long long *queue, int grid, int block,
-                                      int max_slots, int max_dof, hipStream_t s) {
+void fill_node(KernelNode &L, unsigned long long *p, unsigned long long v, int n, int stride) {
+    L.fn = reinterpret_cast<const void *>(&k_fill_u64);
+    L.grid = dim3(1);
+    L.block = dim3(64);
+    L.shmem = 0;
+    L.fill = {p, v, n, stride};
+    L.args[0] = &L.fill.p;
+    L.args[1] = &L.fill.v;
+    L.args[2] = &L.fill.n;
+    L.args[3] = &L.fill.stride;
+}
+
+void edge_batch_node(KernelNode &L, const BatchSet *sets, const int32_t *edge_set, int n_sets,
+                     int64_t total, float res, unsigned long long *queue, int grid, int block,
+                     int tickets, int max_slots, int max_dof) {
     // cache parts as for the other walks (no staging here: the records change per set)
     const void *k = reinterpret_cast<const void *>(&k_validate_edge_batch);
     const size_t waves = (size_t)(block / kWave), max_lds = device_max_lds();
@@ -2006,10 +2022,35 @@ hipError_t launch_validate_edge_batch(const BatchSet *sets, const int32_t *edge_
         }
     }
     const int floats = step_cache_floats(max_slots, max_dof, cf);
-    hipLaunchKernelGGL(k_validate_edge_batch, dim3(grid), dim3(block), waves * floats * sizeof(float),
-                       s, sets, edge_set, n_sets, total, res, qa, qb, out, queue,
-                       work_chunk(total, grid, block), floats, cf);
-    return hipGetLastError();
+    L.fn = k;
+    L.grid = dim3(grid);
+    L.block = dim3(block);
+    L.shmem = waves * floats * sizeof(float);
+    auto &a = L.batch;
+    a.sets = sets;
+    a.edge_set = edge_set;
+    a.n_sets = n_sets;
+    a.total = total;
+    a.res = res;
+    a.qa = a.qb = nullptr;
+    a.out = nullptr;
+    a.queue = queue;
+    a.chunk = work_chunk(total, grid, block, tickets);
+    a.floats = floats;
+    a.cf = cf;
+    void **v = L.args;
+    v[0] = &a.sets;
+    v[1] = &a.edge_set;
+    v[2] = &a.n_sets;
+    v[3] = &a.total;
+    v[4] = &a.res;
+    v[5] = &a.qa;
+    v[6] = &a.qb;
+    v[7] = &a.out;
+    v[8] = &a.queue;
+    v[9] = &a.chunk;
+    v[10] = &a.floats;
+    v[11] = &a.cf;
 }
 
 }  // namespace vk

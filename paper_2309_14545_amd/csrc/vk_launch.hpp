@@ -19,14 +19,17 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const fl
 hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s);
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,
-                                 unsigned long long *queue, int grid, int block, hipStream_t s,
-                                 unsigned long long *flops = nullptr);
+                                 unsigned long long *queue, int grid, int block, int tickets,
+                                 hipStream_t s, unsigned long long *flops = nullptr);
 hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                     int64_t e, float res, uint8_t *out, hipStream_t s);
 // kNN runs as partial lists over candidate parts plus a merge; the partial lists need a
 // workspace of knn_workspace_bytes(n, k) bytes.
 int knn_parts(int64_t n);
 size_t knn_workspace_bytes(int64_t n, int k);
+// An upper bound of knn_workspace_bytes(n, k) over every n <= max_n (the part count falls as n
+// grows, so the bytes are not monotone in n).
+size_t knn_workspace_bound(int64_t max_n, int k);
 hipError_t launch_knn(const float *x, int64_t n, int dim, int k, int32_t *idx, float *d2,
                       void *workspace, hipStream_t s);
 hipError_t launch_knn_pairs(const int32_t *idx, int64_t n, int k, int32_t *pairs, hipStream_t s);
@@ -63,9 +66,36 @@ hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
                            int block, hipStream_t s);
 
-hipError_t launch_validate_edge_batch(const BatchSet *sets, const int32_t *edge_set, int n_sets,
-                                      int64_t total, float res, const float *qa, const float *qb,
-                                      uint8_t *out, unsigned long long *queue, int grid, int block,
-                                      int max_slots, int max_dof, hipStream_t s);
+// A kernel launch spelled out for a graph node: the kernel, its shape and its argument values
+// (args[i] points at the i-th value held in the node itself, so a node must not be copied
+// after it is filled).
+struct KernelNode {
+    const void *fn = nullptr;
+    dim3 grid, block;
+    size_t shmem = 0;
+    struct {
+        unsigned long long *p;
+        unsigned long long v;
+        int n, stride;
+    } fill{};
+    struct {                        // k_validate_edge_batch's arguments, in order
+        const BatchSet *sets;
+        const int32_t *edge_set;
+        int n_sets;
+        int64_t total;
+        float res;
+        const float *qa, *qb;
+        uint8_t *out;
+        unsigned long long *queue;
+        int chunk, floats, cf;
+    } batch{};
+    void *args[12] = {};
+};
+// The queue reset of a persistent launch as a node: writes v to n counters `stride` words apart.
+void fill_node(KernelNode &L, unsigned long long *p, unsigned long long v, int n, int stride);
+// The mixed-robot persistent launch as a node; the caller sets batch.qa, .qb and .out.
+void edge_batch_node(KernelNode &L, const BatchSet *sets, const int32_t *edge_set, int n_sets,
+                     int64_t total, float res, unsigned long long *queue, int grid, int block,
+                     int tickets, int max_slots, int max_dof);
 
 }  // namespace vk

@@ -15,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import rrt_commit, rrt_extend, validate_edges
+from . import reserve, rrt_commit, rrt_extend, validate_edges
 
 
 def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
@@ -70,13 +70,7 @@ def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
     run = launch
     if graphs:
         side = torch.cuda.Stream(device=dev)
-        side.wait_stream(torch.cuda.current_stream(dev))
-        with torch.cuda.stream(side):
-            # the library allocates a stream's work-queue counters at its first edge launch on
-            # that stream: do it before capturing on the stream
-            root = nodes[0, :1, 0]
-            validate_edges(robot, env, root, root, resolution=resolution, out=flags[:1])
-        torch.cuda.current_stream(dev).wait_stream(side)
+        reserve(stream=side)              # the edge launch's work-queue counters on that stream
         captured = {}
         for t in (0, 1):
             for r in (0, 1):

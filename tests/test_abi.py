@@ -141,23 +141,31 @@ def test_null_handles_rejected(vk):
     assert lib.penetration_cost_fwd(None, None, None, 0, 0, None, None) == -1
     assert lib.vk_robot_destroy(None) == -1
     assert lib.vk_env_destroy(None) == -1
-    assert lib.vk_edge_batch_run(None, None) == -1
+    assert lib.vk_edge_batch_run(None, None, None, None, None) == -1
+    assert lib.vk_robot_set_edge_launch(None, 256, 4, 8) == -1
+    assert lib.vk_autotune_edges(None, None, None, None, None, 0, C.c_float(0.03), None, 0, None) == -1
     assert b"NULL" in lib.vk_last_error()
 
 
 def test_launch_configuration_checks(vk):
+    """Launch settings are checked before the handle: invalid values are named as such."""
     lib = vk.lib()
-    assert lib.vk_set_edge_launch(100, 4) == -1
-    assert lib.vk_set_edge_launch(128, 0) == -1
-    assert lib.vk_set_edge_launch(1088, 1) == -1
-    assert lib.vk_set_edge_launch(1024, 2) == 0
-    assert vk.get_edge_launch() == (1024, 2)
-    assert lib.vk_set_edge_launch(128, 3) == 0
-    assert vk.get_edge_launch() == (128, 3)
-    assert lib.vk_set_edge_launch(0, 0) == 0
-    assert vk.get_edge_launch() == (256, 4)
-    assert lib.vk_set_states_split(1, 1) == -1
-    assert lib.vk_set_states_split(-1, 2) == -1
-    assert lib.vk_set_states_split(2, 3) == 0
-    assert vk.get_states_split() == (2, 3)
-    assert lib.vk_set_states_split(0, 1) == 0
+    for args in ((100, 4, 8), (128, 0, 8), (1088, 1, 8), (256, 4, 0), (256, 4, 65), (64, 65, 8)):
+        assert lib.vk_robot_set_edge_launch(None, *args) == -1
+        assert b"robot handle" not in lib.vk_last_error(), args
+    for args in ((1024, 2, 8), (128, 3, 1), (0, 0, 0)):
+        assert lib.vk_robot_set_edge_launch(None, *args) == -1
+        assert b"robot handle" in lib.vk_last_error(), args
+    for num, den in ((1, 1), (-1, 2), (0, 0)):
+        assert lib.vk_robot_set_states_split(None, num, den) == -1
+        assert b"num < den" in lib.vk_last_error()
+    assert lib.vk_robot_set_states_split(None, 2, 3) == -1
+    assert b"robot handle" in lib.vk_last_error()
+
+
+def test_reserve_argument_checks(vk):
+    lib = vk.lib()
+    assert lib.vk_reserve(None, -1, 0, 0) == -1
+    assert lib.vk_reserve(None, 0, -5, 0) == -1
+    assert lib.vk_reserve(None, 0, 100, 33) == -1
+    assert lib.vk_reserve(None, 1 << 31, 0, 0) == -2

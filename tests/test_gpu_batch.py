@@ -30,11 +30,11 @@ def test_batch_parity_and_replays(vk, orc):
     robots, envs, sets, qa, qb, total = _pack(vk, w, max_edges=60)
     out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
     say("edge batch sets", len(sets), "edges", total)
-    batch = vk.EdgeBatch(robots, envs, sets, qa, qb, out)
+    batch = vk.EdgeBatch(robots, envs, sets)
     results = []
     for rep in range(3):
         out.fill_(7)
-        batch.run()
+        batch.run(qa, qb, out)
         results.append(host(out).copy())
         # eager work between replays
         torch.cuda.synchronize()
@@ -60,6 +60,38 @@ def test_batch_parity_and_replays(vk, orc):
     assert bad_total == 0
 
 
+def test_batch_new_arrays_each_run(vk):
+    """One batch replayed on other arrays: every run validates the edges and writes the flags of
+    the arrays it is given (the graph's launch is re-pointed), alternating between two sets of
+    endpoints and two flag buffers, with eager work between runs."""
+    import torch
+    w = workload("mixed", n=16)
+    robots, envs, sets, qa, qb, total = _pack(vk, w, max_edges=50)
+    # the second endpoints: each edge cut to its first twentieth (mostly free where the full
+    # edges mostly collide), in new buffers
+    qa2, qb2 = qa.clone(), qa + 0.05 * (qb - qa)
+    batch = vk.EdgeBatch(robots, envs, sets)
+    outs = [torch.full((total,), 7, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    want = []
+    for a, b in ((qa, qb), (qa2, qb2)):
+        flags = np.zeros(total, np.uint8)
+        ah, bh = host(a), host(b)
+        for (ri, ei, off, ne, oo) in sets:
+            dof = w["robots"][ri]["dof"]
+            flags[oo:oo + ne] = host(vk.validate_edges(
+                robots[ri], envs[ei], dev(ah[off:off + ne * dof].reshape(ne, dof)),
+                dev(bh[off:off + ne * dof].reshape(ne, dof))))
+        want.append(flags)
+    say("new-arrays batch: collision rates", want[0].mean(), want[1].mean())
+    assert not np.array_equal(want[0], want[1])
+    for rep in range(4):
+        k = rep % 2
+        outs[k].fill_(7)
+        batch.run(*((qa, qb) if k == 0 else (qa2, qb2)), outs[k])
+        np.testing.assert_array_equal(host(outs[k]), want[k])
+        _ = (qa * 2).sum().item()
+
+
 def test_empty_batch(vk):
     import torch
     w = workload("mixed", n=2)
@@ -67,8 +99,8 @@ def test_empty_batch(vk):
     envs = [vk.Env(e) for e in w["envs"]]
     out = torch.zeros(1, dtype=torch.uint8, device="cuda")
     z = torch.zeros(1, device="cuda")
-    b = vk.EdgeBatch(robots, envs, [], z, z, out)
-    b.run()
+    b = vk.EdgeBatch(robots, envs, [])
+    b.run(z, z, out)
     torch.cuda.synchronize()
 
 
@@ -97,10 +129,10 @@ def test_batch_with_limit_robots(vk, orc):
     qa, qb, sets, total = pack_edge_sets(w)
     qa_d, qb_d = dev(qa), dev(qb)
     out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
-    batch = vk.EdgeBatch(robots, envs, sets, qa_d, qb_d, out)
-    batch.run()
+    batch = vk.EdgeBatch(robots, envs, sets)
+    batch.run(qa_d, qb_d, out)
     flags = host(out).copy()
-    batch.run()                                  # a second replay gives the same flags
+    batch.run(qa_d, qb_d, out)                   # a second replay gives the same flags
     np.testing.assert_array_equal(host(out), flags)
     bad_total = 0
     for k, (ri, ei, off, ne, oo) in enumerate(sets):
@@ -126,14 +158,14 @@ def test_batch_full_size_sampled(vk, orc):
     qa_h, qb_h, sets, total = pack_edge_sets(w)
     qa, qb = dev(qa_h), dev(qb_h)
     out = torch.full((total,), 7, dtype=torch.uint8, device="cuda")
-    batch, tuned = autotune.tune_batch(lambda: vk.EdgeBatch(robots, envs, sets, qa, qb, out))
+    batch, tuned = autotune.tune_batch(robots, envs, sets, qa, qb, out)
+    assert batch.launch() == (tuned["block"], tuned["per_cu"])
     say(f"mixed batch full size: {len(sets)} sets, {total} edges, launch {tuned}")
     out.fill_(7)
-    batch.run()
+    batch.run(qa, qb, out)
     flags = host(out).copy()
-    batch.run()
+    batch.run(qa, qb, out)
     np.testing.assert_array_equal(host(out), flags)
-    vk.set_edge_launch(0, 0)
     assert set(np.unique(flags)) <= {0, 1}
     g = np.random.default_rng(17)
     owner = np.concatenate([np.full(ne, k) for k, (_, _, _, ne, _) in enumerate(sets)])

@@ -17,7 +17,6 @@ def vk():
     import paper_2309_14545_amd as vk
     vk.lib()
     yield vk
-    vk.set_edge_launch(0, 0)
 
 
 @pytest.mark.parametrize("name", ["edges7_shelf", "edges8_shelf", "edges8p_shelf"])
@@ -68,11 +67,11 @@ def test_schedule_invariance(vk):
     r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
     qa, qb = dev(w["qa"]), dev(w["qb"])
     ref = host(vk.validate_edges(r, e, qa, qb, per_edge=True))
-    for block, bpc in ((64, 1), (128, 3), (256, 8), (192, 2), (256, 1), (512, 4), (1024, 2), (960, 1)):
-        say("launch", block, bpc)
-        vk.set_edge_launch(block, bpc)
+    for block, bpc, tickets in ((64, 1, 8), (128, 3, 1), (256, 8, 16), (192, 2, 4), (256, 1, 64),
+                                (512, 4, 8), (1024, 2, 8), (960, 1, 3)):
+        say("launch", block, bpc, tickets)
+        r.set_edge_launch(block, bpc, tickets)
         np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb)), ref)
-    vk.set_edge_launch(0, 0)
 
 
 def test_small_batch_launch_shapes(vk):
@@ -83,14 +82,13 @@ def test_small_batch_launch_shapes(vk):
     r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
     qa, qb = w["qa"], w["qb"]
     for block, bpc in ((1024, 2), (256, 8)):
-        vk.set_edge_launch(block, bpc)
+        r.set_edge_launch(block, bpc, 8)
         full = host(vk.validate_edges(r, e, dev(qa), dev(qb)))
         assert 0 < full.mean() < 1
         for E in (1, 2, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 4095, 4096, 4097):
             say("launch", block, bpc, "edges", E)
             got = host(vk.validate_edges(r, e, dev(qa[:E]), dev(qb[:E])))
             np.testing.assert_array_equal(got, full[:E])
-    vk.set_edge_launch(0, 0)
 
 
 def test_explicit_state_counts(vk, orc):

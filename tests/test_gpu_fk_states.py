@@ -186,11 +186,8 @@ def test_self_only_states_parity(vk, orc, name):
     cmin, _ = orc.states(robot, {}, q)
     r, e = vk.Robot(robot), vk.Env({})
     for split in ((0, 1), (1, 2)):
-        vk.set_states_split(*split)
-        try:
-            flags = host(vk.validate_states(r, e, dev(q)))
-        finally:
-            vk.set_states_split(0, 1)
+        r.set_states_split(*split)
+        flags = host(vk.validate_states(r, e, dev(q)))
         bad, near = state_mismatches(flags, cmin)
         say(f"self-only states {name} split {split}: mismatches {bad}, near {near}, "
             f"rate {flags.mean():.3f}")
@@ -229,12 +226,9 @@ def test_two_pass_schedule_matches_one_pass(vk, name):
     robot, env, q = _state_case(name)
     r, e = vk.Robot(robot), vk.Env(env)
     qd = dev(q)
-    vk.set_states_split(0, 1)
     ref = host(vk.validate_states(r, e, qd))
-    try:
-        for num, den in ((1, 3), (1, 2), (2, 3), (9, 10)):
-            vk.set_states_split(num, den)
-            np.testing.assert_array_equal(host(vk.validate_states(r, e, qd)), ref)
-            np.testing.assert_array_equal(host(vk.validate_states(r, e, qd[:, :77])), ref[:77])
-    finally:
-        vk.set_states_split(0, 1)
+    assert r.get_states_split() == (0, 1)
+    for num, den in ((1, 3), (1, 2), (2, 3), (9, 10)):
+        r.set_states_split(num, den)
+        np.testing.assert_array_equal(host(vk.validate_states(r, e, qd)), ref)
+        np.testing.assert_array_equal(host(vk.validate_states(r, e, qd[:, :77])), ref[:77])
