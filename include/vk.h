@@ -131,6 +131,20 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
                           uint8_t *collide, void *stream);
 
 /*
+ * validate_states for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same flags from the same kernels, always
+ * in the two-pass schedule (the robot's split, else half of its link steps; a one-step robot
+ * runs one pass), with the survivor list in a fixed scratch array compiled into the library
+ * (16 MiB + 256 B per GPU, held until the process ends) instead of the stream's workspace.  It
+ * needs no vk_reserve and calls no allocating routine.  n may be at most 4,194,304 (2^22),
+ * else VK_ERR_SHAPE.  Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (on different streams, or from several threads) race and must be ordered by the
+ * caller.  Other errors as validate_states.
+ */
+vk_status validate_states_noalloc(vk_robot robot, vk_env env, const float *q, int64_t n,
+                                  int64_t ldq, uint8_t *collide, void *stream);
+
+/*
  * Collision flag of n_edges straight joint-space motions (Sec. III-D).  Edge e from qa to qb is
  * discretised into n_e states q_k = qa + k/(n_e-1) (qb - qa), k = 0..n_e-1, both endpoints
  * included, with n_e = n_states[e] if n_states is given, else

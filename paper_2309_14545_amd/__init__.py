@@ -22,7 +22,8 @@ _STATUS = {-1: "VK_ERR_INVALID_ARG", -2: "VK_ERR_SHAPE", -3: "VK_ERR_UNSUPPORTED
            -4: "VK_ERR_HIP", -5: "VK_ERR_OOM"}
 
 EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_spheres",
-           "vk_env_create", "vk_env_destroy", "vk_edge_states", "fk_spheres", "validate_states", "validate_edges",
+           "vk_env_create", "vk_env_destroy", "vk_edge_states", "fk_spheres", "validate_states",
+           "validate_states_noalloc", "validate_edges",
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
            "vk_knn", "vk_knn_pairs", "vk_tree_nearest", "vk_tree_steer", "vk_tree_append",
            "vk_rrt_extend", "vk_rrt_commit",
@@ -84,6 +85,7 @@ def lib():
         L.vk_edge_states.restype = i64
         L.fk_spheres.argtypes = [vp, vp, i64, i64, vp, i64, vp]
         L.validate_states.argtypes = [vp, vp, vp, i64, i64, vp, vp]
+        L.validate_states_noalloc.argtypes = [vp, vp, vp, i64, i64, vp, vp]
         L.validate_edges.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp]
         L.validate_edges_per_edge.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp]
         L.validate_edges_counted.argtypes = [vp, vp, vp, vp, vp, i64, fp, vp, vp, vp]
@@ -290,6 +292,16 @@ def validate_states(robot: Robot, env: Env, q):
         reserve(states=n)
     _check(lib().validate_states(robot.handle, env.handle, q.data_ptr(), n, n, out.data_ptr(),
                                  _stream()))
+    return out
+
+
+def validate_states_noalloc(robot: Robot, env: Env, q, out):
+    """validate_states into the caller's uint8 [N] tensor ``out``, allocating nothing (the
+    two-pass schedule with the library's fixed scratch array; N <= 2^22)."""
+    q = _soa(robot, q)
+    n = q.shape[1]
+    _check(lib().validate_states_noalloc(robot.handle, env.handle, q.data_ptr(), n, n,
+                                         out.data_ptr(), _stream()))
     return out
 
 

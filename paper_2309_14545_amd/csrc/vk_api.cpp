@@ -1183,6 +1183,27 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
     });
 }
 
+vk_status validate_states_noalloc(vk_robot robot, vk_env env, const float *q, int64_t n,
+                                  int64_t ldq, uint8_t *collide, void *stream) {
+    return guarded([&] {
+        check_pair(robot, env);
+        check_batch(n, ldq, q, collide, "validate_states_noalloc");
+        if (n > noalloc_max_states())
+            raise(VK_ERR_SHAPE, "validate_states_noalloc: n above its maximum of " +
+                                    std::to_string(noalloc_max_states()) + " states");
+        if (n == 0) return;
+        // the two-pass schedule: the robot's split, else half of its link steps
+        int split = states_split(robot->dev, n, robot->split_num.load(), robot->split_den.load());
+        if (split == 0) split = states_split(robot->dev, n, 1, 2);
+        void *scratch = nullptr;
+        if (split > 0) hip_check(noalloc_scratch(&scratch), "validate_states_noalloc scratch");
+        hip_check(launch_validate_states(robot->dev,
+                                         env_for_launch(env, walk_lds_bytes(robot->dev, walk_block(robot->dev, 256))), q, n,
+                                         ldq, collide, split, scratch, (hipStream_t)stream),
+                  "validate_states_noalloc launch");
+    });
+}
+
 static void check_edge_inputs(vk_robot robot, vk_env env, const float *qa, const float *qb,
                               const int32_t *n_states, int64_t n_edges, float resolution) {
     check_pair(robot, env);

@@ -1779,6 +1779,35 @@ int states_split(const RobotDev &rb, int64_t n, int num, int den) {
 
 size_t states_scratch_bytes(int64_t n) { return 256 + (size_t)n * sizeof(int32_t); }
 
+// Scratch of the allocation-free state validation: the survivor counter and list of up to
+// kNoAllocStates states, in a file-scope device array that each GPU the library runs on holds
+// until the process ends.  Host code never uses the array's name as an address (on the host it
+// names a stand-in, not device memory): noalloc_scratch() looks up each device's own address
+// once, with that device current, and hands that out.
+constexpr int64_t kNoAllocStates = int64_t(1) << 22;
+constexpr size_t kNoAllocBytes = 256 + (size_t)kNoAllocStates * sizeof(int32_t);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+int64_t noalloc_max_states() { return kNoAllocStates; }
+
+hipError_t noalloc_scratch(void **ptr) {
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess) return err;
+        it = addr.emplace(dev, p).first;
+    }
+    *ptr = it->second;
+    return hipSuccess;
+}
+
 hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
                                   int64_t ldq, uint8_t *out, int split, void *scratch,
                                   hipStream_t s) {

@@ -16,6 +16,10 @@ size_t states_scratch_bytes(int64_t n);
 hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const float *q, int64_t n,
                                   int64_t ldq, uint8_t *out, int split, void *scratch,
                                   hipStream_t s);
+// The allocation-free form's scratch (a file-scope device array, states_scratch_bytes of up to
+// noalloc_max_states() states): its address on the current device, looked up once per device.
+int64_t noalloc_max_states();
+hipError_t noalloc_scratch(void **ptr);
 hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s);
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,
