@@ -65,7 +65,10 @@ def state_counts(qa, qb, res):
     return np.maximum(2, np.ceil(L / res) + 1).astype(np.int64)
 
 
-def cpu_baseline(w, budget_s=12.0):
+def cpu_baseline(w, gpu_flags, budget_s=12.0, single_budget_s=4.0):
+    """The FP64 oracle on the first 2^k edges (all host threads, then one thread), and the GPU
+    flags of those edges checked against its classes: mismatches outside the near-contact band
+    and the near-contact count."""
     from oracle import oracle as O
     rb, ev = O.Robot(w["robot"]), O.Env(w["env"])
     threads = O.threads(0)
@@ -74,16 +77,38 @@ def cpu_baseline(w, budget_s=12.0):
     while True:
         idx = np.arange(min(n, E))
         t0 = time.perf_counter()
-        O.edges(rb, ev, w["qa"][idx], w["qb"][idx], res=RES, early=True, n_threads=threads)
+        _, cls, _ = O.edges(rb, ev, w["qa"][idx], w["qb"][idx], res=RES, early=True,
+                            n_threads=threads)
         dt = time.perf_counter() - t0
         if dt >= budget_s / 3 or len(idx) == E:
             break
         n *= 2
     states = int(state_counts(w["qa"][idx], w["qb"][idx], RES).sum())
     log(f"cpu oracle: {len(idx)} edges, {states} states in {dt:.2f}s on {threads} threads")
+    gpu = np.asarray(gpu_flags[idx]).astype(np.int64)
+    bad = int((((cls == 0) & (gpu != 0)) | ((cls == 1) & (gpu != 1))).sum())
+    parity = {"edges_checked": int(len(idx)), "mismatches_outside_band": bad,
+              "near_contact_edges": int((cls == 2).sum()), "band_m": 1e-4,
+              "reference": "FP64 oracle, edge classes free / colliding / near contact"}
+    log(f"parity on {len(idx)} edges: {bad} mismatches outside the band, "
+        f"{parity['near_contact_edges']} near-contact edges")
+    m = 64
+    while True:                           # one thread, a smaller sample
+        sidx = np.arange(min(m, E))
+        t0 = time.perf_counter()
+        O.edges(rb, ev, w["qa"][sidx], w["qb"][sidx], res=RES, early=True, n_threads=1)
+        sdt = time.perf_counter() - t0
+        if sdt >= single_budget_s / 3 or len(sidx) == E:
+            break
+        m *= 2
+    sstates = int(state_counts(w["qa"][sidx], w["qb"][sidx], RES).sum())
+    log(f"cpu oracle, one thread: {len(sidx)} edges, {sstates} states in {sdt:.2f}s")
     return {"value": states / dt, "unit": "states/s", "cores": threads, "kind": "oracle",
             "sample": f"first {len(idx)} of the {E} edges ({states} nominal states), FP64 scalar "
-                      f"oracle with first-hit stop per edge, {threads} threads, {dt:.2f} s"}
+                      f"oracle with first-hit stop per edge, {threads} threads, {dt:.2f} s",
+            "single_thread": {"value": sstates / sdt, "unit": "states/s", "cores": 1,
+                              "sample": f"first {len(sidx)} edges ({sstates} nominal states), "
+                                        f"{sdt:.2f} s"}}, parity
 
 
 def _events_ms(fn, steps):
@@ -98,6 +123,22 @@ def _events_ms(fn, steps):
     return [a.elapsed_time(b) for a, b in ev]
 
 
+FLOP_KEYS = ("fk", "cull", "fine", "self", "repose", "surplus")
+
+
+def counted_work(vk, robot, env, qa, qb, out):
+    """FP32 work of one launch from the instrumented kernel: the method's own (FK, culling, fine
+    tests, self pairs), what the implementation adds (re-posing, surplus rake lanes), and the
+    rake slots of real states walked."""
+    import torch
+    f = torch.zeros(8, dtype=torch.int64, device="cuda")
+    vk.validate_edges_counted(robot, env, qa, qb, f, resolution=RES, out=out)
+    fl = [int(x) for x in f.cpu().tolist()]
+    assert fl[0] == sum(fl[1:7])
+    return {"executed": fl[0], "method": sum(fl[1:5]), "breakdown": dict(zip(FLOP_KEYS, fl[1:7])),
+            "rake_slots": fl[7]}
+
+
 def extra_edges(vk, name, steps):
     import torch
     from synthetic import workload
@@ -107,19 +148,43 @@ def extra_edges(vk, name, steps):
     qa, qb = torch.from_numpy(w["qa"]).cuda(), torch.from_numpy(w["qb"]).cuda()
     out = torch.empty(len(w["qa"]), dtype=torch.uint8, device="cuda")
     tune = autotune.tune_edges(robot, env, qa, qb, resolution=RES, cache=None)
-    flops_t = torch.zeros(5, dtype=torch.int64, device="cuda")
-    vk.validate_edges_counted(robot, env, qa, qb, flops_t, resolution=RES, out=out)
+    work = counted_work(vk, robot, env, qa, qb, out)
     vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out)
     torch.cuda.synchronize()
     ms = _events_ms(lambda: vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out), steps)
     nominal = int(state_counts(w["qa"], w["qb"], RES).sum())
     m = float(np.mean(ms))
-    flops = int(flops_t[0].item())
     return {"workload": name, "states_per_s": nominal / (m * 1e-3), "launch_ms": m,
             "nominal_states": nominal, "edge_collision_rate": float(out.float().mean().item()),
-            "executed_tflops": flops / (m * 1e-3) / 1e12,
-            "frac_fp32_peak": flops / (m * 1e-3) / PEAK_FP32,
+            "scene": scene_summary_of(w),
+            "method_tflops": work["method"] / (m * 1e-3) / 1e12,
+            "frac_fp32_peak": work["method"] / (m * 1e-3) / PEAK_FP32,
+            "executed_tflops": work["executed"] / (m * 1e-3) / 1e12,
             "launch": list(tune)}
+
+
+def scene_summary_of(w):
+    from synthetic import scene_summary
+    return scene_summary(w["env"])
+
+
+def extra_fk(vk, name, n, steps):
+    """fk_spheres of n states of the workload's robot: HBM-write-bound (every centre is stored);
+    GB/s of the q read plus the centres written."""
+    import torch
+    from synthetic import workload
+    w = workload(name, n=n)
+    robot = vk.Robot(w["robot"])
+    q = torch.from_numpy(w["q"]).cuda()
+    out = vk.fk_spheres(robot, q)
+    torch.cuda.synchronize()
+    ms = _events_ms(lambda: vk.fk_spheres(robot, q), steps)
+    m = float(np.median(ms))
+    nbytes = q.numel() * 4 + out.numel() * 4
+    return {"workload": f"fk_spheres {name}", "states": n, "spheres": robot.n_spheres,
+            "median_ms": m, "states_per_s": n / (m * 1e-3),
+            "bytes_per_launch": nbytes, "hbm_gb_per_s": nbytes / (m * 1e-3) / 1e9,
+            "frac_hbm_peak": nbytes / (m * 1e-3) / 8.0e12}
 
 
 def extra_states(vk, name, n, steps):
@@ -136,7 +201,7 @@ def extra_states(vk, name, n, steps):
     m = float(np.median(ms))
     return {"workload": name, "states": q.shape[1], "states_per_s": q.shape[1] / (m * 1e-3),
             "median_ms": m, "collision_rate": float(out.float().mean().item()),
-            "schedule_split": tuned["split"]}
+            "schedule_split": list(tuned)}
 
 
 def extra_cost(vk, steps):
@@ -324,15 +389,13 @@ def main():
         autotune.tune_edges(robot, env, qa, qb, resolution=RES, cache=None)
         log(f"autotuned launch: block, per CU, tickets per wave {robot.get_edge_launch()}")
 
-    # executed FP32 work of one launch (instrumented variant, untimed)
-    flops_t = torch.zeros(5, dtype=torch.int64, device="cuda")
-    vk.validate_edges_counted(robot, env, qa, qb, flops_t, resolution=RES, out=out)
+    # FP32 work of one launch (instrumented variant of the same kernel, untimed)
+    work = counted_work(vk, robot, env, qa, qb, out)
     torch.cuda.synchronize()
-    fl = [int(x) for x in flops_t.cpu().tolist()]
-    flops = fl[0]
-    breakdown = dict(zip(("fk", "cull", "fine", "self"), fl[1:]))
-    log(f"executed FLOP per launch {flops:.4e}: " +
-        ", ".join(f"{k} {100.0 * v / max(flops, 1):.1f}%" for k, v in breakdown.items()))
+    flops = work["method"]
+    log(f"FLOP per launch: method {flops:.4e}, executed {work['executed']:.4e}: " +
+        ", ".join(f"{k} {100.0 * v / max(work['executed'], 1):.1f}%"
+                  for k, v in work["breakdown"].items()))
     flags_counted = out.cpu().numpy().copy()
 
     for _ in range(args.warmup):
@@ -409,13 +472,21 @@ def main():
             "traffic_unit": "B per launch",
             "kernel": "k_validate_edges (persistent)",
             "flop_per_launch": flops,
-            "flop_breakdown": breakdown,
+            "flop_counted": "the method's own FLOPs (FK and placement, culling, fine tests, "
+                            "self pairs), without re-posing and surplus rake lanes",
+            "executed": {"flop_per_launch": work["executed"],
+                         "achieved": work["executed"] / (launch_ms * 1e-3) / 1e12,
+                         "frac": work["executed"] / (launch_ms * 1e-3) / PEAK_FP32},
+            "flop_breakdown": work["breakdown"],
+            "rake_slots_per_launch": work["rake_slots"],
             "launch_ms": launch_ms,
         },
     }
     if not args.no_extras:
         extra = {}
         for key, fn in (("edges8_shelf", lambda: extra_edges(vk, "edges8_shelf", 10)),
+                        ("edges7_shelf_near", lambda: extra_edges(vk, "edges7_shelf_near", 10)),
+                        ("fk14", lambda: extra_fk(vk, "states14_cloud", 1 << 20, 10)),
                         ("states7", lambda: extra_states(vk, "states7", None, 20)),
                         ("states7_1M", lambda: extra_states(vk, "states7", 1 << 20, 10)),
                         ("states14_cloud", lambda: extra_states(vk, "states14_cloud", None, 5)),
@@ -423,7 +494,7 @@ def main():
                         ("prm7_shelf", lambda: extra_prm(vk, 10)),
                         ("shortcut7_shelf", lambda: extra_shortcut(vk, 10)),
                         ("rrt7_shelf", lambda: extra_rrt(vk)),
-                        ("mixed", lambda: extra_mixed(vk, 3, 20))):
+                        ("mixed", lambda: extra_mixed(vk, 10, 20))):
             if args.extras and key not in args.extras.split(","):
                 continue
             t0 = time.perf_counter()
@@ -431,7 +502,7 @@ def main():
             log(f"extra {key}: {extra[key]} ({time.perf_counter() - t0:.1f}s)")
         result["extra"] = extra
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(w)
+        result["cpu_baseline"], result["parity"] = cpu_baseline(w, flags)
     print(json.dumps(result), flush=True)
 
 

@@ -269,15 +269,21 @@ vk_status vk_rrt_commit(float *nodes, int32_t *parents, int32_t *sizes, int32_t 
                         uint8_t *solved, uint64_t *edges, void *stream);
 
 /* Measurement variant of validate_edges: the same flags from the same kernel code, which in
- * addition adds to flops[0..4] (five device uint64, not cleared by the call) the FP32
+ * addition adds to flops[0..7] (eight device uint64, not cleared by the call) the FP32
  * operations the launch executed, by the model's count per operation (fused multiply-add = 2;
  * revolute joint 30, mount 63, sphere placement 18, sphere-sphere and self pair 11, capsule 25,
  * box 34, cylinder 35; self-block gates: capsule bound against capsule bound 67, sphere bound
  * against capsule bound 28, placing a capsule half-vector 15; a point-cloud clearance lookup
- * 23), summed over the lanes that execute it.  flops[0] is the total;
- * flops[1..4] split it into FK and sphere placement, culling (voxel lookups and link
- * bounding-sphere tests), fine environment tests and self pairs (with re-posing).  Early exits,
- * skipped tests and lanes masked off by divergent control flow add nothing. */
+ * 23), summed over the lanes that execute it.  flops[0] is the total.  flops[1..4] are the
+ * method's own work: FK and sphere placement, culling (voxel lookups and link bounding-sphere
+ * tests), fine environment tests, and self pairs (their gates and tests).  flops[5..6] are work
+ * the implementation adds: re-posing (an earlier link posed again for a self block, a tree
+ * branch rebuilt from the base, the earlier link's spheres placed again), and everything the
+ * surplus rake lanes execute (an edge of n states leaves 64 * ceil(n / 64) - n lanes of its
+ * rake over; they repeat the last state).  flops[7] counts rake slots of real states walked
+ * (one per lane and rake step up to the step that ends the edge), which the rake schedule and
+ * the first hit alone decide.  Early exits, skipped tests and lanes masked off by divergent
+ * control flow add nothing. */
 vk_status validate_edges_counted(vk_robot robot, vk_env env, const float *qa, const float *qb,
                                  const int32_t *n_states, int64_t n_edges, float resolution,
                                  uint8_t *collide, uint64_t *flops, void *stream);

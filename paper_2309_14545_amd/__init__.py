@@ -335,15 +335,16 @@ def validate_edges(robot: Robot, env: Env, qa, qb, n_states=None, resolution: fl
 
 def validate_edges_counted(robot: Robot, env: Env, qa, qb, flops, n_states=None,
                            resolution: float = 1.0 / 32.0, out=None):
-    """validate_edges plus executed-FLOP accounting into ``flops`` (int64 CUDA tensor [5]:
-    total, FK, culling, fine environment tests, self pairs)."""
+    """validate_edges plus executed-FLOP accounting into ``flops`` (int64 CUDA tensor [8]:
+    total, FK, culling, fine environment tests, self pairs, re-posing, surplus rake lanes, rake
+    slots of real states walked)."""
     torch = _torch()
     qa, qb = _dev_f32(qa, "qa"), _dev_f32(qb, "qb")
     if qa.dim() != 2 or qa.shape != qb.shape or qa.shape[1] != robot.dof:
         raise ValueError(f"qa and qb must both be [E, dof={robot.dof}]")
     if not (isinstance(flops, torch.Tensor) and flops.is_cuda and flops.dtype == torch.int64
-            and flops.numel() >= 5 and flops.is_contiguous()):
-        raise TypeError("flops must be a contiguous int64 CUDA tensor of 5 elements")
+            and flops.numel() >= 8 and flops.is_contiguous()):
+        raise TypeError("flops must be a contiguous int64 CUDA tensor of 8 elements")
     E = qa.shape[0]
     ns_ptr = n_states.contiguous().data_ptr() if n_states is not None else None
     if out is None:

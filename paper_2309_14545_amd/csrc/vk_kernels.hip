@@ -153,10 +153,15 @@ __device__ __forceinline__ void stage_env(float4 *lds, const float4 *__restrict_
 // Executed-work accounting (FLOP model, FMA = 2): every wave-uniform operation below adds its
 // per-lane FLOP count; the instrumented kernel multiplies by the 64 lanes that issue it.
 // NoWork compiles to nothing, so the timed kernels carry no accounting.
-// Work is split in four categories: FK and sphere placement, culling (voxel lookups and
-// per-link bounding-sphere tests), fine environment tests, self pairs (including re-posing
-// links).  Every lane counts the operations it executes (lanes masked off by divergent
-// control flow add nothing); the instrumented kernel sums the lanes.
+// The method's own work is split in four categories: FK and sphere placement, culling (voxel
+// lookups and per-link bounding-sphere tests), fine environment tests, self pairs (their gates
+// and tests).  Two more categories hold work this implementation adds to the method: re-posing
+// (posing an earlier link again for a self block, rebuilding a tree branch, placing the earlier
+// link's spheres again), and surplus rake lanes (the lanes an edge of fewer than 64 * steps
+// states leaves over repeat its last state; everything they execute goes here).  Every lane
+// counts the operations it executes (lanes masked off by divergent control flow add nothing);
+// the instrumented kernel sums the lanes.  `visits` counts the rake slots of real states that a
+// lane walks (whatever the walk's length): the rake schedule and its early exit alone decide it.
 namespace flop {
 constexpr uint32_t kJoint = 30, kMount = 63, kPlace = 18, kSphere = 11, kCapsule = 25,
                    kCylinder = 35, kBox = 34, kPair = 11;
@@ -166,14 +171,22 @@ constexpr uint32_t kCapsuleCapsule = 67, kSphereCapsule = 28, kPlaceHalf = 15;
 // looking up a location in the point-cloud clearance field (cell index, the distance to the
 // cell's centre, the bound)
 constexpr uint32_t kClearance = 23;
-enum Cat { kFk = 0, kCull = 1, kFine = 2, kSelf = 3 };
+enum Cat { kFk = 0, kCull = 1, kFine = 2, kSelf = 3, kRepose = 4, kSurplus = 5, kCats = 6 };
 }
 struct NoWork {
     __device__ __forceinline__ void add(int, uint32_t) {}
+    __device__ __forceinline__ void rake_slot(bool) {}
 };
 struct Work {
-    uint64_t f[4] = {0, 0, 0, 0};
-    __device__ __forceinline__ void add(int c, uint32_t x) { f[c] += x; }
+    uint64_t f[flop::kCats] = {0, 0, 0, 0, 0, 0};
+    uint64_t visits = 0;
+    bool surplus = false;
+    __device__ __forceinline__ void add(int c, uint32_t x) { f[surplus ? flop::kSurplus : c] += x; }
+    // a rake slot begins: a real state of the edge, or a surplus lane repeating the last one
+    __device__ __forceinline__ void rake_slot(bool real) {
+        surplus = !real;
+        visits += real ? 1 : 0;
+    }
 };
 
 // Per-wave LDS cache, per lane, with a slot for each step whose bounds a later self block
@@ -269,7 +282,7 @@ __device__ __forceinline__ void pose_step(const RobotDev &rb, const StepRec &S, 
                 frame_joint_val(T, J, sc->get_val(j, J));
             else
                 frame_joint(T, J, q(j));
-            w.add(flop::kFk, flop::kJoint + (J.has_mount ? flop::kMount : 0));
+            w.add(flop::kRepose, flop::kJoint + (J.has_mount ? flop::kMount : 0));
         }
     }
     const JointRec &J = S.jr;
@@ -302,7 +315,7 @@ __device__ __forceinline__ void pose_block(const RobotDev &rb, const BlockRec &B
             frame_joint_val(Ta, J, sc.get_val(j, J));
         else
             frame_joint(Ta, J, q(j));
-        w.add(flop::kSelf, flop::kJoint + (J.has_mount ? flop::kMount : 0));
+        w.add(flop::kRepose, flop::kJoint + (J.has_mount ? flop::kMount : 0));
     }
     ta_link = B.link;
     ta_depth = B.path_len;
@@ -602,7 +615,8 @@ __device__ bool walk_collide(const RobotDev &rb, const EnvView &ev, const EnvDev
                 const float ty = fmaf(Ta.r[3], E.x, fmaf(Ta.r[4], E.y, fmaf(Ta.r[5], E.z, oy)));
                 const float tz = fmaf(Ta.r[6], E.x, fmaf(Ta.r[7], E.y, fmaf(Ta.r[8], E.z, oz)));
                 const float t2 = fmaf(tx, tx, fmaf(ty, ty, tz * tz));
-                work.add(flop::kSelf, flop::kPlace + flop::kPair);
+                work.add(flop::kRepose, flop::kPlace);
+                work.add(flop::kSelf, flop::kPair);
                 if (!wave_ballot(live && t2 < E.gate2)) continue;
                 if (!rel) {                      // this step's spheres, relative to C
                     VK_PLACE()
@@ -793,6 +807,7 @@ __device__ __forceinline__ uint8_t edge_body(const RobotDev &rb, const V &ev, co
     const float inv = 1.0f / (float)(n - 1);
     for (int k = 0; k < stride; ++k) {
         int idx = lane * stride + k;
+        work.rake_slot(idx < n);
         idx = idx < n ? idx : n - 1;          // surplus lanes repeat the last state
         const float t = idx == n - 1 ? 1.0f : (float)idx * inv;
         QEdge qs{a, b, t};
@@ -887,13 +902,20 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
         }
     }
     if constexpr (COUNT) {
-        unsigned long long v[4] = {work.f[0], work.f[1], work.f[2], work.f[3]};
+        // flops[0] the total, flops[1..6] the categories, flops[7] the rake slots of real states
+        unsigned long long v[flop::kCats + 1];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < flop::kCats; ++c) v[c] = work.f[c];
+        v[flop::kCats] = work.visits;
+#pragma unroll
+        for (int c = 0; c <= flop::kCats; ++c)
             for (int m = 1; m < kWave; m <<= 1) v[c] += __shfl_xor(v[c], m);
-        atomicAdd(flops + 0, lane == 0 ? v[0] + v[1] + v[2] + v[3] : 0ull);
+        unsigned long long total = 0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) atomicAdd(flops + 1 + c, lane == 0 ? v[c] : 0ull);
+        for (int c = 0; c < flop::kCats; ++c) total += v[c];
+        atomicAdd(flops + 0, lane == 0 ? total : 0ull);
+#pragma unroll
+        for (int c = 0; c <= flop::kCats; ++c) atomicAdd(flops + 1 + c, lane == 0 ? v[c] : 0ull);
     }
 }
 

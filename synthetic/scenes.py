@@ -99,17 +99,33 @@ def cube_scene(g: np.random.Generator, n_spheres: int = 32, n_boxes: int = 8,
     return _pack(spheres=spheres, boxes=boxes)
 
 
+def _box_clear(centre, rot, ext, mounts) -> bool:
+    """Exact distance from every mount point to the oriented box is at least KEEP_OUT."""
+    for p in mounts:
+        local = rot.T @ (p - centre)
+        if np.linalg.norm(np.maximum(np.abs(local) - ext, 0.0)) < KEEP_OUT:
+            return False
+    return True
+
+
 def shelf_scene(g: np.random.Generator, n_units: int = 12, n_loose: int = 4,
-                n_capsules: int = 50, mounts=((0.0, 0.0, 0.0),)) -> dict:
+                n_capsules: int = 50, mounts=((0.0, 0.0, 0.0),), radius=(1.0, 1.5),
+                keepout: str = "unit") -> dict:
     """Shelf units in a half ring in front of the base (+x side): 8 boxes per unit (two side
-    panels, a back panel, five boards), loose boxes and upright capsules standing on boards."""
+    panels, a back panel, five boards), loose boxes and upright capsules standing on boards.
+
+    Units stand at a radial distance U[radius].  keepout="unit" keeps each unit's bounding ball
+    out of the mounts' keep-out balls (so units start about 1 m out); keepout="box" checks each
+    panel, loose box and capsule on its own (exact box distance), which lets units stand closer
+    (radius (0.55, 1.1) puts them in the arm's reach)."""
     m = np.asarray(mounts, dtype=np.float64).reshape(-1, 3)
     boxes, boards = [], []
     t = 0.01                                           # half thickness of every panel
+    per_box = keepout == "box"
     for k in range(n_units):
         while True:
             yaw = np.pi * ((k + 0.5 + g.uniform(-0.3, 0.3)) / n_units - 0.5)
-            rad = g.uniform(1.0, 1.5)
+            rad = g.uniform(*radius)
             z0 = g.uniform(-0.3, 0.3)
             w = g.uniform(0.25, 0.4)                   # half width
             dep = g.uniform(0.15, 0.2)                 # half depth
@@ -119,33 +135,45 @@ def shelf_scene(g: np.random.Generator, n_units: int = 12, n_loose: int = 4,
             rot = np.array([[cy, -sy, 0.0], [sy, cy, 0.0], [0.0, 0.0, 1.0]])
             centre = np.array([rad * cy, rad * sy, z0 + h])
             bound = float(np.sqrt(dep * dep + w * w + h * h))
-            if _clear_of(centre, bound, m):
+            parts = []
+            for side in (-1.0, 1.0):                   # side panels
+                parts.append((np.array([0.0, side * w, 0.0]), np.array([dep, t, h])))
+            parts.append((np.array([dep, 0.0, 0.0]), np.array([t, w, h])))   # back panel
+            for i in range(5):                         # boards, bottom to top
+                z = -h + 2.0 * h * i / 4.0
+                parts.append((np.array([0.0, 0.0, z]), np.array([dep, w, t])))
+            if per_box:
+                if all(_box_clear(centre + rot @ off, rot, ext, m) for off, ext in parts):
+                    break
+            elif _clear_of(centre, bound, m):
                 break
-        parts = []
-        for side in (-1.0, 1.0):                       # side panels
-            parts.append((np.array([0.0, side * w, 0.0]), np.array([dep, t, h])))
-        parts.append((np.array([dep, 0.0, 0.0]), np.array([t, w, h])))       # back panel
-        for i in range(5):                             # boards, bottom to top
+        for i in range(5):
             z = -h + 2.0 * h * i / 4.0
-            parts.append((np.array([0.0, 0.0, z]), np.array([dep, w, t])))
             boards.append((centre + rot @ np.array([0.0, 0.0, z]), rot, dep, w))
         for off, ext in parts:
             boxes.append(np.concatenate([centre + rot @ off, rot.reshape(-1), ext]))
     for _ in range(n_loose):                           # small boxes lying on random boards
-        c, rot, dep, w = boards[g.integers(0, len(boards))]
-        e = g.uniform(0.04, 0.1, 3)
-        e[:2] = np.minimum(e[:2], [dep, w])
-        x = g.uniform(-dep + e[0], dep - e[0])
-        y = g.uniform(-w + e[1], w - e[1])
-        boxes.append(np.concatenate([c + rot @ np.array([x, y, t + e[2]]), rot.reshape(-1), e]))
+        while True:
+            c, rot, dep, w = boards[g.integers(0, len(boards))]
+            e = g.uniform(0.04, 0.1, 3)
+            e[:2] = np.minimum(e[:2], [dep, w])
+            x = g.uniform(-dep + e[0], dep - e[0])
+            y = g.uniform(-w + e[1], w - e[1])
+            bc = c + rot @ np.array([x, y, t + e[2]])
+            if not per_box or _box_clear(bc, rot, e, m):
+                break
+        boxes.append(np.concatenate([bc, rot.reshape(-1), e]))
     capsules = []
     for _ in range(n_capsules):
-        c, rot, dep, w = boards[g.integers(0, len(boards))]
-        r = g.uniform(0.02, 0.05)
-        hl = g.uniform(0.04, 0.12)
-        x = g.uniform(-dep + r, dep - r)
-        y = g.uniform(-w + r, w - r)
-        base = c + rot @ np.array([x, y, t + r])
+        while True:
+            c, rot, dep, w = boards[g.integers(0, len(boards))]
+            r = g.uniform(0.02, 0.05)
+            hl = g.uniform(0.04, 0.12)
+            x = g.uniform(-dep + r, dep - r)
+            y = g.uniform(-w + r, w - r)
+            base = c + rot @ np.array([x, y, t + r])
+            if not per_box or _clear_of(base + np.array([0.0, 0.0, hl]), hl + r, m):
+                break
         capsules.append(np.concatenate([base, base + np.array([0.0, 0.0, 2.0 * hl]), [r]]))
     return _pack(capsules=capsules, boxes=boxes)
 

@@ -11,6 +11,8 @@ Workloads (sizes are the defaults; tests pass smaller ``n``):
                    + 8 boxes in a 2 m cube; 4,096 uniform states (SoA [dof][N])
 ``edges7_shelf``   the same 7-DoF robot in the shelf scene (100 boxes + 50 capsules);
                    65,536 edges with endpoints uniform in the limits
+``edges7_shelf_near`` the same robot and batch with the shelf units at U[0.55, 1.1] m (each panel
+                   kept out of the base's keep-out ball on its own), within the arm's reach
 ``edges8_shelf``   8-DoF chain, 4 base + 8x7 spheres (60), 400 pairs; shelf scene; 65,536 edges
 ``edges8p_shelf``  prismatic lift (0-0.4 m) + 7-DoF arm, 4 torso + 7x6 spheres (46), 400 pairs;
                    shelf scene; 65,536 edges uniform in each joint's range
@@ -138,6 +140,11 @@ def workload(name: str, n: int | None = None, variant: int = 0) -> dict:
     if name == "edges7_shelf":
         robot = robot7()
         env = shelf_scene(rng("shelf", "env"))
+        qa, qb = uniform_edges(rng("edges7_shelf", "edges"), robot["dof"], n or 65536)
+        return {"name": name, "robot": robot, "env": env, "qa": qa, "qb": qb}
+    if name == "edges7_shelf_near":
+        robot = robot7()
+        env = shelf_scene(rng("shelf_near", "env"), radius=(0.55, 1.1), keepout="box")
         qa, qb = uniform_edges(rng("edges7_shelf", "edges"), robot["dof"], n or 65536)
         return {"name": name, "robot": robot, "env": env, "qa": qa, "qb": qb}
     if name == "edges8_shelf":
