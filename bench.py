@@ -292,9 +292,26 @@ def extra_rrt(vk, n_queries=1024):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     solved = int(res["solved"].sum())
+    # randomized shortcutting of the solved paths: 64 rounds of 8 candidates per path
+    paths = [p for p in res["paths"] if p is not None]
+    pd, ld = planning.pack_paths(paths, 7)
+    before = planning.path_lengths(pd, ld)
+    warm_p, warm_l = pd.clone(), ld.clone()
+    planning.shortcut(robot, env, warm_p, warm_l, rounds=2, k=8, seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc = planning.shortcut(robot, env, pd, ld, rounds=64, k=8, seed=1)
+    torch.cuda.synchronize()
+    sdt = time.perf_counter() - t0
+    after = planning.path_lengths(pd, ld)
     return {"workload": "rrt7_shelf", "queries": n_queries, "solved": solved,
             "wall_s": dt, "iterations": res["iterations"], "rounds": res["rounds"],
-            "edges_checked": res["edges"], "plans_per_s": solved / dt}
+            "edges_checked": res["edges"], "plans_per_s": solved / dt,
+            "shortcut": {"paths": len(paths), "rounds": sc["rounds"], "candidates_per_path": 8,
+                         "wall_s": sdt, "rounds_per_s": sc["rounds"] / sdt,
+                         "edges_per_s": sc["edges_checked"] / sdt, "accepted": sc["accepted"],
+                         "mean_length_before": float(before.mean()),
+                         "mean_length_after": float(after.mean())}}
 
 
 def extra_mixed(vk, n_batches, reps):

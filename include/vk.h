@@ -268,6 +268,31 @@ vk_status vk_rrt_commit(float *nodes, int32_t *parents, int32_t *sizes, int32_t 
                         const int32_t *from_added, int64_t *meet_this, int64_t *meet_from,
                         uint8_t *solved, uint64_t *edges, void *stream);
 
+/*
+ * Randomized shortcutting of many paths at once (the path simplification of Sec. III-E, run as
+ * rounds over n_paths paths): a round is vk_shortcut_propose, validate_edges_indexed on its
+ * pairs with `paths` as the node array, then vk_shortcut_apply.  Paths are device FP32
+ * [n_paths][max_len][dof] (waypoint w of path p is node p * max_len + w); lens [n_paths] (int32)
+ * holds the waypoints in use.  Every removed stretch of waypoints is replaced by a straight
+ * edge that validate_edges found free, so a path stays valid and its length does not grow.
+ *
+ * vk_shortcut_propose: k candidates per path, pairs [n_paths * k][2] (int32 node indices), from
+ *   the caller's random words rnd [n_paths * k][2] (uint32): i = rnd0 mod (len - 2),
+ *   j = i + 2 + rnd1 mod (len - i - 2), so 0 <= i, i + 2 <= j <= len - 1.  A path with fewer
+ *   than 3 waypoints gets holes (-1, -1).
+ * vk_shortcut_apply: per path, among its candidates with collide == 0 (the flags of the
+ *   validate_edges_indexed call on those pairs), the one with the largest j - i (ties to the
+ *   lower candidate index) is spliced in: waypoints i+1 .. j-1 are removed, the rest move down
+ *   and lens shrinks.  accepted [n_paths] (uint8, optional) is 1 where a shortcut was taken.
+ * Errors: VK_ERR_INVALID_ARG for NULL arrays, n_paths < 0, max_len < 1, k outside [1, 64] or
+ * dof outside [1, 64]; VK_ERR_SHAPE when n_paths * max_len reaches 2^31.
+ */
+vk_status vk_shortcut_propose(const int32_t *lens, int64_t n_paths, int32_t max_len, int32_t k,
+                              const uint32_t *rnd, int32_t *pairs, void *stream);
+vk_status vk_shortcut_apply(float *paths, int32_t *lens, int64_t n_paths, int32_t max_len,
+                            int32_t dof, int32_t k, const int32_t *pairs, const uint8_t *collide,
+                            uint8_t *accepted, void *stream);
+
 /* Measurement variant of validate_edges: the same flags from the same kernel code, which in
  * addition adds to flops[0..7] (eight device uint64, not cleared by the call) the FP32
  * operations the launch executed, by the model's count per operation (fused multiply-add = 2;

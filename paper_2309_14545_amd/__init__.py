@@ -26,7 +26,7 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "validate_states_noalloc", "validate_edges",
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
            "vk_knn", "vk_knn_pairs", "vk_tree_nearest", "vk_tree_steer", "vk_tree_append",
-           "vk_rrt_extend", "vk_rrt_commit",
+           "vk_rrt_extend", "vk_rrt_commit", "vk_shortcut_propose", "vk_shortcut_apply",
            "penetration_cost_fwd", "penetration_cost_bwd",
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_get_launch",
            "vk_edge_batch_destroy", "vk_reserve", "vk_release",
@@ -98,6 +98,8 @@ def lib():
         L.vk_rrt_extend.argtypes = [vp, vp, i32, i32, i64, vp, vp, fp, vp, vp, vp, vp, vp]
         L.vk_rrt_commit.argtypes = [vp, vp, vp, i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                     vp, vp, vp]
+        L.vk_shortcut_propose.argtypes = [vp, i64, i32, i32, vp, vp, vp]
+        L.vk_shortcut_apply.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp, vp]
         L.penetration_cost_fwd.argtypes = [vp, vp, vp, i64, i64, vp, vp]
         L.penetration_cost_bwd.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
         L.vk_edge_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), i32,
@@ -476,6 +478,28 @@ def rrt_commit(nodes, parents, sizes, qnew, near, reached, flags, going, added, 
                                flags.data_ptr(), going.data_ptr(), added.data_ptr(),
                                ptr(from_added), ptr(meet_this), ptr(meet_from), ptr(solved),
                                edges.data_ptr(), _stream()))
+
+
+def shortcut_propose(lens, max_len: int, k: int, rnd, pairs=None):
+    """k shortcut candidates per path as node index pairs [P * k, 2] (see vk_shortcut_propose);
+    rnd: int32/uint32 CUDA tensor of 2 * P * k random words."""
+    torch = _torch()
+    P = lens.shape[0]
+    if pairs is None:
+        pairs = torch.empty((P * k, 2), dtype=torch.int32, device=lens.device)
+    _check(lib().vk_shortcut_propose(lens.data_ptr(), P, int(max_len), int(k), rnd.data_ptr(),
+                                     pairs.data_ptr(), _stream()))
+    return pairs
+
+
+def shortcut_apply(paths, lens, k: int, pairs, flags, accepted=None):
+    """Splice each path's best valid candidate into paths [P, M, dof] / lens [P] in place."""
+    P, M, dof = paths.shape
+    _check(lib().vk_shortcut_apply(paths.data_ptr(), lens.data_ptr(), P, M, dof, int(k),
+                                   pairs.data_ptr(), flags.data_ptr(),
+                                   accepted.data_ptr() if accepted is not None else None,
+                                   _stream()))
+    return accepted
 
 
 def penetration_cost_fwd(robot: Robot, env: Env, q):

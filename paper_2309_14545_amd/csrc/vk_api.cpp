@@ -1409,6 +1409,38 @@ vk_status vk_rrt_commit(float *nodes, int32_t *parents, int32_t *sizes, int32_t 
     });
 }
 
+static void check_paths(int64_t P, int32_t M, int32_t K, int32_t dof) {
+    if (P < 0 || M < 1 || K < 1 || K > 64 || dof < 1 || dof > kMaxDof)
+        raise(VK_ERR_INVALID_ARG, "shortcut: need P >= 0, M >= 1, 1 <= K <= 64, 1 <= dof <= 64");
+    if (P * (int64_t)M >= (int64_t(1) << 31) || P * (int64_t)K >= (int64_t(1) << 31) - (int64_t(1) << 24))
+        raise(VK_ERR_SHAPE, "shortcut: too many waypoints or candidates");
+}
+
+vk_status vk_shortcut_propose(const int32_t *lens, int64_t n_paths, int32_t max_len, int32_t k,
+                              const uint32_t *rnd, int32_t *pairs, void *stream) {
+    return guarded([&] {
+        check_paths(n_paths, max_len, k, 1);
+        if (n_paths == 0) return;
+        if (!lens || !rnd || !pairs) raise(VK_ERR_INVALID_ARG, "vk_shortcut_propose: NULL array");
+        hip_check(launch_shortcut_propose(lens, n_paths, max_len, k, rnd, pairs, (hipStream_t)stream),
+                  "vk_shortcut_propose launch");
+    });
+}
+
+vk_status vk_shortcut_apply(float *paths, int32_t *lens, int64_t n_paths, int32_t max_len,
+                            int32_t dof, int32_t k, const int32_t *pairs, const uint8_t *collide,
+                            uint8_t *accepted, void *stream) {
+    return guarded([&] {
+        check_paths(n_paths, max_len, k, dof);
+        if (n_paths == 0) return;
+        if (!paths || !lens || !pairs || !collide)
+            raise(VK_ERR_INVALID_ARG, "vk_shortcut_apply: NULL array");
+        hip_check(launch_shortcut_apply(paths, lens, n_paths, max_len, dof, k, pairs, collide,
+                                        accepted, (hipStream_t)stream),
+                  "vk_shortcut_apply launch");
+    });
+}
+
 vk_status penetration_cost_fwd(vk_robot robot, vk_env env, const float *q, int64_t n,
                                int64_t ldq, float *cost, void *stream) {
     return guarded([&] {

@@ -1675,6 +1675,61 @@ __global__ void k_knn_pairs(const int32_t *__restrict__ idx, int64_t n, int k,
 }
 
 // ---------------------------------------------------------------------------------------------
+// Randomized shortcutting of many paths at once (the path simplification of Sec. III-E): each
+// round proposes K waypoint pairs per path, validates them all in one edge launch, and splices
+// in one valid shortcut per path.  Paths are [P][M][dof] (waypoint w of path p is node p*M + w),
+// lens [P] the waypoints in use.
+// ---------------------------------------------------------------------------------------------
+// Candidate k of path p from two random words: i uniform-ish in [0, len - 3], j in
+// [i + 2, len - 1], as node indices; a path of fewer than 3 waypoints gets holes (-1, -1).
+__global__ void k_shortcut_propose(const int32_t *__restrict__ lens, int64_t P, int M, int K,
+                                   const uint32_t *__restrict__ rnd, int32_t *__restrict__ pairs) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P * K) return;
+    const int64_t p = s / K;
+    const int len = min(max(lens[p], 0), M);
+    int32_t a = -1, b = -1;
+    if (len >= 3) {
+        const int i = (int)(rnd[2 * s] % (uint32_t)(len - 2));
+        const int j = i + 2 + (int)(rnd[2 * s + 1] % (uint32_t)(len - i - 2));
+        a = (int32_t)(p * M + i);
+        b = (int32_t)(p * M + j);
+    }
+    pairs[2 * s] = a;
+    pairs[2 * s + 1] = b;
+}
+
+// Per path: the valid candidate (flag 0) that skips the most waypoints (ties to the lower k) is
+// spliced in: waypoints i+1 .. j-1 are removed and the tail moves down.  accepted[p] (optional)
+// is 1 where a shortcut was taken.
+__global__ void k_shortcut_apply(float *__restrict__ paths, int32_t *__restrict__ lens, int64_t P,
+                                 int M, int dof, int K, const int32_t *__restrict__ pairs,
+                                 const uint8_t *__restrict__ flags, uint8_t *__restrict__ accepted) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int len = min(max(lens[p], 0), M);
+    int bi = -1, bj = -1;
+    for (int k = 0; k < K; ++k) {
+        const int64_t c = p * K + k;
+        const int32_t a = pairs[2 * c], b = pairs[2 * c + 1];
+        if (a < 0 || b < 0 || flags[c] != 0) continue;
+        const int i = (int)(a - p * M), j = (int)(b - p * M);
+        if (i < 0 || j >= len || j - i < 2) continue;
+        if (j - i > bj - bi) {
+            bi = i;
+            bj = j;
+        }
+    }
+    if (bi >= 0) {
+        float *w = paths + p * (int64_t)M * dof;
+        for (int m = bj; m < len; ++m)
+            for (int d = 0; d < dof; ++d) w[(int64_t)(bi + 1 + m - bj) * dof + d] = w[(int64_t)m * dof + d];
+        lens[p] = len - (bj - bi - 1);
+    }
+    if (accepted) accepted[p] = bi >= 0 ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Host-side launchers (called from the C-ABI layer).
 // ---------------------------------------------------------------------------------------------
 hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int64_t ldq,
@@ -1968,6 +2023,22 @@ hipError_t launch_knn_pairs(const int32_t *idx, int64_t n, int k, int32_t *pairs
     const int bs = 256;
     hipLaunchKernelGGL(k_knn_pairs, dim3((unsigned)((n * k + bs - 1) / bs)), dim3(bs), 0, s, idx,
                        n, k, pairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_shortcut_propose(const int32_t *lens, int64_t P, int M, int K,
+                                  const uint32_t *rnd, int32_t *pairs, hipStream_t s) {
+    const int64_t n = P * K;
+    hipLaunchKernelGGL(k_shortcut_propose, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, lens,
+                       P, M, K, rnd, pairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_shortcut_apply(float *paths, int32_t *lens, int64_t P, int M, int dof, int K,
+                                const int32_t *pairs, const uint8_t *flags, uint8_t *accepted,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_shortcut_apply, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, paths,
+                       lens, P, M, dof, K, pairs, flags, accepted);
     return hipGetLastError();
 }
 

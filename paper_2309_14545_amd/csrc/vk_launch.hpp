@@ -21,6 +21,11 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const fl
 int64_t noalloc_max_states();
 hipError_t noalloc_scratch(void **ptr);
 hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s);
+hipError_t launch_shortcut_propose(const int32_t *lens, int64_t P, int M, int K,
+                                  const uint32_t *rnd, int32_t *pairs, hipStream_t s);
+hipError_t launch_shortcut_apply(float *paths, int32_t *lens, int64_t P, int M, int dof, int K,
+                                const int32_t *pairs, const uint8_t *flags, uint8_t *accepted,
+                                hipStream_t s);
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,
                                  unsigned long long *queue, int grid, int block, int tickets,

@@ -1,4 +1,5 @@
-"""Many-query RRT-Connect on the GPU primitives (the RRT-Connect planner of Sec. III-E).
+"""Many-query RRT-Connect and randomized shortcutting on the GPU primitives (the planner and
+path simplification of Sec. III-E).
 
 RRT-Connect grows one tree from the start and one from the goal.  Each iteration samples a
 configuration, extends one tree toward it by at most `step`, then repeatedly extends the other
@@ -15,7 +16,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import reserve, rrt_commit, rrt_extend, validate_edges
+from . import (reserve, rrt_commit, rrt_extend, shortcut_apply, shortcut_propose, validate_edges,
+               validate_edges_indexed)
 
 
 def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
@@ -120,3 +122,50 @@ def rrt_connect(robot, env, starts, goals, q_lo, q_hi, step: float = 0.6,
         path = half[0][::-1] + half[1][1:]
         paths.append(np.asarray(path, np.float32))
     return {"solved": sol, "paths": paths, "iterations": it, "rounds": rounds, "edges": edges}
+
+
+def pack_paths(paths, dof: int, device="cuda"):
+    """Pack a list of [n_i, dof] waypoint arrays into (paths [P, M, dof], lens [P]) tensors."""
+    import torch
+    P = len(paths)
+    M = max(len(p) for p in paths)
+    buf = np.zeros((P, M, dof), np.float32)
+    lens = np.zeros(P, np.int32)
+    for i, p in enumerate(paths):
+        buf[i, :len(p)] = p
+        lens[i] = len(p)
+    return torch.from_numpy(buf).to(device), torch.from_numpy(lens).to(device)
+
+
+def path_lengths(paths, lens):
+    """Euclidean joint-space length of each packed path (FP64, on the host)."""
+    P = paths.shape[0]
+    w = paths.detach().cpu().numpy().astype(np.float64)
+    n = lens.cpu().numpy()
+    return np.array([np.linalg.norm(np.diff(w[p, :n[p]], axis=0), axis=1).sum() for p in range(P)])
+
+
+def shortcut(robot, env, paths, lens, rounds: int = 64, k: int = 8, seed: int = 0,
+             resolution: float = 1.0 / 32.0):
+    """Randomized shortcutting of P paths at once, in place: paths [P, M, dof] (CUDA float32),
+    lens [P] (CUDA int32).  Each round proposes k waypoint pairs per path, validates all P * k
+    straight edges in one launch and splices in, per path, the valid one that skips the most
+    waypoints (vk_shortcut_*).  The random words of every round are drawn up front from a seeded
+    torch generator on the device.  Returns {"rounds", "accepted" (shortcuts taken),
+    "edges_checked"}."""
+    import torch
+    P, M, dof = paths.shape
+    dev = paths.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    rnd = torch.randint(0, 2 ** 31 - 1, (rounds, 2 * P * k), generator=gen, device=dev,
+                        dtype=torch.int32)
+    nodes = paths.view(P * M, dof)
+    pairs = torch.empty((P * k, 2), dtype=torch.int32, device=dev)
+    flags = torch.empty(P * k, dtype=torch.uint8, device=dev)
+    accepted = torch.empty((rounds, P), dtype=torch.uint8, device=dev)
+    for r in range(rounds):
+        shortcut_propose(lens, M, k, rnd[r], pairs)
+        validate_edges_indexed(robot, env, nodes, pairs, resolution=resolution, out=flags)
+        shortcut_apply(paths, lens, k, pairs, flags, accepted[r])
+    return {"rounds": rounds, "accepted": int(accepted.sum().item()), "edges_checked": rounds * P * k}
