@@ -163,6 +163,33 @@ def extra_edges(vk, name, steps):
             "launch": list(tune)}
 
 
+def extra_specialized(vk, name, steps):
+    """The same edge batch on the robot-specialised kernels (vk_robot_specialize, compiled
+    untimed) against the interpreted kernel, each in its autotuned launch."""
+    import torch
+    from synthetic import workload
+    from paper_2309_14545_amd import autotune
+    w = workload(name)
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = torch.from_numpy(w["qa"]).cuda(), torch.from_numpy(w["qb"]).cuda()
+    out = torch.empty(len(w["qa"]), dtype=torch.uint8, device="cuda")
+    nominal = int(state_counts(w["qa"], w["qb"], RES).sum())
+    res = {"workload": name}
+    for label in ("interpreted", "specialized"):
+        if label == "specialized":
+            t0 = time.perf_counter()
+            robot.specialize(os.path.join(ROOT, "gpurun_out", "vk_spec_cache"))
+            res["compile_s"] = time.perf_counter() - t0
+        autotune.tune_edges(robot, env, qa, qb, resolution=RES, cache=None)
+        vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out)
+        torch.cuda.synchronize()
+        m = float(np.median(_events_ms(
+            lambda: vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out), steps)))
+        res[label] = {"launch_ms": m, "states_per_s": nominal / (m * 1e-3),
+                      "launch": list(robot.get_edge_launch())}
+    return res
+
+
 def scene_summary_of(w):
     from synthetic import scene_summary
     return scene_summary(w["env"])
@@ -511,9 +538,12 @@ def main():
                         ("prm7_shelf", lambda: extra_prm(vk, 10)),
                         ("shortcut7_shelf", lambda: extra_shortcut(vk, 10)),
                         ("rrt7_shelf", lambda: extra_rrt(vk)),
-                        ("mixed", lambda: extra_mixed(vk, 10, 20))):
+                        ("mixed", lambda: extra_mixed(vk, 10, 20)),
+                        ("specialized7", lambda: extra_specialized(vk, "edges7_shelf", 20))):
             if args.extras and key not in args.extras.split(","):
                 continue
+            if not args.extras and key == "specialized7":
+                continue                      # compiling takes a minute: on request only
             t0 = time.perf_counter()
             extra[key] = fn()
             log(f"extra {key}: {extra[key]} ({time.perf_counter() - t0:.1f}s)")

@@ -100,6 +100,29 @@ vk_status vk_robot_destroy(vk_robot robot);
 int32_t vk_robot_dof(vk_robot robot);
 int32_t vk_robot_n_spheres(vk_robot robot);
 
+/*
+ * Per-robot specialisation (Sec. III-B: the paper compiles FK and collision checking per robot
+ * into straight-line code with the robot's constants folded in).  vk_robot_specialize writes
+ * the robot's program (link steps, self-pair blocks and their entries, pose paths, spheres) as
+ * constants into a source of the persistent edge kernels, compiles it for the robot's device
+ * with the HIP runtime compiler, and loads it; from then on the robot's edge calls
+ * (validate_edges, validate_edges_indexed, validate_edges_counted) run these kernels, whose
+ * per-step code is unrolled with the constants as instruction operands, instead of the
+ * library's kernel that reads the program at run time.  Flags are identical.  A set-up call: it
+ * compiles (seconds) unless cache_dir (else NULL) already holds the code object, which it then
+ * loads; it stores new code objects there.  vk_robot_use_specialized switches a specialised
+ * robot between the two kernels (on = 0: the library's); vk_robot_is_specialized tells which
+ * one the robot's calls use (1, 0; -1 for NULL).  vk_robot_spec_source writes the generated
+ * source for a description into buf (cap bytes, NUL-terminated, truncated if short) and
+ * returns its length including the NUL, or -1 for an invalid description (vk_last_error); it
+ * needs no device.  Errors: VK_ERR_HIP when compiling or loading fails (vk_last_error holds the
+ * compiler's log), VK_ERR_INVALID_ARG to switch on a robot not specialised.
+ */
+vk_status vk_robot_specialize(vk_robot robot, const char *cache_dir);
+vk_status vk_robot_use_specialized(vk_robot robot, int32_t on);
+int32_t vk_robot_is_specialized(vk_robot robot);
+int64_t vk_robot_spec_source(const vk_robot_desc *desc, char *buf, int64_t cap);
+
 /* Create / destroy a device-resident environment.  The primitives get a voxel broadphase
  * (per cell, the primitives that may come within 0.5 m, sorted by a distance bound).  A large
  * set of small spheres (more than 1,024, those up to twice the median radius: a point cloud) goes

@@ -22,6 +22,8 @@ _STATUS = {-1: "VK_ERR_INVALID_ARG", -2: "VK_ERR_SHAPE", -3: "VK_ERR_UNSUPPORTED
            -4: "VK_ERR_HIP", -5: "VK_ERR_OOM"}
 
 EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_spheres",
+           "vk_robot_specialize", "vk_robot_use_specialized", "vk_robot_is_specialized",
+           "vk_robot_spec_source",
            "vk_env_create", "vk_env_destroy", "vk_edge_states", "fk_spheres", "validate_states",
            "validate_states_noalloc", "validate_edges",
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
@@ -79,6 +81,12 @@ def lib():
         L.vk_robot_dof.restype = i32
         L.vk_robot_n_spheres.argtypes = [vp]
         L.vk_robot_n_spheres.restype = i32
+        L.vk_robot_specialize.argtypes = [vp, C.c_char_p]
+        L.vk_robot_use_specialized.argtypes = [vp, i32]
+        L.vk_robot_is_specialized.argtypes = [vp]
+        L.vk_robot_is_specialized.restype = i32
+        L.vk_robot_spec_source.argtypes = [C.POINTER(_RobotDesc), C.c_char_p, i64]
+        L.vk_robot_spec_source.restype = i64
         L.vk_env_create.argtypes = [C.POINTER(_EnvDesc), C.POINTER(vp)]
         L.vk_env_destroy.argtypes = [vp]
         L.vk_edge_states.argtypes = [C.POINTER(fp), C.POINTER(fp), i32, fp]
@@ -117,7 +125,8 @@ def lib():
         L.vk_autotune_states.argtypes = [vp, vp, vp, i64, i64, C.c_char_p, i32, vp]
         L.vk_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("vk_robot_dof", "vk_robot_n_spheres", "vk_last_error", "vk_edge_states"):
+            if name not in ("vk_robot_dof", "vk_robot_n_spheres", "vk_last_error", "vk_edge_states",
+                            "vk_robot_is_specialized", "vk_robot_spec_source"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -144,29 +153,59 @@ def _ip(a):
     return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
 
 
+def _robot_desc(desc: dict):
+    """(vk_robot_desc, the arrays it points into) for a dict of numpy arrays."""
+    dof = int(desc["dof"])
+    keep = {
+        "parent_link": _i32(desc["parent_link"], (-1,)) if desc.get("parent_link") is not None else None,
+        "mount": _f32(desc["mount"], (-1, 12)) if desc.get("mount") is not None else None,
+        "dh": _f32(desc["dh"], (-1, 5)),
+        "sphere_link": _i32(desc["sphere_link"], (-1,)),
+        "sphere_xyzr": _f32(desc["sphere_xyzr"], (-1, 4)),
+        "self_pairs": _i32(desc.get("self_pairs", np.zeros((0, 2))), (-1, 2)),
+        "joint_type": _i32(desc["joint_type"], (-1,)) if desc.get("joint_type") is not None else None,
+    }
+    d = _RobotDesc(dof, _ip(keep["parent_link"]), _fp(keep["mount"]), _fp(keep["dh"]), None,
+                   None, len(keep["sphere_link"]), _ip(keep["sphere_link"]),
+                   _fp(keep["sphere_xyzr"]), len(keep["self_pairs"]), _ip(keep["self_pairs"]),
+                   _ip(keep["joint_type"]))
+    return d, keep
+
+
+def spec_source(desc: dict) -> str:
+    """The source vk_robot_specialize compiles for this robot description (no device needed)."""
+    d, _keep = _robot_desc(desc)
+    n = lib().vk_robot_spec_source(C.byref(d), None, 0)
+    if n < 0:
+        raise VkError(-1, lib().vk_last_error().decode())
+    buf = C.create_string_buffer(int(n))
+    lib().vk_robot_spec_source(C.byref(d), buf, n)
+    return buf.value.decode()
+
+
 class Robot:
     """Device-resident robot (see vk_robot_desc).  ``desc`` is a dict of numpy arrays."""
 
     def __init__(self, desc: dict):
         dof = int(desc["dof"])
-        keep = {
-            "parent_link": _i32(desc["parent_link"], (-1,)) if desc.get("parent_link") is not None else None,
-            "mount": _f32(desc["mount"], (-1, 12)) if desc.get("mount") is not None else None,
-            "dh": _f32(desc["dh"], (-1, 5)),
-            "sphere_link": _i32(desc["sphere_link"], (-1,)),
-            "sphere_xyzr": _f32(desc["sphere_xyzr"], (-1, 4)),
-            "self_pairs": _i32(desc.get("self_pairs", np.zeros((0, 2))), (-1, 2)),
-            "joint_type": _i32(desc["joint_type"], (-1,)) if desc.get("joint_type") is not None else None,
-        }
-        d = _RobotDesc(dof, _ip(keep["parent_link"]), _fp(keep["mount"]), _fp(keep["dh"]), None,
-                       None, len(keep["sphere_link"]), _ip(keep["sphere_link"]),
-                       _fp(keep["sphere_xyzr"]), len(keep["self_pairs"]), _ip(keep["self_pairs"]),
-                       _ip(keep["joint_type"]))
+        d, keep = _robot_desc(desc)
         h = C.c_void_p()
         _check(lib().vk_robot_create(C.byref(d), C.byref(h)))
         self.handle = h
         self.dof = dof
         self.n_spheres = len(keep["sphere_link"])
+
+    def specialize(self, cache_dir: str | None = None):
+        """Compile this robot's edge kernels with its program as constants (vk_robot_specialize)
+        and use them; cache_dir keeps the code objects between processes."""
+        _check(lib().vk_robot_specialize(self.handle, cache_dir.encode() if cache_dir else None))
+
+    def use_specialized(self, on: bool = True):
+        _check(lib().vk_robot_use_specialized(self.handle, 1 if on else 0))
+
+    @property
+    def specialized(self) -> bool:
+        return lib().vk_robot_is_specialized(self.handle) == 1
 
     def set_edge_launch(self, block_threads: int = 0, blocks_per_cu: int = 0,
                         tickets_per_wave: int = 0):

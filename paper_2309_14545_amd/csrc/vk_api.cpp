@@ -1,18 +1,23 @@
 // C-ABI layer of libvk: handle creation (robot program, environment records, point-cloud grid),
 // argument checks and kernel launches.  No exception crosses the ABI.
 #include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
 
 #include <algorithm>
 #include <array>
 #include <atomic>
 #include <cctype>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "vk.h"
 #include "vk_launch.hpp"
@@ -280,6 +285,16 @@ struct vk_robot_s {
     void *blob = nullptr;
     RobotDev dev{};
     int dof = 0, n_spheres = 0;
+    // the program records on the host (the source of a specialised program)
+    std::vector<StepRec> steps;
+    std::vector<BlockRec> blocks;
+    std::vector<EntryRec> entries;
+    std::vector<JointRec> path_recs;
+    std::vector<float4> spheres;
+    // kernels compiled for this robot (vk_robot_specialize) and whether calls use them
+    hipModule_t module = nullptr;
+    SpecEdgeKernels spec{};
+    std::atomic<int> use_spec{0};
     // launch settings of this robot's calls (set by the autotuner or the caller)
     std::atomic<int> edge_block{kDefaultEdgeBlock}, edge_bpc{kDefaultEdgeBpc};
     std::atomic<int> edge_tickets{kDefaultTickets};
@@ -307,7 +322,7 @@ struct vk_edge_batch_s {
 
 namespace {
 
-void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
+void build_robot(const vk_robot_desc *d, vk_robot_s *r, bool upload = true) {
     if (!d) raise(VK_ERR_INVALID_ARG, "robot desc is NULL");
     const int dof = d->dof;
     if (dof < 1) raise(VK_ERR_INVALID_ARG, "dof must be >= 1");
@@ -495,14 +510,28 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
                                  d->sphere_xyzr[4 * s + 2], d->sphere_xyzr[4 * s + 3]);
     if (paths.empty()) paths.push_back(0);
 
+    std::vector<JointRec> path_recs(paths.size());
+    for (size_t i = 0; i < paths.size(); ++i) path_recs[i] = joints[std::min<int>(paths[i], dof - 1)];
+    r->steps = steps;
+    r->blocks = blocks;
+    r->entries = entries;
+    r->path_recs = path_recs;
+    r->spheres = spheres;
+    r->dof = dof;
+    r->n_spheres = S;
+    r->dev.dof = dof;
+    r->dev.n_steps = (int)steps.size();
+    r->dev.n_slots = n_slots;
+    r->dev.n_spheres = S;
+    r->dev.n_links = dof + 1;
+    if (!upload) return;
+
     Blob b;
     const size_t o_j = b.add(joints.data(), joints.size() * sizeof(JointRec));
     const size_t o_s = b.add(steps.data(), steps.size() * sizeof(StepRec));
     const size_t o_b = b.add(blocks.data(), blocks.size() * sizeof(BlockRec));
     const size_t o_e = b.add(entries.data(), entries.size() * sizeof(EntryRec));
     const size_t o_p = b.add(paths.data(), paths.size() * sizeof(int));
-    std::vector<JointRec> path_recs(paths.size());
-    for (size_t i = 0; i < paths.size(); ++i) path_recs[i] = joints[std::min<int>(paths[i], dof - 1)];
     const size_t o_pr = b.add(path_recs.data(), path_recs.size() * sizeof(JointRec));
     const size_t o_sp = b.add(spheres.data(), spheres.size() * sizeof(float4));
     const size_t o_ss = b.add(sphere_step.data(), sphere_step.size() * sizeof(int));
@@ -517,13 +546,6 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r) {
     r->dev.path_recs = reinterpret_cast<const JointRec *>(base + o_pr);
     r->dev.spheres = reinterpret_cast<const float4 *>(base + o_sp);
     r->dev.sphere_step = reinterpret_cast<const int32_t *>(base + o_ss);
-    r->dev.dof = dof;
-    r->dev.n_steps = (int)steps.size();
-    r->dev.n_slots = n_slots;
-    r->dev.n_spheres = S;
-    r->dev.n_links = dof + 1;
-    r->dof = dof;
-    r->n_spheres = S;
 }
 
 float int_bits(int v) {
@@ -1085,6 +1107,170 @@ int entry_int(const TuneEntry &e, const char *name) {
     return (int)it->second;
 }
 
+
+// ---- per-robot specialisation ----------------------------------------------------------------
+// The robot's program records written out as constant arrays of a struct R (exact: floats as
+// hexadecimal literals), and the persistent edge kernels instantiated on SpecProg<R>.  The
+// runtime compiler builds this source with the walk's headers, embedded in the library.
+std::string lit(float x) {
+    if (std::isnan(x)) return "__builtin_nanf(\"\")";
+    if (std::isinf(x)) return x > 0 ? "__builtin_inff()" : "-__builtin_inff()";
+    char b[48];
+    std::snprintf(b, sizeof b, "%af", (double)x);
+    return b;
+}
+
+template <class T>
+std::string lits(const T *x, int n) {
+    std::string o = "{";
+    for (int i = 0; i < n; ++i) o += (i ? ", " : "") + lit(x[i]);
+    return o + "}";
+}
+
+std::string joint_lit(const JointRec &J) {
+    static_assert(sizeof(JointRec) == 96, "JointRec fields changed: update joint_lit");
+    return "{" + lit(J.a) + ", " + lit(J.d) + ", " + lit(J.ca) + ", " + lit(J.sa) + ", " +
+           lit(J.theta_off) + ", " + lit(J.s_off) + ", " + lit(J.c_off) + ", " +
+           std::to_string(J.twist) + ", " + std::to_string(J.has_mount) + ", " +
+           std::to_string(J.parent) + ", " + std::to_string(J.prismatic) + ", " + lits(J.m, 12) +
+           ", " + std::to_string(J.index) + "}";
+}
+
+std::string step_lit(const StepRec &S) {
+    static_assert(sizeof(StepRec) == 192, "StepRec fields changed: update step_lit");
+    const int iv[8] = {S.joint, S.restart_off, S.restart_len, S.sph_first, S.sph_count,
+                       S.blk_first, S.blk_count, S.link};
+    std::string o = "{";
+    for (int v : iv) o += std::to_string(v) + ", ";
+    return o + lits(S.coarse, 4) + ", " + lits(S.cap_h, 3) + ", " + lit(S.cap_r) + ", " +
+           lit(S.cap_rq) + ", " + lit(S.cap_uu) + ", " + lit(S.cap_inv) + ", " +
+           std::to_string(S.slot) + ", " + lits(S.pad, 4) + ", " + joint_lit(S.jr) + "}";
+}
+
+std::string block_lit(const BlockRec &B) {
+    static_assert(sizeof(BlockRec) == 48, "BlockRec fields changed: update block_lit");
+    return "{" + std::to_string(B.step_a) + ", " + std::to_string(B.path_off) + ", " +
+           std::to_string(B.path_len) + ", " + std::to_string(B.ent_first) + ", " +
+           std::to_string(B.ent_count) + ", " + std::to_string(B.link) + ", " +
+           std::to_string(B.anc_lo) + "u, " + std::to_string(B.anc_hi) + "u, " +
+           std::to_string(B.slot_a) + ", " + lit(B.ra) + ", " + lit(B.rqa) + ", " + lit(B.pad) + "}";
+}
+
+std::string entry_lit(const EntryRec &E) {
+    static_assert(sizeof(EntryRec) == 64, "EntryRec fields changed: update entry_lit");
+    return "{" + lit(E.x) + ", " + lit(E.y) + ", " + lit(E.z) + ", " + lit(E.r) + ", " +
+           std::to_string(E.mask) + "u, " + lit(E.gate2) + ", " + lit(E.nhr2) + ", " + lit(E.pad) +
+           ", " + lits(E.rr, kSpl) + "}";
+}
+
+template <class T, class F>
+std::string array_lit(const char *type, const char *name, const std::vector<T> &v, F &&one) {
+    std::string o = "    static constexpr " + std::string(type) + " " + name + "[" +
+                    std::to_string(std::max<size_t>(v.size(), 1)) + "] = {\n";
+    if (v.empty()) o += "        " + one(T{}) + ",\n";   // a zero-length array is not C++
+    for (const T &x : v) o += "        " + one(x) + ",\n";
+    return o + "    };\n";
+}
+
+std::string spec_source(const vk_robot_s &r) {
+    std::string o = "// robot-specialised persistent edge kernels (generated)\n#include \"vk_walk.hpp\"\n"
+                    "namespace vk_spec_robot {\nusing namespace vk;\nstruct R {\n";
+    o += "    static constexpr int dof = " + std::to_string(r.dof) + ";\n";
+    o += "    static constexpr int n_steps = " + std::to_string(r.steps.size()) + ";\n";
+    o += array_lit("StepRec", "steps", r.steps, step_lit);
+    o += array_lit("BlockRec", "blocks", r.blocks, block_lit);
+    o += array_lit("EntryRec", "entries", r.entries, entry_lit);
+    o += array_lit("JointRec", "path_recs", r.path_recs, joint_lit);
+    o += "    static constexpr float4 spheres[" + std::to_string(std::max<size_t>(r.spheres.size(), 1)) +
+         "] = {\n";
+    if (r.spheres.empty()) o += "        {0, 0, 0, 0},\n";
+    for (const float4 &x : r.spheres) {
+        const float v[4] = {x.x, x.y, x.z, x.w};
+        o += "        float4" + lits(v, 4) + ",\n";
+    }
+    o += "    };\n};\n}  // namespace vk_spec_robot\n";
+    o += "#define VK_SPEC_EDGES(NAME, STAGE, COUNT)                                              \\\n"
+         "    extern \"C\" __global__ void __launch_bounds__(1024)                                  \\\n"
+         "        __attribute__((amdgpu_waves_per_eu(4, 8)))                                      \\\n"
+         "        NAME(vk::RobotDev rb, vk::EnvDev ed, const float4 *__restrict__ env_rec,         \\\n"
+         "             vk::EdgeSrc src, int64_t n_edges, float res, uint8_t *__restrict__ out,      \\\n"
+         "             unsigned long long *__restrict__ queue, int chunk,                          \\\n"
+         "             unsigned long long *__restrict__ flops, int cf) {                           \\\n"
+         "        vk::validate_edges_body<STAGE, COUNT>(vk::SpecProg<vk_spec_robot::R>{rb}, ed,     \\\n"
+         "                                              env_rec, src, n_edges, res, out, queue,    \\\n"
+         "                                              chunk, flops, cf);                         \\\n"
+         "    }\n";
+    for (int c = 0; c < 2; ++c)
+        for (int m = 0; m < 3; ++m)
+            o += "VK_SPEC_EDGES(vk_spec_edges" + std::string(c ? "_counted_" : "_") + std::to_string(m) +
+                 ", " + std::to_string(m) + ", " + (c ? "true" : "false") + ")\n";
+    return o;
+}
+
+// FNV-1a 64-bit of a string (the code-object cache key)
+uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull) {
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Compile the robot's source for `arch` (or take the code object from cache_dir); returns the
+// code object.
+std::vector<char> spec_compile(const std::string &src, const std::string &arch, const char *cache_dir) {
+    std::vector<std::string> opts = {"--offload-arch=" + arch, "-O3", "-std=c++17",
+                                     "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
+                                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    int n_hdr = 0;
+    const char *const *hdr_names = embedded_header_names(&n_hdr);
+    const char *const *hdr_text = embedded_header_texts();
+    std::string key = src + "|" + arch;
+    for (const auto &x : opts) key += "|" + x;
+    for (int i = 0; i < n_hdr; ++i) key += std::string("|") + hdr_names[i] + "|" + hdr_text[i];
+    char name[64];
+    std::snprintf(name, sizeof name, "vk_spec_%016llx.co", (unsigned long long)fnv1a(key));
+    const std::string path = cache_dir && *cache_dir ? std::string(cache_dir) + "/" + name : "";
+    if (!path.empty()) {
+        if (FILE *f = std::fopen(path.c_str(), "rb")) {
+            std::vector<char> code;
+            char buf[1 << 16];
+            size_t got;
+            while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) code.insert(code.end(), buf, buf + got);
+            std::fclose(f);
+            if (!code.empty()) return code;
+        }
+    }
+    hiprtcProgram prog = nullptr;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "vk_spec.hip", n_hdr, hdr_text, hdr_names) !=
+        HIPRTC_SUCCESS)
+        raise(VK_ERR_HIP, "hiprtcCreateProgram failed");
+    std::vector<const char *> o;
+    for (const auto &x : opts) o.push_back(x.c_str());
+    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)o.size(), o.data());
+    if (rc != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        hiprtcGetProgramLogSize(prog, &n);
+        std::string log(n + 1, '\0');
+        hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        raise(VK_ERR_HIP, "specialised kernels did not compile: " + log.substr(0, 2000));
+    }
+    size_t bytes = 0;
+    hiprtcGetCodeSize(prog, &bytes);
+    std::vector<char> code(bytes);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    if (!path.empty()) {                  // best effort: a cache that cannot be written is skipped
+        const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+        if (FILE *f = std::fopen(tmp.c_str(), "wb")) {
+            const bool ok = std::fwrite(code.data(), 1, code.size(), f) == code.size();
+            if (std::fclose(f) == 0 && ok) std::rename(tmp.c_str(), path.c_str());
+            else std::remove(tmp.c_str());
+        }
+    }
+    return code;
+}
 }  // namespace
 
 extern "C" {
@@ -1105,9 +1291,66 @@ vk_status vk_robot_create(const vk_robot_desc *desc, vk_robot *out) {
     });
 }
 
+vk_status vk_robot_specialize(vk_robot robot, const char *cache_dir) {
+    return guarded([&] {
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        if (robot->module) {
+            robot->use_spec = 1;
+            return;
+        }
+        hipDeviceProp_t prop{};
+        hip_check(hipGetDeviceProperties(&prop, robot->device), "hipGetDeviceProperties");
+        const std::vector<char> code = spec_compile(spec_source(*robot), prop.gcnArchName, cache_dir);
+        int cur = 0;
+        hip_check(hipGetDevice(&cur), "hipGetDevice");
+        if (cur != robot->device) hip_check(hipSetDevice(robot->device), "hipSetDevice");
+        hipModule_t mod = nullptr;
+        hipError_t err = hipModuleLoadData(&mod, code.data());
+        SpecEdgeKernels K;
+        for (int m = 0; m < 3 && err == hipSuccess; ++m) {
+            const std::string e = "vk_spec_edges_" + std::to_string(m), c = "vk_spec_edges_counted_" + std::to_string(m);
+            err = hipModuleGetFunction(&K.edges[m], mod, e.c_str());
+            if (err == hipSuccess) err = hipModuleGetFunction(&K.counted[m], mod, c.c_str());
+        }
+        if (err != hipSuccess && mod) (void)hipModuleUnload(mod);
+        if (cur != robot->device) (void)hipSetDevice(cur);
+        hip_check(err, "loading the specialised kernels");
+        robot->module = mod;
+        robot->spec = K;
+        robot->use_spec = 1;
+    });
+}
+
+vk_status vk_robot_use_specialized(vk_robot robot, int32_t on) {
+    return guarded([&] {
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        if (on && !robot->module) raise(VK_ERR_INVALID_ARG, "the robot has not been specialised");
+        robot->use_spec = on ? 1 : 0;
+    });
+}
+
+int32_t vk_robot_is_specialized(vk_robot robot) { return robot ? robot->use_spec.load() : -1; }
+
+int64_t vk_robot_spec_source(const vk_robot_desc *desc, char *buf, int64_t cap) {
+    int64_t len = -1;
+    const vk_status st = guarded([&] {
+        vk_robot_s r;
+        build_robot(desc, &r, false);
+        const std::string src = spec_source(r);
+        len = (int64_t)src.size() + 1;
+        if (buf && cap > 0) {
+            const size_t n = (size_t)std::min<int64_t>(cap - 1, (int64_t)src.size());
+            std::memcpy(buf, src.data(), n);
+            buf[n] = '\0';
+        }
+    });
+    return st == VK_OK ? len : -1;
+}
+
 vk_status vk_robot_destroy(vk_robot robot) {
     return guarded([&] {
         if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        if (robot->module) (void)hipModuleUnload(robot->module);
         hipError_t err = hipFree(robot->blob);
         delete robot;
         hip_check(err, "hipFree");
@@ -1243,10 +1486,15 @@ static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_
     const int64_t want = (n_edges + block / kWave - 1) / (block / kWave);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
     hip_check(launch_reset_queue(queue, s), "queue reset");
-    hip_check(launch_validate_edges(robot->dev, env_for_launch(env, walk_lds_bytes(robot->dev, block)),
-                                    src, n_edges, resolution, collide, queue, grid, block, tickets,
-                                    s, flops),
-              "validate_edges launch");
+    const EnvDev ed = env_for_launch(env, walk_lds_bytes(robot->dev, block));
+    if (robot->use_spec.load() && robot->module)
+        hip_check(launch_validate_edges_spec(robot->spec, robot->dev, ed, src, n_edges, resolution,
+                                             collide, queue, grid, block, tickets, s, flops),
+                  "validate_edges launch (specialised)");
+    else
+        hip_check(launch_validate_edges(robot->dev, ed, src, n_edges, resolution, collide, queue,
+                                        grid, block, tickets, s, flops),
+                  "validate_edges launch");
 }
 
 vk_status validate_edges(vk_robot robot, vk_env env, const float *qa, const float *qb,

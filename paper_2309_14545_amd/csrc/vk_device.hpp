@@ -2,7 +2,9 @@
 // sphere-vs-primitive overlap tests.  One lane holds one configuration; every robot or
 // environment value is wave-uniform.
 #pragma once
+#ifndef __HIPCC_RTC__                 // the runtime compiler provides the HIP device runtime itself
 #include <hip/hip_runtime.h>
+#endif
 
 #include "vk_types.hpp"
 

@@ -30,6 +30,19 @@ hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const Edg
                                  int64_t n_edges, float res, uint8_t *out,
                                  unsigned long long *queue, int grid, int block, int tickets,
                                  hipStream_t s, unsigned long long *flops = nullptr);
+// The walk's headers, embedded in the library for the runtime compiler (generated at build time).
+const char *const *embedded_header_names(int *n);
+const char *const *embedded_header_texts();
+// The persistent edge kernels compiled for one robot (vk_robot_specialize), by staging mode;
+// `counted` are the instrumented variants.
+struct SpecEdgeKernels {
+    hipFunction_t edges[3] = {nullptr, nullptr, nullptr};
+    hipFunction_t counted[3] = {nullptr, nullptr, nullptr};
+};
+hipError_t launch_validate_edges_spec(const SpecEdgeKernels &K, const RobotDev &rb, const EnvDev &ed,
+                                      const EdgeSrc &src, int64_t n_edges, float res, uint8_t *out,
+                                      unsigned long long *queue, int grid, int block, int tickets,
+                                      hipStream_t s, unsigned long long *flops = nullptr);
 hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                     int64_t e, float res, uint8_t *out, hipStream_t s);
 // kNN runs as partial lists over candidate parts plus a merge; the partial lists need a

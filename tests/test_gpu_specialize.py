@@ -1,0 +1,53 @@
+"""Robot-specialised edge kernels (vk_robot_specialize: the robot's program compiled in at run
+time) give bit-identical flags to the library's interpreted kernel, and agree with the FP64
+oracle outside the near-contact band; switching back and forth changes nothing."""
+import os
+
+import numpy as np
+import pytest
+
+from helpers import dev, host, say, edge_mismatches
+from synthetic import workload
+
+pytestmark = pytest.mark.gpu
+RES = 1.0 / 32.0
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "gpurun_out", "vk_spec_cache")
+
+
+@pytest.fixture(scope="module")
+def vk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2309_14545_amd as vk
+    vk.lib()
+    return vk
+
+
+@pytest.mark.parametrize("name", ["edges7_shelf", "edges8p_shelf"])
+def test_specialized_edges_match(vk, orc, name):
+    import time
+    import torch
+    w = workload(name, n=6000)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = dev(w["qa"]), dev(w["qb"])
+    ref = host(vk.validate_edges(r, e, qa, qb, resolution=RES))
+    os.makedirs(CACHE, exist_ok=True)
+    t0 = time.perf_counter()
+    r.specialize(CACHE)
+    say(f"specialize {name}: {time.perf_counter() - t0:.1f} s")
+    assert r.specialized
+    got = host(vk.validate_edges(r, e, qa, qb, resolution=RES))
+    np.testing.assert_array_equal(got, ref)
+    # indexed edges and the counted variant run the specialised kernels too
+    nodes = torch.cat([qa, qb])
+    pairs = torch.stack([torch.arange(6000, dtype=torch.int32), 6000 + torch.arange(6000, dtype=torch.int32)],
+                        dim=1).cuda()
+    np.testing.assert_array_equal(host(vk.validate_edges_indexed(r, e, nodes, pairs, resolution=RES)), ref)
+    flops = torch.zeros(8, dtype=torch.int64, device="cuda")
+    np.testing.assert_array_equal(host(vk.validate_edges_counted(r, e, qa, qb, flops, resolution=RES)), ref)
+    r.use_specialized(False)
+    assert not r.specialized
+    np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb, resolution=RES)), ref)
+    idx = np.sort(np.random.default_rng(4).choice(6000, 400, replace=False))
+    _, cls, _ = orc.edges(w["robot"], w["env"], w["qa"][idx], w["qb"][idx], res=RES)
+    assert edge_mismatches(got[idx], cls)[0] == 0
