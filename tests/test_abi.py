@@ -169,3 +169,25 @@ def test_reserve_argument_checks(vk):
     assert lib.vk_reserve(None, 0, -5, 0) == -1
     assert lib.vk_reserve(None, 0, 100, 33) == -1
     assert lib.vk_reserve(None, 1 << 31, 0, 0) == -2
+
+
+def test_specialisation_source_is_exact(vk):
+    """vk_robot_spec_source needs no device: the 7-DoF robot's generated source names its step
+    count and carries every sphere as exact hexadecimal floats."""
+    import re
+    from synthetic import workload
+    robot = workload("states7", n=1)["robot"]
+    src = vk.spec_source(robot)
+    steps = int(re.search(r"static constexpr int n_steps = (\d+);", src).group(1))
+    assert steps >= robot["dof"]            # at least one step per moving link
+    body = src[src.index("spheres["):src.index("};", src.index("spheres["))]
+    rows = re.findall(r"float4\{([^}]*)\}", body)
+    xyzr = np.asarray(robot["sphere_xyzr"], np.float32)
+    assert len(rows) == len(xyzr)
+    got = np.array([[float.fromhex(v.strip().rstrip("f")) for v in r.split(",")] for r in rows],
+                   np.float32)
+    np.testing.assert_array_equal(got, xyzr)
+    assert "vk_spec_edges_counted_2" in src
+    bad = dict(robot, sphere_link=np.asarray(robot["sphere_link"])[::-1].copy())
+    with pytest.raises(vk.VkError):
+        vk.spec_source(bad)
