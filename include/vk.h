@@ -431,6 +431,19 @@ vk_status vk_robot_set_states_split(vk_robot robot, int32_t num, int32_t den);
 vk_status vk_robot_get_states_split(vk_robot robot, int32_t *num, int32_t *den);
 
 /*
+ * Step ranges of a small validate_states batch (one pass only).  A batch of fewer than two waves
+ * (64 states each) per compute unit leaves most of the chip idle; each state's walk is then
+ * split over up to max_ranges contiguous ranges of link steps, each walked by its own waves
+ * (posing the earlier steps, testing its own), and a state's flag is 1 when any range finds a
+ * collision: the same flags as the whole walk.  -1 (the default) picks the count for the batch
+ * (enough ranges for two waves per CU, about equal work each, at most 16 and one per step);
+ * 0 or 1 never splits; 2..16 splits into at most that many ranges at any batch size.  Errors:
+ * VK_ERR_INVALID_ARG outside [-1, 16].
+ */
+vk_status vk_robot_set_states_ranges(vk_robot robot, int32_t max_ranges);
+vk_status vk_robot_get_states_ranges(vk_robot robot, int32_t *max_ranges);
+
+/*
  * Autotuner (a set-up call: it allocates, launches and waits for `stream`).  vk_autotune_edges
  * times validate_edges on the given batch (same arguments) for every workgroup size in
  * {64, 128, 256, 512, 1024}, workgroups per CU in {1, 2, 4, 8} (at most 2,048 threads per CU)

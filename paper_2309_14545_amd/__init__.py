@@ -33,7 +33,8 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_get_launch",
            "vk_edge_batch_destroy", "vk_reserve", "vk_release",
            "vk_robot_set_edge_launch", "vk_robot_get_edge_launch", "vk_robot_set_states_split",
-           "vk_robot_get_states_split", "vk_autotune_edges", "vk_autotune_states",
+           "vk_robot_get_states_split", "vk_robot_set_states_ranges", "vk_robot_get_states_ranges",
+           "vk_autotune_edges", "vk_autotune_states",
            "vk_last_error")
 
 
@@ -121,6 +122,8 @@ def lib():
         L.vk_robot_get_edge_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.vk_robot_set_states_split.argtypes = [vp, i32, i32]
         L.vk_robot_get_states_split.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+        L.vk_robot_set_states_ranges.argtypes = [vp, i32]
+        L.vk_robot_get_states_ranges.argtypes = [vp, C.POINTER(i32)]
         L.vk_autotune_edges.argtypes = [vp, vp, vp, vp, vp, i64, fp, C.c_char_p, i32, vp]
         L.vk_autotune_states.argtypes = [vp, vp, vp, i64, i64, C.c_char_p, i32, vp]
         L.vk_last_error.restype = C.c_char_p
@@ -221,6 +224,10 @@ class Robot:
     def set_states_split(self, num: int, den: int = 1):
         """Two-pass schedule of validate_states for this robot; (0, 1) = one pass."""
         _check(lib().vk_robot_set_states_split(self.handle, int(num), int(den)))
+
+    def set_states_ranges(self, max_ranges: int = -1):
+        """Step ranges of small state batches (-1 automatic, 0 or 1 never, k at most k)."""
+        _check(lib().vk_robot_set_states_ranges(self.handle, int(max_ranges)))
 
     def get_states_split(self):
         n, d = C.c_int32(), C.c_int32()

@@ -299,6 +299,7 @@ struct vk_robot_s {
     std::atomic<int> edge_block{kDefaultEdgeBlock}, edge_bpc{kDefaultEdgeBpc};
     std::atomic<int> edge_tickets{kDefaultTickets};
     std::atomic<int> split_num{0}, split_den{1};
+    std::atomic<int> max_ranges{-1};   // step ranges of a small state batch: -1 automatic
 };
 
 struct vk_env_s {
@@ -1409,6 +1410,51 @@ vk_status fk_spheres(vk_robot robot, const float *q, int64_t n, int64_t ldq, flo
     });
 }
 
+// Step ranges for a state batch too small to fill the chip (fewer than two waves per CU): the
+// robot's steps split into contiguous ranges of about equal work (a step weighs 4 plus the
+// entries of its self blocks), enough of them to bring the batch to two waves per CU, at most
+// kMaxRanges and at most one per step.  The robot's max_ranges setting overrides the count
+// (0 or 1: never split).
+StepRanges state_ranges(const vk_robot_s &r, int64_t n) {
+    StepRanges R{};
+    R.n = 1;
+    R.b[0] = 0;
+    R.b[1] = (int)r.steps.size();
+    const int S = (int)r.steps.size();
+    const int setting = r.max_ranges.load();
+    const int64_t waves = (n + kWave - 1) / kWave;
+    int T;
+    if (setting < 0) {
+        const int64_t want = 2 * (int64_t)device_info(r.device).n_cu;
+        if (waves >= want) return R;
+        T = (int)std::min<int64_t>(kMaxRanges, (want + waves - 1) / waves);
+    } else {
+        T = std::min(setting, kMaxRanges);
+    }
+    T = std::min(T, S);
+    if (T <= 1) return R;
+    std::vector<double> w(S, 0.0);
+    double total = 0.0;
+    for (int i = 0; i < S; ++i) {
+        const StepRec &st = r.steps[i];
+        w[i] = st.sph_count > 0 ? 4.0 : 1.0;
+        for (int b = st.blk_first; b < st.blk_first + st.blk_count; ++b) w[i] += r.blocks[b].ent_count;
+        total += w[i];
+    }
+    // range y ends after the first step where the running weight reaches (y + 1) / T of the
+    // total, leaving at least one step for every later range
+    int y = 0;
+    double cum = 0.0;
+    for (int i = 0; i < S && y < T - 1; ++i) {
+        cum += w[i];
+        const int left = S - (i + 1);
+        if ((cum >= total * (y + 1) / T && left >= T - 1 - y) || left == T - 1 - y) R.b[++y] = i + 1;
+    }
+    R.n = y + 1;
+    R.b[R.n] = S;
+    return R;
+}
+
 vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n, int64_t ldq,
                           uint8_t *collide, void *stream) {
     return guarded([&] {
@@ -1419,9 +1465,10 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
         const int split = states_split(robot->dev, n, robot->split_num.load(), robot->split_den.load());
         void *scratch =
             split > 0 ? workspace_for(s, states_scratch_bytes(n), "validate_states").scratch : nullptr;
+        const StepRanges ranges = state_ranges(*robot, n);
         hip_check(launch_validate_states(robot->dev,
                                          env_for_launch(env, walk_lds_bytes(robot->dev, walk_block(robot->dev, 256))), q, n,
-                                         ldq, collide, split, scratch, s),
+                                         ldq, collide, split, scratch, s, &ranges),
                   "validate_states launch");
     });
 }
@@ -1954,6 +2001,23 @@ vk_status vk_robot_get_states_split(vk_robot robot, int32_t *num, int32_t *den) 
         if (!num || !den) raise(VK_ERR_INVALID_ARG, "NULL output");
         *num = robot->split_num;
         *den = robot->split_den;
+    });
+}
+
+vk_status vk_robot_set_states_ranges(vk_robot robot, int32_t max_ranges) {
+    return guarded([&] {
+        if (max_ranges < -1 || max_ranges > kMaxRanges)
+            raise(VK_ERR_INVALID_ARG, "max_ranges must be -1 (automatic) or in [0, 16]");
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        robot->max_ranges = max_ranges;
+    });
+}
+
+vk_status vk_robot_get_states_ranges(vk_robot robot, int32_t *max_ranges) {
+    return guarded([&] {
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        if (!max_ranges) raise(VK_ERR_INVALID_ARG, "NULL output");
+        *max_ranges = robot->max_ranges;
     });
 }
 

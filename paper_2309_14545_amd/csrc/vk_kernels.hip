@@ -55,12 +55,17 @@ __global__ void __launch_bounds__(256) k_fk_spheres(RobotDev rb, const float *__
 // ---------------------------------------------------------------------------------------------
 // validate_states: one lane per state.
 // ---------------------------------------------------------------------------------------------
+// With one step range the whole walk runs and every flag is stored.  A small batch (too few
+// waves to fill the chip) is split over step ranges: block row y tests steps
+// [b[y], b[y + 1]) only, posing the earlier ones; the flags were zeroed and a range stores 1
+// where it finds a collision, so a state's flag is the OR over the ranges, the flag of the
+// whole walk.
 // four waves per SIMD (at most 128 VGPRs): left alone the compiler takes 133 and fits three
 template <int STAGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
     k_validate_states(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                       const float *__restrict__ q, int64_t n, int64_t ldq,
-                      uint8_t *__restrict__ out, int cf) {
+                      uint8_t *__restrict__ out, int cf, StepRanges ranges) {
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
     const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
@@ -73,8 +78,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     bool col = !active;                       // inactive lanes count as decided
     if (active)
         for (int j = 0; j < rb.dof; ++j) col |= !isfinite(qs(j));
-    col = walk_collide<false>(DynProg{rb}, ev, ed, qs, sc, col, 0, rb.n_steps);
-    if (active) out[i] = col ? 1 : 0;
+    if (ranges.n <= 1) {
+        col = walk_collide<false>(DynProg{rb}, ev, ed, qs, sc, col, 0, rb.n_steps);
+        if (active) out[i] = col ? 1 : 0;
+        return;
+    }
+    const int y = blockIdx.y;
+    col = walk_collide<false>(DynProg{rb}, ev, ed, qs, sc, col, ranges.b[y], ranges.b[y + 1]);
+    if (active && col) out[i] = 1;
 }
 
 // Two-pass state validation.  In a wave of independent states the walk lasts until its last
@@ -199,6 +210,11 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
         const uint8_t hit = edge_body(DynProg{S.rb}, ev, S.env, sc, a, b, n);
         out[S.out_offset + local] = hit;      // wave-uniform value
     }
+}
+
+__global__ void k_zero_u8(uint8_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n, int stride) {
@@ -1121,18 +1137,27 @@ hipError_t noalloc_scratch(void **ptr) {
 
 hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
                                   int64_t ldq, uint8_t *out, int split, void *scratch,
-                                  hipStream_t s) {
+                                  hipStream_t s, const StepRanges *ranges) {
     const int bs = walk_block(rb, 256);
-    const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, bs, c); };
     const size_t max_lds_ = device_max_lds();
     if (!scratch) split = 0;
     if (split == 0) {
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, out, cf
+        StepRanges r;
+        r.n = 1;
+        r.b[0] = 0;
+        r.b[1] = rb.n_steps;
+        if (ranges && ranges->n > 1) {
+            r = *ranges;
+            hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n);
+        }
+        const dim3 grid_((unsigned)((n + bs - 1) / bs), (unsigned)r.n), block_(bs);
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, out, cf, r
         VK_STAGED(k_validate_states)
 #undef ARGS_
         return hipGetLastError();
     }
+    const dim3 grid_((unsigned)((n + bs - 1) / bs)), block_(bs);
     unsigned long long *n_surv = static_cast<unsigned long long *>(scratch);
     int32_t *surv = reinterpret_cast<int32_t *>(static_cast<char *>(scratch) + 256);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, n_surv, 0ull, 1, 1);

@@ -11,11 +11,13 @@ hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int6
                              float *out, int64_t ldc, hipStream_t s);
 // State validation; with split > 0 and scratch (states_scratch_bytes(n) bytes) it runs in two
 // passes, the second over the states still free after the first `split` link steps.
+// Without the two passes, `ranges` (optional, n > 1) splits a small batch's walk over step
+// ranges run by separate waves.
 int states_split(const RobotDev &rb, int64_t n, int num, int den);
 size_t states_scratch_bytes(int64_t n);
 hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const float *q, int64_t n,
                                   int64_t ldq, uint8_t *out, int split, void *scratch,
-                                  hipStream_t s);
+                                  hipStream_t s, const StepRanges *ranges = nullptr);
 // The allocation-free form's scratch (a file-scope device array, states_scratch_bytes of up to
 // noalloc_max_states() states): its address on the current device, looked up once per device.
 int64_t noalloc_max_states();

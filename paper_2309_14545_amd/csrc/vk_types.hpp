@@ -176,6 +176,14 @@ struct GridDev {
     float porg[3], pinv, pcell, pq;
 };
 
+// Contiguous ranges of link steps that separate waves walk for one state: range y is
+// [b[y], b[y + 1]), y < n.
+constexpr int kMaxRanges = 16;
+struct StepRanges {
+    int32_t n;
+    int32_t b[kMaxRanges + 1];
+};
+
 // One edge set of a mixed-robot batch.
 // Where the endpoints of edge e come from: rows e of qa and qb (pairs == nullptr), or rows
 // pairs[2e] and pairs[2e+1] of the node array qa ([n_nodes][dof]).  nst, when not null, gives
