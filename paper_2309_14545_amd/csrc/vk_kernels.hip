@@ -259,14 +259,32 @@ struct LinkSlots {
     __device__ __forceinline__ float &at(int link, int c) const {
         return base[(link * 6 + c) * kWave + lane];
     }
-    __device__ __forceinline__ void add(int link, float px, float py, float pz, float fx,
-                                        float fy, float fz) const {
+    // a force and its moment about the world origin, summed in registers by the caller over
+    // the spheres of one step or the entries of one self block: one update of the link's slots
+    __device__ __forceinline__ void add_fm(int link, float fx, float fy, float fz, float mx,
+                                           float my, float mz) const {
         at(link, 0) += fx;
         at(link, 1) += fy;
         at(link, 2) += fz;
-        at(link, 3) += py * fz - pz * fy;      // moment about the world origin: p x f
-        at(link, 4) += pz * fx - px * fz;
-        at(link, 5) += px * fy - py * fx;
+        at(link, 3) += mx;
+        at(link, 4) += my;
+        at(link, 5) += mz;
+    }
+};
+
+// Running force and moment (about the world origin, p x f) of forces f applied at points p.
+struct ForceSum {
+    float fx = 0.0f, fy = 0.0f, fz = 0.0f, mx = 0.0f, my = 0.0f, mz = 0.0f;
+    __device__ __forceinline__ void add(float px, float py, float pz, float gx, float gy, float gz) {
+        fx += gx;
+        fy += gy;
+        fz += gz;
+        mx = fmaf(py, gz, mx) - pz * gy;
+        my = fmaf(pz, gx, my) - px * gz;
+        mz = fmaf(px, gy, mz) - py * gx;
+    }
+    __device__ __forceinline__ void to(const LinkSlots &s, int link) const {
+        s.add_fm(link, fx, fy, fz, mx, my, mz);
     }
 };
 
@@ -373,6 +391,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
                 if (!wave_ballot(live && d2 < rc * rc)) continue;
             }
             pose_block(DynProg{rb}, B, Ta, ta_link, ta_depth, sc, q);
+            ForceSum fa;                         // the forces on A's spheres from this block
             for (int e = 0; e < B.ent_count; ++e) {
                 const EntryRec E = ld(rb.entries, B.ent_first + e);
                 float tx, ty, tz;
@@ -402,13 +421,16 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
                         }
                     }
                 }
-                if (GRAD) slots.add(B.link, tx, ty, tz, gtx, gty, gtz);
+                if (GRAD) fa.add(tx, ty, tz, gtx, gty, gtz);
             }
+            if (GRAD) fa.to(slots, B.link);
         }
         if (GRAD) {
+            ForceSum fs;                         // the forces on this step's spheres
 #pragma unroll
             for (int k = 0; k < kSpl; ++k)
-                if (k < cnt) slots.add(S.link, cx[k], cy[k], cz[k], fx[k], fy[k], fz[k]);
+                if (k < cnt) fs.add(cx[k], cy[k], cz[k], fx[k], fy[k], fz[k]);
+            fs.to(slots, S.link);
         }
     }
     return cost;
