@@ -131,6 +131,13 @@ int64_t vk_robot_spec_source(const vk_robot_desc *desc, char *buf, int64_t cap);
  * point from below anywhere in the cell; 5.6 MB of device memory in all, 5.2 MB of it the
  * field, for the 20,000 points of a 2.7 m x 2.2 m x 2 m scene).  Queries are unchanged: these structures only skip tests that cannot hit. */
 vk_status vk_env_create(const vk_env_desc *desc, vk_env *out);
+/* Host-only dry run of vk_env_create (no device needed): checks the description as create
+ * does and builds the same structures.  Returns the device bytes the environment would take
+ * (-1 for an invalid description, with vk_last_error), and writes the first n_out of: spheres,
+ * capsules, cylinders, boxes kept as primitives, spheres moved to the point grid, voxel cells,
+ * voxel candidate entries, point-grid cells, clearance-field cells. */
+int64_t vk_env_describe(const vk_env_desc *desc, int64_t *out, int32_t n_out);
+
 vk_status vk_env_destroy(vk_env env);
 
 /*

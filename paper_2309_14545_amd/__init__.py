@@ -24,7 +24,7 @@ _STATUS = {-1: "VK_ERR_INVALID_ARG", -2: "VK_ERR_SHAPE", -3: "VK_ERR_UNSUPPORTED
 EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_spheres",
            "vk_robot_specialize", "vk_robot_use_specialized", "vk_robot_is_specialized",
            "vk_robot_spec_source",
-           "vk_env_create", "vk_env_destroy", "vk_edge_states", "fk_spheres", "validate_states",
+           "vk_env_create", "vk_env_destroy", "vk_env_describe", "vk_edge_states", "fk_spheres", "validate_states",
            "validate_states_noalloc", "validate_edges",
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
            "vk_knn", "vk_knn_pairs", "vk_tree_nearest", "vk_tree_steer", "vk_tree_append",
@@ -90,6 +90,8 @@ def lib():
         L.vk_robot_spec_source.restype = i64
         L.vk_env_create.argtypes = [C.POINTER(_EnvDesc), C.POINTER(vp)]
         L.vk_env_destroy.argtypes = [vp]
+        L.vk_env_describe.argtypes = [C.POINTER(_EnvDesc), C.POINTER(i64), i32]
+        L.vk_env_describe.restype = i64
         L.vk_edge_states.argtypes = [C.POINTER(fp), C.POINTER(fp), i32, fp]
         L.vk_edge_states.restype = i64
         L.fk_spheres.argtypes = [vp, vp, i64, i64, vp, i64, vp]
@@ -129,7 +131,7 @@ def lib():
         L.vk_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("vk_robot_dof", "vk_robot_n_spheres", "vk_last_error", "vk_edge_states",
-                            "vk_robot_is_specialized", "vk_robot_spec_source"):
+                            "vk_robot_is_specialized", "vk_robot_spec_source", "vk_env_describe"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -240,17 +242,37 @@ class Robot:
             self.handle = None
 
 
+def _env_desc(desc: dict):
+    """(vk_env_desc, the arrays it points into) for a dict of numpy arrays."""
+    arrs = {}
+    for key, w in (("spheres", 4), ("capsules", 7), ("cylinders", 8), ("boxes", 15)):
+        a = desc.get(key)
+        arrs[key] = _f32(a if a is not None else np.zeros((0, w)), (-1, w))
+    d = _EnvDesc(len(arrs["spheres"]), _fp(arrs["spheres"]), len(arrs["capsules"]),
+                 _fp(arrs["capsules"]), len(arrs["cylinders"]), _fp(arrs["cylinders"]),
+                 len(arrs["boxes"]), _fp(arrs["boxes"]))
+    return d, arrs
+
+
+ENV_FIELDS = ("spheres", "capsules", "cylinders", "boxes", "points", "voxel_cells",
+              "voxel_entries", "grid_cells", "field_cells")
+
+
+def env_describe(desc: dict) -> dict:
+    """vk_env_describe: what vk_env_create would build (no device needed)."""
+    d, _keep = _env_desc(desc)
+    out = (C.c_int64 * len(ENV_FIELDS))()
+    b = lib().vk_env_describe(C.byref(d), out, len(ENV_FIELDS))
+    if b < 0:
+        raise VkError(-1, lib().vk_last_error().decode())
+    return dict(zip(ENV_FIELDS, list(out)), device_bytes=int(b))
+
+
 class Env:
     """Device-resident environment (see vk_env_desc)."""
 
     def __init__(self, desc: dict):
-        arrs = {}
-        for key, w in (("spheres", 4), ("capsules", 7), ("cylinders", 8), ("boxes", 15)):
-            a = desc.get(key)
-            arrs[key] = _f32(a if a is not None else np.zeros((0, w)), (-1, w))
-        d = _EnvDesc(len(arrs["spheres"]), _fp(arrs["spheres"]), len(arrs["capsules"]),
-                     _fp(arrs["capsules"]), len(arrs["cylinders"]), _fp(arrs["cylinders"]),
-                     len(arrs["boxes"]), _fp(arrs["boxes"]))
+        d, arrs = _env_desc(desc)
         h = C.c_void_p()
         _check(lib().vk_env_create(C.byref(d), C.byref(h)))
         self.handle = h

@@ -307,6 +307,8 @@ struct vk_env_s {
     void *blob = nullptr;
     EnvDev dev{};
     int64_t n_points = 0;              // spheres kept in the point grid
+    int64_t n_vlist = 0, n_field = 0;  // voxel candidate entries, clearance-field cells
+    size_t host_bytes = 0;             // device memory the environment takes
 };
 
 struct vk_edge_batch_s {
@@ -608,7 +610,7 @@ double host_sd(const HostPrim &p, const double *x) {
     }
 }
 
-void build_env(const vk_env_desc *d, vk_env_s *e) {
+void build_env(const vk_env_desc *d, vk_env_s *e, bool upload = true) {
     if (!d) raise(VK_ERR_INVALID_ARG, "env desc is NULL");
     const int ns = d->n_spheres, nc = d->n_capsules, ny = d->n_cylinders, nb = d->n_boxes;
     if (ns < 0 || nc < 0 || ny < 0 || nb < 0) raise(VK_ERR_INVALID_ARG, "negative primitive count");
@@ -901,6 +903,10 @@ void build_env(const vk_env_desc *d, vk_env_s *e) {
     const size_t o_l = bl.add(vlist.data(), vlist.size() * sizeof(int2));
     const size_t o_f = bl.add(pfield.data(), pfield.size());
     const size_t o_g = bl.add(&gd, sizeof gd);     // its pointers are set after the upload
+    e->host_bytes = bl.host.size();
+    e->n_vlist = (int64_t)vlist.size();
+    e->n_field = (int64_t)pfield.size();
+    if (!upload) return;
     e->device = current_device();
     e->blob = bl.upload();
     char *base = static_cast<char *>(e->blob);
@@ -1387,6 +1393,21 @@ vk_status vk_env_create(const vk_env_desc *desc, vk_env *out) {
         }
         *out = e;
     });
+}
+
+int64_t vk_env_describe(const vk_env_desc *desc, int64_t *out, int32_t n_out) {
+    int64_t bytes = -1;
+    const vk_status st = guarded([&] {
+        if (n_out < 0 || (n_out > 0 && !out)) raise(VK_ERR_INVALID_ARG, "vk_env_describe: bad output");
+        vk_env_s e;
+        build_env(desc, &e, false);
+        const int64_t v[7] = {e.dev.n_sph, e.dev.n_cap, e.dev.n_cyl, e.dev.n_box, e.n_points,
+                              (int64_t)e.dev.n_vox, e.n_vlist};
+        const int64_t more[2] = {(int64_t)e.dev.n_cells, e.n_field};
+        for (int i = 0; i < n_out && i < 9; ++i) out[i] = i < 7 ? v[i] : more[i - 7];
+        bytes = (int64_t)e.host_bytes;
+    });
+    return st == VK_OK ? bytes : -1;
 }
 
 vk_status vk_env_destroy(vk_env env) {
