@@ -190,6 +190,32 @@ def extra_specialized(vk, name, steps):
     return res
 
 
+def extra_fine(vk, steps, res=1.0 / 256.0, n=8192):
+    """The shelf batch at a fine resolution (1/256 rad: up to ~1,500 states per edge), one wave
+    per edge against the autotuned parts per edge."""
+    import torch
+    from synthetic import workload
+    from paper_2309_14545_amd import autotune
+    w = workload("edges7_shelf", n=n)
+    robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = torch.from_numpy(w["qa"]).cuda(), torch.from_numpy(w["qb"]).cuda()
+    out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    nominal = int(state_counts(w["qa"], w["qb"], res).sum())
+    autotune.tune_edges(robot, env, qa, qb, resolution=res, cache=None)
+    parts = robot.edge_parts
+    res_ = {"workload": f"edges7_shelf at {res} rad", "edges": n, "nominal_states": nominal,
+            "launch": list(robot.get_edge_launch())}
+    for label, p in (("one_wave_per_edge", 1), ("tuned_parts", parts)):
+        robot.set_edge_parts(p)
+        vk.validate_edges(robot, env, qa, qb, resolution=res, out=out)
+        torch.cuda.synchronize()
+        m = float(np.median(_events_ms(
+            lambda: vk.validate_edges(robot, env, qa, qb, resolution=res, out=out), steps)))
+        res_[label] = {"parts": p, "launch_ms": m, "states_per_s": nominal / (m * 1e-3)}
+    res_["edge_collision_rate"] = float(out.float().mean().item())
+    return res_
+
+
 def scene_summary_of(w):
     from synthetic import scene_summary
     return scene_summary(w["env"])
@@ -531,6 +557,7 @@ def main():
         for key, fn in (("edges8_shelf", lambda: extra_edges(vk, "edges8_shelf", 10)),
                         ("edges7_shelf_near", lambda: extra_edges(vk, "edges7_shelf_near", 10)),
                         ("fk14", lambda: extra_fk(vk, "states14_cloud", 1 << 20, 10)),
+                        ("edges7_fine", lambda: extra_fine(vk, 10)),
                         ("states7", lambda: extra_states(vk, "states7", None, 20)),
                         ("states7_1M", lambda: extra_states(vk, "states7", 1 << 20, 10)),
                         ("states14_cloud", lambda: extra_states(vk, "states14_cloud", None, 5)),

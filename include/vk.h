@@ -430,6 +430,18 @@ vk_status vk_release(void *stream);
  * Invalid values: VK_ERR_INVALID_ARG.  Settings may change between calls; a call uses the
  * values it reads when it is made.
  */
+/*
+ * Waves sharing one edge (long edges: the rake of Sec. III-D spread over several 64-lane
+ * waves).  With parts P > 1 every edge becomes P work items; part p walks the rake steps
+ * p, p + P, p + 2P, ... of the edge (each part starts with a step that samples the whole
+ * motion), a part that finds a collision sets the edge's flag, and the others stop before
+ * their next step.  Flags are those of P = 1.  An edge of n states has ceil(n / 64) rake steps,
+ * so parts pay off when that is well above P (fine resolutions, long explicit counts); for
+ * short edges the extra items only cost queue tickets.  1..64 (else VK_ERR_INVALID_ARG),
+ * default 1; vk_robot_get_edge_parts returns it (-1 for NULL).
+ */
+vk_status vk_robot_set_edge_parts(vk_robot robot, int32_t parts);
+int32_t vk_robot_get_edge_parts(vk_robot robot);
 vk_status vk_robot_set_edge_launch(vk_robot robot, int32_t block_threads, int32_t blocks_per_cu,
                                    int32_t tickets_per_wave);
 vk_status vk_robot_get_edge_launch(vk_robot robot, int32_t *block_threads, int32_t *blocks_per_cu,
@@ -455,7 +467,8 @@ vk_status vk_robot_get_states_ranges(vk_robot robot, int32_t *max_ranges);
  * times validate_edges on the given batch (same arguments) for every workgroup size in
  * {64, 128, 256, 512, 1024}, workgroups per CU in {1, 2, 4, 8} (at most 2,048 threads per CU)
  * and tickets per wave in {4, 8, 16}, each the median of 7 launches after one untimed launch,
- * and sets the fastest on the robot.  vk_autotune_states does the same for the validate_states
+ * then parts per edge in {1, 2, 4, 8} at the fastest of those, and sets the fastest on the
+ * robot.  vk_autotune_states does the same for the validate_states
  * schedules one pass, and two passes split after 1/3, 1/2 and 2/3 of the steps.  With a
  * cache_path (else NULL), results are kept in that JSON file keyed by the workload's class
  * (device, dof, sphere count, primitive count and batch size, the counts rounded up to powers of

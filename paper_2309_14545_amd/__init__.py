@@ -32,7 +32,8 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "penetration_cost_fwd", "penetration_cost_bwd",
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_get_launch",
            "vk_edge_batch_destroy", "vk_reserve", "vk_release",
-           "vk_robot_set_edge_launch", "vk_robot_get_edge_launch", "vk_robot_set_states_split",
+           "vk_robot_set_edge_launch", "vk_robot_get_edge_launch", "vk_robot_set_edge_parts",
+           "vk_robot_get_edge_parts", "vk_robot_set_states_split",
            "vk_robot_get_states_split", "vk_robot_set_states_ranges", "vk_robot_get_states_ranges",
            "vk_autotune_edges", "vk_autotune_states",
            "vk_last_error")
@@ -122,6 +123,9 @@ def lib():
         L.vk_release.argtypes = [vp]
         L.vk_robot_set_edge_launch.argtypes = [vp, i32, i32, i32]
         L.vk_robot_get_edge_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.vk_robot_set_edge_parts.argtypes = [vp, i32]
+        L.vk_robot_get_edge_parts.argtypes = [vp]
+        L.vk_robot_get_edge_parts.restype = i32
         L.vk_robot_set_states_split.argtypes = [vp, i32, i32]
         L.vk_robot_get_states_split.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.vk_robot_set_states_ranges.argtypes = [vp, i32]
@@ -131,7 +135,8 @@ def lib():
         L.vk_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("vk_robot_dof", "vk_robot_n_spheres", "vk_last_error", "vk_edge_states",
-                            "vk_robot_is_specialized", "vk_robot_spec_source", "vk_env_describe"):
+                            "vk_robot_is_specialized", "vk_robot_spec_source", "vk_env_describe",
+                            "vk_robot_get_edge_parts"):
                 getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -217,6 +222,14 @@ class Robot:
         """Launch shape of this robot's edge launches (all 0: the defaults 256, 4, 8)."""
         _check(lib().vk_robot_set_edge_launch(self.handle, int(block_threads), int(blocks_per_cu),
                                               int(tickets_per_wave)))
+
+    def set_edge_parts(self, parts: int = 1):
+        """Waves sharing one edge's rake (long edges); 1 = one wave per edge."""
+        _check(lib().vk_robot_set_edge_parts(self.handle, int(parts)))
+
+    @property
+    def edge_parts(self) -> int:
+        return int(lib().vk_robot_get_edge_parts(self.handle))
 
     def get_edge_launch(self):
         b, p, t = C.c_int32(), C.c_int32(), C.c_int32()

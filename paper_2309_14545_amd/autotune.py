@@ -34,8 +34,8 @@ def _path(cache):
 
 def tune_edges(robot, env, qa, qb, n_states=None, resolution: float = 1.0 / 32.0,
                cache: str | None = DEFAULT_CACHE, force: bool = False):
-    """Pick and set the robot's fastest edge launch for this batch; returns (block, per_cu,
-    tickets)."""
+    """Pick and set the robot's fastest edge launch for this batch (the launch shape, then the
+    parts per edge); returns (block, per_cu, tickets)."""
     qa, qb = _dev_f32(qa, "qa"), _dev_f32(qb, "qb")
     ns = n_states.contiguous().data_ptr() if n_states is not None else None
     _check(lib().vk_autotune_edges(robot.handle, env.handle, qa.data_ptr(), qb.data_ptr(), ns,

@@ -298,6 +298,7 @@ struct vk_robot_s {
     // launch settings of this robot's calls (set by the autotuner or the caller)
     std::atomic<int> edge_block{kDefaultEdgeBlock}, edge_bpc{kDefaultEdgeBpc};
     std::atomic<int> edge_tickets{kDefaultTickets};
+    std::atomic<int> edge_parts{1};    // waves sharing one edge's rake (long edges)
     std::atomic<int> split_num{0}, split_den{1};
     std::atomic<int> max_ranges{-1};   // step ranges of a small state batch: -1 automatic
 };
@@ -1202,10 +1203,10 @@ std::string spec_source(const vk_robot_s &r) {
          "        NAME(vk::RobotDev rb, vk::EnvDev ed, const float4 *__restrict__ env_rec,         \\\n"
          "             vk::EdgeSrc src, int64_t n_edges, float res, uint8_t *__restrict__ out,      \\\n"
          "             unsigned long long *__restrict__ queue, int chunk,                          \\\n"
-         "             unsigned long long *__restrict__ flops, int cf) {                           \\\n"
+         "             unsigned long long *__restrict__ flops, int cf, int parts) {                \\\n"
          "        vk::validate_edges_body<STAGE, COUNT>(vk::SpecProg<vk_spec_robot::R>{rb}, ed,     \\\n"
          "                                              env_rec, src, n_edges, res, out, queue,    \\\n"
-         "                                              chunk, flops, cf);                         \\\n"
+         "                                              chunk, flops, cf, parts);                  \\\n"
          "    }\n";
     for (int c = 0; c < 2; ++c)
         for (int m = 0; m < 3; ++m)
@@ -1542,26 +1543,28 @@ static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_
     unsigned long long *queue = workspace_for(s, 0, "validate_edges").queue;
     int block = robot->edge_block.load();
     const int bpc = robot->edge_bpc.load(), tickets = robot->edge_tickets.load();
+    const int parts = robot->edge_parts.load();
     // a workgroup's per-wave caches must fit the LDS: smaller workgroups for large robots
     while (block > kWave && walk_lds_bytes(robot->dev, block) > di.max_lds) block -= kWave;
     // a batch too small to give every CU a workgroup of this size (planner rounds of a few
     // thousand edges) is spread over more CUs in smaller workgroups of at least four waves:
     // such launches are bound by the latency of one walk, not by throughput
-    if (n_edges < (int64_t)di.n_cu * (block / kWave)) {
-        const int64_t waves = std::max<int64_t>(4, (n_edges + di.n_cu - 1) / di.n_cu);
+    const int64_t items = n_edges * parts;
+    if (items < (int64_t)di.n_cu * (block / kWave)) {
+        const int64_t waves = std::max<int64_t>(4, (items + di.n_cu - 1) / di.n_cu);
         block = (int)std::min<int64_t>(block, waves * kWave);
     }
-    const int64_t want = (n_edges + block / kWave - 1) / (block / kWave);
+    const int64_t want = (items + block / kWave - 1) / (block / kWave);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
     hip_check(launch_reset_queue(queue, s), "queue reset");
     const EnvDev ed = env_for_launch(env, walk_lds_bytes(robot->dev, block));
     if (robot->use_spec.load() && robot->module)
         hip_check(launch_validate_edges_spec(robot->spec, robot->dev, ed, src, n_edges, resolution,
-                                             collide, queue, grid, block, tickets, s, flops),
+                                             collide, queue, grid, block, tickets, parts, s, flops),
                   "validate_edges launch (specialised)");
     else
         hip_check(launch_validate_edges(robot->dev, ed, src, n_edges, resolution, collide, queue,
-                                        grid, block, tickets, s, flops),
+                                        grid, block, tickets, parts, s, flops),
                   "validate_edges launch");
 }
 
@@ -2042,6 +2045,16 @@ vk_status vk_robot_get_states_ranges(vk_robot robot, int32_t *max_ranges) {
     });
 }
 
+vk_status vk_robot_set_edge_parts(vk_robot robot, int32_t parts) {
+    return guarded([&] {
+        if (parts < 1 || parts > 64) raise(VK_ERR_INVALID_ARG, "parts must be in [1, 64]");
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        robot->edge_parts = parts;
+    });
+}
+
+int32_t vk_robot_get_edge_parts(vk_robot robot) { return robot ? robot->edge_parts.load() : -1; }
+
 vk_status vk_robot_set_edge_launch(vk_robot robot, int32_t block_threads, int32_t blocks_per_cu,
                                    int32_t tickets_per_wave) {
     return guarded([&] {
@@ -2082,7 +2095,8 @@ vk_status vk_autotune_edges(vk_robot robot, vk_env env, const float *qa, const f
         if (!force && hit != cache.end()) {
             const int block = entry_int(hit->second, "block"), bpc = entry_int(hit->second, "per_cu"),
                       tickets = entry_int(hit->second, "tickets");
-            bool valid = true;
+            const int parts = hit->second.count("parts") ? entry_int(hit->second, "parts") : 1;
+            bool valid = parts >= 1 && parts <= 64;
             try {
                 check_launch(block, bpc, tickets);
             } catch (const VkError &) {
@@ -2092,6 +2106,7 @@ vk_status vk_autotune_edges(vk_robot robot, vk_env env, const float *qa, const f
                 robot->edge_block = block;
                 robot->edge_bpc = bpc;
                 robot->edge_tickets = tickets;
+                robot->edge_parts = parts;
                 return;
             }
         }
@@ -2099,8 +2114,10 @@ vk_status vk_autotune_edges(vk_robot robot, vk_env env, const float *qa, const f
         uint8_t *flags = nullptr;
         hip_check(hipMalloc(&flags, (size_t)n_edges), "autotune flags");
         std::vector<std::array<double, 4>> results;   // ms, block, per_cu, tickets
+        std::vector<std::array<double, 2>> by_parts;  // ms, parts
         try {
             const EdgeSrc src{qa, qb, nullptr, 0, n_states};
+            robot->edge_parts = 1;
             for (int block : {64, 128, 256, 512, 1024})
                 for (int bpc : {1, 2, 4, 8}) {
                     if (block * bpc > 2048) continue;      // more waves than a CU holds
@@ -2114,18 +2131,31 @@ vk_status vk_autotune_edges(vk_robot robot, vk_env env, const float *qa, const f
                         results.push_back({ms, (double)block, (double)bpc, (double)tickets});
                     }
                 }
+            const auto best = *std::min_element(results.begin(), results.end());
+            robot->edge_block = (int)best[1];
+            robot->edge_bpc = (int)best[2];
+            robot->edge_tickets = (int)best[3];
+            by_parts.push_back({best[0], 1.0});
+            for (int parts : {2, 4, 8}) {
+                robot->edge_parts = parts;
+                by_parts.push_back({time_median(s, [&] {
+                                        run_edges(robot, env, src, n_edges, resolution, flags,
+                                                  nullptr, stream);
+                                    }),
+                                    (double)parts});
+            }
         } catch (...) {
+            robot->edge_parts = 1;
             (void)hipFree(flags);
             throw;
         }
         hip_check(hipFree(flags), "hipFree");
-        const auto best = *std::min_element(results.begin(), results.end());
-        robot->edge_block = (int)best[1];
-        robot->edge_bpc = (int)best[2];
-        robot->edge_tickets = (int)best[3];
+        const auto bp = *std::min_element(by_parts.begin(), by_parts.end());
+        robot->edge_parts = (int)bp[1];
         if (cache_path && *cache_path) {
             TuneCache now = load_tune_cache(cache_path);
-            now[key] = {{"block", best[1]}, {"per_cu", best[2]}, {"tickets", best[3]}, {"ms", best[0]}};
+            now[key] = {{"block", (double)robot->edge_block.load()}, {"per_cu", (double)robot->edge_bpc.load()},
+                        {"tickets", (double)robot->edge_tickets.load()}, {"parts", bp[1]}, {"ms", bp[0]}};
             save_tune_cache(cache_path, now);
         }
     });

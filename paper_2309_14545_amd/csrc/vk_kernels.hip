@@ -159,9 +159,9 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
     k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                      EdgeSrc src, int64_t n_edges, float res,
                      uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
-                     int chunk, unsigned long long *__restrict__ flops, int cf) {
+                     int chunk, unsigned long long *__restrict__ flops, int cf, int parts) {
     validate_edges_body<STAGE, COUNT>(DynProg{rb}, ed, env_rec, src, n_edges, res, out, queue,
-                                      chunk, flops, cf);
+                                      chunk, flops, cf, parts);
 }
 
 template <int STAGE>
@@ -1339,12 +1339,15 @@ static int work_chunk(int64_t n_items, int grid, int block, int tickets) {
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,
                                  unsigned long long *queue, int grid, int block, int tickets,
-                                 hipStream_t s, unsigned long long *flops) {
+                                 int parts, hipStream_t s, unsigned long long *flops) {
     const dim3 grid_(grid), block_(block);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, block, c); };
     const size_t max_lds_ = device_max_lds();
-    const int chunk = work_chunk(n_edges, grid, block, tickets);
-#define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, cf
+    const int chunk = work_chunk(n_edges * parts, grid, block, tickets);
+    if (parts > 1)
+        hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)((n_edges + 255) / 256)), dim3(256), 0, s, out,
+                           n_edges);
+#define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, cf, parts
     if (flops) {
         VK_STAGED(k_validate_edges, , true)
     } else {
@@ -1374,11 +1377,14 @@ static int resident_blocks_fn(hipFunction_t f, int block, size_t lds) {
 hipError_t launch_validate_edges_spec(const SpecEdgeKernels &K, const RobotDev &rb,
                                       const EnvDev &ed_in, const EdgeSrc &src, int64_t n_edges,
                                       float res, uint8_t *out, unsigned long long *queue, int grid,
-                                      int block, int tickets, hipStream_t s,
+                                      int block, int tickets, int parts, hipStream_t s,
                                       unsigned long long *flops) {
     const hipFunction_t *fk = flops ? K.counted : K.edges;
     const size_t max_lds = device_max_lds();
-    const int chunk = work_chunk(n_edges, grid, block, tickets);
+    const int chunk = work_chunk(n_edges * parts, grid, block, tickets);
+    if (parts > 1)
+        hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)((n_edges + 255) / 256)), dim3(256), 0, s, out,
+                           n_edges);
     // the cache parts and the staging mode as VK_STAGED chooses them for the library's kernels
     EnvDev ed = ed_in;
     int cf = 0, mode = 0, best = -1;
@@ -1412,7 +1418,7 @@ hipError_t launch_validate_edges_spec(const SpecEdgeKernels &K, const RobotDev &
     const float4 *rec = ed.rec;
     EdgeSrc src_ = src;
     void *args[] = {&rb_, &ed, &rec, &src_, &n_edges, &res, &out, &queue,
-                    const_cast<int *>(&chunk), &flops, &cf};
+                    const_cast<int *>(&chunk), &flops, &cf, &parts};
     return hipModuleLaunchKernel(fk[mode], (unsigned)grid, 1, 1, (unsigned)block, 1, 1, (unsigned)sh,
                                  s, args, nullptr);
 }

@@ -31,7 +31,7 @@ hipError_t launch_shortcut_apply(float *paths, int32_t *lens, int64_t P, int M, 
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,
                                  unsigned long long *queue, int grid, int block, int tickets,
-                                 hipStream_t s, unsigned long long *flops = nullptr);
+                                 int parts, hipStream_t s, unsigned long long *flops = nullptr);
 // The walk's headers, embedded in the library for the runtime compiler (generated at build time).
 const char *const *embedded_header_names(int *n);
 const char *const *embedded_header_texts();
@@ -44,7 +44,7 @@ struct SpecEdgeKernels {
 hipError_t launch_validate_edges_spec(const SpecEdgeKernels &K, const RobotDev &rb, const EnvDev &ed,
                                       const EdgeSrc &src, int64_t n_edges, float res, uint8_t *out,
                                       unsigned long long *queue, int grid, int block, int tickets,
-                                      hipStream_t s, unsigned long long *flops = nullptr);
+                                      int parts, hipStream_t s, unsigned long long *flops = nullptr);
 hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                     int64_t e, float res, uint8_t *out, hipStream_t s);
 // kNN runs as partial lists over candidate parts plus a merge; the partial lists need a

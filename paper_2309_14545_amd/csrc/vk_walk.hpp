@@ -839,10 +839,20 @@ __device__ __forceinline__ int edge_ends(const EdgeSrc &src, int dof, int64_t e,
     return 0;
 }
 
+// Has another part of the edge already found a collision (its flag set)?  A coherent load:
+// the flag may have been stored by a wave on another compute unit.
+__device__ __forceinline__ bool edge_flagged(const uint8_t *flag) {
+    return __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Part `part` of `parts` of the edge's rake: the rake steps k = part, part + parts, ... (all of
+// them for parts == 1).  Every part starts with a step that samples the whole motion, and a
+// part stops early once another part has flagged the edge (flag, read only when parts > 1).
 template <class P, class V, class W = NoWork>
 __device__ __forceinline__ uint8_t edge_body(const P &pg, const V &ev, const EnvDev &ed,
                                              const StepCache &sc, const float *a, const float *b,
-                                             int n, W &&work = W()) {
+                                             int n, W &&work = W(), int part = 0, int parts = 1,
+                                             const uint8_t *flag = nullptr) {
     bool bad = false;
     for (int j = 0; j < pg.dof(); ++j) bad |= !isfinite(ld(a, j)) || !isfinite(ld(b, j));
     if (bad) return 1;
@@ -851,7 +861,8 @@ __device__ __forceinline__ uint8_t edge_body(const P &pg, const V &ev, const Env
     const int lane = threadIdx.x & (kWave - 1);
     const int stride = (n + kWave - 1) / kWave;
     const float inv = 1.0f / (float)(n - 1);
-    for (int k = 0; k < stride; ++k) {
+    for (int k = part; k < stride; k += parts) {
+        if (parts > 1 && k != part && edge_flagged(flag)) return 0;
         int idx = lane * stride + k;
         work.rake_slot(idx < n);
         idx = idx < n ? idx : n - 1;          // surplus lanes repeat the last state
@@ -915,15 +926,20 @@ __device__ __forceinline__ bool pull(Puller &p, int lane, int64_t &first, int64_
 }
 
 
-// The persistent edge launch: waves pull chunks of edges from the work queue and validate each
-// edge with the rake (the kernels of both program sources call this).
+// The persistent edge launch: waves pull chunks of work items from the work queue and walk
+// each with the rake (the kernels of both program sources call this).  With parts == 1 an
+// item is an edge and its flag is stored as found.  With parts > 1 (long edges) item i is part
+// i / n_edges of edge i % n_edges (part-major, so the parts of one edge sit in different queue
+// ranges and run on different waves at about the same time); the flags were zeroed and a part
+// stores 1 when it finds a collision.
 template <int STAGE, bool COUNT, class P>
 __device__ __forceinline__ void validate_edges_body(const P &pg, const EnvDev &ed,
                                                     const float4 *__restrict__ env_rec,
                                                     const EdgeSrc &src, int64_t n_edges, float res,
                                                     uint8_t *__restrict__ out,
                                                     unsigned long long *__restrict__ queue, int chunk,
-                                                    unsigned long long *__restrict__ flops, int cf) {
+                                                    unsigned long long *__restrict__ flops, int cf,
+                                                    int parts) {
     const RobotDev &rb = pg.rb;
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
@@ -933,18 +949,23 @@ __device__ __forceinline__ void validate_edges_body(const P &pg, const EnvDev &e
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int lane = threadIdx.x & (kWave - 1);
     typename std::conditional<COUNT, Work, NoWork>::type work;
-    Puller pl = make_puller(queue, n_edges, chunk);
+    Puller pl = make_puller(queue, n_edges * parts, chunk);
     int64_t first, count;
     while (pull(pl, lane, first, count)) {
-        for (int64_t e = first; e < first + count; ++e) {
+        for (int64_t item = first; item < first + count; ++item) {
+            const int part = parts > 1 ? (int)(item / n_edges) : 0;
+            const int64_t e = parts > 1 ? item - part * n_edges : item;
             const float *a = nullptr, *b = nullptr;
             const int kind = edge_ends(src, pg.dof(), e, a, b);
             uint8_t hit = kind == 2 ? 1 : 0;
             if (kind == 0) {
                 const int n = src.nst ? ld(src.nst, e) : edge_count(a, b, pg.dof(), res);
-                hit = edge_body(pg, ev, ed, sc, a, b, n, work);
+                hit = edge_body(pg, ev, ed, sc, a, b, n, work, part, parts, out + e);
             }
-            out[e] = hit;                     // wave-uniform value, same address in every lane
+            if (parts == 1)
+                out[e] = hit;                 // wave-uniform value, same address in every lane
+            else if (hit)
+                out[e] = 1;
         }
     }
     if constexpr (COUNT) {

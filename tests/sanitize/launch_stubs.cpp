@@ -33,11 +33,11 @@ hipError_t launch_shortcut_apply(float *, int32_t *, int64_t, int, int, int, con
     no_device("launch_shortcut_apply");
 }
 hipError_t launch_validate_edges(const RobotDev &, const EnvDev &, const EdgeSrc &, int64_t, float,
-                                 uint8_t *, unsigned long long *, int, int, int, hipStream_t,
+                                 uint8_t *, unsigned long long *, int, int, int, int, hipStream_t,
                                  unsigned long long *) { no_device("launch_validate_edges"); }
 hipError_t launch_validate_edges_spec(const SpecEdgeKernels &, const RobotDev &, const EnvDev &,
                                       const EdgeSrc &, int64_t, float, uint8_t *,
-                                      unsigned long long *, int, int, int, hipStream_t,
+                                      unsigned long long *, int, int, int, int, hipStream_t,
                                       unsigned long long *) {
     no_device("launch_validate_edges_spec");
 }

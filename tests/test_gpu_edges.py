@@ -178,3 +178,47 @@ def test_edges_beyond_the_state_limit(vk):
     ns[7] = 2 ** 24 + 1
     f2 = host(vk.validate_edges(r, e, dev(w["qa"]), dev(w["qb"]), n_states=dev(ns)))
     assert f2[7] == 1
+
+
+@pytest.mark.parametrize("res", [1.0 / 256.0, 1.0 / 1024.0])
+def test_long_edges_split_over_waves(vk, orc, res):
+    """Long edges (fine resolutions: up to ~1,500 and ~6,000 states) with their rake split over
+    several waves give bitwise the flags of one wave per edge, for every part count, and agree
+    with the oracle outside the band."""
+    w = workload("edges7_shelf", n=1200 if res > 1e-3 else 300)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = dev(w["qa"]), dev(w["qb"])
+    ref = host(vk.validate_edges(r, e, qa, qb, resolution=res))
+    for parts in (2, 3, 4, 8, 64):
+        r.set_edge_parts(parts)
+        assert r.edge_parts == parts
+        np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb, resolution=res)), ref,
+                                      err_msg=f"parts {parts}")
+    idx = np.sort(np.random.default_rng(6).choice(len(w["qa"]), 60, replace=False))
+    _, cls, _ = orc.edges(w["robot"], w["env"], w["qa"][idx], w["qb"][idx], res=res)
+    bad, near = edge_mismatches(ref[idx], cls)
+    say(f"long edges at {res:.5f} rad: {len(ref)} edges, rate {ref.mean():.3f}, sample mismatches "
+        f"{bad}, near {near}")
+    assert bad == 0
+
+
+def test_parts_with_explicit_counts_and_indexed_edges(vk):
+    """Parts with explicit state counts (2 .. 5,000) and with index-pair edges (holes and
+    out-of-range indices included) equal one wave per edge."""
+    import torch
+    w = workload("edges7_shelf", n=900)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = dev(w["qa"]), dev(w["qb"])
+    ns = torch.from_numpy(np.random.default_rng(9).integers(2, 5000, 900).astype(np.int32)).cuda()
+    nodes = torch.cat([qa, qb])
+    pairs = torch.stack([torch.arange(900, dtype=torch.int32), 900 + torch.arange(900, dtype=torch.int32)], 1)
+    pairs[5] = torch.tensor([-1, -1], dtype=torch.int32)
+    pairs[7] = torch.tensor([3, 5000], dtype=torch.int32)
+    pairs = pairs.cuda()
+    ref_n = host(vk.validate_edges(r, e, qa, qb, n_states=ns))
+    ref_i = host(vk.validate_edges_indexed(r, e, nodes, pairs))
+    assert ref_i[5] == 0 and ref_i[7] == 1
+    for parts in (2, 5, 16):
+        r.set_edge_parts(parts)
+        np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb, n_states=ns)), ref_n)
+        np.testing.assert_array_equal(host(vk.validate_edges_indexed(r, e, nodes, pairs)), ref_i)
