@@ -269,9 +269,11 @@ def extra_cost(vk, steps):
     torch.cuda.synchronize()
     fwd = _events_ms(lambda: vk.penetration_cost_fwd(robot, env, q), steps)
     bwd = _events_ms(lambda: vk.penetration_cost_bwd(robot, env, q, gc), steps)
-    f, b = float(np.median(fwd)), float(np.median(bwd))
-    return {"workload": "cost7", "states": n, "fwd_ms": f, "bwd_ms": b,
-            "fwd_bwd_states_per_s": n / ((f + b) * 1e-3)}
+    both = _events_ms(lambda: vk.penetration_cost_fwd_grad(robot, env, q), steps)
+    f, b, fb = float(np.median(fwd)), float(np.median(bwd)), float(np.median(both))
+    return {"workload": "cost7", "states": n, "fwd_ms": f, "bwd_ms": b, "fwd_grad_ms": fb,
+            "fwd_bwd_states_per_s": n / ((f + b) * 1e-3),
+            "fwd_grad_states_per_s": n / (fb * 1e-3)}
 
 
 def extra_prm(vk, steps):

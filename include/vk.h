@@ -363,6 +363,17 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
                                void *stream);
 
 /*
+ * The cost and its gradient from one adjoint walk (the adjoint computes the cost anyway):
+ * cost [n] exactly as penetration_cost_fwd gives it, and grad_q[j][i] = d cost_i / d q_j as
+ * penetration_cost_bwd gives it for grad_cost = 1.  One launch instead of two for a forward and
+ * backward pass (the autograd function calls this in its forward when q needs a gradient and
+ * scales the result by grad_cost in its backward).  Arguments and errors as the two calls.
+ */
+vk_status penetration_cost_fwd_grad(vk_robot robot, vk_env env, const float *q, int64_t n,
+                                    int64_t ldq, float *cost, float *grad_q, int64_t ldg,
+                                    void *stream);
+
+/*
  * Mixed-robot edge batches: several edge sets, each with its own robot and environment, run as
  * one persistent launch, held in a HIP graph {work-queue reset -> launch} built at create and
  * replayed by vk_edge_batch_run.  Set k covers edges [qa_offset / dof_k, ... + n_edges) of the

@@ -29,7 +29,7 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "validate_edges_per_edge", "validate_edges_counted", "validate_edges_indexed",
            "vk_knn", "vk_knn_pairs", "vk_tree_nearest", "vk_tree_steer", "vk_tree_append",
            "vk_rrt_extend", "vk_rrt_commit", "vk_shortcut_propose", "vk_shortcut_apply",
-           "penetration_cost_fwd", "penetration_cost_bwd",
+           "penetration_cost_fwd", "penetration_cost_bwd", "penetration_cost_fwd_grad",
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_get_launch",
            "vk_edge_batch_destroy", "vk_reserve", "vk_release",
            "vk_robot_set_edge_launch", "vk_robot_get_edge_launch", "vk_robot_set_edge_parts",
@@ -114,6 +114,7 @@ def lib():
         L.vk_shortcut_apply.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp, vp]
         L.penetration_cost_fwd.argtypes = [vp, vp, vp, i64, i64, vp, vp]
         L.penetration_cost_bwd.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
+        L.penetration_cost_fwd_grad.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
         L.vk_edge_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp), i32,
                                            C.POINTER(_EdgeSet), i32, fp, i32, i32, C.POINTER(vp)]
         L.vk_edge_batch_run.argtypes = [vp, vp, vp, vp, vp]
@@ -608,23 +609,39 @@ def penetration_cost_bwd(robot: Robot, env: Env, q, grad_cost):
     return out
 
 
+def penetration_cost_fwd_grad(robot: Robot, env: Env, q):
+    """(cost [N], d cost / d q [dof, N]) from one adjoint launch."""
+    torch = _torch()
+    q = _soa(robot, q)
+    n = q.shape[1]
+    cost = torch.empty(n, dtype=torch.float32, device=q.device)
+    grad = torch.empty((robot.dof, n), dtype=torch.float32, device=q.device)
+    _check(lib().penetration_cost_fwd_grad(robot.handle, env.handle, q.data_ptr(), n, n,
+                                           cost.data_ptr(), grad.data_ptr(), n, _stream()))
+    return cost, grad
+
+
 def _make_cost_function():
     torch = _torch()
 
     class PenetrationCost(torch.autograd.Function):
-        """cost = PenetrationCost.apply(q, robot, env): differentiable in q ([dof, N])."""
+        """cost = PenetrationCost.apply(q, robot, env): differentiable in q ([dof, N]).  When q
+        needs a gradient, the forward runs the adjoint walk once (cost and d cost / d q), and
+        the backward scales that gradient by grad_cost; otherwise the forward runs the cost
+        kernel alone."""
 
         @staticmethod
         def forward(ctx, q, robot, env):
-            ctx.robot, ctx.env = robot, env
-            ctx.save_for_backward(q)
-            return penetration_cost_fwd(robot, env, q)
+            if not ctx.needs_input_grad[0]:
+                return penetration_cost_fwd(robot, env, q)
+            cost, grad = penetration_cost_fwd_grad(robot, env, q)
+            ctx.save_for_backward(grad)
+            return cost
 
         @staticmethod
         def backward(ctx, grad_cost):
-            (q,) = ctx.saved_tensors
-            g = penetration_cost_bwd(ctx.robot, ctx.env, q, grad_cost.contiguous())
-            return g, None, None
+            (grad,) = ctx.saved_tensors
+            return grad * grad_cost.reshape(1, -1), None, None
 
     return PenetrationCost
 

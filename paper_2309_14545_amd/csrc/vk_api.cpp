@@ -1774,6 +1774,22 @@ vk_status penetration_cost_fwd(vk_robot robot, vk_env env, const float *q, int64
     });
 }
 
+// the adjoint launch shared by penetration_cost_bwd and penetration_cost_fwd_grad
+static void run_cost_bwd(vk_robot robot, vk_env env, const float *q, int64_t n, int64_t ldq,
+                         const float *grad_cost, float *grad_q, int64_t ldg, float *cost,
+                         void *stream) {
+    const DeviceInfo &di = device_info(robot->device);
+    // three waves per workgroup: the per-link force slots make the LDS the limit, and
+    // three 3-wave workgroups of the 7-DoF robot fit a CU where only two 4-wave ones do
+    int block = 192;
+    while (block > 64 && cost_bwd_slot_bytes(robot->dev, block, 0) > di.max_lds) block -= 64;
+    const size_t slots = cost_bwd_slot_bytes(robot->dev, block, 0);
+    if (slots > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the backward kernel");
+    hip_check(launch_cost_bwd(robot->dev, env_for_launch(env, slots), q, n, ldq, grad_cost, grad_q,
+                              ldg, block, (hipStream_t)stream, cost),
+              "penetration cost adjoint launch");
+}
+
 vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64_t n,
                                int64_t ldq, const float *grad_cost, float *grad_q, int64_t ldg,
                                void *stream) {
@@ -1783,16 +1799,20 @@ vk_status penetration_cost_bwd(vk_robot robot, vk_env env, const float *q, int64
         if (n > 0 && !grad_cost) raise(VK_ERR_INVALID_ARG, "grad_cost is NULL");
         if (ldg < n) raise(VK_ERR_SHAPE, "penetration_cost_bwd: ldg < n");
         if (n == 0) return;
-        const DeviceInfo &di = device_info(robot->device);
-        // three waves per workgroup: the per-link force slots make the LDS the limit, and
-        // three 3-wave workgroups of the 7-DoF robot fit a CU where only two 4-wave ones do
-        int block = 192;
-        while (block > 64 && cost_bwd_slot_bytes(robot->dev, block, 0) > di.max_lds) block -= 64;
-        const size_t slots = cost_bwd_slot_bytes(robot->dev, block, 0);
-        if (slots > di.max_lds) raise(VK_ERR_UNSUPPORTED, "robot too large for the backward kernel");
-        hip_check(launch_cost_bwd(robot->dev, env_for_launch(env, slots), q, n, ldq, grad_cost,
-                                  grad_q, ldg, block, (hipStream_t)stream),
-                  "penetration_cost_bwd launch");
+        run_cost_bwd(robot, env, q, n, ldq, grad_cost, grad_q, ldg, nullptr, stream);
+    });
+}
+
+vk_status penetration_cost_fwd_grad(vk_robot robot, vk_env env, const float *q, int64_t n,
+                                    int64_t ldq, float *cost, float *grad_q, int64_t ldg,
+                                    void *stream) {
+    return guarded([&] {
+        check_pair(robot, env);
+        check_batch(n, ldq, q, grad_q, "penetration_cost_fwd_grad");
+        if (n > 0 && !cost) raise(VK_ERR_INVALID_ARG, "cost is NULL");
+        if (ldg < n) raise(VK_ERR_SHAPE, "penetration_cost_fwd_grad: ldg < n");
+        if (n == 0) return;
+        run_cost_bwd(robot, env, q, n, ldq, nullptr, grad_q, ldg, cost, stream);
     });
 }
 

@@ -463,7 +463,8 @@ template <int STAGE>
 __global__ void __launch_bounds__(256)
     k_cost_bwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                const float *__restrict__ q, int64_t n, int64_t ldq,
-               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg, int cf) {
+               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg,
+               float *__restrict__ cost_out, int cf) {
     extern __shared__ float4 lds_dyn[];
     // layout: [slots for every wave of the block][env records]
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -483,7 +484,10 @@ __global__ void __launch_bounds__(256)
     QState qs{q, ldq, active ? i : 0};
     bool finite = true;
     for (int j = 0; j < rb.dof; ++j) finite &= isfinite(qs(j));
-    cost_walk<true>(rb, ev, ed, qs, sc, active && finite, slots);
+    // the gradient's walk computes the cost too (in the forward walk's order): with cost_out it
+    // is stored, and without gcost the gradient is d cost / d q itself
+    const float cost = cost_walk<true>(rb, ev, ed, qs, sc, active && finite, slots);
+    if (cost_out && active) cost_out[i] = finite ? cost : __builtin_nanf("");
 
     // suffix sums: child link totals into the parent (parents have smaller indices)
     for (int l = rb.n_links - 1; l >= 1; --l) {
@@ -491,7 +495,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int c = 0; c < 6; ++c) slots.at(p, c) += slots.at(l, c);
     }
-    const float gc = active ? gcost[i] : 0.0f;
+    const float gc = active ? (gcost ? gcost[i] : 1.0f) : 0.0f;
     // one more forward pass for the joint frames P_j = T_parent(j) * M_j
     Frame T;
     frame_identity(T);
@@ -1453,11 +1457,11 @@ size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, int cf) {
 
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
                            int64_t ldq, const float *gcost, float *grad, int64_t ldg, int block,
-                           hipStream_t s) {
+                           hipStream_t s, float *cost) {
     const dim3 grid_((unsigned)((n + block - 1) / block)), block_(block);
     const auto lds_ = [&](int c) { return cost_bwd_slot_bytes(rb, block, c); };
     const size_t max_lds_ = device_max_lds();
-#define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg, cf
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg, cost, cf
     VK_STAGED(k_cost_bwd)
 #undef ARGS_
     return hipGetLastError();

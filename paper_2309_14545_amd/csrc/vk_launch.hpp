@@ -86,9 +86,11 @@ size_t walk_lds_bytes(const RobotDev &rb, int block, int cf = 0);
 // Workgroup size of the state and cost-forward launches: `want` threads, fewer (whole waves,
 // at least one) when the per-wave walk caches of a long robot would not fit the LDS.
 int walk_block(const RobotDev &rb, int want);
+// The adjoint: grad = gcost * d cost / d q (gcost NULL: the plain gradient); with `cost` the
+// per-state cost is stored too.
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
-                           int block, hipStream_t s);
+                           int block, hipStream_t s, float *cost = nullptr);
 
 // A kernel launch spelled out for a graph node: the kernel, its shape and its argument values
 // (args[i] points at the i-th value held in the node itself, so a node must not be copied

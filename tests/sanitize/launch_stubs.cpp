@@ -73,7 +73,7 @@ size_t cost_bwd_slot_bytes(const RobotDev &, int, int) { no_device("cost_bwd_slo
 size_t walk_lds_bytes(const RobotDev &, int, int) { no_device("walk_lds_bytes"); }
 int walk_block(const RobotDev &, int) { no_device("walk_block"); }
 hipError_t launch_cost_bwd(const RobotDev &, const EnvDev &, const float *, int64_t, int64_t,
-                           const float *, float *, int64_t, int, hipStream_t) {
+                           const float *, float *, int64_t, int, hipStream_t, float *) {
     no_device("launch_cost_bwd");
 }
 void fill_node(KernelNode &, unsigned long long *, unsigned long long, int, int) { no_device("fill_node"); }

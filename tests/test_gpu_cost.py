@@ -143,3 +143,30 @@ def test_cost_non_finite(vk):
     assert np.isnan(c[5]) and np.isfinite(np.delete(c, 5)).all()
     g = host(vk.penetration_cost_bwd(r, e, dev(q), dev(np.ones(q.shape[1], np.float32))))
     assert np.isnan(g[:, 5]).all() and np.isfinite(np.delete(g, 5, axis=1)).all()
+
+
+def test_fwd_grad_equals_the_two_calls(vk):
+    """penetration_cost_fwd_grad (one adjoint walk) gives bitwise the cost of
+    penetration_cost_fwd and the gradient of penetration_cost_bwd with grad_cost = 1; the
+    autograd function built on it matches penetration_cost_bwd for any grad_cost."""
+    import torch
+    w = workload("cost7", n=64)
+    q = w["q"].copy()
+    q[4, 17] = np.inf
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qd = dev(q)
+    n = q.shape[1]
+    cost, grad = vk.penetration_cost_fwd_grad(r, e, qd)
+    c_ref = host(vk.penetration_cost_fwd(r, e, qd))
+    g_ref = host(vk.penetration_cost_bwd(r, e, qd, torch.ones(n, device="cuda")))
+    np.testing.assert_array_equal(host(cost), c_ref)
+    np.testing.assert_array_equal(host(grad), g_ref)
+    assert np.isnan(host(cost)[17]) and (host(cost) > 0).any()
+    gc = torch.from_numpy(np.random.default_rng(1).normal(size=n).astype(np.float32)).cuda()
+    qg = dev(w["q"]).requires_grad_(True)
+    (vk.penetration_cost(qg, r, e) * gc).sum().backward()
+    direct = vk.penetration_cost_bwd(r, e, qg.detach(), gc)
+    torch.testing.assert_close(qg.grad, direct, rtol=0, atol=0)
+    with torch.no_grad():                     # no gradient wanted: the cost kernel alone
+        np.testing.assert_array_equal(host(vk.penetration_cost(dev(w["q"]), r, e)),
+                                      host(vk.penetration_cost_fwd(r, e, dev(w["q"]))))
