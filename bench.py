@@ -8,10 +8,12 @@ whole batch in one persistent launch (`validate_edges`); the plain one-launch-pe
 (`validate_edges_per_edge`) is timed on the same batch for comparison.
 
 `value` = nominal states (sum of the edges' state counts) per second of the batched step,
-inputs resident in HBM.  The roofline entry divides the FP32 operations the launch actually
-executes (counted by the instrumented variant of the same kernel) by the mean launch time
-measured with HIP events on the launch stream.  `cpu_baseline` is the FP64 oracle on a bounded
-sample of the same edges, on all host cores.
+inputs resident in HBM.  The roofline entry divides the method's own FP32 operations in one
+launch (FK and sphere placement, culling, fine tests, self pairs; counted by the instrumented
+variant of the same kernel, which also reports what re-posing and surplus rake lanes add) by the
+mean launch time measured with HIP events on the launch stream.  `cpu_baseline` is the FP64
+oracle on a bounded sample of the same edges, on all host cores and on one, and `parity` checks
+the GPU flags of that sample against the oracle's classes.
 
 Progress goes to stderr; stdout carries exactly one JSON line.
 """
@@ -35,9 +37,9 @@ PEAK_FP32_UNPACKED = 78.6e12  # without packed FP32 instructions (this build dis
 # the counters were taken on: bench reports it while the sources hash the same, else null.
 TRAFFIC = {
     "workload": "edges7_shelf",
-    "fetch_kib": 7294.6, "fetch_scale": 2.0, "write_kib": 7507.7, "write_scale": 1.0,
-    "sources": {"vk_kernels.hip": "80f73c9d8c0c5ccb", "vk_device.hpp": "5d8b77bd9180a572",
-                "vk_types.hpp": "2be14aa53786df5c"},
+    "fetch_kib": 7222.5, "fetch_scale": 2.0, "write_kib": 8389.1, "write_scale": 1.0,
+    "sources": {"vk_kernels.hip": "436914be4debd425", "vk_device.hpp": "be73a313bc9ad869",
+                "vk_types.hpp": "a0c4a8292bb2936e", "vk_walk.hpp": "fc3ee92a57f149da"},
 }
 
 

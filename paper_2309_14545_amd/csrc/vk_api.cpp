@@ -1204,7 +1204,7 @@ std::string spec_source(const vk_robot_s &r) {
          "             vk::EdgeSrc src, int64_t n_edges, float res, uint8_t *__restrict__ out,      \\\n"
          "             unsigned long long *__restrict__ queue, int chunk,                          \\\n"
          "             unsigned long long *__restrict__ flops, int cf, int parts) {                \\\n"
-         "        vk::validate_edges_body<STAGE, COUNT>(vk::SpecProg<vk_spec_robot::R>{rb}, ed,     \\\n"
+         "        vk::validate_edges_body<STAGE, COUNT, true>(vk::SpecProg<vk_spec_robot::R>{rb}, ed,\\\n"
          "                                              env_rec, src, n_edges, res, out, queue,    \\\n"
          "                                              chunk, flops, cf, parts);                  \\\n"
          "    }\n";

@@ -154,14 +154,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 #define VK_EDGE_WAVES 4
 #endif
 
-template <int STAGE, bool COUNT>
+template <int STAGE, bool COUNT, bool MULTI>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_EDGE_WAVES, 8)))
     k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                      EdgeSrc src, int64_t n_edges, float res,
                      uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
                      int chunk, unsigned long long *__restrict__ flops, int cf, int parts) {
-    validate_edges_body<STAGE, COUNT>(DynProg{rb}, ed, env_rec, src, n_edges, res, out, queue,
-                                      chunk, flops, cf, parts);
+    validate_edges_body<STAGE, COUNT, MULTI>(DynProg{rb}, ed, env_rec, src, n_edges, res, out,
+                                             queue, chunk, flops, cf, parts);
 }
 
 template <int STAGE>
@@ -1352,10 +1352,18 @@ hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const 
         hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)((n_edges + 255) / 256)), dim3(256), 0, s, out,
                            n_edges);
 #define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, cf, parts
-    if (flops) {
-        VK_STAGED(k_validate_edges, , true)
+    if (parts > 1) {
+        if (flops) {
+            VK_STAGED(k_validate_edges, , true, true)
+        } else {
+            VK_STAGED(k_validate_edges, , false, true)
+        }
     } else {
-        VK_STAGED(k_validate_edges, , false)
+        if (flops) {
+            VK_STAGED(k_validate_edges, , true, false)
+        } else {
+            VK_STAGED(k_validate_edges, , false, false)
+        }
     }
 #undef ARGS_
     return hipGetLastError();
@@ -1386,9 +1394,9 @@ hipError_t launch_validate_edges_spec(const SpecEdgeKernels &K, const RobotDev &
     const hipFunction_t *fk = flops ? K.counted : K.edges;
     const size_t max_lds = device_max_lds();
     const int chunk = work_chunk(n_edges * parts, grid, block, tickets);
-    if (parts > 1)
-        hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)((n_edges + 255) / 256)), dim3(256), 0, s, out,
-                           n_edges);
+    // the specialised kernels are compiled in the multi-part form, which stores only the 1s
+    hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)((n_edges + 255) / 256)), dim3(256), 0, s, out,
+                       n_edges);
     // the cache parts and the staging mode as VK_STAGED chooses them for the library's kernels
     EnvDev ed = ed_in;
     int cf = 0, mode = 0, best = -1;

@@ -932,14 +932,17 @@ __device__ __forceinline__ bool pull(Puller &p, int lane, int64_t &first, int64_
 // i / n_edges of edge i % n_edges (part-major, so the parts of one edge sit in different queue
 // ranges and run on different waves at about the same time); the flags were zeroed and a part
 // stores 1 when it finds a collision.
-template <int STAGE, bool COUNT, class P>
+// MULTI = false compiles the one-wave form (parts is then taken as 1), which keeps the multi-part
+// bookkeeping out of the register allocation of the common case.
+template <int STAGE, bool COUNT, bool MULTI, class P>
 __device__ __forceinline__ void validate_edges_body(const P &pg, const EnvDev &ed,
                                                     const float4 *__restrict__ env_rec,
                                                     const EdgeSrc &src, int64_t n_edges, float res,
                                                     uint8_t *__restrict__ out,
                                                     unsigned long long *__restrict__ queue, int chunk,
                                                     unsigned long long *__restrict__ flops, int cf,
-                                                    int parts) {
+                                                    int parts_in) {
+    const int parts = MULTI ? parts_in : 1;
     const RobotDev &rb = pg.rb;
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
@@ -953,16 +956,17 @@ __device__ __forceinline__ void validate_edges_body(const P &pg, const EnvDev &e
     int64_t first, count;
     while (pull(pl, lane, first, count)) {
         for (int64_t item = first; item < first + count; ++item) {
-            const int part = parts > 1 ? (int)(item / n_edges) : 0;
-            const int64_t e = parts > 1 ? item - part * n_edges : item;
+            const int part = MULTI ? (int)(item / n_edges) : 0;
+            const int64_t e = MULTI ? item - part * n_edges : item;
             const float *a = nullptr, *b = nullptr;
             const int kind = edge_ends(src, pg.dof(), e, a, b);
             uint8_t hit = kind == 2 ? 1 : 0;
             if (kind == 0) {
                 const int n = src.nst ? ld(src.nst, e) : edge_count(a, b, pg.dof(), res);
-                hit = edge_body(pg, ev, ed, sc, a, b, n, work, part, parts, out + e);
+                hit = MULTI ? edge_body(pg, ev, ed, sc, a, b, n, work, part, parts, out + e)
+                            : edge_body(pg, ev, ed, sc, a, b, n, work);
             }
-            if (parts == 1)
+            if (!MULTI)
                 out[e] = hit;                 // wave-uniform value, same address in every lane
             else if (hit)
                 out[e] = 1;
