@@ -461,14 +461,16 @@ vk_status vk_robot_set_states_split(vk_robot robot, int32_t num, int32_t den);
 vk_status vk_robot_get_states_split(vk_robot robot, int32_t *num, int32_t *den);
 
 /*
- * Step ranges of a small validate_states batch (one pass only).  A batch of fewer than two waves
- * (64 states each) per compute unit leaves most of the chip idle; each state's walk is then
- * split over up to max_ranges contiguous ranges of link steps, each walked by its own waves
- * (posing the earlier steps, testing its own), and a state's flag is 1 when any range finds a
- * collision: the same flags as the whole walk.  -1 (the default) picks the count for the batch
- * (enough ranges for two waves per CU, about equal work each, at most 16 and one per step);
- * 0 or 1 never splits; 2..16 splits into at most that many ranges at any batch size.  Errors:
- * VK_ERR_INVALID_ARG outside [-1, 16].
+ * Test ranges of a small validate_states batch (one pass only).  A batch of fewer than eight waves
+ * (64 states each) per compute unit leaves the chip short of waves and is bound by the latency
+ * of one wave's walk.  Each state's walk is then split over up to max_ranges contiguous ranges of
+ * its tests (in walk order: each link step's environment part, then each of that step's
+ * self-pair blocks), each run by its own waves (posing the earlier steps, running its own
+ * tests), and a state's flag is 1 when any range finds a collision: the same flags as the whole
+ * walk.  -1 (the default) picks the count for the batch (about equal work per range, at most
+ * one per test and 32 in all, and no more than keep the split batch within 16 waves per CU);
+ * 0 or 1 never splits; 2..32 splits into at most that many ranges at any batch size.  Errors:
+ * VK_ERR_INVALID_ARG outside [-1, 32].
  */
 vk_status vk_robot_set_states_ranges(vk_robot robot, int32_t max_ranges);
 vk_status vk_robot_get_states_ranges(vk_robot robot, int32_t *max_ranges);

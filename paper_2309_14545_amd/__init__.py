@@ -242,7 +242,7 @@ class Robot:
         _check(lib().vk_robot_set_states_split(self.handle, int(num), int(den)))
 
     def set_states_ranges(self, max_ranges: int = -1):
-        """Step ranges of small state batches (-1 automatic, 0 or 1 never, k at most k)."""
+        """Test ranges of small state batches (-1 automatic, 0 or 1 never, k at most k <= 32)."""
         _check(lib().vk_robot_set_states_ranges(self.handle, int(max_ranges)))
 
     def get_states_split(self):

@@ -300,7 +300,7 @@ struct vk_robot_s {
     std::atomic<int> edge_tickets{kDefaultTickets};
     std::atomic<int> edge_parts{1};    // waves sharing one edge's rake (long edges)
     std::atomic<int> split_num{0}, split_den{1};
-    std::atomic<int> max_ranges{-1};   // step ranges of a small state batch: -1 automatic
+    std::atomic<int> max_ranges{-1};   // test ranges of a small state batch: -1 automatic
 };
 
 struct vk_env_s {
@@ -1432,48 +1432,59 @@ vk_status fk_spheres(vk_robot robot, const float *q, int64_t n, int64_t ldq, flo
     });
 }
 
-// Step ranges for a state batch too small to fill the chip (fewer than two waves per CU): the
-// robot's steps split into contiguous ranges of about equal work (a step weighs 4 plus the
-// entries of its self blocks), enough of them to bring the batch to two waves per CU, at most
-// kMaxRanges and at most one per step.  The robot's max_ranges setting overrides the count
-// (0 or 1: never split).
+// The walk's tests in walk order: each link step's environment part, then its self blocks (the
+// kernels number them so; blocks are numbered across steps in step order).
+static int n_tests(const vk_robot_s &r) { return (int)(r.steps.size() + r.blocks.size()); }
+
+// Number of the first test of link step st (n_tests for st past the last step).
+static int step_test(const vk_robot_s &r, int st) {
+    return st >= (int)r.steps.size() ? n_tests(r) : st + r.steps[st].blk_first;
+}
+
+// Test ranges for a state batch too small to fill the chip (fewer than eight waves per CU): the
+// walk's tests split into contiguous ranges of about equal work (an environment part weighs 4,
+// a self block 1 plus its entries), as many as keep the split batch within 16 waves per CU, at
+// most one per test and kMaxRanges in all.  Each range's waves also pose the steps before it,
+// so the split costs work; a batch this small is bound by the latency of one wave's walk, which
+// the split shortens.  The robot's max_ranges setting overrides the count (0 or 1: never
+// split).
 StepRanges state_ranges(const vk_robot_s &r, int64_t n) {
     StepRanges R{};
+    const int I = n_tests(r);
     R.n = 1;
     R.b[0] = 0;
-    R.b[1] = (int)r.steps.size();
-    const int S = (int)r.steps.size();
+    R.b[1] = I;
     const int setting = r.max_ranges.load();
     const int64_t waves = (n + kWave - 1) / kWave;
     int T;
     if (setting < 0) {
-        const int64_t want = 2 * (int64_t)device_info(r.device).n_cu;
-        if (waves >= want) return R;
-        T = (int)std::min<int64_t>(kMaxRanges, (want + waves - 1) / waves);
+        const int64_t n_cu = device_info(r.device).n_cu;
+        T = (int)std::min<int64_t>(kMaxRanges, 16 * n_cu / waves);
     } else {
         T = std::min(setting, kMaxRanges);
     }
-    T = std::min(T, S);
+    T = std::min(T, I);
     if (T <= 1) return R;
-    std::vector<double> w(S, 0.0);
+    std::vector<double> w;
+    w.reserve(I);
     double total = 0.0;
-    for (int i = 0; i < S; ++i) {
-        const StepRec &st = r.steps[i];
-        w[i] = st.sph_count > 0 ? 4.0 : 1.0;
-        for (int b = st.blk_first; b < st.blk_first + st.blk_count; ++b) w[i] += r.blocks[b].ent_count;
-        total += w[i];
+    for (const StepRec &st : r.steps) {
+        w.push_back(st.sph_count > 0 ? 4.0 : 1.0);
+        for (int b = st.blk_first; b < st.blk_first + st.blk_count; ++b)
+            w.push_back(1.0 + r.blocks[b].ent_count);
     }
-    // range y ends after the first step where the running weight reaches (y + 1) / T of the
-    // total, leaving at least one step for every later range
+    for (double x : w) total += x;
+    // range y ends after the first test where the running weight reaches (y + 1) / T of the
+    // total, leaving at least one test for every later range
     int y = 0;
     double cum = 0.0;
-    for (int i = 0; i < S && y < T - 1; ++i) {
+    for (int i = 0; i < I && y < T - 1; ++i) {
         cum += w[i];
-        const int left = S - (i + 1);
+        const int left = I - (i + 1);
         if ((cum >= total * (y + 1) / T && left >= T - 1 - y) || left == T - 1 - y) R.b[++y] = i + 1;
     }
     R.n = y + 1;
-    R.b[R.n] = S;
+    R.b[R.n] = I;
     return R;
 }
 
@@ -1484,7 +1495,8 @@ vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n,
         check_batch(n, ldq, q, collide, "validate_states");
         if (n == 0) return;
         hipStream_t s = (hipStream_t)stream;
-        const int split = states_split(robot->dev, n, robot->split_num.load(), robot->split_den.load());
+        const int split = step_test(*robot, states_split(robot->dev, n, robot->split_num.load(),
+                                                         robot->split_den.load()));
         void *scratch =
             split > 0 ? workspace_for(s, states_scratch_bytes(n), "validate_states").scratch : nullptr;
         const StepRanges ranges = state_ranges(*robot, n);
@@ -1507,6 +1519,7 @@ vk_status validate_states_noalloc(vk_robot robot, vk_env env, const float *q, in
         // the two-pass schedule: the robot's split, else half of its link steps
         int split = states_split(robot->dev, n, robot->split_num.load(), robot->split_den.load());
         if (split == 0) split = states_split(robot->dev, n, 1, 2);
+        split = step_test(*robot, split);
         void *scratch = nullptr;
         if (split > 0) hip_check(noalloc_scratch(&scratch), "validate_states_noalloc scratch");
         hip_check(launch_validate_states(robot->dev,
@@ -2051,7 +2064,7 @@ vk_status vk_robot_get_states_split(vk_robot robot, int32_t *num, int32_t *den) 
 vk_status vk_robot_set_states_ranges(vk_robot robot, int32_t max_ranges) {
     return guarded([&] {
         if (max_ranges < -1 || max_ranges > kMaxRanges)
-            raise(VK_ERR_INVALID_ARG, "max_ranges must be -1 (automatic) or in [0, 16]");
+            raise(VK_ERR_INVALID_ARG, "max_ranges must be -1 (automatic) or in [0, 32]");
         if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
         robot->max_ranges = max_ranges;
     });

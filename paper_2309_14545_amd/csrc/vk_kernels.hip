@@ -55,11 +55,11 @@ __global__ void __launch_bounds__(256) k_fk_spheres(RobotDev rb, const float *__
 // ---------------------------------------------------------------------------------------------
 // validate_states: one lane per state.
 // ---------------------------------------------------------------------------------------------
-// With one step range the whole walk runs and every flag is stored.  A small batch (too few
-// waves to fill the chip) is split over step ranges: block row y tests steps
-// [b[y], b[y + 1]) only, posing the earlier ones; the flags were zeroed and a range stores 1
-// where it finds a collision, so a state's flag is the OR over the ranges, the flag of the
-// whole walk.
+// With one range the whole walk runs and every flag is stored.  A small batch (too few waves to
+// fill the chip) is split into ranges of the walk's tests (each step's environment part and
+// each of its self blocks, numbered in walk order): block row y runs tests [b[y], b[y + 1])
+// only, posing the earlier steps; the flags were zeroed and a range stores 1 where it finds a
+// collision, so a state's flag is the OR over the ranges, the flag of the whole walk.
 // four waves per SIMD (at most 128 VGPRs): left alone the compiler takes 133 and fits three
 template <int STAGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     if (active)
         for (int j = 0; j < rb.dof; ++j) col |= !isfinite(qs(j));
     if (ranges.n <= 1) {
-        col = walk_collide<false>(DynProg{rb}, ev, ed, qs, sc, col, 0, rb.n_steps);
+        col = walk_collide<false>(DynProg{rb}, ev, ed, qs, sc, col, 0, kAllTests);
         if (active) out[i] = col ? 1 : 0;
         return;
     }
@@ -90,10 +90,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
 
 // Two-pass state validation.  In a wave of independent states the walk lasts until its last
 // live lane ends, so when most states collide early a few free lanes keep whole waves walking
-// at low occupancy of their lanes.  Pass 1 tests the first `split` link steps of every state
-// and appends the states still free to a survivor list (one atomic per wave); pass 2 walks the
-// survivors packed densely into waves, posing the first `split` steps again and testing the
-// rest.  Flags are those of the single pass.
+// at low occupancy of their lanes.  Pass 1 runs the walk's tests before number `split` (the
+// first test of a link step; tests are numbered as for the ranges above) on every state and
+// appends the states still free to a survivor list (one atomic per wave); pass 2 walks the
+// survivors packed densely into waves, posing the earlier steps again and running the rest.
+// Flags are those of the single pass.
 // four waves per SIMD: without the bound the compiler takes 131 VGPRs, three waves; at 128 it
 // spills one or two and the point-cloud batch runs 2.5 % faster
 template <int STAGE>
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     const int64_t i = active ? surv[g] : 0;
     QState qs{q, ldq, i};
     bool col = !active;
-    col = walk_collide<false>(DynProg{rb}, ev, ed, qs, sc, col, split, rb.n_steps);
+    col = walk_collide<false>(DynProg{rb}, ev, ed, qs, sc, col, split, kAllTests);
     if (active) out[i] = col ? 1 : 0;
 }
 
@@ -1122,7 +1123,7 @@ static const int kCacheOrder[4] = {kCacheCaps | kCacheJoints, kCacheCaps, kCache
     }
 
 // Link steps pass 1 of the two-pass state validation tests, for a fraction num/den of the
-// robot's steps (0: one pass).
+// robot's steps (0: one pass).  The kernels take the number of the first test of that step.
 int states_split(const RobotDev &rb, int64_t n, int num, int den) {
     if (num <= 0 || den <= 0) return 0;
     const int split = (int)((int64_t)rb.n_steps * num / den);

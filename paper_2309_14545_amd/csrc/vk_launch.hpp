@@ -10,9 +10,11 @@ namespace vk {
 hipError_t launch_fk_spheres(const RobotDev &rb, const float *q, int64_t n, int64_t ldq,
                              float *out, int64_t ldc, hipStream_t s);
 // State validation; with split > 0 and scratch (states_scratch_bytes(n) bytes) it runs in two
-// passes, the second over the states still free after the first `split` link steps.
-// Without the two passes, `ranges` (optional, n > 1) splits a small batch's walk over step
-// ranges run by separate waves.
+// passes, the second over the states still free after the walk's tests before number `split`
+// (tests numbered as for StepRanges).  Without the two passes, `ranges` (optional, n > 1)
+// splits a small batch's walk over test ranges run by separate waves.
+// states_split gives the link step where the first pass ends (0: one pass); the caller turns
+// it into that step's first test number.
 int states_split(const RobotDev &rb, int64_t n, int num, int den);
 size_t states_scratch_bytes(int64_t n);
 hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const float *q, int64_t n,

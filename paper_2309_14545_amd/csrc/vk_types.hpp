@@ -176,9 +176,11 @@ struct GridDev {
     float porg[3], pinv, pcell, pq;
 };
 
-// Contiguous ranges of link steps that separate waves walk for one state: range y is
-// [b[y], b[y + 1]), y < n.
-constexpr int kMaxRanges = 16;
+// Contiguous ranges of the walk's tests that separate waves run for one state: range y is
+// [b[y], b[y + 1]), y < n.  The tests are numbered in walk order: step s's environment part is
+// number s + blk_first(s) and its self blocks follow it; kAllTests is past every robot's last.
+constexpr int kMaxRanges = 32;
+constexpr int kAllTests = 1 << 30;
 struct StepRanges {
     int32_t n;
     int32_t b[kMaxRanges + 1];

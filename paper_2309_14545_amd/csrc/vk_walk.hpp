@@ -555,12 +555,16 @@ __device__ __forceinline__ bool grid_hit(const EnvView &ev, const GridDev &g, fl
         }                                                                           \
     }
 
-// The interleaved FK + collision walk of one configuration per lane.  Steps [test_from, test_to)
-// are tested; earlier steps are posed and cached only, and the walk stops at test_to.
-//   EDGE = true : returns as soon as any lane of the wave collides (the edge is invalid);
-//                 the return value is then wave-uniform.
+// The interleaved FK + collision walk of one configuration per lane.
+//   EDGE = true : every test runs; returns as soon as any lane of the wave collides (the edge
+//                 is invalid); the return value is then wave-uniform.
 //   EDGE = false: per-lane result; lanes that collided stop contributing, and the walk ends
 //                 when every lane has collided.  `col` on entry marks lanes already decided.
+//                 Only the tests numbered [test_from, test_to) run.  The tests are numbered in
+//                 walk order: step s's environment part is number s + blk_first(s), its self
+//                 blocks follow it (blocks are numbered across steps in step order).  Steps
+//                 before the range are posed and cached only, and the walk stops before the
+//                 first step past it.
 // The step loop is a loop at run time.  The parts that depend on the step's records (posing and
 // caching the link, placing its spheres, its self-pair blocks) go through pg.at_step, which for
 // a robot-specialised program selects code compiled for that step with its records as
@@ -577,12 +581,16 @@ __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, con
     bool live = !col;
     if (!EDGE && !wave_ballot(live)) return col;
     const int n_steps = pg.n_steps();
-    for (int st = 0; st < n_steps && st < test_to; ++st) {
+    for (int st = 0; st < n_steps; ++st) {
         // pose the step's link, cache its bounds; the values the environment part reads
-        int cnt = 0;
+        int cnt = 0, ibase = 0;
         float Cx = 0.0f, Cy = 0.0f, Cz = 0.0f, CR = 0.0f, hx = 0.0f, hy = 0.0f, hz = 0.0f;
         pg.at_step(st, [&](auto K) __attribute__((always_inline)) {
             const StepRec S = pg.step(K);
+            if (!EDGE) {
+                ibase = st + S.blk_first;      // number of the step's environment part
+                if (ibase >= test_to) return 0;
+            }
             pose_step(pg, S, Tm, q, work, &sc);
             cnt = S.sph_count;
             if (cnt == 0) return 0;
@@ -600,8 +608,9 @@ __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, con
             }
             return 0;
         });
+        if (!EDGE && ibase >= test_to) break;
         if (cnt == 0) continue;
-        if (st < test_from) continue;         // tested by an earlier pass: pose and cache only
+        const bool env_part = EDGE || ibase >= test_from;
         // the step's fine spheres, placed on first use (uniform decision)
         float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl];
         bool placed = false;
@@ -615,80 +624,83 @@ __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, con
         placed = true;                                                              \
     }
 
-        // environment: voxel broadphase per lane (candidates sorted by a lower bound of their
-        // distance to the cell; stop at the first bound >= CR), then the exact link-sphere
-        // test (mid-phase) and the link's fine spheres
-        if (CR <= ed.vcap) {
-            int b, e;
-            work.add(flop::kCull, 6);
-            voxel_range(ev, ed, Cx, Cy, Cz, CR, b, e);
-            if (!live) e = b;
-            if (wave_ballot(b < e)) {
-                VK_PLACE()
-                for (int p = b; p < e; ++p) {
-                    const int2 ent = ed.vlist[p];
-                    if (__int_as_float(ent.y) >= CR) break;
-                    const int t = ent.x >> 28, i = ent.x & 0x0fffffff;
-                    work.add(flop::kCull, flop::kBox);
-                    if (hit_any(ev, t, i, Cx, Cy, Cz, CR)) {
-                        work.add(flop::kFine, flop::kBox * cnt);
-#pragma unroll
-                        for (int k = 0; k < kSpl; ++k)
-                            if (k < cnt) col |= hit_any(ev, t, i, cx[k], cy[k], cz[k], cr[k]);
+        if (env_part) {
+            // environment: voxel broadphase per lane (candidates sorted by a lower bound of their
+            // distance to the cell; stop at the first bound >= CR), then the exact link-sphere
+            // test (mid-phase) and the link's fine spheres
+            if (CR <= ed.vcap) {
+                int b, e;
+                work.add(flop::kCull, 6);
+                voxel_range(ev, ed, Cx, Cy, Cz, CR, b, e);
+                if (!live) e = b;
+                if (wave_ballot(b < e)) {
+                    VK_PLACE()
+                    for (int p = b; p < e; ++p) {
+                        const int2 ent = ed.vlist[p];
+                        if (__int_as_float(ent.y) >= CR) break;
+                        const int t = ent.x >> 28, i = ent.x & 0x0fffffff;
+                        work.add(flop::kCull, flop::kBox);
+                        if (hit_any(ev, t, i, Cx, Cy, Cz, CR)) {
+                            work.add(flop::kFine, flop::kBox * cnt);
+    #pragma unroll
+                            for (int k = 0; k < kSpl; ++k)
+                                if (k < cnt) col |= hit_any(ev, t, i, cx[k], cy[k], cz[k], cr[k]);
+                        }
+                    }
+                    if (EDGE) {
+                        if (wave_ballot(col)) return true;
+                    } else {
+                        live = !col;
+                        if (!wave_ballot(live)) return col;
                     }
                 }
-                if (EDGE) {
-                    if (wave_ballot(col)) return true;
-                } else {
-                    live = !col;
-                    if (!wave_ballot(live)) return col;
-                }
-            }
-        } else {
-            // a link bounding sphere larger than the voxel lists cover: every primitive
-            VK_PLACE()
-            for (int i = 0; i < ev.n_sph; ++i) {
-                const float4 o = ev.rec[ev.off_sph + i];
-                VK_GATE(flop::kSphere, hit_sphere(Cx, Cy, Cz, CR, o),
-                        hit_sphere(cx[k], cy[k], cz[k], cr[k], o))
-            }
-            for (int i = 0; i < ev.n_cap; ++i) {
-                const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
-                VK_GATE(flop::kCapsule, hit_capsule(Cx, Cy, Cz, CR, A, B),
-                        hit_capsule(cx[k], cy[k], cz[k], cr[k], A, B))
-            }
-            for (int i = 0; i < ev.n_cyl; ++i) {
-                const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
-                VK_GATE(flop::kCylinder, hit_cylinder(Cx, Cy, Cz, CR, A, B),
-                        hit_cylinder(cx[k], cy[k], cz[k], cr[k], A, B))
-            }
-            for (int i = 0; i < ev.n_box; ++i) {
-                const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
-                             Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
-                VK_GATE(flop::kBox, hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
-                        hit_box(cx[k], cy[k], cz[k], cr[k], X, Y, Z, O))
-            }
-        }
-        // points: the clearance field rules out a link (its bounding sphere) or a sphere whose
-        // neighbourhood holds no point within its radius before the grid is scanned
-        if (ed.n_cells > 0) {
-            const GridDev G = ld(ed.grid, 0);
-            const bool near = live && !col && point_clearance(G, Cx, Cy, Cz) < CR;
-            work.add(flop::kCull, flop::kClearance);
-            if (wave_ballot(near)) {
+            } else {
+                // a link bounding sphere larger than the voxel lists cover: every primitive
                 VK_PLACE()
-#pragma unroll
-                for (int k = 0; k < kSpl; ++k)
-                    if (k < cnt && near && !col &&
-                        point_clearance(G, cx[k], cy[k], cz[k]) < cr[k])
-                        col |= grid_hit<!EDGE>(ev, G, cx[k], cy[k], cz[k], cr[k]);
-                if (EDGE) {
-                    if (wave_ballot(col)) return true;
-                } else {
-                    live = !col;
-                    if (!wave_ballot(live)) return col;
+                for (int i = 0; i < ev.n_sph; ++i) {
+                    const float4 o = ev.rec[ev.off_sph + i];
+                    VK_GATE(flop::kSphere, hit_sphere(Cx, Cy, Cz, CR, o),
+                            hit_sphere(cx[k], cy[k], cz[k], cr[k], o))
+                }
+                for (int i = 0; i < ev.n_cap; ++i) {
+                    const float4 A = ev.rec[ev.off_cap + 2 * i], B = ev.rec[ev.off_cap + 2 * i + 1];
+                    VK_GATE(flop::kCapsule, hit_capsule(Cx, Cy, Cz, CR, A, B),
+                            hit_capsule(cx[k], cy[k], cz[k], cr[k], A, B))
+                }
+                for (int i = 0; i < ev.n_cyl; ++i) {
+                    const float4 A = ev.rec[ev.off_cyl + 2 * i], B = ev.rec[ev.off_cyl + 2 * i + 1];
+                    VK_GATE(flop::kCylinder, hit_cylinder(Cx, Cy, Cz, CR, A, B),
+                            hit_cylinder(cx[k], cy[k], cz[k], cr[k], A, B))
+                }
+                for (int i = 0; i < ev.n_box; ++i) {
+                    const float4 X = ev.rec[ev.off_box + 4 * i], Y = ev.rec[ev.off_box + 4 * i + 1],
+                                 Z = ev.rec[ev.off_box + 4 * i + 2], O = ev.rec[ev.off_box + 4 * i + 3];
+                    VK_GATE(flop::kBox, hit_box(Cx, Cy, Cz, CR, X, Y, Z, O),
+                            hit_box(cx[k], cy[k], cz[k], cr[k], X, Y, Z, O))
                 }
             }
+            // points: the clearance field rules out a link (its bounding sphere) or a sphere whose
+            // neighbourhood holds no point within its radius before the grid is scanned
+            if (ed.n_cells > 0) {
+                const GridDev G = ld(ed.grid, 0);
+                const bool near = live && !col && point_clearance(G, Cx, Cy, Cz) < CR;
+                work.add(flop::kCull, flop::kClearance);
+                if (wave_ballot(near)) {
+                    VK_PLACE()
+    #pragma unroll
+                    for (int k = 0; k < kSpl; ++k)
+                        if (k < cnt && near && !col &&
+                            point_clearance(G, cx[k], cy[k], cz[k]) < cr[k])
+                            col |= grid_hit<!EDGE>(ev, G, cx[k], cy[k], cz[k], cr[k]);
+                    if (EDGE) {
+                        if (wave_ballot(col)) return true;
+                    } else {
+                        live = !col;
+                        if (!wave_ballot(live)) return col;
+                    }
+                }
+            }
+
         }
 
         // self pairs completed by this step: gate each block with the earlier step's link
@@ -794,7 +806,12 @@ __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, con
                 }
                 return false;
             };
-            for (int b = 0; b < S.blk_count; ++b)
+            int b_lo = 0, b_hi = S.blk_count;
+            if (!EDGE) {                       // the blocks inside [test_from, test_to)
+                b_lo = max(0, test_from - ibase - 1);
+                b_hi = min(S.blk_count, test_to - ibase - 1);
+            }
+            for (int b = b_lo; b < b_hi; ++b)
                 if (block(b)) break;
             return end;
         };

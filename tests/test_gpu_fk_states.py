@@ -236,19 +236,23 @@ def test_two_pass_schedule_matches_one_pass(vk, name):
 
 @pytest.mark.parametrize("name", ["states7", "bimanual14_cube", "chain7_big_env", "lift8_shelf"])
 def test_step_ranges_match_the_whole_walk(vk, orc, name):
-    """Small batches split over step ranges (each range's waves pose the earlier steps and test
-    their own) give bitwise the flags of the whole walk, for every range count, at ragged sizes,
-    and the automatic choice agrees with the oracle outside the band."""
+    """Small batches split over ranges of the walk's tests (each range's waves pose the earlier
+    steps and run their own environment parts and self blocks) give bitwise the flags of the
+    whole walk, for range counts from two to one per test, at ragged sizes, and the automatic
+    choice agrees with the oracle outside the band."""
     robot, env, q = _state_case(name)
     r, e = vk.Robot(robot), vk.Env(env)
     qd = dev(q)
     r.set_states_ranges(0)
     ref = host(vk.validate_states(r, e, qd))
-    for k in (2, 3, 5, 16):
+    for k in (2, 3, 5, 16, 23, 32):
         r.set_states_ranges(k)
         for n in (1, 63, 65, q.shape[1]):
             got = host(vk.validate_states(r, e, qd[:, :n].contiguous()))
             np.testing.assert_array_equal(got, ref[:n], err_msg=f"{name} ranges {k} n {n}")
+    for bad in (-2, 33):
+        with pytest.raises(vk.VkError):
+            r.set_states_ranges(bad)
     r.set_states_ranges(-1)
     auto = host(vk.validate_states(r, e, qd))
     np.testing.assert_array_equal(auto, ref)
