@@ -453,6 +453,23 @@ vk_status vk_release(void *stream);
  */
 vk_status vk_robot_set_edge_parts(vk_robot robot, int32_t parts);
 int32_t vk_robot_get_edge_parts(vk_robot robot);
+
+/*
+ * Test ranges of a small edge batch (validate_edges, validate_edges_indexed).  A batch of a few
+ * dozen one-wave items (edges times their rake parts) is bound by the latency of one wave's walk
+ * (Sec. III-D: the whole rake of an edge walks every test in every state).  Each edge's walk is then split over up to max_ranges ranges of its tests (in walk
+ * order: each link step's environment part, then that step's self-pair blocks; ranges of equal
+ * test count), each run by its own waves over the edge's whole rake (posing the earlier steps),
+ * and an edge's flag is 1 when any range finds a collision: the flags of the unsplit walk.
+ * -1 (the default) splits only batches of at most one wave per two compute units, into about
+ * one wave per two compute units in all (at most one range per test and 32); 0 or 1 never
+ * splits; 2..32 splits into at
+ * most that many ranges at any batch size.  validate_edges_counted never splits.  Errors:
+ * VK_ERR_INVALID_ARG outside [-1, 32].  vk_robot_get_edge_ranges returns the setting (-2 for
+ * NULL).
+ */
+vk_status vk_robot_set_edge_ranges(vk_robot robot, int32_t max_ranges);
+int32_t vk_robot_get_edge_ranges(vk_robot robot);
 vk_status vk_robot_set_edge_launch(vk_robot robot, int32_t block_threads, int32_t blocks_per_cu,
                                    int32_t tickets_per_wave);
 vk_status vk_robot_get_edge_launch(vk_robot robot, int32_t *block_threads, int32_t *blocks_per_cu,

@@ -35,6 +35,7 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "vk_robot_set_edge_launch", "vk_robot_get_edge_launch", "vk_robot_set_edge_parts",
            "vk_robot_get_edge_parts", "vk_robot_set_states_split",
            "vk_robot_get_states_split", "vk_robot_set_states_ranges", "vk_robot_get_states_ranges",
+           "vk_robot_set_edge_ranges", "vk_robot_get_edge_ranges",
            "vk_autotune_edges", "vk_autotune_states",
            "vk_last_error")
 
@@ -130,6 +131,9 @@ def lib():
         L.vk_robot_set_states_split.argtypes = [vp, i32, i32]
         L.vk_robot_get_states_split.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.vk_robot_set_states_ranges.argtypes = [vp, i32]
+        L.vk_robot_set_edge_ranges.argtypes = [vp, i32]
+        L.vk_robot_get_edge_ranges.argtypes = [vp]
+        L.vk_robot_get_edge_ranges.restype = i32
         L.vk_robot_get_states_ranges.argtypes = [vp, C.POINTER(i32)]
         L.vk_autotune_edges.argtypes = [vp, vp, vp, vp, vp, i64, fp, C.c_char_p, i32, vp]
         L.vk_autotune_states.argtypes = [vp, vp, vp, i64, i64, C.c_char_p, i32, vp]
@@ -231,6 +235,13 @@ class Robot:
     @property
     def edge_parts(self) -> int:
         return int(lib().vk_robot_get_edge_parts(self.handle))
+
+    def set_edge_ranges(self, max_ranges: int = -1):
+        """Test ranges of small edge batches (-1 automatic, 0 or 1 never, k at most k <= 32)."""
+        _check(lib().vk_robot_set_edge_ranges(self.handle, int(max_ranges)))
+
+    def edge_ranges(self) -> int:
+        return int(lib().vk_robot_get_edge_ranges(self.handle))
 
     def get_edge_launch(self):
         b, p, t = C.c_int32(), C.c_int32(), C.c_int32()

@@ -299,6 +299,7 @@ struct vk_robot_s {
     std::atomic<int> edge_block{kDefaultEdgeBlock}, edge_bpc{kDefaultEdgeBpc};
     std::atomic<int> edge_tickets{kDefaultTickets};
     std::atomic<int> edge_parts{1};    // waves sharing one edge's rake (long edges)
+    std::atomic<int> edge_ranges{-1};  // test ranges of a small edge batch: -1 automatic
     std::atomic<int> split_num{0}, split_den{1};
     std::atomic<int> max_ranges{-1};   // test ranges of a small state batch: -1 automatic
 };
@@ -526,6 +527,7 @@ void build_robot(const vk_robot_desc *d, vk_robot_s *r, bool upload = true) {
     r->dev.dof = dof;
     r->dev.n_steps = (int)steps.size();
     r->dev.n_slots = n_slots;
+    r->dev.n_tests = (int)(steps.size() + blocks.size());
     r->dev.n_spheres = S;
     r->dev.n_links = dof + 1;
     if (!upload) return;
@@ -1203,10 +1205,10 @@ std::string spec_source(const vk_robot_s &r) {
          "        NAME(vk::RobotDev rb, vk::EnvDev ed, const float4 *__restrict__ env_rec,         \\\n"
          "             vk::EdgeSrc src, int64_t n_edges, float res, uint8_t *__restrict__ out,      \\\n"
          "             unsigned long long *__restrict__ queue, int chunk,                          \\\n"
-         "             unsigned long long *__restrict__ flops, int cf, int parts) {                \\\n"
+         "             unsigned long long *__restrict__ flops, int cf, int parts, int tparts) {    \\\n"
          "        vk::validate_edges_body<STAGE, COUNT, true>(vk::SpecProg<vk_spec_robot::R>{rb}, ed,\\\n"
          "                                              env_rec, src, n_edges, res, out, queue,    \\\n"
-         "                                              chunk, flops, cf, parts);                  \\\n"
+         "                                              chunk, flops, cf, parts, tparts);          \\\n"
          "    }\n";
     for (int c = 0; c < 2; ++c)
         for (int m = 0; m < 3; ++m)
@@ -1488,6 +1490,24 @@ StepRanges state_ranges(const vk_robot_s &r, int64_t n) {
     return R;
 }
 
+// Test ranges of an edge batch of `waves` one-wave items (edges times rake parts): a batch of
+// at most one wave per two CUs splits each edge's walk into ranges of its tests, about one
+// wave per two CUs in all (at most one per test and kMaxRanges); the robot's edge_ranges
+// setting overrides the count (0 or 1: never split).  The ranges of the edge kernels are of
+// equal test count.  Edges are cheaper than states to split wrongly (a short edge's walk is a
+// few states), so the automatic split is reserved for a few dozen edges, where one walk's
+// latency is the launch: one full-length 7-DoF edge took 61 us unsplit and 44 us split.
+static int edge_test_ranges(const vk_robot_s &r, int64_t waves) {
+    const int setting = r.edge_ranges.load();
+    int64_t T;
+    if (setting < 0)
+        T = waves > 0 ? (int64_t)device_info(r.device).n_cu / (2 * waves) : 1;
+    else
+        T = setting;
+    T = std::min<int64_t>(std::min<int64_t>(T, kMaxRanges), n_tests(r));
+    return T < 2 ? 1 : (int)T;
+}
+
 vk_status validate_states(vk_robot robot, vk_env env, const float *q, int64_t n, int64_t ldq,
                           uint8_t *collide, void *stream) {
     return guarded([&] {
@@ -1557,27 +1577,33 @@ static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_
     int block = robot->edge_block.load();
     const int bpc = robot->edge_bpc.load(), tickets = robot->edge_tickets.load();
     const int parts = robot->edge_parts.load();
+    const int tparts = flops ? 1 : edge_test_ranges(*robot, n_edges * parts);
     // a workgroup's per-wave caches must fit the LDS: smaller workgroups for large robots
     while (block > kWave && walk_lds_bytes(robot->dev, block) > di.max_lds) block -= kWave;
     // a batch too small to give every CU a workgroup of this size (planner rounds of a few
     // thousand edges) is spread over more CUs in smaller workgroups of at least four waves:
     // such launches are bound by the latency of one walk, not by throughput
-    const int64_t items = n_edges * parts;
+    const int64_t items = n_edges * parts * tparts;
     if (items < (int64_t)di.n_cu * (block / kWave)) {
         const int64_t waves = std::max<int64_t>(4, (items + di.n_cu - 1) / di.n_cu);
         block = (int)std::min<int64_t>(block, waves * kWave);
     }
     const int64_t want = (items + block / kWave - 1) / (block / kWave);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)di.n_cu * bpc));
-    hip_check(launch_reset_queue(queue, s), "queue reset");
+    // edges split over several waves (and the specialised kernels, built in that form) store
+    // only the 1s: their flags are zeroed with the queue reset
+    const bool spec = robot->use_spec.load() && robot->module;
+    const bool multi = spec || parts > 1 || tparts > 1;
+    hip_check(launch_reset_queue(queue, s, multi ? collide : nullptr, n_edges), "queue reset");
     const EnvDev ed = env_for_launch(env, walk_lds_bytes(robot->dev, block));
-    if (robot->use_spec.load() && robot->module)
+    if (spec)
         hip_check(launch_validate_edges_spec(robot->spec, robot->dev, ed, src, n_edges, resolution,
-                                             collide, queue, grid, block, tickets, parts, s, flops),
+                                             collide, queue, grid, block, tickets, parts, tparts,
+                                             s, flops),
                   "validate_edges launch (specialised)");
     else
         hip_check(launch_validate_edges(robot->dev, ed, src, n_edges, resolution, collide, queue,
-                                        grid, block, tickets, parts, s, flops),
+                                        grid, block, tickets, parts, tparts, s, flops),
                   "validate_edges launch");
 }
 
@@ -2087,6 +2113,17 @@ vk_status vk_robot_set_edge_parts(vk_robot robot, int32_t parts) {
 }
 
 int32_t vk_robot_get_edge_parts(vk_robot robot) { return robot ? robot->edge_parts.load() : -1; }
+
+vk_status vk_robot_set_edge_ranges(vk_robot robot, int32_t max_ranges) {
+    return guarded([&] {
+        if (max_ranges < -1 || max_ranges > kMaxRanges)
+            raise(VK_ERR_INVALID_ARG, "max_ranges must be -1 (automatic) or in [0, 32]");
+        if (!robot) raise(VK_ERR_INVALID_ARG, "robot handle is NULL");
+        robot->edge_ranges = max_ranges;
+    });
+}
+
+int32_t vk_robot_get_edge_ranges(vk_robot robot) { return robot ? robot->edge_ranges.load() : -2; }
 
 vk_status vk_robot_set_edge_launch(vk_robot robot, int32_t block_threads, int32_t blocks_per_cu,
                                    int32_t tickets_per_wave) {

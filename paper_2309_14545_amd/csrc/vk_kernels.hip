@@ -160,9 +160,10 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(VK_ED
     k_validate_edges(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
                      EdgeSrc src, int64_t n_edges, float res,
                      uint8_t *__restrict__ out, unsigned long long *__restrict__ queue,
-                     int chunk, unsigned long long *__restrict__ flops, int cf, int parts) {
+                     int chunk, unsigned long long *__restrict__ flops, int cf, int parts,
+                     int tparts) {
     validate_edges_body<STAGE, COUNT, MULTI>(DynProg{rb}, ed, env_rec, src, n_edges, res, out,
-                                             queue, chunk, flops, cf, parts);
+                                             queue, chunk, flops, cf, parts, tparts);
 }
 
 template <int STAGE>
@@ -221,6 +222,14 @@ __global__ void k_zero_u8(uint8_t *p, int64_t n) {
 __global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int n, int stride) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[(size_t)i * stride] = v;
+}
+
+// The queue counters and a batch's flags zeroed by one launch (edges split over several waves
+// store only the 1s).
+__global__ void k_reset_queue_flags(unsigned long long *queue, uint8_t *out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kQueues) queue[i * kQueueWords] = 0ull;
+    if (i < n) out[i] = 0;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1328,8 +1337,13 @@ hipError_t launch_shortcut_apply(float *paths, int32_t *lens, int64_t P, int M, 
     return hipGetLastError();
 }
 
-hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, queue, 0ull, kQueues, kQueueWords);
+hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s, uint8_t *flags,
+                              int64_t n_flags) {
+    if (flags && n_flags > 0)
+        hipLaunchKernelGGL(k_reset_queue_flags, dim3((unsigned)((n_flags + 255) / 256)), dim3(256), 0,
+                           s, queue, flags, n_flags);
+    else
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, queue, 0ull, kQueues, kQueueWords);
     return hipGetLastError();
 }
 
@@ -1344,16 +1358,14 @@ static int work_chunk(int64_t n_items, int grid, int block, int tickets) {
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed_in, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,
                                  unsigned long long *queue, int grid, int block, int tickets,
-                                 int parts, hipStream_t s, unsigned long long *flops) {
+                                 int parts, int tparts, hipStream_t s, unsigned long long *flops) {
     const dim3 grid_(grid), block_(block);
     const auto lds_ = [&](int c) { return walk_lds_bytes(rb, block, c); };
     const size_t max_lds_ = device_max_lds();
-    const int chunk = work_chunk(n_edges * parts, grid, block, tickets);
-    if (parts > 1)
-        hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)((n_edges + 255) / 256)), dim3(256), 0, s, out,
-                           n_edges);
-#define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, cf, parts
-    if (parts > 1) {
+    const bool multi = parts > 1 || tparts > 1;   // flags zeroed with the queue reset
+    const int chunk = work_chunk(n_edges * parts * tparts, grid, block, tickets);
+#define ARGS_ rb, ed, ed.rec, src, n_edges, res, out, queue, chunk, flops, cf, parts, tparts
+    if (multi) {
         if (flops) {
             VK_STAGED(k_validate_edges, , true, true)
         } else {
@@ -1390,14 +1402,13 @@ static int resident_blocks_fn(hipFunction_t f, int block, size_t lds) {
 hipError_t launch_validate_edges_spec(const SpecEdgeKernels &K, const RobotDev &rb,
                                       const EnvDev &ed_in, const EdgeSrc &src, int64_t n_edges,
                                       float res, uint8_t *out, unsigned long long *queue, int grid,
-                                      int block, int tickets, int parts, hipStream_t s,
-                                      unsigned long long *flops) {
+                                      int block, int tickets, int parts, int tparts,
+                                      hipStream_t s, unsigned long long *flops) {
     const hipFunction_t *fk = flops ? K.counted : K.edges;
     const size_t max_lds = device_max_lds();
-    const int chunk = work_chunk(n_edges * parts, grid, block, tickets);
-    // the specialised kernels are compiled in the multi-part form, which stores only the 1s
-    hipLaunchKernelGGL(k_zero_u8, dim3((unsigned)((n_edges + 255) / 256)), dim3(256), 0, s, out,
-                       n_edges);
+    // the specialised kernels are compiled in the multi-part form, which stores only the 1s:
+    // the flags were zeroed with the queue reset
+    const int chunk = work_chunk(n_edges * parts * tparts, grid, block, tickets);
     // the cache parts and the staging mode as VK_STAGED chooses them for the library's kernels
     EnvDev ed = ed_in;
     int cf = 0, mode = 0, best = -1;
@@ -1431,7 +1442,7 @@ hipError_t launch_validate_edges_spec(const SpecEdgeKernels &K, const RobotDev &
     const float4 *rec = ed.rec;
     EdgeSrc src_ = src;
     void *args[] = {&rb_, &ed, &rec, &src_, &n_edges, &res, &out, &queue,
-                    const_cast<int *>(&chunk), &flops, &cf, &parts};
+                    const_cast<int *>(&chunk), &flops, &cf, &parts, &tparts};
     return hipModuleLaunchKernel(fk[mode], (unsigned)grid, 1, 1, (unsigned)block, 1, 1, (unsigned)sh,
                                  s, args, nullptr);
 }

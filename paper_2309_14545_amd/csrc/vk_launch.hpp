@@ -24,7 +24,9 @@ hipError_t launch_validate_states(const RobotDev &rb, const EnvDev &ed, const fl
 // noalloc_max_states() states): its address on the current device, looked up once per device.
 int64_t noalloc_max_states();
 hipError_t noalloc_scratch(void **ptr);
-hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s);
+// Zero the work-queue counters, and with `flags` also n_flags flags (one launch).
+hipError_t launch_reset_queue(unsigned long long *queue, hipStream_t s, uint8_t *flags = nullptr,
+                              int64_t n_flags = 0);
 hipError_t launch_shortcut_propose(const int32_t *lens, int64_t P, int M, int K,
                                   const uint32_t *rnd, int32_t *pairs, hipStream_t s);
 hipError_t launch_shortcut_apply(float *paths, int32_t *lens, int64_t P, int M, int dof, int K,
@@ -33,7 +35,8 @@ hipError_t launch_shortcut_apply(float *paths, int32_t *lens, int64_t P, int M, 
 hipError_t launch_validate_edges(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                  int64_t n_edges, float res, uint8_t *out,
                                  unsigned long long *queue, int grid, int block, int tickets,
-                                 int parts, hipStream_t s, unsigned long long *flops = nullptr);
+                                 int parts, int tparts, hipStream_t s,
+                                 unsigned long long *flops = nullptr);
 // The walk's headers, embedded in the library for the runtime compiler (generated at build time).
 const char *const *embedded_header_names(int *n);
 const char *const *embedded_header_texts();
@@ -46,7 +49,8 @@ struct SpecEdgeKernels {
 hipError_t launch_validate_edges_spec(const SpecEdgeKernels &K, const RobotDev &rb, const EnvDev &ed,
                                       const EdgeSrc &src, int64_t n_edges, float res, uint8_t *out,
                                       unsigned long long *queue, int grid, int block, int tickets,
-                                      int parts, hipStream_t s, unsigned long long *flops = nullptr);
+                                      int parts, int tparts, hipStream_t s,
+                                      unsigned long long *flops = nullptr);
 hipError_t launch_validate_edge_one(const RobotDev &rb, const EnvDev &ed, const EdgeSrc &src,
                                     int64_t e, float res, uint8_t *out, hipStream_t s);
 // kNN runs as partial lists over candidate parts plus a merge; the partial lists need a

@@ -122,6 +122,7 @@ struct RobotDev {
     const int32_t *sphere_step;    // [S] step index of each sphere (cost backward)
     int32_t dof, n_steps, n_spheres, n_links;
     int32_t n_slots;               // steps with a walk-cache slot
+    int32_t n_tests;               // the walk's tests: n_steps environment parts + the blocks
 };
 
 // Environment.  Primitive records, packed as float4 in one buffer:

@@ -556,21 +556,20 @@ __device__ __forceinline__ bool grid_hit(const EnvView &ev, const GridDev &g, fl
     }
 
 // The interleaved FK + collision walk of one configuration per lane.
-//   EDGE = true : every test runs; returns as soon as any lane of the wave collides (the edge
-//                 is invalid); the return value is then wave-uniform.
+//   EDGE = true : returns as soon as any lane of the wave collides (the edge is invalid); the
+//                 return value is then wave-uniform.
 //   EDGE = false: per-lane result; lanes that collided stop contributing, and the walk ends
 //                 when every lane has collided.  `col` on entry marks lanes already decided.
-//                 Only the tests numbered [test_from, test_to) run.  The tests are numbered in
-//                 walk order: step s's environment part is number s + blk_first(s), its self
-//                 blocks follow it (blocks are numbered across steps in step order).  Steps
-//                 before the range are posed and cached only, and the walk stops before the
-//                 first step past it.
+// With RANGED only the tests numbered [test_from, test_to) run, else all of them.  The tests
+// are numbered in walk order: step s's environment part is number s + blk_first(s), its self
+// blocks follow it (blocks are numbered across steps in step order).  Steps before the range
+// are posed and cached only, and the walk stops before the first step past it.
 // The step loop is a loop at run time.  The parts that depend on the step's records (posing and
 // caching the link, placing its spheres, its self-pair blocks) go through pg.at_step, which for
 // a robot-specialised program selects code compiled for that step with its records as
 // constants; the environment part, which depends on the records only through a few values,
 // exists once.
-template <bool EDGE, class P, class Q, class W = NoWork>
+template <bool EDGE, bool RANGED = !EDGE, class P, class Q, class W = NoWork>
 __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, const EnvDev &ed, const Q &q,
                              const StepCache &sc, bool col, int test_from, int test_to,
                              W &&work = W()) {
@@ -587,7 +586,7 @@ __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, con
         float Cx = 0.0f, Cy = 0.0f, Cz = 0.0f, CR = 0.0f, hx = 0.0f, hy = 0.0f, hz = 0.0f;
         pg.at_step(st, [&](auto K) __attribute__((always_inline)) {
             const StepRec S = pg.step(K);
-            if (!EDGE) {
+            if (RANGED) {
                 ibase = st + S.blk_first;      // number of the step's environment part
                 if (ibase >= test_to) return 0;
             }
@@ -608,9 +607,9 @@ __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, con
             }
             return 0;
         });
-        if (!EDGE && ibase >= test_to) break;
+        if (RANGED && ibase >= test_to) break;
         if (cnt == 0) continue;
-        const bool env_part = EDGE || ibase >= test_from;
+        const bool env_part = !RANGED || ibase >= test_from;
         // the step's fine spheres, placed on first use (uniform decision)
         float cx[kSpl], cy[kSpl], cz[kSpl], cr[kSpl];
         bool placed = false;
@@ -807,7 +806,7 @@ __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, con
                 return false;
             };
             int b_lo = 0, b_hi = S.blk_count;
-            if (!EDGE) {                       // the blocks inside [test_from, test_to)
+            if (RANGED) {                      // the blocks inside [test_from, test_to)
                 b_lo = max(0, test_from - ibase - 1);
                 b_hi = min(S.blk_count, test_to - ibase - 1);
             }
@@ -865,11 +864,13 @@ __device__ __forceinline__ bool edge_flagged(const uint8_t *flag) {
 // Part `part` of `parts` of the edge's rake: the rake steps k = part, part + parts, ... (all of
 // them for parts == 1).  Every part starts with a step that samples the whole motion, and a
 // part stops early once another part has flagged the edge (flag, read only when parts > 1).
-template <class P, class V, class W = NoWork>
+// With RANGED only the walk's tests [test_from, test_to) run in each state.
+template <bool RANGED = false, class P, class V, class W = NoWork>
 __device__ __forceinline__ uint8_t edge_body(const P &pg, const V &ev, const EnvDev &ed,
                                              const StepCache &sc, const float *a, const float *b,
                                              int n, W &&work = W(), int part = 0, int parts = 1,
-                                             const uint8_t *flag = nullptr) {
+                                             const uint8_t *flag = nullptr, int test_from = 0,
+                                             int test_to = kAllTests) {
     bool bad = false;
     for (int j = 0; j < pg.dof(); ++j) bad |= !isfinite(ld(a, j)) || !isfinite(ld(b, j));
     if (bad) return 1;
@@ -885,7 +886,8 @@ __device__ __forceinline__ uint8_t edge_body(const P &pg, const V &ev, const Env
         idx = idx < n ? idx : n - 1;          // surplus lanes repeat the last state
         const float t = idx == n - 1 ? 1.0f : (float)idx * inv;
         QEdge qs{a, b, t};
-        if (walk_collide<true>(pg, ev, ed, qs, sc, false, 0, pg.n_steps(), work)) return 1;
+        if (walk_collide<true, RANGED>(pg, ev, ed, qs, sc, false, test_from, test_to, work))
+            return 1;
     }
     return 0;
 }
@@ -944,13 +946,16 @@ __device__ __forceinline__ bool pull(Puller &p, int lane, int64_t &first, int64_
 
 
 // The persistent edge launch: waves pull chunks of work items from the work queue and walk
-// each with the rake (the kernels of both program sources call this).  With parts == 1 an
-// item is an edge and its flag is stored as found.  With parts > 1 (long edges) item i is part
-// i / n_edges of edge i % n_edges (part-major, so the parts of one edge sit in different queue
-// ranges and run on different waves at about the same time); the flags were zeroed and a part
-// stores 1 when it finds a collision.
-// MULTI = false compiles the one-wave form (parts is then taken as 1), which keeps the multi-part
-// bookkeeping out of the register allocation of the common case.
+// each with the rake (the kernels of both program sources call this).  With one part per edge
+// an item is an edge and its flag is stored as found.  An edge can also be split over
+// parts x tparts waves: `parts` split its rake steps (long edges) and `tparts` split the walk's
+// tests into that many ranges of about equal count (small batches, whose launch is bound by
+// the latency of one walk).  Item i is then part p = i / n_edges of edge i % n_edges (part-major,
+// so the parts of one edge sit in different queue ranges and run on different waves at about
+// the same time), with rake part p % parts and test range p / parts; the flags were zeroed and
+// a part stores 1 when it finds a collision.
+// MULTI = false compiles the one-wave form (parts and tparts are then taken as 1), which keeps
+// the multi-part bookkeeping out of the register allocation of the common case.
 template <int STAGE, bool COUNT, bool MULTI, class P>
 __device__ __forceinline__ void validate_edges_body(const P &pg, const EnvDev &ed,
                                                     const float4 *__restrict__ env_rec,
@@ -958,8 +963,9 @@ __device__ __forceinline__ void validate_edges_body(const P &pg, const EnvDev &e
                                                     uint8_t *__restrict__ out,
                                                     unsigned long long *__restrict__ queue, int chunk,
                                                     unsigned long long *__restrict__ flops, int cf,
-                                                    int parts_in) {
+                                                    int parts_in, int tparts_in) {
     const int parts = MULTI ? parts_in : 1;
+    const int tparts = MULTI ? tparts_in : 1;
     const RobotDev &rb = pg.rb;
     extern __shared__ float4 lds_dyn[];
     float *lf = reinterpret_cast<float *>(lds_dyn);
@@ -969,18 +975,26 @@ __device__ __forceinline__ void validate_edges_body(const P &pg, const EnvDev &e
     const EnvView ev = make_view<STAGE>(ed, lds_env);
     const int lane = threadIdx.x & (kWave - 1);
     typename std::conditional<COUNT, Work, NoWork>::type work;
-    Puller pl = make_puller(queue, n_edges * parts, chunk);
+    Puller pl = make_puller(queue, n_edges * parts * tparts, chunk);
     int64_t first, count;
     while (pull(pl, lane, first, count)) {
         for (int64_t item = first; item < first + count; ++item) {
-            const int part = MULTI ? (int)(item / n_edges) : 0;
-            const int64_t e = MULTI ? item - part * n_edges : item;
+            const int p = MULTI ? (int)(item / n_edges) : 0;
+            const int64_t e = MULTI ? item - p * n_edges : item;
+            const int part = MULTI ? p % parts : 0;
+            int t0 = 0, t1 = kAllTests;
+            if (MULTI && tparts > 1) {
+                const int y = p / parts;
+                t0 = (int)((int64_t)y * rb.n_tests / tparts);
+                t1 = (int)((int64_t)(y + 1) * rb.n_tests / tparts);
+            }
             const float *a = nullptr, *b = nullptr;
             const int kind = edge_ends(src, pg.dof(), e, a, b);
             uint8_t hit = kind == 2 ? 1 : 0;
             if (kind == 0) {
                 const int n = src.nst ? ld(src.nst, e) : edge_count(a, b, pg.dof(), res);
-                hit = MULTI ? edge_body(pg, ev, ed, sc, a, b, n, work, part, parts, out + e)
+                hit = MULTI ? edge_body<MULTI>(pg, ev, ed, sc, a, b, n, work, part, parts, out + e,
+                                               t0, t1)
                             : edge_body(pg, ev, ed, sc, a, b, n, work);
             }
             if (!MULTI)

@@ -25,7 +25,9 @@ hipError_t launch_validate_states(const RobotDev &, const EnvDev &, const float 
 }
 int64_t noalloc_max_states() { return int64_t(1) << 22; }
 hipError_t noalloc_scratch(void **) { no_device("noalloc_scratch"); }
-hipError_t launch_reset_queue(unsigned long long *, hipStream_t) { no_device("launch_reset_queue"); }
+hipError_t launch_reset_queue(unsigned long long *, hipStream_t, uint8_t *, int64_t) {
+    no_device("launch_reset_queue");
+}
 hipError_t launch_shortcut_propose(const int32_t *, int64_t, int, int, const uint32_t *, int32_t *,
                                   hipStream_t) { no_device("launch_shortcut_propose"); }
 hipError_t launch_shortcut_apply(float *, int32_t *, int64_t, int, int, int, const int32_t *,
@@ -33,11 +35,11 @@ hipError_t launch_shortcut_apply(float *, int32_t *, int64_t, int, int, int, con
     no_device("launch_shortcut_apply");
 }
 hipError_t launch_validate_edges(const RobotDev &, const EnvDev &, const EdgeSrc &, int64_t, float,
-                                 uint8_t *, unsigned long long *, int, int, int, int, hipStream_t,
-                                 unsigned long long *) { no_device("launch_validate_edges"); }
+                                 uint8_t *, unsigned long long *, int, int, int, int, int,
+                                 hipStream_t, unsigned long long *) { no_device("launch_validate_edges"); }
 hipError_t launch_validate_edges_spec(const SpecEdgeKernels &, const RobotDev &, const EnvDev &,
                                       const EdgeSrc &, int64_t, float, uint8_t *,
-                                      unsigned long long *, int, int, int, int, hipStream_t,
+                                      unsigned long long *, int, int, int, int, int, hipStream_t,
                                       unsigned long long *) {
     no_device("launch_validate_edges_spec");
 }

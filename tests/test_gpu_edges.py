@@ -222,3 +222,51 @@ def test_parts_with_explicit_counts_and_indexed_edges(vk):
         r.set_edge_parts(parts)
         np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb, n_states=ns)), ref_n)
         np.testing.assert_array_equal(host(vk.validate_edges_indexed(r, e, nodes, pairs)), ref_i)
+
+
+@pytest.mark.parametrize("name", ["edges7_shelf", "edges8_shelf", "edges8p_shelf"])
+def test_small_batches_split_over_test_ranges(vk, orc, name):
+    """Small edge batches with each edge's walk split over ranges of its tests (environment
+    parts and self blocks, each range posing the earlier steps over the edge's whole rake) give
+    bitwise the flags of the unsplit walk, for range counts from two to one per test, at ragged
+    sizes, with rake parts, with explicit state counts and with index-pair edges; the automatic
+    choice agrees with the oracle outside the band."""
+    import torch
+    w = workload(name, n=700)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = dev(w["qa"]), dev(w["qb"])
+    ns = torch.from_numpy(np.random.default_rng(11).integers(2, 400, 700).astype(np.int32)).cuda()
+    nodes = torch.cat([qa, qb])
+    pairs = torch.stack([torch.arange(700, dtype=torch.int32),
+                         700 + torch.arange(700, dtype=torch.int32)], 1)
+    pairs[3] = torch.tensor([-1, 2], dtype=torch.int32)
+    pairs = pairs.cuda()
+    r.set_edge_ranges(0)
+    assert r.edge_ranges() == 0
+    ref = host(vk.validate_edges(r, e, qa, qb)).copy()
+    ref_n = host(vk.validate_edges(r, e, qa, qb, n_states=ns)).copy()
+    ref_i = host(vk.validate_edges_indexed(r, e, nodes, pairs)).copy()
+    assert 0 < ref.mean() < 1 and ref_i[3] == 0
+    for k in (2, 3, 7, 16, 32):
+        r.set_edge_ranges(k)
+        for E in (1, 63, 65, 700):
+            got = host(vk.validate_edges(r, e, qa[:E].contiguous(), qb[:E].contiguous()))
+            np.testing.assert_array_equal(got, ref[:E], err_msg=f"{name} ranges {k} E {E}")
+        np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb, n_states=ns)), ref_n)
+        np.testing.assert_array_equal(host(vk.validate_edges_indexed(r, e, nodes, pairs)), ref_i)
+        r.set_edge_parts(2)
+        np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb)), ref,
+                                      err_msg=f"{name} ranges {k} parts 2")
+        r.set_edge_parts(1)
+    for bad in (-2, 33):
+        with pytest.raises(vk.VkError):
+            r.set_edge_ranges(bad)
+    r.set_edge_ranges(-1)
+    auto = host(vk.validate_edges(r, e, qa, qb))
+    np.testing.assert_array_equal(auto, ref)
+    idx = np.arange(0, 700, 7)
+    _, cls, _ = orc.edges(w["robot"], w["env"], w["qa"][idx], w["qb"][idx], res=RES)
+    bad, near = edge_mismatches(auto[idx], cls)
+    say(f"test ranges {name}: {len(auto)} edges, rate {auto.mean():.3f}, sample mismatches {bad}, "
+        f"near {near}")
+    assert bad == 0
