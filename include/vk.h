@@ -421,6 +421,20 @@ vk_status vk_edge_batch_destroy(vk_edge_batch batch);
  * VK_ERR_INVALID_ARG for negative sizes or max_knn_k > 32, VK_ERR_OOM.
  */
 vk_status vk_reserve(void *stream, int64_t max_states, int64_t max_knn_samples, int32_t max_knn_k);
+/*
+ * Workspace for the adjoint of the squared-penetration cost over the sphere model (Sec. III-C;
+ * penetration_cost_bwd, penetration_cost_fwd_grad) on `stream`, for up to max_states states of
+ * this robot.  The adjoint keeps per-link force and moment slots for
+ * every state (24 bytes per link); in LDS they hold it to a few waves per CU, so a batch that
+ * needs more than one round of those waves keeps them in this workspace instead and runs at
+ * four waves per SIMD (262,144 7-DoF states: 175 -> 148 us).  For sizes whose slots stay in LDS
+ * nothing beyond the queue counters is reserved.  Without the workspace the calls keep the slots
+ * in LDS: the results are the same either way.  A set-up call like vk_reserve (it allocates, and
+ * fails with VK_ERR_SHAPE on a stream under capture when the workspace would grow).  Errors:
+ * VK_ERR_INVALID_ARG for a NULL robot or max_states < 0, VK_ERR_SHAPE above 2^31 - 1 states.
+ */
+vk_status vk_reserve_cost(void *stream, vk_robot robot, int64_t max_states);
+
 vk_status vk_release(void *stream);
 
 /*
@@ -497,7 +511,8 @@ vk_status vk_robot_get_states_ranges(vk_robot robot, int32_t *max_ranges);
  * times validate_edges on the given batch (same arguments) for every workgroup size in
  * {64, 128, 256, 512, 1024}, workgroups per CU in {1, 2, 4, 8} (at most 2,048 threads per CU)
  * and tickets per wave in {4, 8, 16}, each the median of 7 launches after one untimed launch,
- * then parts per edge in {1, 2, 4, 8} at the fastest of those, and sets the fastest on the
+ * times the four fastest again in three interleaved rounds (each scored by the median of its
+ * rounds), then parts per edge in {1, 2, 4, 8} at the winner, and sets the fastest on the
  * robot.  vk_autotune_states does the same for the validate_states
  * schedules one pass, and two passes split after 1/3, 1/2 and 2/3 of the steps.  With a
  * cache_path (else NULL), results are kept in that JSON file keyed by the workload's class

@@ -31,7 +31,7 @@ EXPORTS = ("vk_robot_create", "vk_robot_destroy", "vk_robot_dof", "vk_robot_n_sp
            "vk_rrt_extend", "vk_rrt_commit", "vk_shortcut_propose", "vk_shortcut_apply",
            "penetration_cost_fwd", "penetration_cost_bwd", "penetration_cost_fwd_grad",
            "vk_edge_batch_create", "vk_edge_batch_run", "vk_edge_batch_get_launch",
-           "vk_edge_batch_destroy", "vk_reserve", "vk_release",
+           "vk_edge_batch_destroy", "vk_reserve", "vk_reserve_cost", "vk_release",
            "vk_robot_set_edge_launch", "vk_robot_get_edge_launch", "vk_robot_set_edge_parts",
            "vk_robot_get_edge_parts", "vk_robot_set_states_split",
            "vk_robot_get_states_split", "vk_robot_set_states_ranges", "vk_robot_get_states_ranges",
@@ -122,6 +122,7 @@ def lib():
         L.vk_edge_batch_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
         L.vk_edge_batch_destroy.argtypes = [vp]
         L.vk_reserve.argtypes = [vp, i64, i64, i32]
+        L.vk_reserve_cost.argtypes = [vp, vp, i64]
         L.vk_release.argtypes = [vp]
         L.vk_robot_set_edge_launch.argtypes = [vp, i32, i32, i32]
         L.vk_robot_get_edge_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
@@ -345,11 +346,29 @@ def reserve(states: int = 0, knn_samples: int = 0, knn_k: int = 0, stream=None):
     _reserved[key] = want
 
 
+_reserved_cost = {}
+
+
+def reserve_cost(robot, states: int, stream=None):
+    """vk_reserve_cost for the current (or given) torch stream: the adjoint's workspace for up to
+    `states` states of `robot` (large batches keep its force slots there instead of in LDS).  A
+    set-up call: do it before capturing a graph on the stream."""
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    per = _reserved_cost.setdefault((torch.cuda.current_device(), st.cuda_stream), {})
+    key = robot.handle.value                  # the handle's address
+    if per.get(key, -1) >= int(states):
+        return
+    _check(lib().vk_reserve_cost(C.c_void_p(st.cuda_stream), robot.handle, int(states)))
+    per[key] = int(states)
+
+
 def release(stream=None):
     """vk_release for the current (or given) torch stream."""
     torch = _torch()
     st = stream if stream is not None else torch.cuda.current_stream()
     _reserved.pop((torch.cuda.current_device(), st.cuda_stream), None)
+    _reserved_cost.pop((torch.cuda.current_device(), st.cuda_stream), None)
     _check(lib().vk_release(C.c_void_p(st.cuda_stream)))
 
 
@@ -615,6 +634,7 @@ def penetration_cost_bwd(robot: Robot, env: Env, q, grad_cost):
     if g.shape != (n,):
         raise ValueError("grad_cost must be [N]")
     out = torch.empty((robot.dof, n), dtype=torch.float32, device=q.device)
+    reserve_cost(robot, n)
     _check(lib().penetration_cost_bwd(robot.handle, env.handle, q.data_ptr(), n, n, g.data_ptr(),
                                       out.data_ptr(), n, _stream()))
     return out
@@ -627,6 +647,7 @@ def penetration_cost_fwd_grad(robot: Robot, env: Env, q):
     n = q.shape[1]
     cost = torch.empty(n, dtype=torch.float32, device=q.device)
     grad = torch.empty((robot.dof, n), dtype=torch.float32, device=q.device)
+    reserve_cost(robot, n)
     _check(lib().penetration_cost_fwd_grad(robot.handle, env.handle, q.data_ptr(), n, n,
                                            cost.data_ptr(), grad.data_ptr(), n, _stream()))
     return cost, grad

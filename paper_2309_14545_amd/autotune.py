@@ -2,7 +2,8 @@
 
 The edge and state autotuners are native (``vk_autotune_edges`` / ``vk_autotune_states`` in
 libvk): they time every candidate launch setting on the caller's batch with HIP events (median of
-7 launches), set the fastest on the robot handle, and keep it in a JSON cache keyed by the
+7 launches; the edge tuner times its four fastest again over three interleaved rounds), set the
+fastest on the robot handle, and keep it in a JSON cache keyed by the
 workload's class (device, robot size, environment size, batch size), so that a later process
 with the same class reuses it without timing.  The knobs of the persistent edge launch are the
 workgroup size (waves per workgroup share one LDS copy of the environment), the workgroups per

@@ -262,12 +262,22 @@ struct CostAcc;
         _Pragma("unroll") for (int k = 0; k < kSpl; ++k) if (k < cnt) VK_PEN(SDEXPR) \
     }
 
-// Per-link force/moment slots live in LDS: slot (link, component) for each lane of the wave.
+// Per-link force/moment slots (in LDS or in global scratch): slot (link, component) for each
+// lane of the wave.
 struct LinkSlots {
     float *base;               // [n_links][6][64] for this wave
     int lane;
     __device__ __forceinline__ float &at(int link, int c) const {
         return base[(link * 6 + c) * kWave + lane];
+    }
+    // a link's six values, read and written as a group
+    __device__ __forceinline__ void load6(int link, float (&v)[6]) const {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = at(link, c);
+    }
+    __device__ __forceinline__ void store6(int link, const float (&v)[6]) const {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) at(link, c) = v[c];
     }
     // a force and its moment about the world origin, summed in registers by the caller over
     // the spheres of one step or the entries of one self block: one update of the link's slots
@@ -433,14 +443,31 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
                 }
                 if (GRAD) fa.add(tx, ty, tz, gtx, gty, gtz);
             }
-            if (GRAD) fa.to(slots, B.link);
+            if (GRAD) {
+                float pre[6];
+                slots.load6(B.link, pre);
+                pre[0] += fa.fx;
+                pre[1] += fa.fy;
+                pre[2] += fa.fz;
+                pre[3] += fa.mx;
+                pre[4] += fa.my;
+                pre[5] += fa.mz;
+                slots.store6(B.link, pre);
+            }
         }
         if (GRAD) {
             ForceSum fs;                         // the forces on this step's spheres
 #pragma unroll
             for (int k = 0; k < kSpl; ++k)
                 if (k < cnt) fs.add(cx[k], cy[k], cz[k], fx[k], fy[k], fz[k]);
-            fs.to(slots, S.link);
+            if (S.joint >= 0) {
+                // the link's first step: nothing has reached its slots since they were zeroed
+                // (self blocks update only earlier links), so they are written, not updated
+                const float v[6] = {fs.fx, fs.fy, fs.fz, fs.mx, fs.my, fs.mz};
+                slots.store6(S.link, v);
+            } else {
+                fs.to(slots, S.link);
+            }
         }
     }
     return cost;
@@ -469,23 +496,33 @@ __global__ void __launch_bounds__(256)
 // Backward: forces per link accumulated in LDS, suffix sums over the tree, then
 // dq_j = z_j . (M_j - o_j x F_j) with (F_j, M_j) the force and moment (about the origin) of
 // everything joint j moves and (z_j, o_j) the axis and origin of joint j's frame.
-template <int STAGE>
-__global__ void __launch_bounds__(256)
-    k_cost_bwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
-               const float *__restrict__ q, int64_t n, int64_t ldq,
-               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg,
-               float *__restrict__ cost_out, int cf) {
+// The slots live in LDS ([slots of every wave of the block][walk caches][env records]) or, with
+// GSLOT, in global memory (gslots: every wave's slots, in wave order), which frees the LDS that
+// holds the backward kernel's occupancy down.
+template <int STAGE, bool GSLOT>
+__device__ __forceinline__ void cost_bwd_body(const RobotDev &rb, const EnvDev &ed,
+                                              const float4 *__restrict__ env_rec,
+                                              const float *__restrict__ q, int64_t n, int64_t ldq,
+                                              const float *__restrict__ gcost,
+                                              float *__restrict__ grad, int64_t ldg,
+                                              float *__restrict__ cost_out, int cf,
+                                              float *__restrict__ gslots) {
     extern __shared__ float4 lds_dyn[];
-    // layout: [slots for every wave of the block][env records]
     const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const int slot_floats = rb.n_links * 6 * kWave;
-    float *slot_base = reinterpret_cast<float *>(lds_dyn);
-    float *lf = slot_base + slot_floats * (blockDim.x / kWave);
+    float *slot_base, *lf;
+    if (GSLOT) {
+        slot_base = gslots + ((int64_t)blockIdx.x * (blockDim.x / kWave) + wave) * slot_floats;
+        lf = reinterpret_cast<float *>(lds_dyn);
+    } else {
+        slot_base = reinterpret_cast<float *>(lds_dyn) + wave * slot_floats;
+        lf = reinterpret_cast<float *>(lds_dyn) + slot_floats * (blockDim.x / kWave);
+    }
     const StepCache sc = step_cache(lf, rb.n_slots, rb.dof, cf);
     float4 *lds_env = after_caches(lf, rb.n_slots, rb.dof, cf);
     if (STAGE) stage_env(lds_env, env_rec, ed.n_stage);
     const EnvView ev = make_view<STAGE>(ed, lds_env);
-    LinkSlots slots{slot_base + wave * slot_floats, lane};
+    LinkSlots slots{slot_base, lane};
     for (int l = 0; l < rb.n_links; ++l)
         for (int c = 0; c < 6; ++c) slots.at(l, c) = 0.0f;
 
@@ -542,6 +579,27 @@ __global__ void __launch_bounds__(256)
         frame_dh(T, J, qs(j));
         cur = l;
     }
+}
+
+template <int STAGE>
+__global__ void __launch_bounds__(256)
+    k_cost_bwd(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+               const float *__restrict__ q, int64_t n, int64_t ldq,
+               const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg,
+               float *__restrict__ cost_out, int cf) {
+    cost_bwd_body<STAGE, false>(rb, ed, env_rec, q, n, ldq, gcost, grad, ldg, cost_out, cf,
+                                nullptr);
+}
+
+// four waves per SIMD (at most 128 VGPRs): with the slots out of the LDS the registers are the
+// occupancy limit
+template <int STAGE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+    k_cost_bwd_g(RobotDev rb, EnvDev ed, const float4 *__restrict__ env_rec,
+                 const float *__restrict__ q, int64_t n, int64_t ldq,
+                 const float *__restrict__ gcost, float *__restrict__ grad, int64_t ldg,
+                 float *__restrict__ cost_out, int cf, float *__restrict__ gslots) {
+    cost_bwd_body<STAGE, true>(rb, ed, env_rec, q, n, ldq, gcost, grad, ldg, cost_out, cf, gslots);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1475,12 +1533,30 @@ size_t cost_bwd_slot_bytes(const RobotDev &rb, int block, int cf) {
            walk_lds_bytes(rb, block, cf);
 }
 
+size_t cost_bwd_global_slot_bytes(const RobotDev &rb, int64_t n, int block) {
+    const int64_t blocks = (n + block - 1) / block;
+    return (size_t)blocks * (block / kWave) * rb.n_links * 6 * kWave * sizeof(float);
+}
+
+int cost_bwd_lds_waves_per_cu(const RobotDev &rb, int block) {
+    return resident_blocks(reinterpret_cast<const void *>(&k_cost_bwd<1>), block,
+                           cost_bwd_slot_bytes(rb, block, 0)) *
+           (block / kWave);
+}
+
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed_in, const float *q, int64_t n,
                            int64_t ldq, const float *gcost, float *grad, int64_t ldg, int block,
-                           hipStream_t s, float *cost) {
+                           hipStream_t s, float *cost, float *gslots) {
     const dim3 grid_((unsigned)((n + block - 1) / block)), block_(block);
-    const auto lds_ = [&](int c) { return cost_bwd_slot_bytes(rb, block, c); };
     const size_t max_lds_ = device_max_lds();
+    if (gslots) {
+        const auto lds_ = [&](int c) { return walk_lds_bytes(rb, block, c); };
+#define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg, cost, cf, gslots
+        VK_STAGED(k_cost_bwd_g)
+#undef ARGS_
+        return hipGetLastError();
+    }
+    const auto lds_ = [&](int c) { return cost_bwd_slot_bytes(rb, block, c); };
 #define ARGS_ rb, ed, ed.rec, q, n, ldq, gcost, grad, ldg, cost, cf
     VK_STAGED(k_cost_bwd)
 #undef ARGS_

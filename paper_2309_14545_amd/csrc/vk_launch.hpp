@@ -93,10 +93,15 @@ size_t walk_lds_bytes(const RobotDev &rb, int block, int cf = 0);
 // at least one) when the per-wave walk caches of a long robot would not fit the LDS.
 int walk_block(const RobotDev &rb, int want);
 // The adjoint: grad = gcost * d cost / d q (gcost NULL: the plain gradient); with `cost` the
-// per-state cost is stored too.
+// per-state cost is stored too.  With gslots (cost_bwd_global_slot_bytes(rb, n, block) bytes)
+// the per-link force slots go to that global scratch instead of the LDS.
 hipError_t launch_cost_bwd(const RobotDev &rb, const EnvDev &ed, const float *q,
                            int64_t n, int64_t ldq, const float *gcost, float *grad, int64_t ldg,
-                           int block, hipStream_t s, float *cost = nullptr);
+                           int block, hipStream_t s, float *cost = nullptr,
+                           float *gslots = nullptr);
+size_t cost_bwd_global_slot_bytes(const RobotDev &rb, int64_t n, int block);
+// Resident waves per CU of the adjoint with its slots in LDS (workgroups of `block` threads).
+int cost_bwd_lds_waves_per_cu(const RobotDev &rb, int block);
 
 // A kernel launch spelled out for a graph node: the kernel, its shape and its argument values
 // (args[i] points at the i-th value held in the node itself, so a node must not be copied

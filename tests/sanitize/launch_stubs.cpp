@@ -75,9 +75,13 @@ size_t cost_bwd_slot_bytes(const RobotDev &, int, int) { no_device("cost_bwd_slo
 size_t walk_lds_bytes(const RobotDev &, int, int) { no_device("walk_lds_bytes"); }
 int walk_block(const RobotDev &, int) { no_device("walk_block"); }
 hipError_t launch_cost_bwd(const RobotDev &, const EnvDev &, const float *, int64_t, int64_t,
-                           const float *, float *, int64_t, int, hipStream_t, float *) {
+                           const float *, float *, int64_t, int, hipStream_t, float *, float *) {
     no_device("launch_cost_bwd");
 }
+size_t cost_bwd_global_slot_bytes(const RobotDev &, int64_t, int) {
+    no_device("cost_bwd_global_slot_bytes");
+}
+int cost_bwd_lds_waves_per_cu(const RobotDev &, int) { no_device("cost_bwd_lds_waves_per_cu"); }
 void fill_node(KernelNode &, unsigned long long *, unsigned long long, int, int) { no_device("fill_node"); }
 void edge_batch_node(KernelNode &, const BatchSet *, const int32_t *, int, int64_t, float,
                      unsigned long long *, int, int, int, int, int) { no_device("edge_batch_node"); }

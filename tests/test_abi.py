@@ -169,6 +169,8 @@ def test_reserve_argument_checks(vk):
     assert lib.vk_reserve(None, 0, -5, 0) == -1
     assert lib.vk_reserve(None, 0, 100, 33) == -1
     assert lib.vk_reserve(None, 1 << 31, 0, 0) == -2
+    assert lib.vk_reserve_cost(None, None, 10) == -1          # NULL robot
+    assert b"robot" in lib.vk_last_error()
 
 
 def test_specialisation_source_is_exact(vk):

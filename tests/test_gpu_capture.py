@@ -81,3 +81,28 @@ def test_hot_calls_need_a_workspace(vk):
     st = vk.lib().validate_edges(r.handle, e.handle, qa.data_ptr(), qb.data_ptr(), None, 64,
                                  C.c_float(1.0 / 32.0), out.data_ptr(), s)
     assert st == -2
+
+
+def test_capture_adjoint_with_global_slots(vk):
+    """The cost and gradient of a batch large enough to keep the adjoint's force slots in the
+    stream's workspace, captured after vk_reserve_cost and replayed with eager work between the
+    replays, equal the eager result every time."""
+    import torch
+    w = workload("cost7")
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    q = dev(np.ascontiguousarray(w["q"]))
+    ref_c, ref_g = (host(t).copy() for t in vk.penetration_cost_fwd_grad(r, e, q))
+    side = torch.cuda.Stream()
+    vk.reserve_cost(r, q.shape[1], stream=side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side, capture_error_mode="thread_local"):
+        cost, grad = vk.penetration_cost_fwd_grad(r, e, q)
+    for rep in range(3):
+        cost.fill_(-1.0)
+        grad.fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host(cost), ref_c)
+        np.testing.assert_array_equal(host(grad), ref_g)
+        say("adjoint capture replay", rep, "ok")
+        _ = (q * 2).sum().item()

@@ -170,3 +170,42 @@ def test_fwd_grad_equals_the_two_calls(vk):
     with torch.no_grad():                     # no gradient wanted: the cost kernel alone
         np.testing.assert_array_equal(host(vk.penetration_cost(dev(w["q"]), r, e)),
                                       host(vk.penetration_cost_fwd(r, e, dev(w["q"]))))
+
+
+def test_adjoint_slots_in_global_memory(vk, orc):
+    """A batch that needs more than one round of the adjoint's LDS-bound waves keeps its force
+    slots in the stream's workspace (vk_reserve_cost): the cost and gradient equal those of the
+    LDS slots (the same sums in the same order), on a stream without the workspace, for the
+    262,144-state batch and a ragged size; sampled states agree with the oracle's gradient."""
+    import ctypes as C
+    import torch
+    w = workload("cost7")
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    lib = vk.lib()
+    for n in (262144, 200003):
+        q = dev(np.ascontiguousarray(w["q"][:, :n]))
+        outs = []
+        for reserve in (False, True):
+            side = torch.cuda.Stream()
+            with torch.cuda.stream(side):
+                s = C.c_void_p(side.cuda_stream)
+                if reserve:
+                    assert lib.vk_reserve_cost(s, r.handle, n) == 0
+                cost = torch.empty(n, device="cuda")
+                grad = torch.empty((7, n), device="cuda")
+                assert lib.penetration_cost_fwd_grad(r.handle, e.handle, q.data_ptr(), n, n,
+                                                     cost.data_ptr(), grad.data_ptr(), n, s) == 0
+                side.synchronize()
+                outs.append((host(cost).copy(), host(grad).copy()))
+                vk.release(side)
+        np.testing.assert_array_equal(outs[0][0], outs[1][0])
+        np.testing.assert_array_equal(outs[0][1], outs[1][1])
+        say(f"adjoint slots: n {n}, LDS and global slots equal, cost > 0 in "
+            f"{(outs[1][0] > 0).mean():.2f} of the states")
+    idx = np.arange(0, 262144, 8191)
+    ref = orc.cost_grads(w["robot"], w["env"], np.ascontiguousarray(w["q"][:, idx]))
+    q = dev(np.ascontiguousarray(w["q"]))
+    _, grad = vk.penetration_cost_fwd_grad(r, e, q)           # the binding reserves: global slots
+    got = host(grad)[:, idx].astype(np.float64)
+    den = max(np.linalg.norm(ref), 1e-30)
+    assert np.linalg.norm(got - ref) / den <= 1e-4
