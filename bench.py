@@ -30,7 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32 = 157.3e12          # MI355X vector FP32, packed (published)
-PEAK_FP32_UNPACKED = 78.6e12  # without packed FP32 instructions (this build disables them)
+PEAK_FP32_UNPACKED = 78.6e12  # without packed FP32 instructions (the library is compiled without them)
 
 # HBM bytes per launch of the headline kernel from two rocprofv3 passes (FETCH_SIZE x 2.0 and
 # WRITE_SIZE x 1.0, the factors a 1 GiB device copy gives), valid only for the kernel sources
@@ -180,7 +180,9 @@ def extra_specialized(vk, name, steps):
     for label in ("interpreted", "specialized"):
         if label == "specialized":
             t0 = time.perf_counter()
-            robot.specialize(os.path.join(ROOT, "gpurun_out", "vk_spec_cache"))
+            cache = os.path.join(os.path.expanduser("~"), ".cache", "vk_spec_cache")
+            os.makedirs(cache, exist_ok=True)
+            robot.specialize(cache)
             res["compile_s"] = time.perf_counter() - t0
         autotune.tune_edges(robot, env, qa, qb, resolution=RES, cache=None)
         vk.validate_edges(robot, env, qa, qb, resolution=RES, out=out)
@@ -423,7 +425,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the validation path shards into independent edge "
-              "ranges with no exchange, and this build runs and reports a single MI355X "
+              "ranges with no exchange, and the benchmark runs and reports a single MI355X "
               "(use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 

@@ -11,7 +11,7 @@ from synthetic import workload
 
 pytestmark = pytest.mark.gpu
 RES = 1.0 / 32.0
-CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "gpurun_out", "vk_spec_cache")
+CACHE = os.path.join(os.path.expanduser("~"), ".cache", "vk_spec_cache")
 
 
 @pytest.fixture(scope="module")
