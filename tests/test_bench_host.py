@@ -17,13 +17,14 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_follows_the_kernel_sources(monkeypatch):
-    """The counters count while the kernel sources hash as recorded, and read null otherwise."""
+    """The counters count while the kernel sources and the build hash as recorded, and read
+    null otherwise."""
     import hashlib
     import bench
-    csrc = os.path.join(ROOT, "paper_2309_14545_amd", "csrc")
+    pkg = os.path.join(ROOT, "paper_2309_14545_amd")
     now = {}
     for f in bench.TRAFFIC["sources"]:
-        with open(os.path.join(csrc, f), "rb") as fh:
+        with open(os.path.join(pkg, f), "rb") as fh:
             now[f] = hashlib.sha256(fh.read()).hexdigest()[:16]
     fresh = dict(bench.TRAFFIC, sources=now)
     monkeypatch.setattr(bench, "TRAFFIC", fresh)
