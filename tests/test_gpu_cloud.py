@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from helpers import dev, host, say, state_mismatches
+from helpers import dev, host, say, state_mismatches, edge_mismatches
 from synthetic import workload, rng, uniform_states, point_cloud_scene
 
 pytestmark = pytest.mark.gpu
@@ -83,3 +83,27 @@ def test_small_sphere_sets_stay_flat(vk, orc):
     flags = host(vk.validate_states(vk.Robot(w["robot"]), vk.Env(env), dev(q)))
     cmin, _ = orc.states(w["robot"], env, q)
     assert state_mismatches(flags, cmin)[0] == 0
+
+
+def test_cloud_edges_parity(vk, orc, cloud):
+    """Edges among the cloud (the edge walk's own grid scan, cells in plain row order) against
+    the FP64 oracle, and the same flags with each edge's tests split over ranges of waves and
+    with its rake split over parts."""
+    w = cloud
+    env = {"spheres": w["env"]["spheres"][300:]}           # the cloud alone: free and colliding
+    g = rng("gpu-cloud", "edges")
+    qa = np.ascontiguousarray(uniform_states(g, 14, 200).T)
+    qb = np.ascontiguousarray(qa + np.float32(0.15) * (uniform_states(g, 14, 200).T - qa))
+    r, e = vk.Robot(w["robot"]), vk.Env(env)
+    r.set_edge_ranges(0)
+    ref = host(vk.validate_edges(r, e, dev(qa), dev(qb))).copy()
+    _, cls, _ = orc.edges(w["robot"], env, qa, qb, res=1.0 / 32.0)
+    bad, near = edge_mismatches(ref, cls)
+    say(f"  cloud edges: {len(ref)}, rate {ref.mean():.3f}, mismatches {bad}, near {near}")
+    assert bad == 0 and 0.05 < ref.mean() < 0.95
+    for k in (4, 32):
+        r.set_edge_ranges(k)
+        np.testing.assert_array_equal(host(vk.validate_edges(r, e, dev(qa), dev(qb))), ref)
+    r.set_edge_ranges(0)
+    r.set_edge_parts(3)
+    np.testing.assert_array_equal(host(vk.validate_edges(r, e, dev(qa), dev(qb))), ref)
