@@ -45,6 +45,14 @@ def test_specialized_edges_match(vk, orc, name):
     np.testing.assert_array_equal(host(vk.validate_edges_indexed(r, e, nodes, pairs, resolution=RES)), ref)
     flops = torch.zeros(8, dtype=torch.int64, device="cuda")
     np.testing.assert_array_equal(host(vk.validate_edges_counted(r, e, qa, qb, flops, resolution=RES)), ref)
+    # small batches with their tests split over waves, and rake parts, in the specialised kernels
+    for ranges, parts in ((32, 1), (5, 2)):
+        r.set_edge_ranges(ranges)
+        r.set_edge_parts(parts)
+        np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa[:100], qb[:100], resolution=RES)),
+                                      ref[:100], err_msg=f"ranges {ranges} parts {parts}")
+    r.set_edge_ranges(-1)
+    r.set_edge_parts(1)
     r.use_specialized(False)
     assert not r.specialized
     np.testing.assert_array_equal(host(vk.validate_edges(r, e, qa, qb, resolution=RES)), ref)
