@@ -461,13 +461,14 @@ __device__ __forceinline__ void place_step(const P &pg, const StepRec &S, const 
 // Grid broadphase over a large set of small spheres.  A point of radius <= gmax_r can touch a
 // robot sphere (c, r) only if its centre lies within r + gmax_r of c, i.e. in one of the cells
 // that the box c -+ (r + gmax_r) touches; the cells of one row are contiguous in the sorted
-// point array, so each (z, y) row of that box is one contiguous range.  Per lane (the cells
-// differ between configurations); `visit(p)` returns true to stop.  With CENTRE_FIRST the row
-// holding the centre is scanned first (the state walks); the edge walk keeps the plain order,
-// whose fewer live registers spare it two register spills on scenes without points.
+// point array, so each (z, y) row of that box is one contiguous range [b, e) of it.  Per lane
+// (the cells differ between configurations); `row(b, e)` returns true to stop.  With
+// CENTRE_FIRST the row holding the centre is visited first (the state walks); the edge walk
+// keeps the plain order, whose fewer live registers spare it two register spills on scenes
+// without points.
 template <bool CENTRE_FIRST, class F>
-__device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, float cx, float cy,
-                                          float cz, float r, F &&visit) {
+__device__ __forceinline__ void grid_rows(const EnvView &ev, const GridDev &g, float cx, float cy,
+                                          float cz, float r, F &&row) {
     const float *cell = ev.cell;
     // the cells that the box c -+ (r + largest point radius) touches (widened a little for the
     // float rounding of the cell coordinates)
@@ -485,29 +486,45 @@ __device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, f
     if (!CENTRE_FIRST) {
         for (int z = z0; z <= z1; ++z)
             for (int y = y0; y <= y1; ++y) {
-                const int row = (z * g.gdim[1] + y) * g.gdim[0];
-                const int b = __float_as_int(cell[row + x0]), e = __float_as_int(cell[row + x1 + 1]);
-                for (int p = b; p < e; ++p)
-                    if (visit(g.pts[p])) return;
+                const int rw = (z * g.gdim[1] + y) * g.gdim[0];
+                if (row(__float_as_int(cell[rw + x0]), __float_as_int(cell[rw + x1 + 1]))) return;
             }
         return;
     }
     // every (z, y) row once, the row holding the centre first: a sphere that touches a point
-    // usually touches one there, and its lane then stops early
+    // usually touches one there, and its lane then stops early.  The next row's bounds are
+    // loaded before the current row is visited, so their loads overlap its points' loads.
     if (y0 > y1 || z0 > z1) return;
     const int ny = y1 - y0 + 1, nrow = ny * (z1 - z0 + 1);
     const auto at = [&](float c, float o, int a, int b) {
         return min(max((int)fminf(fmaxf(floorf((c - o) * g.ginv), -lim), lim), a), b);
     };
     const int first = (at(cz, g.gorg[2], z0, z1) - z0) * ny + (at(cy, g.gorg[1], y0, y1) - y0);
-    for (int k = 0; k < nrow; ++k) {
+    const auto bounds = [&](int k, int &b, int &e) {
         const int i = k == 0 ? first : (k <= first ? k - 1 : k);
         const int zi = i / ny, z = z0 + zi, y = y0 + i - zi * ny;
-        const int row = (z * g.gdim[1] + y) * g.gdim[0];
-        const int b = __float_as_int(cell[row + x0]), e = __float_as_int(cell[row + x1 + 1]);
-        for (int p = b; p < e; ++p)
-            if (visit(g.pts[p])) return;
+        const int rw = (z * g.gdim[1] + y) * g.gdim[0];
+        b = __float_as_int(cell[rw + x0]);
+        e = __float_as_int(cell[rw + x1 + 1]);
+    };
+    int nb, ne;
+    bounds(0, nb, ne);
+    for (int k = 0; k < nrow; ++k) {
+        const int b = nb, e = ne;
+        if (k + 1 < nrow) bounds(k + 1, nb, ne);
+        if (row(b, e)) return;
     }
+}
+
+// Every point of the rows above, one at a time; `visit(p)` returns true to stop.
+template <bool CENTRE_FIRST, class F>
+__device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, float cx, float cy,
+                                          float cz, float r, F &&visit) {
+    grid_rows<CENTRE_FIRST>(ev, g, cx, cy, cz, r, [&](int b, int e) {
+        for (int p = b; p < e; ++p)
+            if (visit(g.pts[p])) return true;
+        return false;
+    });
 }
 
 // Lower bound of the clearance of location (x, y, z) to every point of the grid: the field's
@@ -529,13 +546,33 @@ __device__ __forceinline__ float point_clearance(const GridDev &g, float x, floa
     return v - sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
 }
 
+// Does sphere (c, r) touch a point of the grid?  The state walks (CENTRE_FIRST) read a row's
+// points kGridBatch at a time, so that a lane waits for one round of loads per batch rather
+// than per point (the loads past the row's end repeat its last point; the answer is the same
+// whichever order finds the hit).  Three: with four or more in flight the state kernels spill
+// over a hundred registers.  The edge walk keeps the one-at-a-time loop, the smaller code.
+constexpr int kGridBatch = 3;
 template <bool CENTRE_FIRST>
 __device__ __forceinline__ bool grid_hit(const EnvView &ev, const GridDev &g, float cx, float cy,
                                          float cz, float r) {
     bool hit = false;
-    grid_scan<CENTRE_FIRST>(ev, g, cx, cy, cz, r, [&](const float4 &p) {
-        hit = hit_sphere(cx, cy, cz, r, p);
+    if (!CENTRE_FIRST) {
+        grid_scan<false>(ev, g, cx, cy, cz, r, [&](const float4 &p) {
+            hit = hit_sphere(cx, cy, cz, r, p);
+            return hit;
+        });
         return hit;
+    }
+    grid_rows<true>(ev, g, cx, cy, cz, r, [&](int b, int e) {
+        for (int p = b; p < e; p += kGridBatch) {
+            float4 o[kGridBatch];
+#pragma unroll
+            for (int u = 0; u < kGridBatch; ++u) o[u] = g.pts[min(p + u, e - 1)];
+#pragma unroll
+            for (int u = 0; u < kGridBatch; ++u) hit |= hit_sphere(cx, cy, cz, r, o[u]);
+            if (hit) return true;
+        }
+        return false;
     });
     return hit;
 }
