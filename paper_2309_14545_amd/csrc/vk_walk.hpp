@@ -546,24 +546,16 @@ __device__ __forceinline__ float point_clearance(const GridDev &g, float x, floa
     return v - sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
 }
 
-// Does sphere (c, r) touch a point of the grid?  The state walks (CENTRE_FIRST) read a row's
-// points kGridBatch at a time, so that a lane waits for one round of loads per batch rather
-// than per point (the loads past the row's end repeat its last point; the answer is the same
-// whichever order finds the hit).  Three: with four or more in flight the state kernels spill
-// over a hundred registers.  The edge walk keeps the one-at-a-time loop, the smaller code.
+// Does sphere (c, r) touch a point of the grid?  A row's points are read kGridBatch at a time,
+// so that a lane waits for one round of loads per batch rather than per point (the loads past
+// the row's end repeat its last point; the answer is the same whichever order finds the hit).
+// Three: with four or more in flight the state kernels spill over a hundred registers.
 constexpr int kGridBatch = 3;
 template <bool CENTRE_FIRST>
 __device__ __forceinline__ bool grid_hit(const EnvView &ev, const GridDev &g, float cx, float cy,
                                          float cz, float r) {
     bool hit = false;
-    if (!CENTRE_FIRST) {
-        grid_scan<false>(ev, g, cx, cy, cz, r, [&](const float4 &p) {
-            hit = hit_sphere(cx, cy, cz, r, p);
-            return hit;
-        });
-        return hit;
-    }
-    grid_rows<true>(ev, g, cx, cy, cz, r, [&](int b, int e) {
+    grid_rows<CENTRE_FIRST>(ev, g, cx, cy, cz, r, [&](int b, int e) {
         for (int p = b; p < e; p += kGridBatch) {
             float4 o[kGridBatch];
 #pragma unroll
