@@ -383,7 +383,7 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
 #pragma unroll
                 for (int k = 0; k < kSpl; ++k) {
                     if (k >= cnt || point_clearance(G, cx[k], cy[k], cz[k]) >= cr[k]) continue;
-                    grid_scan<false>(ev, G, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
+                    grid_scan(ev, G, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
                         VK_PEN(sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
                         return false;
                     });

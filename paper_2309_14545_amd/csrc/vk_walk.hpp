@@ -461,12 +461,9 @@ __device__ __forceinline__ void place_step(const P &pg, const StepRec &S, const 
 // Grid broadphase over a large set of small spheres.  A point of radius <= gmax_r can touch a
 // robot sphere (c, r) only if its centre lies within r + gmax_r of c, i.e. in one of the cells
 // that the box c -+ (r + gmax_r) touches; the cells of one row are contiguous in the sorted
-// point array, so each (z, y) row of that box is one contiguous range [b, e) of it.  Per lane
-// (the cells differ between configurations); `row(b, e)` returns true to stop.  With
-// CENTRE_FIRST the row holding the centre is visited first (the state walks); the edge walk
-// keeps the plain order, whose fewer live registers spare it two register spills on scenes
-// without points.
-template <bool CENTRE_FIRST, class F>
+// point array, so each (z, y) row of that box is one contiguous range [b, e) of it.
+// `row(b, e)` returns true to stop.
+template <class F>
 __device__ __forceinline__ void grid_rows(const EnvView &ev, const GridDev &g, float cx, float cy,
                                           float cz, float r, F &&row) {
     const float *cell = ev.cell;
@@ -483,44 +480,18 @@ __device__ __forceinline__ void grid_rows(const EnvView &ev, const GridDev &g, f
     const int y0 = lo(cy, g.gorg[1]), y1 = hi(cy, g.gorg[1], g.gdim[1]);
     const int z0 = lo(cz, g.gorg[2]), z1 = hi(cz, g.gorg[2], g.gdim[2]);
     if (x0 > x1) return;
-    if (!CENTRE_FIRST) {
-        for (int z = z0; z <= z1; ++z)
-            for (int y = y0; y <= y1; ++y) {
-                const int rw = (z * g.gdim[1] + y) * g.gdim[0];
-                if (row(__float_as_int(cell[rw + x0]), __float_as_int(cell[rw + x1 + 1]))) return;
-            }
-        return;
-    }
-    // every (z, y) row once, the row holding the centre first: a sphere that touches a point
-    // usually touches one there, and its lane then stops early.  The next row's bounds are
-    // loaded before the current row is visited, so their loads overlap its points' loads.
-    if (y0 > y1 || z0 > z1) return;
-    const int ny = y1 - y0 + 1, nrow = ny * (z1 - z0 + 1);
-    const auto at = [&](float c, float o, int a, int b) {
-        return min(max((int)fminf(fmaxf(floorf((c - o) * g.ginv), -lim), lim), a), b);
-    };
-    const int first = (at(cz, g.gorg[2], z0, z1) - z0) * ny + (at(cy, g.gorg[1], y0, y1) - y0);
-    const auto bounds = [&](int k, int &b, int &e) {
-        const int i = k == 0 ? first : (k <= first ? k - 1 : k);
-        const int zi = i / ny, z = z0 + zi, y = y0 + i - zi * ny;
-        const int rw = (z * g.gdim[1] + y) * g.gdim[0];
-        b = __float_as_int(cell[rw + x0]);
-        e = __float_as_int(cell[rw + x1 + 1]);
-    };
-    int nb, ne;
-    bounds(0, nb, ne);
-    for (int k = 0; k < nrow; ++k) {
-        const int b = nb, e = ne;
-        if (k + 1 < nrow) bounds(k + 1, nb, ne);
-        if (row(b, e)) return;
-    }
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y) {
+            const int rw = (z * g.gdim[1] + y) * g.gdim[0];
+            if (row(__float_as_int(cell[rw + x0]), __float_as_int(cell[rw + x1 + 1]))) return;
+        }
 }
 
 // Every point of the rows above, one at a time; `visit(p)` returns true to stop.
-template <bool CENTRE_FIRST, class F>
+template <class F>
 __device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, float cx, float cy,
                                           float cz, float r, F &&visit) {
-    grid_rows<CENTRE_FIRST>(ev, g, cx, cy, cz, r, [&](int b, int e) {
+    grid_rows(ev, g, cx, cy, cz, r, [&](int b, int e) {
         for (int p = b; p < e; ++p)
             if (visit(g.pts[p])) return true;
         return false;
@@ -546,16 +517,16 @@ __device__ __forceinline__ float point_clearance(const GridDev &g, float x, floa
     return v - sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
 }
 
-// Does sphere (c, r) touch a point of the grid?  A row's points are read kGridBatch at a time,
-// so that a lane waits for one round of loads per batch rather than per point (the loads past
-// the row's end repeat its last point; the answer is the same whichever order finds the hit).
-// Three: with four or more in flight the state kernels spill over a hundred registers.
+// Does sphere (c, r) touch a point of the grid?  Per lane: a row's points are read kGridBatch
+// at a time, so that a lane waits for one round of loads per batch rather than per point (the
+// loads past the row's end repeat its last point; the answer is the same whichever order finds
+// the hit).  Three: with four or more in flight the walk kernels spilled over a hundred
+// registers.
 constexpr int kGridBatch = 3;
-template <bool CENTRE_FIRST>
 __device__ __forceinline__ bool grid_hit(const EnvView &ev, const GridDev &g, float cx, float cy,
                                          float cz, float r) {
     bool hit = false;
-    grid_rows<CENTRE_FIRST>(ev, g, cx, cy, cz, r, [&](int b, int e) {
+    grid_rows(ev, g, cx, cy, cz, r, [&](int b, int e) {
         for (int p = b; p < e; p += kGridBatch) {
             float4 o[kGridBatch];
 #pragma unroll
@@ -567,6 +538,31 @@ __device__ __forceinline__ bool grid_hit(const EnvView &ev, const GridDev &g, fl
         return false;
     });
     return hit;
+}
+
+// The same test for a sphere that every lane holds (wave-uniform c, r): the lanes read 64
+// consecutive points of a row at a time.  Called in wave-uniform control flow with every lane
+// of the wave active; the answer is wave-uniform.
+__device__ __forceinline__ bool grid_hit_wave(const EnvView &ev, const GridDev &g, float cx,
+                                              float cy, float cz, float r) {
+    const int lane = threadIdx.x & (kWave - 1);
+    bool hit = false;
+    grid_rows(ev, g, cx, cy, cz, r, [&](int b, int e) {
+        for (int p0 = b; p0 < e; p0 += kWave) {
+            const int p = min(p0 + lane, e - 1);
+            if (wave_ballot(hit_sphere(cx, cy, cz, r, g.pts[p]))) {
+                hit = true;
+                return true;
+            }
+        }
+        return false;
+    });
+    return hit;
+}
+
+// One lane's value, wave-uniform.
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 // Gated fine test: the step's bounding sphere (coarse) must touch the primitive in some live
@@ -716,10 +712,25 @@ __device__ __forceinline__ bool walk_collide(const P &pg, const EnvView &ev, con
                 if (wave_ballot(near)) {
                     VK_PLACE()
     #pragma unroll
-                    for (int k = 0; k < kSpl; ++k)
-                        if (k < cnt && near && !col &&
-                            point_clearance(G, cx[k], cy[k], cz[k]) < cr[k])
-                            col |= grid_hit<!EDGE>(ev, G, cx[k], cy[k], cz[k], cr[k]);
+                    for (int k = 0; k < kSpl; ++k) {
+                        const bool scan = k < cnt && near && !col &&
+                                          point_clearance(G, cx[k], cy[k], cz[k]) < cr[k];
+                        if (!EDGE) {
+                            // independent states: the spheres that must scan, one at a time,
+                            // each by the whole wave
+                            const int lane = threadIdx.x & (kWave - 1);
+                            for (unsigned long long m = wave_ballot(scan); m; m &= m - 1) {
+                                const int l = __builtin_ctzll(m);
+                                if (grid_hit_wave(ev, G, lane_value(cx[k], l), lane_value(cy[k], l),
+                                                  lane_value(cz[k], l), lane_value(cr[k], l)))
+                                    col |= lane == l;
+                            }
+                        } else if (scan) {
+                            // the lanes of an edge hold neighbouring states whose spheres
+                            // mostly scan together: each lane scans its own
+                            col |= grid_hit(ev, G, cx[k], cy[k], cz[k], cr[k]);
+                        }
+                    }
                     if (EDGE) {
                         if (wave_ballot(col)) return true;
                     } else {
