@@ -56,6 +56,57 @@ def test_cloud_full_size_sampled(vk, orc):
     assert state_mismatches(flags[idx], cmin)[0] == 0
 
 
+def test_cloud_every_schedule(vk, orc, cloud):
+    """The cloud alone under each state schedule (one pass unsplit, two passes at three split
+    points): every state kernel scans the grid with the whole wave, one sphere at a time, and
+    a batch of 3,000 states leaves the last wave partly empty."""
+    w = cloud
+    env = {"spheres": w["env"]["spheres"][300:]}
+    q = uniform_states(rng("gpu-cloud", "q-sched"), 14, 3000)
+    cmin, _ = orc.states(w["robot"], env, q)
+    robot, e = vk.Robot(w["robot"]), vk.Env(env)
+    robot.set_states_ranges(0)
+    seen = []
+    for split in ((0, 1), (1, 3), (1, 2), (2, 3)):
+        robot.set_states_split(*split)
+        flags = host(vk.validate_states(robot, e, dev(q)))
+        bad, near = state_mismatches(flags, cmin)
+        say(f"  split {split}: mismatches {bad}, near {near}, rate {flags.mean():.3f}")
+        assert bad == 0
+        seen.append(flags)
+    for f in seen[1:]:
+        assert np.array_equal(f, seen[0])
+
+
+def test_dense_patch_long_rows(vk, orc, cloud):
+    """8,000 points on a 0.3 m square: a grid row then holds hundreds of points, so a sphere's
+    wave-wide scan takes several 64-point rounds per row (and the edge walk's per-lane scan
+    several three-point rounds)."""
+    w = cloud
+    g = rng("gpu-cloud", "patch")
+    n = 8000
+    pts = np.stack([g.uniform(0.4, 0.7, n), g.uniform(-0.15, 0.15, n),
+                    0.4 + g.normal(0.0, 0.003, n), np.full(n, 0.01)], axis=1)
+    env = {"spheres": pts.astype(np.float32)}
+    q = uniform_states(rng("gpu-cloud", "q-patch"), 14, 1000)
+    cmin, _ = orc.states(w["robot"], env, q)
+    robot, e = vk.Robot(w["robot"]), vk.Env(env)
+    for split in ((0, 1), (1, 2)):
+        robot.set_states_split(*split)
+        flags = host(vk.validate_states(robot, e, dev(q)))
+        bad, near = state_mismatches(flags, cmin)
+        say(f"  dense patch, split {split}: mismatches {bad}, near {near}, rate {flags.mean():.3f}")
+        assert bad == 0
+        assert 0.02 < flags.mean() < 0.98
+    qa = np.ascontiguousarray(q[:, :500].T)
+    qb = np.ascontiguousarray(qa + np.float32(0.1) * (q[:, 500:].T - qa))
+    eflags = host(vk.validate_edges(robot, e, dev(qa), dev(qb)))
+    _, cls, _ = orc.edges(w["robot"], env, qa, qb, res=1.0 / 32.0)
+    bad, near = edge_mismatches(eflags, cls)
+    say(f"  dense patch edges: mismatches {bad}, near {near}, rate {eflags.mean():.3f}")
+    assert bad == 0
+
+
 def test_cloud_cost(vk, orc, cloud):
     w = cloud
     env = {"spheres": w["env"]["spheres"]}
