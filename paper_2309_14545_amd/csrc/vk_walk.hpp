@@ -462,8 +462,9 @@ __device__ __forceinline__ void place_step(const P &pg, const StepRec &S, const 
 // robot sphere (c, r) only if its centre lies within r + gmax_r of c, i.e. in one of the cells
 // that the box c -+ (r + gmax_r) touches; the cells of one row are contiguous in the sorted
 // point array, so each (z, y) row of that box is one contiguous range [b, e) of it.
-// `row(b, e)` returns true to stop.
-template <class F>
+// `row(b, e)` returns true to stop.  With AHEAD the next row's bounds are loaded before the
+// current row is visited (for the wave-wide scan, where they are scalar loads).
+template <bool AHEAD = false, class F>
 __device__ __forceinline__ void grid_rows(const EnvView &ev, const GridDev &g, float cx, float cy,
                                           float cz, float r, F &&row) {
     const float *cell = ev.cell;
@@ -480,11 +481,31 @@ __device__ __forceinline__ void grid_rows(const EnvView &ev, const GridDev &g, f
     const int y0 = lo(cy, g.gorg[1]), y1 = hi(cy, g.gorg[1], g.gdim[1]);
     const int z0 = lo(cz, g.gorg[2]), z1 = hi(cz, g.gorg[2], g.gdim[2]);
     if (x0 > x1) return;
-    for (int z = z0; z <= z1; ++z)
-        for (int y = y0; y <= y1; ++y) {
-            const int rw = (z * g.gdim[1] + y) * g.gdim[0];
-            if (row(__float_as_int(cell[rw + x0]), __float_as_int(cell[rw + x1 + 1]))) return;
+    if (!AHEAD) {
+        for (int z = z0; z <= z1; ++z)
+            for (int y = y0; y <= y1; ++y) {
+                const int rw = (z * g.gdim[1] + y) * g.gdim[0];
+                if (row(__float_as_int(cell[rw + x0]), __float_as_int(cell[rw + x1 + 1]))) return;
+            }
+        return;
+    }
+    if (y0 > y1 || z0 > z1) return;
+    int z = z0, y = y0, rw = (z0 * g.gdim[1] + y0) * g.gdim[0];
+    int nb = __float_as_int(cell[rw + x0]), ne = __float_as_int(cell[rw + x1 + 1]);
+    for (;;) {
+        const int b = nb, e = ne;
+        if (++y > y1) {
+            y = y0;
+            ++z;
         }
+        const bool more = z <= z1;
+        if (more) {
+            rw = (z * g.gdim[1] + y) * g.gdim[0];
+            nb = __float_as_int(cell[rw + x0]);
+            ne = __float_as_int(cell[rw + x1 + 1]);
+        }
+        if (row(b, e) || !more) return;
+    }
 }
 
 // Every point of the rows above, one at a time; `visit(p)` returns true to stop.
@@ -547,7 +568,7 @@ __device__ __forceinline__ bool grid_hit_wave(const EnvView &ev, const GridDev &
                                               float cy, float cz, float r) {
     const int lane = threadIdx.x & (kWave - 1);
     bool hit = false;
-    grid_rows(ev, g, cx, cy, cz, r, [&](int b, int e) {
+    grid_rows<true>(ev, g, cx, cy, cz, r, [&](int b, int e) {
         for (int p0 = b; p0 < e; p0 += kWave) {
             const int p = min(p0 + lane, e - 1);
             if (wave_ballot(hit_sphere(cx, cy, cz, r, g.pts[p]))) {
