@@ -263,10 +263,10 @@ def extra_states(vk, name, n, steps):
             "schedule_split": list(tuned)}
 
 
-def extra_cost(vk, steps):
+def extra_cost(vk, steps, name="cost7", n=None):
     import torch
     from synthetic import workload
-    w = workload("cost7")
+    w = workload(name, n=n) if n else workload(name)
     robot, env = vk.Robot(w["robot"]), vk.Env(w["env"])
     q = torch.from_numpy(w["q"]).cuda()
     n = q.shape[1]
@@ -277,7 +277,7 @@ def extra_cost(vk, steps):
     bwd = _events_ms(lambda: vk.penetration_cost_bwd(robot, env, q, gc), steps)
     both = _events_ms(lambda: vk.penetration_cost_fwd_grad(robot, env, q), steps)
     f, b, fb = float(np.median(fwd)), float(np.median(bwd)), float(np.median(both))
-    return {"workload": "cost7", "states": n, "fwd_ms": f, "bwd_ms": b, "fwd_grad_ms": fb,
+    return {"workload": name, "states": n, "fwd_ms": f, "bwd_ms": b, "fwd_grad_ms": fb,
             "fwd_bwd_states_per_s": n / ((f + b) * 1e-3),
             "fwd_grad_states_per_s": n / (fb * 1e-3)}
 
@@ -570,6 +570,7 @@ def main():
                         ("states7_1M", lambda: extra_states(vk, "states7", 1 << 20, 10)),
                         ("states14_cloud", lambda: extra_states(vk, "states14_cloud", None, 5)),
                         ("cost7", lambda: extra_cost(vk, 10)),
+                        ("cost14_cloud", lambda: extra_cost(vk, 10, "states14_cloud", 1 << 16)),
                         ("prm7_shelf", lambda: extra_prm(vk, 10)),
                         ("shortcut7_shelf", lambda: extra_shortcut(vk, 10)),
                         ("rrt7_shelf", lambda: extra_rrt(vk)),

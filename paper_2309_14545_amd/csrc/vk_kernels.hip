@@ -379,16 +379,53 @@ __device__ float cost_walk(const RobotDev &rb, const EnvView &ev, const EnvDev &
                              sd_box(cx[k], cy[k], cz[k], X, Y, Z, O, gx, gy, gz))
             }
         }
-        if (ed.n_cells > 0 && live) {
+        if (ed.n_cells > 0) {
+            // the spheres whose neighbourhood may hold a point, one at a time, each by the whole
+            // wave: 64 points of a row per round, the penetration sums added over the wave
             const GridDev G = ld(ed.grid, 0);
-            if (point_clearance(G, Cx, Cy, Cz) < CR) {
+            const bool near = live && point_clearance(G, Cx, Cy, Cz) < CR;
+            if (wave_ballot(near)) {
+                const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
                 for (int k = 0; k < kSpl; ++k) {
-                    if (k >= cnt || point_clearance(G, cx[k], cy[k], cz[k]) >= cr[k]) continue;
-                    grid_scan(ev, G, cx[k], cy[k], cz[k], cr[k], [&](const float4 &o) {
-                        VK_PEN(sd_sphere(cx[k], cy[k], cz[k], o, gx, gy, gz))
-                        return false;
-                    });
+                    const bool scan = near && k < cnt &&
+                                      point_clearance(G, cx[k], cy[k], cz[k]) < cr[k];
+                    for (unsigned long long m = wave_ballot(scan); m; m &= m - 1) {
+                        const int l = __builtin_ctzll(m);
+                        const float sx = lane_value(cx[k], l), sy = lane_value(cy[k], l),
+                                    sz = lane_value(cz[k], l), sr = lane_value(cr[k], l);
+                        float c = 0.0f, ux = 0.0f, uy = 0.0f, uz = 0.0f;
+                        grid_rows<true>(ev, G, sx, sy, sz, sr, [&](int b, int e) {
+                            for (int p = b + lane; p - lane < e; p += kWave) {
+                                if (p >= e) continue;
+                                float gx, gy, gz;
+                                const float pen = sr - sd_sphere(sx, sy, sz, G.pts[p], gx, gy, gz);
+                                if (pen > 0.0f) {
+                                    c = fmaf(pen, pen, c);
+                                    if (GRAD) {
+                                        ux = fmaf(-2.0f * pen, gx, ux);
+                                        uy = fmaf(-2.0f * pen, gy, uy);
+                                        uz = fmaf(-2.0f * pen, gz, uz);
+                                    }
+                                }
+                            }
+                            return false;
+                        });
+                        c = wave_sum(c);
+                        if (GRAD) {
+                            ux = wave_sum(ux);
+                            uy = wave_sum(uy);
+                            uz = wave_sum(uz);
+                        }
+                        if (lane == l) {
+                            cost += c;
+                            if (GRAD) {
+                                fx[k] += ux;
+                                fy[k] += uy;
+                                fz[k] += uz;
+                            }
+                        }
+                    }
                 }
             }
         }

@@ -581,6 +581,12 @@ __device__ __forceinline__ bool grid_hit_wave(const EnvView &ev, const GridDev &
     return hit;
 }
 
+// Sum over the wave's 64 lanes, the same value (bit for bit) in every lane.
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
 // One lane's value, wave-uniform.
 __device__ __forceinline__ float lane_value(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));

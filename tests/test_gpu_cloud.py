@@ -98,6 +98,17 @@ def test_dense_patch_long_rows(vk, orc, cloud):
         say(f"  dense patch, split {split}: mismatches {bad}, near {near}, rate {flags.mean():.3f}")
         assert bad == 0
         assert 0.02 < flags.mean() < 0.98
+    # the cost: a sphere's points summed over several 64-point rounds per row
+    qc = q[:, :256]
+    c = host(vk.penetration_cost_fwd(robot, e, dev(qc))).astype(np.float64)
+    ref = orc.costs(w["robot"], env, qc)
+    assert (ref > 0).sum() > 10
+    assert np.all(np.abs(c - ref) <= 1e-6 + 2e-4 * ref)
+    g = host(vk.penetration_cost_bwd(robot, e, dev(qc), dev(np.ones(256, np.float32))))
+    gr = orc.cost_grads(w["robot"], env, qc)
+    rel = np.linalg.norm(g.astype(np.float64) - gr) / np.linalg.norm(gr)
+    say(f"  dense patch cost: {(ref > 0).sum()} states penetrate, gradient rel {rel:.2e}")
+    assert rel <= 1e-4
     qa = np.ascontiguousarray(q[:, :500].T)
     qb = np.ascontiguousarray(qa + np.float32(0.1) * (q[:, 500:].T - qa))
     eflags = host(vk.validate_edges(robot, e, dev(qa), dev(qb)))
@@ -120,6 +131,10 @@ def test_cloud_cost(vk, orc, cloud):
     rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
     say("  cloud cost gradient rel", rel)
     assert rel <= 1e-4
+    # the one-walk call sums the points' penetrations in the same order: bitwise the same
+    cf, gf = vk.penetration_cost_fwd_grad(vk.Robot(w["robot"]), vk.Env(env), dev(q))
+    np.testing.assert_array_equal(host(cf), c.astype(np.float32))
+    np.testing.assert_array_equal(host(gf), g.astype(np.float32))
 
 
 def test_small_sphere_sets_stay_flat(vk, orc):
