@@ -508,17 +508,6 @@ __device__ __forceinline__ void grid_rows(const EnvView &ev, const GridDev &g, f
     }
 }
 
-// Every point of the rows above, one at a time; `visit(p)` returns true to stop.
-template <class F>
-__device__ __forceinline__ void grid_scan(const EnvView &ev, const GridDev &g, float cx, float cy,
-                                          float cz, float r, F &&visit) {
-    grid_rows(ev, g, cx, cy, cz, r, [&](int b, int e) {
-        for (int p = b; p < e; ++p)
-            if (visit(g.pts[p])) return true;
-        return false;
-    });
-}
-
 // Lower bound of the clearance of location (x, y, z) to every point of the grid: the field's
 // value at the centre of the cell holding the location, less the distance to that centre
 // (clearance changes by at most the distance moved, so the bound holds whichever cell FP32
