@@ -406,7 +406,8 @@ vk_status vk_edge_batch_get_launch(vk_edge_batch batch, int32_t *block_threads,
 vk_status vk_edge_batch_destroy(vk_edge_batch batch);
 
 /*
- * Workspace.  The persistent edge launches need work-queue counters (32 KiB), two-pass
+ * Workspace.  The persistent edge launches need work-queue counters (33 slots of 32 KiB: a launch
+ * takes the next slot of a ring that one small launch zeroes whenever it wraps), two-pass
  * validate_states a survivor list (4 bytes per state) and vk_knn partial lists; they take them
  * from a workspace the library keeps per (device, stream).  vk_reserve creates it for `stream`
  * on the current device, or grows it to cover calls of up to max_states states (two-pass

@@ -92,8 +92,16 @@ int current_device() {
 // partial lists).  Calls on one stream are ordered, so they share it.  Only vk_reserve
 // allocates it; a grown workspace keeps its earlier buffers alive (a graph captured on the
 // stream may still point at them) until vk_release.
+// The queue counters come in kQueueRing + 1 slots of kQueueBytes.  The first kQueueRing are
+// handed out in turn, one per edge launch, and all zeroed by one small launch when the ring
+// wraps, so most launches need no reset of their own.  The last slot is zeroed by the launch
+// that takes it: edges split over several waves (their flags are zeroed with it) and launches
+// on a stream being captured into a graph (every replay of the graph must start from zero).
+constexpr int kQueueRing = 32;
+constexpr size_t kQueueSlotWords = (size_t)kQueues * kQueueWords;
 struct Workspace {
     unsigned long long *queue = nullptr;
+    int next_slot = kQueueRing;            // the ring's next clean slot; kQueueRing: all used
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     std::vector<void *> retired;
@@ -1566,6 +1574,37 @@ static void check_edges(vk_robot robot, vk_env env, const float *qa, const float
     if (n_edges > 0 && !collide) raise(VK_ERR_INVALID_ARG, "NULL edge array");
 }
 
+// A clean slot of the queue ring of (current device, s) for one launch; `wrapped` is set when
+// every slot has been used, and then all of them must be zeroed (in stream order) first.
+static int take_queue_slot(hipStream_t s, bool &wrapped) {
+    const int dev = current_device();
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace &w = g_ws.at(std::make_pair(dev, s));
+    wrapped = w.next_slot >= kQueueRing;
+    if (wrapped) w.next_slot = 0;
+    return w.next_slot++;
+}
+
+// Zero the counters of every ring slot with one launch.
+static hipError_t zero_queue_ring(unsigned long long *queue, hipStream_t s) {
+    KernelNode L;
+    fill_node(L, queue, 0ull, kQueueRing * kQueues, kQueueWords);
+    L.grid = dim3((kQueueRing * kQueues + kWave - 1) / kWave);
+    const hipError_t err = hipLaunchKernel(L.fn, L.grid, L.block, L.args, L.shmem, s);
+    return err != hipSuccess ? err : hipGetLastError();
+}
+
+// Is `s` being captured into a graph?  (A failed query counts as yes: the launch then takes the
+// slot it zeroes itself, which is right either way.)
+static bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) {
+        (void)hipGetLastError();
+        return true;
+    }
+    return cap != hipStreamCaptureStatusNone;
+}
+
 static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_edges,
                       float resolution, uint8_t *collide, unsigned long long *flops,
                       void *stream) {
@@ -1573,7 +1612,7 @@ static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_
     hipStream_t s = (hipStream_t)stream;
     const int dev = robot->device;
     const DeviceInfo &di = device_info(dev);
-    unsigned long long *queue = workspace_for(s, 0, "validate_edges").queue;
+    unsigned long long *const ring = workspace_for(s, 0, "validate_edges").queue;
     int block = robot->edge_block.load();
     const int bpc = robot->edge_bpc.load(), tickets = robot->edge_tickets.load();
     const int parts = robot->edge_parts.load();
@@ -1594,7 +1633,16 @@ static void run_edges(vk_robot robot, vk_env env, const EdgeSrc &src, int64_t n_
     // only the 1s: their flags are zeroed with the queue reset
     const bool spec = robot->use_spec.load() && robot->module;
     const bool multi = spec || parts > 1 || tparts > 1;
-    hip_check(launch_reset_queue(queue, s, multi ? collide : nullptr, n_edges), "queue reset");
+    unsigned long long *queue = nullptr;
+    if (multi || stream_capturing(s)) {
+        queue = ring + (size_t)kQueueRing * kQueueSlotWords;
+        hip_check(launch_reset_queue(queue, s, multi ? collide : nullptr, n_edges), "queue reset");
+    } else {
+        bool wrapped = false;
+        const int slot = take_queue_slot(s, wrapped);
+        if (wrapped) hip_check(zero_queue_ring(ring, s), "queue ring reset");
+        queue = ring + (size_t)slot * kQueueSlotWords;
+    }
     const EnvDev ed = env_for_launch(env, walk_lds_bytes(robot->dev, block));
     if (spec)
         hip_check(launch_validate_edges_spec(robot->spec, robot->dev, ed, src, n_edges, resolution,
@@ -2067,7 +2115,7 @@ static void reserve_workspace(hipStream_t s, size_t bytes) {
                             "grow; reserve before the capture");
     if (need_queue) {
         void *p = nullptr;
-        hip_check(hipMalloc(&p, kQueueBytes), "vk_reserve: queue counters");
+        hip_check(hipMalloc(&p, (kQueueRing + 1) * kQueueBytes), "vk_reserve: queue counters");
         w.queue = static_cast<unsigned long long *>(p);
     }
     if (need_scratch) {

@@ -270,3 +270,36 @@ def test_small_batches_split_over_test_ranges(vk, orc, name):
     say(f"test ranges {name}: {len(auto)} edges, rate {auto.mean():.3f}, sample mismatches {bad}, "
         f"near {near}")
     assert bad == 0
+
+
+def test_queue_ring_over_many_launches(vk, orc):
+    """Edge launches take the slots of the stream's queue ring in turn and the ring is zeroed
+    when it wraps: 80 launches in a row (two and a half wraps), without a synchronisation
+    between them, interleaved with split launches (which zero a slot of their own), on a second
+    stream too, all give the first launch's flags, and those agree with the oracle."""
+    import torch
+    w = workload("edges7_shelf", n=300)
+    r, e = vk.Robot(w["robot"]), vk.Env(w["env"])
+    qa, qb = dev(w["qa"]), dev(w["qb"])
+    r.set_edge_ranges(0)
+    ref = host(vk.validate_edges(r, e, qa, qb)).copy()
+    _, cls, _ = orc.edges(w["robot"], w["env"], w["qa"], w["qb"], res=1.0 / 32.0)
+    assert edge_mismatches(ref, cls)[0] == 0 and 0 < ref.mean() < 1
+    r.set_edge_ranges(-1)
+    small_ref = ref[:17]
+    outs, smalls = [], []
+    for i in range(80):
+        outs.append(vk.validate_edges(r, e, qa, qb))
+        if i % 7 == 3:                        # 17 edges: split over test ranges automatically
+            smalls.append(vk.validate_edges(r, e, qa[:17].contiguous(), qb[:17].contiguous()))
+    for o in outs:
+        np.testing.assert_array_equal(host(o), ref)
+    for o in smalls:
+        np.testing.assert_array_equal(host(o), small_ref)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        got = [vk.validate_edges(r, e, qa, qb) for _ in range(40)]
+    side.synchronize()
+    for o in got:
+        np.testing.assert_array_equal(host(o), ref)
